@@ -1,0 +1,175 @@
+"""ctypes wrapper around the plain C FP64 oracle (test infrastructure only).
+
+Every function here marshals numpy arrays into the C routines of
+qsl_oracle.c; no arithmetic of the method is done in Python.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qsl_oracle.c")
+_LIB = os.path.join(_HERE, "libqsl_oracle.so")
+_lib = None
+
+_dp = ct.POINTER(ct.c_double)
+_ip = ct.POINTER(ct.c_int32)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no FP contraction)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-shared",
+           "-fPIC", "-std=c99", "-D_DEFAULT_SOURCE", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _Sys(ct.Structure):
+    _fields_ = [("n_atoms", ct.c_int32), ("atom_xyz", _dp),
+                ("n_shells", ct.c_int32), ("shell_atom", _ip), ("shell_l", _ip),
+                ("shell_nprim", _ip), ("prim_exp", _dp), ("prim_coef", _dp),
+                ("n_up", ct.c_int32), ("n_dn", ct.c_int32), ("screen_T", ct.c_double)]
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ct.CDLL(_LIB)
+        S = ct.POINTER(_Sys)
+        lib.orc_n_basis.argtypes = [S]
+        lib.orc_n_basis.restype = ct.c_int
+        lib.orc_normalize.argtypes = [S, _dp]
+        lib.orc_cart_factor.argtypes = [ct.c_int] * 4
+        lib.orc_cart_factor.restype = ct.c_double
+        lib.orc_ao_eval.argtypes = [S, _dp, _ip, _dp, ct.c_int, _ip]
+        lib.orc_ao_eval.restype = ct.c_int
+        lib.orc_lu_inverse.argtypes = [_dp, ct.c_int, _dp, _dp, _ip]
+        lib.orc_lu_inverse.restype = ct.c_int
+        lib.orc_forward.argtypes = [S, _dp, _dp, ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ct.POINTER(ct.c_int8), _dp, _dp, _dp, _dp,
+                                    ct.POINTER(ct.c_uint32), ct.c_int32]
+        lib.orc_backward.argtypes = [S, _dp, _dp, ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     _dp, ct.c_int32]
+        lib.orc_max_threads.restype = ct.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a, t=_dp):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+class OracleSystem:
+    """Holds contiguous copies of a system description for the C oracle."""
+
+    def __init__(self, sys):
+        self.xyz = np.ascontiguousarray(sys.atom_xyz, np.float64)
+        self.sa = np.ascontiguousarray(sys.shell_atom, np.int32)
+        self.sl = np.ascontiguousarray(sys.shell_l, np.int32)
+        self.sn = np.ascontiguousarray(sys.shell_nprim, np.int32)
+        self.ex = np.ascontiguousarray(sys.prim_exp, np.float64)
+        self.co = np.ascontiguousarray(sys.prim_coef, np.float64)
+        self.n_up, self.n_dn = int(sys.n_up), int(sys.n_dn)
+        self.T = float(sys.screen_T)
+        self.c = _Sys(self.xyz.shape[0], _p(self.xyz), self.sl.shape[0], _p(self.sa, _ip),
+                      _p(self.sl, _ip), _p(self.sn, _ip), _p(self.ex), _p(self.co),
+                      self.n_up, self.n_dn, self.T)
+
+    @property
+    def ref(self):
+        return ct.byref(self.c)
+
+
+def _osys(sys):
+    return sys if isinstance(sys, OracleSystem) else OracleSystem(sys)
+
+
+def n_basis(sys) -> int:
+    o = _osys(sys)
+    return load().orc_n_basis(o.ref)
+
+
+def normalize(sys) -> np.ndarray:
+    o = _osys(sys)
+    out = np.zeros_like(o.co)
+    load().orc_normalize(o.ref, _p(out))
+    return out
+
+
+def cart_factor(l, a, b, c) -> float:
+    return load().orc_cart_factor(l, a, b, c)
+
+
+def ao_eval(sys, r):
+    """Screened AOs at one point: (idx[s], B[5, s], near_tie)."""
+    o = _osys(sys)
+    nb = n_basis(o)
+    idx = np.zeros(nb + 1, np.int32)
+    B = np.zeros((5, nb + 1))
+    nt = np.zeros(1, np.int32)
+    r = np.ascontiguousarray(r, np.float64)
+    n = load().orc_ao_eval(o.ref, _p(r), _p(idx, _ip), _p(B), nb + 1, _p(nt, _ip))
+    return idx[:n].copy(), B[:, :n].copy(), bool(nt[0])
+
+
+def lu_inverse(m):
+    m = np.ascontiguousarray(m, np.float64)
+    n = m.shape[0]
+    inv = np.zeros_like(m)
+    ld = np.zeros(1)
+    sg = np.zeros(1, np.int32)
+    ok = load().orc_lu_inverse(_p(m), n, _p(inv), _p(ld), _p(sg, _ip))
+    return bool(ok), float(ld[0]), int(sg[0]), inv
+
+
+def forward(sys, A_up, A_dn, R, want_abs=False, nthreads=0):
+    """Full FP64 forward.  Returns a dict of numpy arrays."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, np.float64)
+    W, N = R.shape[0], R.shape[1]
+    nu, nd = o.n_up, o.n_dn
+    A_up = np.ascontiguousarray(A_up, np.float64)
+    A_dn = np.ascontiguousarray(A_dn, np.float64)
+    out = dict(
+        C_up=np.zeros((W, 5, nu, nu)), C_dn=np.zeros((W, 5, nd, nd)),
+        logdet=np.zeros((W, 2)), sign=np.zeros((W, 2), np.int8),
+        Dinv_up=np.zeros((W, nu, nu)), Dinv_dn=np.zeros((W, nd, nd)),
+        drift=np.zeros((W, N, 3)), lap=np.zeros((W, N)), status=np.zeros(W, np.uint32))
+    if want_abs:
+        out["Cabs_up"] = np.zeros((W, 5, nu, nu))
+        out["Cabs_dn"] = np.zeros((W, 5, nd, nd))
+    load().orc_forward(o.ref, _p(A_up), _p(A_dn), W, _p(R), _p(out["C_up"]), _p(out["C_dn"]),
+                       _p(out.get("Cabs_up")), _p(out.get("Cabs_dn")), _p(out["logdet"]),
+                       _p(out["sign"], ct.POINTER(ct.c_int8)), _p(out["Dinv_up"]),
+                       _p(out["Dinv_dn"]), _p(out["drift"]), _p(out["lap"]),
+                       _p(out["status"], ct.POINTER(ct.c_uint32)), int(nthreads))
+    return out
+
+
+def backward(sys, A_up, A_dn, R, Dinv_up, Dinv_dn, g, nthreads=0):
+    """Adjoint of log|det|: returns (dR[W,N,3], dA_up, dA_dn)."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, np.float64)
+    W, N = R.shape[0], R.shape[1]
+    A_up = np.ascontiguousarray(A_up, np.float64)
+    A_dn = np.ascontiguousarray(A_dn, np.float64)
+    Dinv_up = np.ascontiguousarray(Dinv_up, np.float64)
+    Dinv_dn = np.ascontiguousarray(Dinv_dn, np.float64)
+    g = np.ascontiguousarray(g, np.float64)
+    dR = np.zeros((W, N, 3))
+    dA_up = np.zeros_like(A_up)
+    dA_dn = np.zeros_like(A_dn)
+    load().orc_backward(o.ref, _p(A_up), _p(A_dn), W, _p(R), _p(Dinv_up), _p(Dinv_dn), _p(g),
+                        _p(dR), _p(dA_up), _p(dA_dn), int(nthreads))
+    return dR, dA_up, dA_dn
+
+
+def max_threads() -> int:
+    return int(load().orc_max_threads())

@@ -1,0 +1,7 @@
+"""Seeded synthetic inputs shared by the FP64 oracle and the GPU library.
+
+This package only draws random numbers and lays them out; it contains none
+of the method's arithmetic (no normalisation, no screening, no AO values, no
+products, no determinants).
+"""
+from .gen import CONFIGS, make_system, make_mos, make_walkers, make_config  # noqa: F401
