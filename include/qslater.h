@@ -1,0 +1,225 @@
+/*
+ * qslater.h -- C ABI of the MI355X (gfx950) Slater-matrix builder.
+ *
+ * The library computes, for a batch of QMC walkers, the quantities of
+ * Scemama, Caffarel, Oseret, Jalby, "Quantum Monte Carlo for large chemical
+ * systems" (arXiv:1209.6630):
+ *
+ *   AOs      chi(r) = (x-Qx)^nx (y-Qy)^ny (z-Qz)^nz sum_k c_k exp(-gamma_k |r-Q|^2)
+ *            (section "The quantum Monte Carlo method", critical CPU part,
+ *            equations for chi and g), screened as in section "Exploiting the
+ *            highly localized character of atomic basis functions";
+ *   MOs      phi_i(r) = sum_j a_ij chi_j(r)                    (equation (mo));
+ *   products C_n = A B_n, n = 1..5: values, d/dx, d/dy, d/dz, Laplacian
+ *            of the MOs at every electron of a spin                (equation (abc));
+ *   Slater   D_ij = phi_i(r_j); log|det D|, sign, D^-1 (Slater determinant
+ *            equation; inversion step of section "Overall performance");
+ *   drift    sum_j D^(1)_{l,ij} D^-1_ji and Laplacian sum_j D^(2)_{l,ij} D^-1_ji
+ *            (the two "vector products" equations of the critical CPU part);
+ *   adjoint  d(sum_w g_w . logdet_w)/dA and /dR (not in the paper: chain rule
+ *            through equation (mo) and the Slater matrix definition).
+ *
+ * Conventions used by every call:
+ *   - AO order: atom-major, shells in the order given, Cartesian components
+ *     x,y,z for p and xx,xy,xz,yy,yz,zz for d.  qsl_ao_info reports it.
+ *   - Screening: primitive k is kept iff gamma_k * r^2 <= screen_T, decided in
+ *     FP64 as r^2 = (dx*dx + dy*dy) + dz*dz without fused multiply-add, in
+ *     every precision mode.  A shell with no kept primitive contributes 0.
+ *   - Every Cartesian AO has unit norm (the library normalises the raw
+ *     contraction weights).
+ *   - Electrons of a walker: the first n_up are spin up, the next n_dn down.
+ *   - Per spin s with n = n_s: C^s is stored [W][5][n][n] as C[w][c][e][i]
+ *     (electron e, MO i fastest); D[i][e] = C[w][0][e][i]; Dinv^s is stored
+ *     [W][n][n] as Dinv[w][e][i] with sum_i Dinv[e][i] D[i][e'] = delta.
+ *   - Pointers named "device" must be device memory of the current HIP
+ *     device; the library never frees caller memory.
+ *   - Every call returns a qsl_status; no C++ exception crosses the ABI.
+ *     qsl_last_error() returns a thread-local description of the last
+ *     failure.  Numerical conditions (singular D, near-tie screening, non
+ *     finite values) are reported per walker in `status`, not as errors.
+ *   - Calls that take a stream only enqueue work on that stream (a
+ *     hipStream_t passed as void*; NULL is the default stream).
+ *   - A qsl_system must not be modified (qsl_set_mo) while a call that
+ *     reads it is in flight.  Calls on different streams with separate
+ *     workspaces may overlap.
+ */
+#ifndef QSLATER_H
+#define QSLATER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QSL_OK = 0,
+    QSL_ERR_INVALID_ARG = 1,  /* NULL where required, bad value, bad spin */
+    QSL_ERR_UNSUPPORTED = 2,  /* l > 2, too many primitives, size limit   */
+    QSL_ERR_SHAPE = 3,        /* sizes that do not match the system       */
+    QSL_ERR_WORKSPACE = 4,    /* workspace NULL or smaller than required  */
+    QSL_ERR_HIP = 5,          /* a HIP runtime call failed (see last_error) */
+    QSL_ERR_OOM = 6           /* device allocation failed                 */
+} qsl_status;
+
+/* Arithmetic of the AO->MO products (equation (abc)).  Screening is FP64
+ * in every mode; LU, log|det|, inverse, drift and Laplacian are FP64. */
+typedef enum {
+    QSL_FP64 = 0,   /* AOs FP64, products FP64 (MFMA f64); C is double  */
+    QSL_FP32 = 1,   /* AOs FP32, products FP32 (MFMA f32); C is float   */
+    QSL_BF16X3 = 2  /* AOs FP32, products as hi/lo BF16 split, three BF16
+                       MFMA products with FP32 accumulation; C is float  */
+} qsl_mode;
+
+/* Per-walker status bits. */
+#define QSL_STATUS_SINGULAR 1u   /* an exact zero pivot: logdet=-inf, sign=0 */
+#define QSL_STATUS_NEAR_TIE 2u   /* some kept/dropped primitive had
+                                    |gamma r^2 - T| <= 1e-12 T (best effort) */
+#define QSL_STATUS_NONFINITE 4u  /* a non-finite logdet/drift/Laplacian     */
+
+/* Limits. */
+#define QSL_LMAX 2
+#define QSL_PMAX 8               /* primitives per shell */
+
+typedef struct qsl_system qsl_system;
+
+/* System description (host memory; copied by qsl_system_create). */
+typedef struct {
+    int32_t n_atoms;
+    const double* atom_xyz;     /* [n_atoms][3], bohr                           */
+    int32_t n_shells;
+    const int32_t* shell_atom;  /* [n_shells], non-decreasing (atom-major)      */
+    const int32_t* shell_l;     /* [n_shells], 0..QSL_LMAX                      */
+    const int32_t* shell_nprim; /* [n_shells], 1..QSL_PMAX                      */
+    const double* prim_exp;     /* [sum nprim], gamma_k > 0                      */
+    const double* prim_coef;    /* [sum nprim], raw contraction weights d_k      */
+    int32_t n_up, n_dn;         /* electrons per spin, n_up >= n_dn >= 0         */
+    double screen_T;            /* screening threshold T (<= 0 means 30)        */
+    uint32_t flags;             /* reserved, must be 0                           */
+} qsl_system_desc;
+
+/*
+ * Create a system: validates the description, normalises the contraction
+ * weights, builds the AO order and the device tables (atoms, shells,
+ * primitives, padded AO slots).  Everything is copied; the caller keeps its
+ * arrays.  Allocates device memory on the current device.
+ * Errors: INVALID_ARG (NULL, n_up < n_dn, non-finite coordinate, gamma <= 0,
+ * shell_atom not non-decreasing or out of range), UNSUPPORTED (l > 2,
+ * nprim > QSL_PMAX), OOM, HIP.
+ */
+qsl_status qsl_system_create(const qsl_system_desc* desc, qsl_system** out);
+
+/* Free a system and its device tables.  NULL is accepted. */
+qsl_status qsl_system_destroy(qsl_system* sys);
+
+/* Number of AOs N_b (the column count of A^s). Returns -1 for NULL. */
+int64_t qsl_n_basis(const qsl_system* sys);
+
+/*
+ * AO order: for AO j, ao_atom[j], ao_shell[j] and its powers
+ * ao_nxyz[3j..3j+2] = (nx, ny, nz).  Host arrays of N_b (3 N_b) entries;
+ * any may be NULL.
+ */
+qsl_status qsl_ao_info(const qsl_system* sys, int32_t* ao_atom, int32_t* ao_shell,
+                       int8_t* ao_nxyz);
+
+/*
+ * Set the MO coefficients a_ij of spin s (0 = up, 1 = down): A is n_s x N_b,
+ * row-major with leading dimension ld >= N_b (equation (mo)), in host memory
+ * (on_device = 0) or device memory (on_device = 1).  The library keeps its
+ * own FP64, FP32 and hi/lo BF16 copies in its padded layout (A is constant
+ * between calls).  Enqueued on `stream`; A may be reused once the stream has
+ * passed this call (host A: as soon as the call returns).
+ * Errors: INVALID_ARG (spin, NULL, ld < N_b), HIP.
+ */
+qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld,
+                      int32_t on_device, void* stream);
+
+/* Forward arguments.  Output pointers are device memory.  C and Dinv are
+ * required (the inversion reads C_1, the drift reads Dinv); logdet, sign,
+ * drift, lap and status may be NULL to skip them. */
+typedef struct {
+    int64_t W;                /* walkers                                        */
+    const double* R;          /* [W][n_up+n_dn][3] device, bohr                  */
+    int32_t mode;             /* qsl_mode                                        */
+    void* C[2];               /* per spin [W][5][n_s][n_s]: double (FP64) or float */
+    double* logdet;           /* [W][2]  natural log |det D^s|                   */
+    int8_t* sign;             /* [W][2]  -1, 0, +1                                */
+    double* Dinv[2];          /* per spin [W][n_s][n_s]                           */
+    double* drift;            /* [W][n_up+n_dn][3]: (1/Det) dDet/dx_e             */
+    double* lap;              /* [W][n_up+n_dn]:    (1/Det) lap_e Det             */
+    uint32_t* status;         /* [W] QSL_STATUS_* bits                            */
+    void* ws;                 /* device workspace (see qsl_workspace_size)        */
+    size_t ws_bytes;
+} qsl_fwd_args;
+
+/*
+ * Device workspace bytes needed by qsl_forward / qsl_backward for W walkers
+ * in `mode`.  The same workspace may serve both calls (not concurrently).
+ * Errors: INVALID_ARG.
+ */
+qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, size_t* bytes);
+
+/*
+ * Forward: screening and compaction of the surviving AO windows per tile of
+ * electrons, fused AO evaluation + AO->MO products on MFMA, FP64
+ * Gauss-Jordan elimination with partial pivoting for log|det|, sign and
+ * D^-1, then drift and Laplacian.  Enqueued on `stream`.
+ * Errors: INVALID_ARG (NULL R, W < 0, bad mode, MOs of a spin never set),
+ * WORKSPACE, UNSUPPORTED (a spin with more electrons than the inversion
+ * supports), HIP.
+ */
+qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* args, void* stream);
+
+/* Backward arguments (adjoint of L = sum_w sum_s g[w][s] logdet[w][s]). */
+typedef struct {
+    int64_t W;
+    const double* R;          /* [W][N][3] device, as given to the forward        */
+    int32_t mode;             /* products in this mode (as the forward)           */
+    const double* Dinv[2];    /* per spin [W][n_s][n_s] from the forward          */
+    const double* g_logdet;   /* [W][2] device: dL/dlogdet                        */
+    double* dR;               /* [W][N][3] device, overwritten (NULL: skip)       */
+    double* dA[2];            /* per spin [n_s][N_b] device (NULL: skip)          */
+    int32_t accumulate_dA;    /* 1: dA += ..., 0: dA = ...                        */
+    void* ws;
+    size_t ws_bytes;
+} qsl_bwd_args;
+
+/*
+ * Backward: recomputes the AO values and gradients (never stored by the
+ * forward), forms G = g D^-1, H = A^T G at the surviving AOs for dR, and
+ * accumulates dA over walkers.  Derivatives hold the screened survivor sets
+ * fixed.  Walkers flagged singular must have g = 0.  Enqueued on `stream`.
+ * Errors: INVALID_ARG, WORKSPACE, HIP.
+ */
+qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* args, void* stream);
+
+/*
+ * Kernel timing (for benchmarks and profilers).  While enabled, every
+ * kernel the library enqueues is bracketed by two HIP events recorded on the
+ * stream it is launched on; qsl_profile_read synchronises those events and
+ * returns, per kernel name, the number of launches and their summed
+ * duration in milliseconds.  `reset` = 1 clears the accumulated records.
+ * Process-wide; not thread-safe against concurrent enqueues.
+ * Errors: INVALID_ARG (NULL count), HIP.
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} qsl_kernel_time;
+
+qsl_status qsl_profile_enable(int32_t on);
+qsl_status qsl_profile_read(qsl_kernel_time* out, int32_t capacity, int32_t* count, int32_t reset);
+
+/* Text of a status code (static storage). */
+const char* qsl_status_string(qsl_status s);
+
+/* Thread-local description of the last error ("" if none). */
+const char* qsl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QSLATER_H */

@@ -1,0 +1,201 @@
+"""Python binding of the Slater-matrix builder: argument marshalling only.
+
+Torch supplies device memory and the current HIP stream; every step of the
+computation runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import BwdArgs, FwdArgs, MODES, SystemDesc, check, lib
+
+
+def _ptr(t):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def mode_id(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+class System:
+    """A molecular system (atoms, contracted Cartesian Gaussian shells) and the
+    MO coefficients of both spins, resident on the current GPU."""
+
+    def __init__(self, atom_xyz, shell_atom, shell_l, shell_nprim, prim_exp, prim_coef,
+                 n_up, n_dn, screen_T=30.0):
+        self._keep = [np.ascontiguousarray(atom_xyz, np.float64),
+                      np.ascontiguousarray(shell_atom, np.int32),
+                      np.ascontiguousarray(shell_l, np.int32),
+                      np.ascontiguousarray(shell_nprim, np.int32),
+                      np.ascontiguousarray(prim_exp, np.float64),
+                      np.ascontiguousarray(prim_coef, np.float64)]
+        xyz, sa, sl, sn, ex, co = self._keep
+        dp, ip = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int32)
+        desc = SystemDesc(xyz.shape[0], xyz.ctypes.data_as(dp), sl.shape[0], sa.ctypes.data_as(ip),
+                          sl.ctypes.data_as(ip), sn.ctypes.data_as(ip), ex.ctypes.data_as(dp),
+                          co.ctypes.data_as(dp), int(n_up), int(n_dn), float(screen_T), 0)
+        h = ct.c_void_p()
+        check(lib().qsl_system_create(ct.byref(desc), ct.byref(h)))
+        self._h = h
+        self.n_up, self.n_dn = int(n_up), int(n_dn)
+        self.n_basis = int(lib().qsl_n_basis(h))
+        self._ws = {}
+
+    @classmethod
+    def from_synth(cls, s):
+        return cls(s.atom_xyz, s.shell_atom, s.shell_l, s.shell_nprim, s.prim_exp, s.prim_coef,
+                   s.n_up, s.n_dn, s.screen_T)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qsl_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_elec(self):
+        return self.n_up + self.n_dn
+
+    def n_spin(self, spin):
+        return self.n_dn if spin else self.n_up
+
+    def ao_info(self):
+        nb = self.n_basis
+        at = np.zeros(nb, np.int32)
+        sh = np.zeros(nb, np.int32)
+        nxyz = np.zeros(3 * nb, np.int8)
+        check(lib().qsl_ao_info(self._h, at.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                sh.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                                nxyz.ctypes.data_as(ct.POINTER(ct.c_int8))))
+        return at, sh, nxyz.reshape(nb, 3)
+
+    def set_mo(self, spin, A):
+        """A: [n_spin, N_basis] float64, a CUDA tensor or a host array."""
+        if isinstance(A, torch.Tensor) and A.is_cuda:
+            A = A.to(torch.float64).contiguous()
+            check(lib().qsl_set_mo(self._h, spin, _ptr(A), A.shape[1], 1, _stream()))
+            torch.cuda.current_stream().synchronize()
+        else:
+            a = np.ascontiguousarray(np.asarray(A, np.float64))
+            check(lib().qsl_set_mo(self._h, spin, ct.c_void_p(a.ctypes.data), a.shape[1], 0, _stream()))
+
+    def workspace(self, W, mode):
+        n = ct.c_size_t()
+        check(lib().qsl_workspace_size(self._h, int(W), mode_id(mode), ct.byref(n)))
+        key = torch.cuda.current_device()
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < n.value:
+            ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+            self._ws[key] = ws
+        return ws
+
+    def alloc_outputs(self, W, mode, drift=True):
+        dev = "cuda"
+        cdt = torch.float64 if mode_id(mode) == 0 else torch.float32
+        nu, nd, N = self.n_up, self.n_dn, self.n_elec
+        out = dict(
+            C_up=torch.empty((W, 5, nu, nu), dtype=cdt, device=dev),
+            C_dn=torch.empty((W, 5, nd, nd), dtype=cdt, device=dev),
+            logdet=torch.empty((W, 2), dtype=torch.float64, device=dev),
+            sign=torch.empty((W, 2), dtype=torch.int8, device=dev),
+            Dinv_up=torch.empty((W, nu, nu), dtype=torch.float64, device=dev),
+            Dinv_dn=torch.empty((W, nd, nd), dtype=torch.float64, device=dev),
+            status=torch.empty((W,), dtype=torch.int32, device=dev),
+        )
+        if drift:
+            out["drift"] = torch.empty((W, N, 3), dtype=torch.float64, device=dev)
+            out["lap"] = torch.empty((W, N), dtype=torch.float64, device=dev)
+        return out
+
+    def forward(self, R, mode="fp64", out=None, drift=True):
+        """R: CUDA float64 [W, N, 3].  Returns a dict of CUDA tensors."""
+        assert R.is_cuda and R.dtype == torch.float64 and R.is_contiguous()
+        W = R.shape[0]
+        assert R.shape[1:] == (self.n_elec, 3), "R must be [W, n_up+n_dn, 3]"
+        if out is None:
+            out = self.alloc_outputs(W, mode, drift)
+        ws = self.workspace(W, mode)
+        a = FwdArgs()
+        a.W = W
+        a.R = R.data_ptr()
+        a.mode = mode_id(mode)
+        a.C[0] = out["C_up"].data_ptr()
+        a.C[1] = out["C_dn"].data_ptr()
+        a.logdet = out["logdet"].data_ptr()
+        a.sign = out["sign"].data_ptr()
+        a.Dinv[0] = out["Dinv_up"].data_ptr()
+        a.Dinv[1] = out["Dinv_dn"].data_ptr()
+        a.drift = out["drift"].data_ptr() if "drift" in out else None
+        a.lap = out["lap"].data_ptr() if "lap" in out else None
+        a.status = out["status"].data_ptr()
+        a.ws = ws.data_ptr()
+        a.ws_bytes = ws.numel()
+        check(lib().qsl_forward(self._h, ct.byref(a), _stream()))
+        return out
+
+    def backward(self, R, Dinv_up, Dinv_dn, g, mode="fp64", dR=None, dA=None, accumulate=False,
+                 want_dR=True, want_dA=True):
+        """Adjoint of sum g[w,s] logdet[w,s].  Returns (dR, dA_up, dA_dn)."""
+        W = R.shape[0]
+        dev = "cuda"
+        if want_dR and dR is None:
+            dR = torch.empty((W, self.n_elec, 3), dtype=torch.float64, device=dev)
+        if want_dA and dA is None:
+            dA = (torch.zeros((self.n_up, self.n_basis), dtype=torch.float64, device=dev),
+                  torch.zeros((self.n_dn, self.n_basis), dtype=torch.float64, device=dev))
+        g = g.to(torch.float64).contiguous()
+        ws = self.workspace(W, mode)
+        a = BwdArgs()
+        a.W = W
+        a.R = R.data_ptr()
+        a.mode = mode_id(mode)
+        a.Dinv[0] = Dinv_up.data_ptr()
+        a.Dinv[1] = Dinv_dn.data_ptr()
+        a.g_logdet = g.data_ptr()
+        a.dR = dR.data_ptr() if want_dR else None
+        a.dA[0] = dA[0].data_ptr() if want_dA else None
+        a.dA[1] = dA[1].data_ptr() if want_dA else None
+        a.accumulate_dA = 1 if accumulate else 0
+        a.ws = ws.data_ptr()
+        a.ws_bytes = ws.numel()
+        check(lib().qsl_backward(self._h, ct.byref(a), _stream()))
+        return dR, (dA[0] if want_dA else None), (dA[1] if want_dA else None)
+
+
+class SlaterLogDet(torch.autograd.Function):
+    """logdet[W, 2] of the up/down Slater matrices; differentiable in R, A_up
+    and A_dn through the library's hand-written adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, R, A_up, A_dn, system, mode="fp64"):
+        system.set_mo(0, A_up.detach())
+        system.set_mo(1, A_dn.detach())
+        out = system.forward(R.detach().contiguous(), mode)
+        ctx.system, ctx.mode = system, mode
+        ctx.save_for_backward(R.detach(), out["Dinv_up"], out["Dinv_dn"])
+        ctx.mark_non_differentiable(out["sign"])
+        return out["logdet"], out["sign"]
+
+    @staticmethod
+    def backward(ctx, g_logdet, _g_sign):
+        R, Di_up, Di_dn = ctx.saved_tensors
+        dR, dA_up, dA_dn = ctx.system.backward(R, Di_up, Di_dn, g_logdet, ctx.mode)
+        return dR, dA_up, dA_dn, None, None
+
+
+def slater_logdet(R, A_up, A_dn, system, mode="fp64"):
+    return SlaterLogDet.apply(R, A_up, A_dn, system, mode)

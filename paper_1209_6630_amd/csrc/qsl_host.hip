@@ -1,0 +1,515 @@
+// Host side of the C ABI: validation, normalisation of the contraction
+// weights, the padded AO-slot layout, device tables and the orchestration
+// of the kernels on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qsl_internal.h"
+
+namespace qsl {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static qsl_status hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return QSL_ERR_HIP;
+}
+
+static qsl_status bad(qsl_status code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+// (2m-1)!! for m = 0..2
+static double odd_fact(int m) { return m == 2 ? 3.0 : 1.0; }
+
+// Cartesian powers of component c of a shell with angular momentum l.
+static void powers(int l, int c, int p[3]) {
+    static const int P1[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+    static const int P2[6][3] = {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}};
+    for (int k = 0; k < 3; ++k) p[k] = l == 0 ? 0 : (l == 1 ? P1[c][k] : P2[c][k]);
+}
+
+// Byte arena: host staging of all device tables, copied in one transfer.
+struct Arena {
+    std::vector<char> buf;
+    size_t add(const void* src, size_t bytes) {
+        size_t off = (buf.size() + 255) & ~size_t(255);
+        buf.resize(off + std::max<size_t>(bytes, 1));
+        if (bytes) memcpy(buf.data() + off, src, bytes);
+        return off;
+    }
+    size_t reserve(size_t bytes) {
+        size_t off = (buf.size() + 255) & ~size_t(255);
+        buf.resize(off + std::max<size_t>(bytes, 1));
+        return off;
+    }
+};
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void fill_f64_kernel(double* p, double v, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Kernels instead of hipMemsetAsync so that callers may capture the
+// sequence into a graph.
+static hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    fill_u32_kernel<<<blocks, 256, 0, st>>>(p, v, n);
+    return hipGetLastError();
+}
+static hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    fill_f64_kernel<<<blocks, 256, 0, st>>>(p, v, n);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- profiling
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof_pending;
+struct ProfAgg {
+    std::string name;
+    int64_t launches;
+    double ms;
+};
+static std::vector<ProfAgg> g_prof_agg;
+
+ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+    if (!g_prof_on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+    hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    hipEventRecord(b, st);
+    g_prof_pending.push_back({name, a, b});
+}
+
+// Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win].
+struct WsLayout {
+    size_t nwin_off[2], win_off[2], total;
+};
+
+static WsLayout ws_layout(const DevSys& d, int64_t W) {
+    WsLayout L{};
+    size_t off = 0;
+    for (int s = 0; s < 2; ++s) {
+        int n = n_spin(d, s);
+        size_t tiles = n ? (size_t)W * tiles_per_walker(n) : 0;
+        L.nwin_off[s] = off;
+        off = round_up(off + tiles * sizeof(int), 256);
+        L.win_off[s] = off;
+        off = round_up(off + tiles * (size_t)d.n_win * sizeof(int), 256);
+    }
+    L.total = std::max<size_t>(off, 256);
+    return L;
+}
+
+}  // namespace qsl
+
+using namespace qsl;
+
+extern "C" {
+
+const char* qsl_status_string(qsl_status s) {
+    switch (s) {
+        case QSL_OK: return "ok";
+        case QSL_ERR_INVALID_ARG: return "invalid argument";
+        case QSL_ERR_UNSUPPORTED: return "unsupported";
+        case QSL_ERR_SHAPE: return "shape mismatch";
+        case QSL_ERR_WORKSPACE: return "workspace too small";
+        case QSL_ERR_HIP: return "HIP runtime error";
+        case QSL_ERR_OOM: return "out of device memory";
+    }
+    return "unknown status";
+}
+
+const char* qsl_last_error(void) { return g_last_error.c_str(); }
+
+qsl_status qsl_profile_enable(int32_t on) {
+    g_prof_on = on != 0;
+    return QSL_OK;
+}
+
+qsl_status qsl_profile_read(qsl_kernel_time* out, int32_t capacity, int32_t* count, int32_t reset) {
+    if (!count) return bad(QSL_ERR_INVALID_ARG, "NULL count");
+    for (auto& r : g_prof_pending) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "profile event");
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+        bool found = false;
+        for (auto& g : g_prof_agg)
+            if (g.name == r.name) { g.launches++; g.ms += ms; found = true; break; }
+        if (!found) g_prof_agg.push_back({r.name, 1, (double)ms});
+    }
+    g_prof_pending.clear();
+    int n = 0;
+    for (auto& g : g_prof_agg) {
+        if (out && n < capacity) {
+            memset(out[n].name, 0, sizeof(out[n].name));
+            strncpy(out[n].name, g.name.c_str(), sizeof(out[n].name) - 1);
+            out[n].launches = g.launches;
+            out[n].total_ms = g.ms;
+        }
+        ++n;
+    }
+    *count = n;
+    if (reset) g_prof_agg.clear();
+    return QSL_OK;
+}
+
+qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
+    try {
+        set_error("");
+        if (!d || !out) return bad(QSL_ERR_INVALID_ARG, "NULL descriptor or output");
+        *out = nullptr;
+        if (d->flags != 0) return bad(QSL_ERR_INVALID_ARG, "flags must be 0");
+        if (d->n_atoms < 0 || d->n_shells < 0) return bad(QSL_ERR_INVALID_ARG, "negative counts");
+        if (d->n_up < 0 || d->n_dn < 0 || d->n_up < d->n_dn)
+            return bad(QSL_ERR_INVALID_ARG, "need n_up >= n_dn >= 0");
+        if (d->n_atoms && !d->atom_xyz) return bad(QSL_ERR_INVALID_ARG, "NULL atom_xyz");
+        if (d->n_shells && (!d->shell_atom || !d->shell_l || !d->shell_nprim || !d->prim_exp || !d->prim_coef))
+            return bad(QSL_ERR_INVALID_ARG, "NULL shell or primitive array");
+        for (int i = 0; i < 3 * d->n_atoms; ++i)
+            if (!std::isfinite(d->atom_xyz[i])) return bad(QSL_ERR_INVALID_ARG, "non-finite atom coordinate");
+        const double T = d->screen_T > 0 ? d->screen_T : 30.0;
+        int n_prim = 0;
+        for (int s = 0; s < d->n_shells; ++s) {
+            int a = d->shell_atom[s], l = d->shell_l[s], np = d->shell_nprim[s];
+            if (a < 0 || a >= d->n_atoms) return bad(QSL_ERR_INVALID_ARG, "shell_atom out of range");
+            if (s && a < d->shell_atom[s - 1]) return bad(QSL_ERR_INVALID_ARG, "shell_atom must be non-decreasing");
+            if (l < 0) return bad(QSL_ERR_INVALID_ARG, "negative l");
+            if (l > QSL_LMAX) return bad(QSL_ERR_UNSUPPORTED, "angular momentum above 2");
+            if (np < 1) return bad(QSL_ERR_INVALID_ARG, "shell without primitives");
+            if (np > QSL_PMAX) return bad(QSL_ERR_UNSUPPORTED, "more than QSL_PMAX primitives");
+            n_prim += np;
+        }
+        for (int k = 0; k < n_prim; ++k) {
+            if (!(d->prim_exp[k] > 0) || !std::isfinite(d->prim_exp[k]))
+                return bad(QSL_ERR_INVALID_ARG, "exponents must be positive and finite");
+            if (!std::isfinite(d->prim_coef[k])) return bad(QSL_ERR_INVALID_ARG, "non-finite weight");
+        }
+
+        qsl_system* S = new qsl_system();
+        S->n_prim = n_prim;
+        hipGetDevice(&S->device);
+
+        // shells: first primitive, normalised weights
+        std::vector<int> p0(d->n_shells), sh_np(d->n_shells), sh_l(d->n_shells), sh_at(d->n_shells);
+        std::vector<double> c64(n_prim), ex(d->prim_exp, d->prim_exp + n_prim);
+        std::vector<float> c32(n_prim);
+        int off = 0;
+        for (int s = 0; s < d->n_shells; ++s) {
+            int l = d->shell_l[s], np = d->shell_nprim[s];
+            p0[s] = off; sh_np[s] = np; sh_l[s] = l; sh_at[s] = d->shell_atom[s];
+            // overlap of two unit-norm primitives x^l e^{-g r^2}: (2 sqrt(g_k g_m)/(g_k+g_m))^(l+3/2)
+            double S2 = 0.0;
+            for (int k = 0; k < np; ++k)
+                for (int m = 0; m < np; ++m) {
+                    double gk = ex[off + k], gm = ex[off + m];
+                    S2 += d->prim_coef[off + k] * d->prim_coef[off + m] *
+                          pow(2.0 * sqrt(gk * gm) / (gk + gm), l + 1.5);
+                }
+            for (int k = 0; k < np; ++k) {
+                double gk = ex[off + k];
+                double Nk = pow(2.0 * gk / M_PI, 0.75) * pow(4.0 * gk, 0.5 * l) / sqrt(odd_fact(l));
+                c64[off + k] = d->prim_coef[off + k] * Nk / sqrt(S2);
+                c32[off + k] = (float)c64[off + k];
+            }
+            off += np;
+        }
+
+        // AO order, padded slots and windows
+        std::vector<double> atom_gmin(std::max(d->n_atoms, 1), std::numeric_limits<double>::infinity());
+        for (int s = 0; s < d->n_shells; ++s)
+            for (int k = 0; k < sh_np[s]; ++k)
+                atom_gmin[sh_at[s]] = std::min(atom_gmin[sh_at[s]], ex[p0[s] + k]);
+        std::vector<int> slot_shell, slot_pow, slot_ao;
+        std::vector<double> slot_f;
+        int ao = 0, s = 0;
+        for (int a = 0; a < d->n_atoms; ++a) {
+            size_t start = slot_shell.size();
+            for (; s < d->n_shells && sh_at[s] == a; ++s) {
+                int l = sh_l[s];
+                for (int c = 0; c < (l + 1) * (l + 2) / 2; ++c) {
+                    int p[3];
+                    powers(l, c, p);
+                    slot_shell.push_back(s);
+                    slot_pow.push_back(p[0] | (p[1] << 4) | (p[2] << 8) | (l << 12));
+                    slot_f.push_back(sqrt(odd_fact(l) / (odd_fact(p[0]) * odd_fact(p[1]) * odd_fact(p[2]))));
+                    slot_ao.push_back(ao);
+                    S->ao_atom.push_back(a);
+                    S->ao_shell.push_back(s);
+                    for (int k = 0; k < 3; ++k) S->ao_nxyz.push_back((int8_t)p[k]);
+                    ++ao;
+                }
+            }
+            while ((slot_shell.size() - start) % WIN) {
+                slot_shell.push_back(-1); slot_pow.push_back(0); slot_f.push_back(0.0); slot_ao.push_back(-1);
+            }
+        }
+        const int n_slots = (int)slot_shell.size(), n_win = n_slots / WIN;
+        std::vector<int> win_atom(std::max(n_win, 1));
+        std::vector<double> win_gmin(std::max(n_win, 1), std::numeric_limits<double>::infinity());
+        for (int q = 0; q < n_win; ++q) {
+            for (int j = 0; j < WIN; ++j) {
+                int sh = slot_shell[q * WIN + j];
+                if (sh < 0) continue;
+                win_atom[q] = sh_at[sh];
+                for (int k = 0; k < sh_np[sh]; ++k) win_gmin[q] = std::min(win_gmin[q], ex[p0[sh] + k]);
+            }
+        }
+        S->slot_ao = slot_ao;
+
+        // device tables in one allocation
+        Arena ar;
+        size_t o_xyz = ar.add(d->atom_xyz, sizeof(double) * 3 * d->n_atoms);
+        size_t o_agm = ar.add(atom_gmin.data(), sizeof(double) * atom_gmin.size());
+        size_t o_sat = ar.add(sh_at.data(), sizeof(int) * sh_at.size());
+        size_t o_sl = ar.add(sh_l.data(), sizeof(int) * sh_l.size());
+        size_t o_sp0 = ar.add(p0.data(), sizeof(int) * p0.size());
+        size_t o_snp = ar.add(sh_np.data(), sizeof(int) * sh_np.size());
+        size_t o_ex = ar.add(ex.data(), sizeof(double) * ex.size());
+        size_t o_c64 = ar.add(c64.data(), sizeof(double) * c64.size());
+        size_t o_c32 = ar.add(c32.data(), sizeof(float) * c32.size());
+        size_t o_ssh = ar.add(slot_shell.data(), sizeof(int) * slot_shell.size());
+        size_t o_spw = ar.add(slot_pow.data(), sizeof(int) * slot_pow.size());
+        size_t o_sf = ar.add(slot_f.data(), sizeof(double) * slot_f.size());
+        size_t o_sao = ar.add(slot_ao.data(), sizeof(int) * slot_ao.size());
+        size_t o_wat = ar.add(win_atom.data(), sizeof(int) * win_atom.size());
+        size_t o_wgm = ar.add(win_gmin.data(), sizeof(double) * win_gmin.size());
+        // MO copies per spin
+        size_t o_mo[2][6];
+        int ldn[2];
+        for (int sp = 0; sp < 2; ++sp) {
+            int n = sp ? d->n_dn : d->n_up;
+            ldn[sp] = n ? (int)round_up(n, 128) : 0;
+            size_t cells = (size_t)n_slots * ldn[sp];
+            o_mo[sp][0] = ar.reserve(cells * 8);
+            o_mo[sp][1] = ar.reserve(cells * 4);
+            for (int k = 2; k < 6; ++k) o_mo[sp][k] = ar.reserve(cells * 2);
+        }
+        void* blk = nullptr;
+        hipError_t e = hipMalloc(&blk, ar.buf.size());
+        if (e != hipSuccess) {
+            delete S;
+            set_error(std::string("hipMalloc of system tables: ") + hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? QSL_ERR_OOM : QSL_ERR_HIP;
+        }
+        e = hipMemcpy(blk, ar.buf.data(), ar.buf.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { hipFree(blk); delete S; return hip_fail(e, "upload of system tables"); }
+        S->dev_block = blk;
+        char* b = (char*)blk;
+        DevSys& D = S->d;
+        D.n_atoms = d->n_atoms; D.n_shells = d->n_shells; D.n_slots = n_slots; D.n_win = n_win;
+        D.n_basis = ao; D.n_up = d->n_up; D.n_dn = d->n_dn; D.T = T;
+        D.atom_xyz = (const double*)(b + o_xyz); D.atom_gmin = (const double*)(b + o_agm);
+        D.shell_atom = (const int*)(b + o_sat); D.shell_l = (const int*)(b + o_sl);
+        D.shell_p0 = (const int*)(b + o_sp0); D.shell_np = (const int*)(b + o_snp);
+        D.prim_exp = (const double*)(b + o_ex); D.prim_c64 = (const double*)(b + o_c64);
+        D.prim_c32 = (const float*)(b + o_c32);
+        D.slot_shell = (const int*)(b + o_ssh); D.slot_pow = (const int*)(b + o_spw);
+        D.slot_f = (const double*)(b + o_sf); D.slot_ao = (const int*)(b + o_sao);
+        D.win_atom = (const int*)(b + o_wat); D.win_gmin = (const double*)(b + o_wgm);
+        for (int sp = 0; sp < 2; ++sp) {
+            DevMO& m = S->mo[sp];
+            m.n = sp ? d->n_dn : d->n_up;
+            m.ldn = ldn[sp];
+            m.AT64 = (double*)(b + o_mo[sp][0]);
+            m.AT32 = (float*)(b + o_mo[sp][1]);
+            m.Ahi = (uint16_t*)(b + o_mo[sp][2]);
+            m.Alo = (uint16_t*)(b + o_mo[sp][3]);
+            m.AThi = (uint16_t*)(b + o_mo[sp][4]);
+            m.ATlo = (uint16_t*)(b + o_mo[sp][5]);
+            m.set = (m.n == 0);
+        }
+        *out = S;
+        return QSL_OK;
+    } catch (const std::bad_alloc&) {
+        return bad(QSL_ERR_OOM, "host allocation failed");
+    } catch (...) {
+        return bad(QSL_ERR_INVALID_ARG, "unexpected exception");
+    }
+}
+
+qsl_status qsl_system_destroy(qsl_system* sys) {
+    if (!sys) return QSL_OK;
+    if (sys->dev_block) hipFree(sys->dev_block);
+    delete sys;
+    return QSL_OK;
+}
+
+int64_t qsl_n_basis(const qsl_system* sys) { return sys ? sys->d.n_basis : -1; }
+
+qsl_status qsl_ao_info(const qsl_system* sys, int32_t* ao_atom, int32_t* ao_shell, int8_t* ao_nxyz) {
+    if (!sys) return bad(QSL_ERR_INVALID_ARG, "NULL system");
+    int nb = sys->d.n_basis;
+    for (int j = 0; j < nb; ++j) {
+        if (ao_atom) ao_atom[j] = sys->ao_atom[j];
+        if (ao_shell) ao_shell[j] = sys->ao_shell[j];
+        if (ao_nxyz)
+            for (int k = 0; k < 3; ++k) ao_nxyz[3 * j + k] = sys->ao_nxyz[3 * j + k];
+    }
+    return QSL_OK;
+}
+
+qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld, int32_t on_device,
+                      void* stream) {
+    if (!sys) return bad(QSL_ERR_INVALID_ARG, "NULL system");
+    if (spin != 0 && spin != 1) return bad(QSL_ERR_INVALID_ARG, "spin must be 0 or 1");
+    DevMO& m = sys->mo[spin];
+    if (m.n == 0) return QSL_OK;
+    if (!A) return bad(QSL_ERR_INVALID_ARG, "NULL A");
+    if (ld < sys->d.n_basis) return bad(QSL_ERR_INVALID_ARG, "ld < N_basis");
+    hipStream_t st = (hipStream_t)stream;
+    const double* src = A;
+    double* tmp = nullptr;
+    hipError_t e;
+    if (!on_device) {
+        size_t bytes = sizeof(double) * (size_t)m.n * ld;
+        e = hipMalloc(&tmp, bytes);
+        if (e != hipSuccess) return hip_fail(e, "staging of A");
+        e = hipMemcpy(tmp, A, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { hipFree(tmp); return hip_fail(e, "copy of A"); }
+        src = tmp;
+    }
+    e = launch_build_mo(sys->d, m, src, ld, st);
+    if (e != hipSuccess) { if (tmp) hipFree(tmp); return hip_fail(e, "MO copy kernel"); }
+    if (tmp) {
+        e = hipStreamSynchronize(st);
+        hipFree(tmp);
+        if (e != hipSuccess) return hip_fail(e, "set_mo synchronize");
+    }
+    m.set = true;
+    return QSL_OK;
+}
+
+qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, size_t* bytes) {
+    if (!sys || !bytes) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
+    if (W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
+    if (mode < QSL_FP64 || mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
+    *bytes = ws_layout(sys->d, W).total;
+    return QSL_OK;
+}
+
+qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
+    if (!sys || !a) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
+    if (a->W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
+    if (a->mode < QSL_FP64 || a->mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
+    if (a->W == 0) return QSL_OK;
+    if (!a->R) return bad(QSL_ERR_INVALID_ARG, "NULL R");
+    const DevSys& d = sys->d;
+    for (int s = 0; s < 2; ++s) {
+        int n = n_spin(d, s);
+        if (!n) continue;
+        if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
+        if (!a->C[s] || !a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "C and Dinv outputs are required");
+        if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
+    }
+    WsLayout L = ws_layout(d, a->W);
+    if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
+    hipStream_t st = (hipStream_t)stream;
+    char* ws = (char*)a->ws;
+    hipError_t e;
+    if (a->status && (e = fill_u32(a->status, 0u, a->W, st)) != hipSuccess) return hip_fail(e, "status clear");
+    const int N = d.n_up + d.n_dn;
+    for (int s = 0; s < 2; ++s) {
+        int n = n_spin(d, s);
+        int* nwin = (int*)(ws + L.nwin_off[s]);
+        int* win = (int*)(ws + L.win_off[s]);
+        if (n) {
+            {
+                ProfScope ps("screen", st);
+                if ((e = launch_screen(d, s, a->W, a->R, nwin, win, a->status, st)) != hipSuccess)
+                    return hip_fail(e, "screen kernel");
+            }
+            {
+                ProfScope ps(a->mode == QSL_FP64 ? "contract_fp64" : a->mode == QSL_FP32 ? "contract_fp32" : "contract_bf16x3", st);
+                if ((e = launch_contract(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->C[s], a->status, st)) != hipSuccess)
+                    return hip_fail(e, "contraction kernel");
+            }
+        }
+        {
+            ProfScope ps("gauss_jordan", st);
+            if ((e = launch_gj(a->mode, a->C[s], n, a->W, s, a->Dinv[s], a->logdet, a->sign, a->status, st)) != hipSuccess)
+                return hip_fail(e, "inversion kernel");
+        }
+        if (n && (a->drift || a->lap)) {
+            ProfScope ps("drift_lap", st);
+            if ((e = launch_epilogue(a->mode, a->C[s], a->Dinv[s], n, a->W, s, N, s ? d.n_up : 0, a->drift, a->lap,
+                                     a->logdet, a->status, st)) != hipSuccess)
+                return hip_fail(e, "epilogue kernel");
+        }
+    }
+    return QSL_OK;
+}
+
+qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
+    if (!sys || !a) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
+    if (a->W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
+    if (a->mode < QSL_FP64 || a->mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
+    const DevSys& d = sys->d;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    const int N = d.n_up + d.n_dn;
+    for (int s = 0; s < 2; ++s) {
+        if (a->dA[s] && !a->accumulate_dA && n_spin(d, s)) {
+            if ((e = fill_f64(a->dA[s], 0.0, (int64_t)n_spin(d, s) * d.n_basis, st)) != hipSuccess)
+                return hip_fail(e, "dA clear");
+        }
+    }
+    if (a->W == 0) return QSL_OK;
+    if (!a->R || !a->g_logdet) return bad(QSL_ERR_INVALID_ARG, "NULL R or g_logdet");
+    for (int s = 0; s < 2; ++s) {
+        if (!n_spin(d, s)) continue;
+        if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
+        if (!a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "NULL Dinv");
+    }
+    WsLayout L = ws_layout(d, a->W);
+    if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
+    char* ws = (char*)a->ws;
+    if (a->dR && (e = fill_f64(a->dR, 0.0, a->W * N * 3, st)) != hipSuccess) return hip_fail(e, "dR clear");
+    for (int s = 0; s < 2; ++s) {
+        int n = n_spin(d, s);
+        if (!n) continue;
+        int* nwin = (int*)(ws + L.nwin_off[s]);
+        int* win = (int*)(ws + L.win_off[s]);
+        {
+            ProfScope ps("screen", st);
+            if ((e = launch_screen(d, s, a->W, a->R, nwin, win, nullptr, st)) != hipSuccess)
+                return hip_fail(e, "screen kernel");
+        }
+        ProfScope ps("adjoint", st);
+        if ((e = launch_backward(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->Dinv[s], a->g_logdet, a->dR,
+                                 a->dA[s], st)) != hipSuccess)
+            return hip_fail(e, "backward kernel");
+    }
+    return QSL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Internal definitions of the gfx950 Slater-matrix builder (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qslater.h"
+
+namespace qsl {
+
+// Electrons per tile: one MFMA row block of 32.
+constexpr int TE = 32;
+// AO slots per window: the AOs of every atom are padded to a multiple of 8
+// slots, so a window belongs to exactly one atom and is one 8-wide k-group of
+// a bf16 MFMA operand.
+constexpr int WIN = 8;
+// Largest Slater matrix inverted in registers by one workgroup.
+constexpr int GJ_NMAX = 224;
+
+// Device view of a system, passed to kernels by value.
+struct DevSys {
+    int n_atoms, n_shells, n_slots, n_win, n_basis;
+    int n_up, n_dn;
+    double T;
+    const double* atom_xyz;   // [n_atoms*3]
+    const double* atom_gmin;  // [n_atoms] min exponent of the atom
+    const int* shell_atom;    // [n_shells]
+    const int* shell_l;       // [n_shells]
+    const int* shell_p0;      // [n_shells] first primitive
+    const int* shell_np;      // [n_shells]
+    const double* prim_exp;   // [n_prim]
+    const double* prim_c64;   // [n_prim] normalised weights
+    const float* prim_c32;    // [n_prim]
+    const int* slot_shell;    // [n_slots] shell of the slot, -1 for padding
+    const int* slot_pow;      // [n_slots] a | b<<4 | c<<8 | l<<12
+    const double* slot_f;     // [n_slots] Cartesian factor
+    const int* slot_ao;       // [n_slots] ABI AO index, -1 for padding
+    const int* win_atom;      // [n_win]
+    const double* win_gmin;   // [n_win] min exponent over shells meeting the window
+};
+
+// MO coefficient copies of one spin, padded: n rows -> ldn (multiple of 128).
+struct DevMO {
+    int n = 0, ldn = 0;
+    bool set = false;
+    double* AT64 = nullptr;     // [n_slots][ldn]
+    float* AT32 = nullptr;      // [n_slots][ldn]
+    uint16_t* Ahi = nullptr;    // [ldn][n_slots] bf16 bits
+    uint16_t* Alo = nullptr;
+    uint16_t* AThi = nullptr;   // [n_slots][ldn]
+    uint16_t* ATlo = nullptr;
+};
+
+}  // namespace qsl
+
+struct qsl_system {
+    qsl::DevSys d{};
+    qsl::DevMO mo[2];
+    void* dev_block = nullptr;  // one allocation holding all device tables
+    int device = 0;
+    int n_prim = 0;
+    // host copies of the AO order
+    std::vector<int> ao_atom, ao_shell;
+    std::vector<int8_t> ao_nxyz;
+    std::vector<int> slot_ao;
+};
+
+namespace qsl {
+
+void set_error(const std::string& msg);
+
+inline int n_spin(const DevSys& s, int spin) { return spin ? s.n_dn : s.n_up; }
+inline int tiles_per_walker(int n) { return (n + TE - 1) / TE; }
+
+// ------------------------------------------------------------------ device
+
+// Exact FP64 squared distance, evaluated as (dx*dx + dy*dy) + dz*dz with
+// no fused multiply-add, so that every screening decision is identical in
+// every precision mode.
+__device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ double exp_t(double x) { return exp(x); }
+__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+
+// Radial part of a contracted shell over its kept primitives:
+// g = sum c_k e_k, g1 = sum -2 gamma_k c_k e_k, g2 = sum c_k e_k (4 gamma_k^2 r^2 - 6 gamma_k)
+template <typename T>
+__device__ __forceinline__ void shell_radial(const DevSys& s, int sh, double r2, T& g, T& g1, T& g2,
+                                             bool& tie) {
+    const int p0 = s.shell_p0[sh], np = s.shell_np[sh];
+    g = T(0); g1 = T(0); g2 = T(0);
+    const double tieb = 1e-12 * s.T;
+    for (int k = 0; k < np; ++k) {
+        const double gk = s.prim_exp[p0 + k];
+        const double t = __dmul_rn(gk, r2);
+        tie |= fabs(t - s.T) <= tieb;
+        if (t <= s.T) {
+            T c;
+            if constexpr (sizeof(T) == 8) c = (T)s.prim_c64[p0 + k];
+            else c = s.prim_c32[p0 + k];
+            const T ek = c * exp_t(-(T)t);
+            const T gT = (T)gk;
+            g += ek;
+            g1 += T(-2) * gT * ek;
+            g2 += ek * (T(4) * gT * gT * (T)r2 - T(6) * gT);
+        }
+    }
+}
+
+// Value, d/dx, d/dy, d/dz and Laplacian of the Cartesian AO in `slot`,
+// given its shell's radial sums and the displacement from its atom.
+template <typename T>
+__device__ __forceinline__ void slot_values(const DevSys& s, int slot, T X, T Y, T Z, T g, T g1,
+                                            T g2, T out[5]) {
+    const int pw = s.slot_pow[slot];
+    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
+    const T f = (T)s.slot_f[slot];
+    const T px[3] = {T(1), X, X * X}, py[3] = {T(1), Y, Y * Y}, pz[3] = {T(1), Z, Z * Z};
+    const T P = f * px[a] * py[b] * pz[c];
+    const T Px = a ? f * T(a) * px[a - 1] * py[b] * pz[c] : T(0);
+    const T Py = b ? f * T(b) * px[a] * py[b - 1] * pz[c] : T(0);
+    const T Pz = c ? f * T(c) * px[a] * py[b] * pz[c - 1] : T(0);
+    // l <= 2, so a second derivative of x^a is 2 when a == 2 and 0 otherwise
+    const T L = (a == 2 ? T(2) * f * py[b] * pz[c] : T(0)) + (b == 2 ? T(2) * f * px[a] * pz[c] : T(0)) +
+                (c == 2 ? T(2) * f * px[a] * py[b] : T(0));
+    out[0] = P * g;
+    out[1] = Px * g + P * g1 * X;
+    out[2] = Py * g + P * g1 * Y;
+    out[3] = Pz * g + P * g1 * Z;
+    // Delta . grad P = l P for a homogeneous polynomial of degree l
+    out[4] = L * g + T(2 * l) * g1 * P + P * g2;
+}
+
+// bf16 round-to-nearest-even of a float, as raw bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Timing of kernel launches with HIP events (enabled by qsl_profile_enable).
+struct ProfScope {
+    ProfScope(const char* name, hipStream_t st);
+    ~ProfScope();
+    const char* name;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_screen(const DevSys& s, int spin, int64_t W, const double* R, int* tile_nwin,
+                         int* tile_win, uint32_t* status, hipStream_t st);
+hipError_t launch_contract(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W,
+                           const double* R, const int* tile_nwin, const int* tile_win, void* C,
+                           uint32_t* status, hipStream_t st);
+hipError_t launch_gj(int mode, const void* C, int n, int64_t W, int spin, double* Dinv,
+                     double* logdet, int8_t* sign, uint32_t* status, hipStream_t st);
+hipError_t launch_epilogue(int mode, const void* C, const double* Dinv, int n, int64_t W, int spin,
+                           int N, int e_off, double* drift, double* lap, const double* logdet,
+                           uint32_t* status, hipStream_t st);
+hipError_t launch_backward(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W,
+                           const double* R, const int* tile_nwin, const int* tile_win,
+                           const double* Dinv, const double* g, double* dR, double* dA,
+                           hipStream_t st);
+hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A_dev, int64_t ld,
+                           hipStream_t st);
+hipError_t launch_scale_copy(double* dst, const double* src, int64_t n, hipStream_t st);
+
+}  // namespace qsl

@@ -1,0 +1,90 @@
+// Small kernels: padded MO-coefficient copies and the drift/Laplacian
+// epilogue.
+#include "qsl_internal.h"
+
+namespace qsl {
+
+// A^s (n x N_b, row-major, leading dimension ld, FP64) -> the library's
+// padded copies: AT64/AT32 [slot][ldn], Ahi/Alo [ldn][slot], AThi/ATlo
+// [slot][ldn]; hi = bf16(x), lo = bf16(x - hi) of the FP32 value x.
+__global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restrict__ A, int64_t ld,
+                                double* AT64, float* AT32, uint16_t* Ahi, uint16_t* Alo, uint16_t* AThi,
+                                uint16_t* ATlo) {
+    const int64_t total = (int64_t)s.n_slots * ldn;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int slot = (int)(q / ldn), mo = (int)(q % ldn);
+        const int ao = s.slot_ao[slot];
+        const double v = (ao >= 0 && mo < n) ? A[(int64_t)mo * ld + ao] : 0.0;
+        const float f = (float)v;
+        const uint16_t h = bf16_rne(f);
+        const uint16_t l = bf16_rne(f - bf16_to_f(h));
+        AT64[q] = v;
+        AT32[q] = f;
+        AThi[q] = h;
+        ATlo[q] = l;
+        Ahi[(int64_t)mo * s.n_slots + slot] = h;
+        Alo[(int64_t)mo * s.n_slots + slot] = l;
+    }
+}
+
+hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A, int64_t ld, hipStream_t st) {
+    const int64_t total = (int64_t)s.n_slots * mo.ldn;
+    if (!total) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
+    build_mo_kernel<<<blocks, 256, 0, st>>>(s, mo.n, mo.ldn, A, ld, mo.AT64, mo.AT32, mo.Ahi, mo.Alo, mo.AThi,
+                                            mo.ATlo);
+    return hipGetLastError();
+}
+
+// drift[e] = sum_i Dinv[e][i] C_{2..4}[e][i], lap[e] = sum_i Dinv[e][i] C_5[e][i]
+// (the determinant's "vector products"), one wavefront per electron.
+template <typename Tc>
+__global__ __launch_bounds__(256) void epilogue_kernel(const Tc* __restrict__ C, const double* __restrict__ Dinv,
+                                                       int n, int64_t W, int spin, int N, int e_off,
+                                                       double* __restrict__ drift, double* __restrict__ lap,
+                                                       const double* __restrict__ logdet,
+                                                       uint32_t* __restrict__ status) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= W * n) return;
+    const int64_t w = row / n;
+    const int e = (int)(row % n);
+    const double* d = Dinv + (w * n + e) * n;
+    const size_t nn = (size_t)n * n;
+    const Tc* Cw = C + (size_t)w * 5 * nn + (size_t)e * n;
+    double acc[4] = {0, 0, 0, 0};
+    for (int i = lane; i < n; i += 64) {
+        const double di = d[i];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = fma(di, (double)Cw[(size_t)(c + 1) * nn + i], acc[c]);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += __shfl_xor(acc[c], o);
+    if (lane == 0) {
+        const int64_t ge = w * N + e_off + e;
+        if (drift)
+            for (int c = 0; c < 3; ++c) drift[ge * 3 + c] = acc[c];
+        if (lap) lap[ge] = acc[3];
+        bool fin = isfinite(acc[0]) && isfinite(acc[1]) && isfinite(acc[2]) && isfinite(acc[3]);
+        bool sing = logdet && isinf(logdet[2 * w + spin]) && logdet[2 * w + spin] < 0;
+        if (!fin && !sing && status) atomicOr(status + w, QSL_STATUS_NONFINITE);
+    }
+}
+
+hipError_t launch_epilogue(int mode, const void* C, const double* Dinv, int n, int64_t W, int spin, int N, int e_off,
+                           double* drift, double* lap, const double* logdet, uint32_t* status, hipStream_t st) {
+    const int64_t rows = W * n;
+    if (!rows) return hipSuccess;
+    const unsigned blocks = (unsigned)((rows + 3) / 4);
+    if (mode == QSL_FP64)
+        epilogue_kernel<double><<<blocks, 256, 0, st>>>((const double*)C, Dinv, n, W, spin, N, e_off, drift, lap,
+                                                        logdet, status);
+    else
+        epilogue_kernel<float><<<blocks, 256, 0, st>>>((const float*)C, Dinv, n, W, spin, N, e_off, drift, lap,
+                                                       logdet, status);
+    return hipGetLastError();
+}
+
+}  // namespace qsl
