@@ -146,13 +146,14 @@ def main():
     ns = [sysm.n_up, sysm.n_dn]
     contract_flops = [10.0 * n * n * nnz * W for n in ns]          # 5 products x 2 flops x MOs x survivors
     gj_flops = [2.0 * n ** 3 * W for n in ns]                        # 2 n^3 per matrix
-    adjoint_flops = [4.0 * n * n * nnz * W for n in ns]              # dA and H, 2 flops each
+    adjoint_flops = [2.0 * n * n * nnz * W for n in ns]              # H or dA: 2 flops per (electron, survivor, MO)
     cbytes = 8 if mode == "fp64" else 4
     epi_bytes = [(8.0 * n * n + 4 * cbytes * n * n + 32.0 * n) * W for n in ns]
     kinds = {
         f"contract_{mode}": (sum(contract_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         "gauss_jordan": (sum(gj_flops), "alu", PEAK_FP64_VALU, "TFLOP/s"),
-        "adjoint": (sum(adjoint_flops), "alu", PEAK_FP64_VALU if mode == "fp64" else PEAK_FP32_VALU, "TFLOP/s"),
+        "adjoint_h": (sum(adjoint_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
+        "adjoint_dA": (sum(adjoint_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         "drift_lap": (sum(epi_bytes), "hbm", HBM_PEAK, "GB/s"),
     }
     kernels = {}

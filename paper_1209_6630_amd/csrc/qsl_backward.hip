@@ -2,152 +2,448 @@
 // chain rule through the MO expansion (mo) and D_ij = phi_i(r_j)).
 //
 // With G[e][i] = g Dinv[e][i] = dL/dC_1[e][i]:
-//   dA^s[i][j] = sum_w sum_e G[e][i] chi_j(r_e)
 //   dR_e       = sum_j H[e][j] grad chi_j(r_e),  H[e][j] = sum_i G[e][i] a_ij
-// over the screened survivors (held fixed).  The AO values and gradients
-// are recomputed here, tile by tile, with the forward's window lists; they
-// are never stored by the forward.  One workgroup owns a tile of 32
-// electrons and a block of 32 MOs; dA and dR are accumulated with atomics.
+//   dA^s[i][j] = sum_w sum_e G[e][i] chi_j(r_e)
+// over the screened survivors (held fixed).  The AO values and gradients are
+// recomputed here; the forward never stores them.
+//
+// Two kernels, both on MFMA in the forward's precision mode:
+//  adj_h   one workgroup per tile of 32 electrons (one walker): G in LDS,
+//          gradients of the tile's surviving AOs into LDS chunk by chunk,
+//          H = G A (M = 32 electrons, N = 64 slots, K = MOs), dR = H . grad chi.
+//  adj_dA  one workgroup per (electron range t, block of walkers, block of
+//          surviving windows, block of MOs).  Electrons with the same index
+//          sit in the same region of space across walkers, so the walker
+//          block shares one window list.  The dA block (MOs x slots) stays in
+//          the accumulators of eight waves while the walkers stream through
+//          as the contraction dimension (32 electrons each); one coalesced
+//          atomic flush per workgroup (FP32 into a workspace accumulator, or
+//          FP64).
 #include "qsl_internal.h"
 
 namespace qsl {
 
-constexpr int BW_THREADS = 256;
-constexpr int BW_MB = 32;  // MOs per workgroup
-constexpr int BW_KW = 8;   // windows per chunk
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
 
+constexpr int ADJ_MB = 224;             // MOs per workgroup (7 blocks of 32)
+constexpr int ADJ_NIB = ADJ_MB / 32;
+
+template <int MODE>
+using TOf = typename std::conditional<MODE == QSL_FP64, double, float>::type;
+
+// 32 x 32 accumulator block, 16 values per lane.  f32 modes: one 32x32 MFMA
+// block (row 8(q/4) + 4(lane/32) + q%4, column lane%32).  FP64: 2 x 2
+// blocks of 16x16 (row 16 bi + lane/16 + 4r, column 16 bj + lane%16).
+template <int MODE>
+struct Blk {
+    using T = TOf<MODE>;
+    T v[16];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = T(0);
+    }
+    __device__ __forceinline__ static int row(int q, int lane) {
+        if constexpr (MODE == QSL_FP64) return ((q >> 3) << 4) + (lane >> 4) + 4 * (q & 3);
+        else return 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+    }
+    __device__ __forceinline__ static int col(int q, int lane) {
+        if constexpr (MODE == QSL_FP64) return (((q >> 2) & 1) << 4) + (lane & 15);
+        else return lane & 31;
+    }
+};
+
+// acc += A(32 rows) x B(32 cols) over k in [k0, k1) for the FP32 and FP64
+// modes; fa(row, k) and fb(k, col) fetch the operands.
+template <int MODE, typename FA, typename FB>
+__device__ __forceinline__ void mma_f(Blk<MODE>& acc, int k0, int k1, int lane, FA fa, FB fb) {
+    if constexpr (MODE == QSL_FP32) {
+        f32x16 a16;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a16[q] = acc.v[q];
+        const int kk = lane >> 5, rc = lane & 31;
+        for (int k = k0; k < k1; k += 2)
+            a16 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa(rc, k + kk), fb(k + kk, rc), a16, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc.v[q] = a16[q];
+    } else {
+        f64x4 a4[2][2];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a4[q >> 3][(q >> 2) & 1][q & 3] = acc.v[q];
+        const int kk = lane >> 4, rc = lane & 15;
+        for (int k = k0; k < k1; k += 4) {
+            double a[2], b[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) { a[h] = fa(h * 16 + rc, k + kk); b[h] = fb(k + kk, h * 16 + rc); }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    a4[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], a4[bi][bj], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc.v[q] = a4[q >> 3][(q >> 2) & 1][q & 3];
+    }
+}
+
+// AO value (d = 0) and gradient (d = 1..3) of one electron at the 8 slots of
+// window q (zeros for padding slots and for q < 0).
 template <typename T>
-__global__ __launch_bounds__(BW_THREADS) void backward_kernel(DevSys s, int spin, int n, int tpw, int ldn,
-                                                              const double* __restrict__ R,
-                                                              const int* __restrict__ tile_nwin,
-                                                              const int* __restrict__ tile_win,
-                                                              const T* __restrict__ AT,
-                                                              const double* __restrict__ Dinv,
-                                                              const double* __restrict__ g,
-                                                              double* __restrict__ dR, double* __restrict__ dA) {
-    constexpr int KC = BW_KW * WIN;
+__device__ __forceinline__ void window_values(const DevSys& s, int q, const double r[3], T vals[4][WIN]) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int j = 0; j < WIN; ++j) vals[d][j] = T(0);
+    if (q < 0) return;
+    const int at = s.win_atom[q];
+    const double dx = r[0] - s.atom_xyz[3 * at];
+    const double dy = r[1] - s.atom_xyz[3 * at + 1];
+    const double dz = r[2] - s.atom_xyz[3 * at + 2];
+    const double r2 = dist2_exact(dx, dy, dz);
+    int prev = -1;
+    T gg = 0, g1 = 0, g2 = 0;
+    bool tie = false;
+#pragma unroll
+    for (int j = 0; j < WIN; ++j) {
+        const int slot = q * WIN + j;
+        const int sh = s.slot_shell[slot];
+        if (sh < 0) continue;
+        if (sh != prev) { shell_radial<T>(s, sh, r2, gg, g1, g2, tie); prev = sh; }
+        T v[5];
+        slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, gg, g1, g2, v);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) vals[d][j] = v[d];
+    }
+}
+
+// ---------------------------------------------------------------- adj_h
+
+constexpr int AH_THREADS = 256;
+constexpr int AH_KW = 8;                 // windows per chunk
+constexpr int AH_KC = AH_KW * WIN;       // 64 slots
+
+template <int MODE>
+__global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(DevSys s, int spin, int n, int64_t W, int ldn,
+                                                           const double* __restrict__ R,
+                                                           const int* __restrict__ tile_nwin,
+                                                           const int* __restrict__ tile_win,
+                                                           const uint16_t* __restrict__ AThi,
+                                                           const uint16_t* __restrict__ ATlo,
+                                                           const float* __restrict__ A32,
+                                                           const double* __restrict__ A64,
+                                                           const double* __restrict__ Dinv,
+                                                           const double* __restrict__ g, double* __restrict__ dR) {
+    using T = TOf<MODE>;
+    constexpr bool BF = MODE == QSL_BF16X3;
+    constexpr int LDG = ADJ_MB + (BF ? 8 : 1);
     __shared__ double epos[TE][3];
-    __shared__ int wq[BW_KW];
-    __shared__ T G[TE][BW_MB + 1];
-    __shared__ T Bv[4][TE][KC + 1];
-    __shared__ T red[BW_THREADS / TE][TE][3];
+    __shared__ int wq[AH_KW];
+    __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? 2 * 2 * TE * LDG : sizeof(T) * TE * LDG];
+    __shared__ T dX[3][TE][AH_KC + 1];
+    __shared__ T Hb[2][TE][AH_KC + 1];
 
     const int tile = blockIdx.x;
-    const int i0 = blockIdx.y * BW_MB;
-    const int w = tile / tpw;
-    const int e0 = (tile % tpw) * TE;
+    const int w = (int)(tile % W);
+    const int e0 = (int)(tile / W) * TE;
     const int ne = min(TE, n - e0);
+    const int i0 = blockIdx.y * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint16_t* Gh = (uint16_t*)gbuf;
+    uint16_t* Gl = Gh + TE * LDG;
+    T* Gt = (T*)gbuf;
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
         epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
     }
     const double gw = g[2 * w + spin];
-    for (int q = tid; q < TE * BW_MB; q += BW_THREADS) {
-        const int e = q / BW_MB, ii = q % BW_MB;
-        const bool ok = e < ne && i0 + ii < n;
-        G[e][ii] = ok ? (T)(gw * Dinv[((size_t)w * n + e0 + e) * n + i0 + ii]) : T(0);
+    for (int q = tid; q < TE * ADJ_MB; q += AH_THREADS) {
+        const int e = q / ADJ_MB, ii = q % ADJ_MB;
+        double v = 0.0;
+        if (gw != 0.0 && e < ne && i0 + ii < n) v = gw * Dinv[((size_t)w * n + e0 + e) * n + i0 + ii];
+        if constexpr (BF) {
+            const float f = (float)v;
+            const uint16_t h = bf16_rne(f);
+            Gh[e * LDG + ii] = h;
+            Gl[e * LDG + ii] = bf16_rne(f - bf16_to_f(h));
+        } else {
+            Gt[e * LDG + ii] = (T)v;
+        }
     }
     const int nwin = tile_nwin[tile];
     const int* wins = tile_win + (size_t)tile * s.n_win;
-    T dr[3] = {0, 0, 0};
-    bool tie = false;
-    __syncthreads();
+    T dr = 0;  // tid < 96: (electron tid % 32, component tid / 32)
 
-    for (int c0 = 0; c0 < nwin; c0 += BW_KW) {
-        {   // AO value and gradient of (electron, window) into LDS
+    for (int c0 = 0; c0 < nwin; c0 += AH_KW) {
+        __syncthreads();
+        {
             const int e = tid & (TE - 1), wl = tid / TE;
             const int q = c0 + wl < nwin ? wins[c0 + wl] : -1;
             if (e == 0) wq[wl] = q;
             T vals[4][WIN];
-            for (int d = 0; d < 4; ++d)
-                for (int j = 0; j < WIN; ++j) vals[d][j] = T(0);
-            if (q >= 0 && e < ne) {
-                const int at = s.win_atom[q];
-                const double dx = epos[e][0] - s.atom_xyz[3 * at];
-                const double dy = epos[e][1] - s.atom_xyz[3 * at + 1];
-                const double dz = epos[e][2] - s.atom_xyz[3 * at + 2];
-                const double r2 = dist2_exact(dx, dy, dz);
-                int prev = -1;
-                T gg = 0, g1 = 0, g2 = 0;
-                for (int j = 0; j < WIN; ++j) {
-                    const int slot = q * WIN + j;
-                    const int sh = s.slot_shell[slot];
-                    if (sh < 0) continue;
-                    if (sh != prev) { shell_radial<T>(s, sh, r2, gg, g1, g2, tie); prev = sh; }
-                    T v[5];
-                    slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, gg, g1, g2, v);
-                    for (int d = 0; d < 4; ++d) vals[d][j] = v[d];
-                }
-            }
-            for (int d = 0; d < 4; ++d)
-                for (int j = 0; j < WIN; ++j) Bv[d][e][wl * WIN + j] = vals[d][j];
+            const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+            window_values<T>(s, e < ne ? q : -1, r, vals);
+#pragma unroll
+            for (int j = 0; j < WIN; ++j)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dX[d][e][wl * WIN + j] = vals[1 + d][j];
         }
         __syncthreads();
-        {   // dA[i][slot] += sum_e G[e][i] chi_slot(r_e)
-            const int ii = tid & (BW_MB - 1), sg = tid / BW_MB;  // 8 slot groups of 8 slots
-            if (i0 + ii < n) {
-                for (int j = 0; j < WIN; ++j) {
-                    const int c = sg * WIN + j;
-                    const int q = wq[c / WIN];
-                    if (q < 0) continue;
-                    const int ao = s.slot_ao[q * WIN + (c % WIN)];
-                    if (ao < 0) continue;
-                    T v = 0;
-                    for (int e = 0; e < TE; ++e) v += G[e][ii] * Bv[0][e][c];
-                    if (dA && v != T(0)) atomicAdd(dA + (size_t)(i0 + ii) * s.n_basis + ao, (double)v);
+        {   // wave: 32-slot block nb, half kh of the MOs
+            const int nb = wave & 1, kh = wave >> 1;
+            const int kb = kh * (ADJ_MB / 2), ke = kb + ADJ_MB / 2;
+            Blk<MODE> acc;
+            acc.zero();
+            if constexpr (BF) {
+                f32x16 a16;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) a16[q] = 0.f;
+                const int c = nb * 32 + (lane & 31);
+                const int slot = (wq[c / WIN] < 0 ? 0 : wq[c / WIN]) * WIN + (c % WIN);
+                const int oct = lane >> 5;
+                for (int k0 = kb; k0 < ke; k0 += 16) {
+                    const int ig = min(i0 + k0 + 8 * oct, ldn - 8);
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(AThi + (size_t)slot * ldn + ig));
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(ATlo + (size_t)slot * ldn + ig));
+                    const int off = (lane & 31) * LDG + k0 + 8 * oct;
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(Gh + off));
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(Gl + off));
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a16, 0, 0, 0);
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, a16, 0, 0, 0);
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, a16, 0, 0, 0);
                 }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc.v[q] = a16[q];
+            } else {
+                int slotc[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = nb * 32 + (MODE == QSL_FP64 ? h * 16 + (lane & 15) : (lane & 31));
+                    slotc[h] = (wq[c / WIN] < 0 ? 0 : wq[c / WIN]) * WIN + (c % WIN);
+                }
+                auto fa = [&](int r, int k) -> T { return Gt[r * LDG + k]; };
+                auto fb = [&](int k, int cc) -> T {
+                    const int ig = min(i0 + k, ldn - 1);
+                    if constexpr (MODE == QSL_FP64) return A64[(size_t)ig * s.n_slots + slotc[cc >> 4]];
+                    else return A32[(size_t)ig * s.n_slots + slotc[0]];
+                };
+                mma_f<MODE>(acc, kb, ke, lane, fa, fb);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) Hb[kh][Blk<MODE>::row(q, lane)][nb * 32 + Blk<MODE>::col(q, lane)] = acc.v[q];
+        }
+        __syncthreads();
+        if (tid < 96) {
+            const int e = tid & (TE - 1), comp = tid >> 5;
+            T acc = 0;
+#pragma unroll 8
+            for (int c = 0; c < AH_KC; ++c) acc += (Hb[0][e][c] + Hb[1][e][c]) * dX[comp][e][c];
+            dr += acc;
+        }
+    }
+    if (tid < 96 && dR) {
+        const int e = tid & (TE - 1), comp = tid >> 5;
+        if (e < ne) atomicAdd(dR + ((size_t)w * N + eoff + e0 + e) * 3 + comp, (double)dr);
+    }
+}
+
+// --------------------------------------------------------------- adj_dA
+
+constexpr int AD_THREADS = 512;          // 8 waves
+
+template <int MODE>
+struct AdCfg {
+    using T = TOf<MODE>;
+    static constexpr bool BF = MODE == QSL_BF16X3;
+    static constexpr int NWB = MODE == QSL_FP64 ? 16 : 32;   // windows per block
+    static constexpr int NS = NWB * WIN;                     // slots per block
+    static constexpr int SB = NS / 32;                       // 32-slot blocks
+    static constexpr int NBLK = ADJ_NIB * SB;                // 32x32 output blocks
+    static constexpr int PB = (NBLK + 7) / 8;                // blocks per wave
+    static constexpr int LDGT = BF ? TE + 8 : TE + 1;        // G^T [i][e]
+    static constexpr int LDX = BF ? TE + 8 : NS + 1;         // chi: [slot][e] (bf16) or [e][slot]
+};
+
+template <int MODE>
+__global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(DevSys s, int spin, int n, int64_t W, int gw,
+                                                            const double* __restrict__ R,
+                                                            const int* __restrict__ grp_nwin,
+                                                            const int* __restrict__ grp_win,
+                                                            const double* __restrict__ Dinv,
+                                                            const double* __restrict__ g,
+                                                            double* __restrict__ dA64, float* __restrict__ dA32) {
+    using C = AdCfg<MODE>;
+    using T = typename C::T;
+    constexpr bool BF = C::BF;
+    constexpr int NWB = C::NWB, NS = C::NS, SB = C::SB, NBLK = C::NBLK, PB = C::PB, LDGT = C::LDGT, LDX = C::LDX;
+    __shared__ double epos[TE][3];
+    __shared__ int wq[NWB];
+    __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? 2 * 2 * ADJ_MB * LDGT : sizeof(T) * ADJ_MB * LDGT];
+    __shared__ __attribute__((aligned(16))) unsigned char xbuf[BF ? 2 * 2 * NS * LDX : sizeof(T) * TE * LDX];
+
+    const int ngw = (int)((W + gw - 1) / gw);
+    const int grp = blockIdx.x;
+    const int t = grp / ngw, wb = grp % ngw;
+    const int w0 = wb * gw;
+    const int nw = (int)min<int64_t>(gw, W - w0);
+    const int e0 = t * TE;
+    const int ne = min(TE, n - e0);
+    const int nwin = grp_nwin[grp];
+    const int q0 = blockIdx.y * NWB;
+    if (q0 >= nwin) return;
+    const int nq = min(NWB, nwin - q0);
+    const int i0 = blockIdx.z * ADJ_MB;
+    const int N = s.n_up + s.n_dn;
+    const int eoff = spin ? s.n_up : 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint16_t* GTh = (uint16_t*)gbuf;
+    uint16_t* GTl = GTh + ADJ_MB * LDGT;
+    T* GTt = (T*)gbuf;
+    uint16_t* Xh = (uint16_t*)xbuf;
+    uint16_t* Xl = Xh + NS * LDX;
+    T* Xt = (T*)xbuf;
+
+    if (tid < NWB) wq[tid] = tid < nq ? grp_win[(size_t)grp * s.n_win + q0 + tid] : -1;
+    Blk<MODE> acc[PB];
+#pragma unroll
+    for (int k = 0; k < PB; ++k) acc[k].zero();
+
+    for (int wl = 0; wl < nw; ++wl) {
+        const int w = w0 + wl;
+        __syncthreads();  // previous walker's operands are consumed
+        if (tid < TE * 3) {
+            const int e = tid / 3, k = tid % 3;
+            epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
+        }
+        const double gwv = g[2 * w + spin];
+        for (int q = tid; q < TE * ADJ_MB; q += AD_THREADS) {
+            const int e = q / ADJ_MB, ii = q % ADJ_MB;
+            double v = 0.0;
+            if (gwv != 0.0 && e < ne && i0 + ii < n) v = gwv * Dinv[((size_t)w * n + e0 + e) * n + i0 + ii];
+            if constexpr (BF) {
+                const float f = (float)v;
+                const uint16_t h = bf16_rne(f);
+                GTh[ii * LDGT + e] = h;
+                GTl[ii * LDGT + e] = bf16_rne(f - bf16_to_f(h));
+            } else {
+                GTt[ii * LDGT + e] = (T)v;
             }
         }
-        {   // H[e][slot] = sum_i G[e][i] a_i,slot ; dR_e += H grad chi
-            const int e = tid & (TE - 1), sg = tid / TE;
+        __syncthreads();
+        // AO values of (electron, window) into LDS
+        for (int p = tid; p < TE * NWB; p += AD_THREADS) {
+            const int e = p & (TE - 1), wli = p / TE;
+            T vals[4][WIN];
+            const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+            window_values<T>(s, e < ne ? wq[wli] : -1, r, vals);
+#pragma unroll
             for (int j = 0; j < WIN; ++j) {
-                const int c = sg * WIN + j;
-                const int q = wq[c / WIN];
-                if (q < 0) continue;
-                const int slot = q * WIN + (c % WIN);
-                const T* a = AT + (size_t)slot * ldn + i0;
-                T h = 0;
-                for (int ii = 0; ii < BW_MB; ++ii) h += G[e][ii] * a[ii];
-                dr[0] += h * Bv[1][e][c];
-                dr[1] += h * Bv[2][e][c];
-                dr[2] += h * Bv[3][e][c];
+                const int c = wli * WIN + j;
+                if constexpr (BF) {
+                    const uint16_t h = bf16_rne(vals[0][j]);
+                    Xh[c * LDX + e] = h;
+                    Xl[c * LDX + e] = bf16_rne(vals[0][j] - bf16_to_f(h));
+                } else {
+                    Xt[e * LDX + c] = vals[0][j];
+                }
             }
         }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PB; ++k) {
+            const int b = wave + 8 * k;
+            if (b >= NBLK) continue;
+            const int ib = b / SB, sb = b % SB;
+            if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
+            if constexpr (BF) {
+                f32x16 a16;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) a16[q] = acc[k].v[q];
+                const int oct = lane >> 5;
+#pragma unroll
+                for (int k0 = 0; k0 < TE; k0 += 16) {
+                    const int offa = (ib * 32 + (lane & 31)) * LDGT + k0 + 8 * oct;
+                    const int offb = (sb * 32 + (lane & 31)) * LDX + k0 + 8 * oct;
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(GTh + offa));
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(GTl + offa));
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(Xh + offb));
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(Xl + offb));
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a16, 0, 0, 0);
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, a16, 0, 0, 0);
+                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, a16, 0, 0, 0);
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc[k].v[q] = a16[q];
+            } else {
+                auto fa = [&](int r, int kk) -> T { return GTt[(ib * 32 + r) * LDGT + kk]; };
+                auto fb = [&](int kk, int cc) -> T { return Xt[kk * LDX + sb * 32 + cc]; };
+                mma_f<MODE>(acc[k], 0, TE, lane, fa, fb);
+            }
+        }
     }
-    {
-        const int e = tid & (TE - 1), sg = tid / TE;
-        for (int k = 0; k < 3; ++k) red[sg][e][k] = dr[k];
-    }
-    __syncthreads();
-    if (tid < TE * 3) {
-        const int e = tid / 3, k = tid % 3;
-        if (e < ne && dR) {
-            T v = 0;
-            for (int q = 0; q < BW_THREADS / TE; ++q) v += red[q][e][k];
-            atomicAdd(dR + ((size_t)w * N + eoff + e0 + e) * 3 + k, (double)v);
+    // one coalesced flush: the lanes of one accumulator register cover
+    // consecutive slots of one MO row
+#pragma unroll
+    for (int k = 0; k < PB; ++k) {
+        const int b = wave + 8 * k;
+        if (b >= NBLK) continue;
+        const int ib = b / SB, sb = b % SB;
+        if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int i = i0 + ib * 32 + Blk<MODE>::row(q, lane);
+            const int c = sb * 32 + Blk<MODE>::col(q, lane);
+            const int qw = wq[c / WIN];
+            const T v = acc[k].v[q];
+            if (i >= n || qw < 0 || v == T(0)) continue;
+            const int ao = s.slot_ao[qw * WIN + (c % WIN)];
+            if (ao < 0) continue;
+            if constexpr (MODE == QSL_FP64) {
+                if (dA64) atomicAdd(dA64 + (size_t)i * s.n_basis + ao, v);
+            } else {
+                if (dA32) atomicAdd(dA32 + (size_t)i * s.n_basis + ao, v);
+            }
         }
     }
 }
 
-hipError_t launch_backward(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
-                           const int* tile_nwin, const int* tile_win, const double* Dinv, const double* g,
-                           double* dR, double* dA, hipStream_t st) {
+hipError_t launch_adj_h(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
+                        const int* tile_nwin, const int* tile_win, const double* Dinv, const double* g, double* dR,
+                        hipStream_t st) {
     const int n = n_spin(s, spin);
-    const int tpw = tiles_per_walker(n);
-    const int64_t tiles = W * tpw;
-    if (!tiles || (!dR && !dA)) return hipSuccess;
-    dim3 grid((unsigned)tiles, (n + BW_MB - 1) / BW_MB);
-    if (mode == QSL_FP64)
-        backward_kernel<double><<<grid, BW_THREADS, 0, st>>>(s, spin, n, tpw, mo.ldn, R, tile_nwin, tile_win,
-                                                             mo.AT64, Dinv, g, dR, dA);
-    else
-        backward_kernel<float><<<grid, BW_THREADS, 0, st>>>(s, spin, n, tpw, mo.ldn, R, tile_nwin, tile_win,
-                                                            mo.AT32, Dinv, g, dR, dA);
+    const int64_t tiles = W * tiles_per_walker(n);
+    if (!tiles || !dR) return hipSuccess;
+    dim3 grid((unsigned)tiles, (n + ADJ_MB - 1) / ADJ_MB);
+#define QSL_AH_ARGS s, spin, n, W, mo.ldn, R, tile_nwin, tile_win, mo.AThi, mo.ATlo, mo.A32, mo.A64, Dinv, g, dR
+    if (mode == QSL_FP64) adj_h_kernel<QSL_FP64><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
+    else if (mode == QSL_FP32) adj_h_kernel<QSL_FP32><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
+    else adj_h_kernel<QSL_BF16X3><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
+#undef QSL_AH_ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_da(const DevSys& s, int spin, int mode, int64_t W, int gw, const double* R, const int* grp_nwin,
+                         const int* grp_win, const double* Dinv, const double* g, double* dA64, float* dA32,
+                         hipStream_t st) {
+    const int n = n_spin(s, spin);
+    const int64_t groups = (int64_t)tiles_per_walker(n) * ((W + gw - 1) / gw);
+    if (!groups || (!dA64 && !dA32)) return hipSuccess;
+    const int mob = (n + ADJ_MB - 1) / ADJ_MB;
+#define QSL_AD_ARGS s, spin, n, W, gw, R, grp_nwin, grp_win, Dinv, g, dA64, dA32
+    if (mode == QSL_FP64) {
+        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_FP64>::NWB - 1) / AdCfg<QSL_FP64>::NWB, mob);
+        adj_da_kernel<QSL_FP64><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
+    } else if (mode == QSL_FP32) {
+        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_FP32>::NWB - 1) / AdCfg<QSL_FP32>::NWB, mob);
+        adj_da_kernel<QSL_FP32><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
+    } else {
+        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_BF16X3>::NWB - 1) / AdCfg<QSL_BF16X3>::NWB, mob);
+        adj_da_kernel<QSL_BF16X3><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
+    }
+#undef QSL_AD_ARGS
     return hipGetLastError();
 }
 

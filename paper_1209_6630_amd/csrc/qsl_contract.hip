@@ -38,7 +38,7 @@ struct CT {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin, int n, int tpw, int ldn,
+__global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin, int n, int64_t W, int ldn,
                                                               const double* __restrict__ R,
                                                               const int* __restrict__ tile_nwin,
                                                               const int* __restrict__ tile_win,
@@ -58,10 +58,12 @@ __global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin
     constexpr int BELEMS = 5 * TE * LD;
     __shared__ __attribute__((aligned(16))) unsigned char bbuf[MODE == QSL_BF16X3 ? 2 * BELEMS * 2 : BELEMS * sizeof(T)];
 
+    // tiles are numbered t * W + w (electron range t of walker w), so that
+    // concurrently resident workgroups share the same AO windows of A
     const int tile = blockIdx.x;
     const int n0 = blockIdx.y * P::NB;
-    const int w = tile / tpw;
-    const int e0 = (tile % tpw) * TE;
+    const int w = (int)(tile % W);
+    const int e0 = (int)(tile / W) * TE;
     const int ne = min(TE, n - e0);
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
@@ -229,19 +231,19 @@ hipError_t launch_contract(const DevSys& s, const DevMO& mo, int spin, int mode,
     switch (mode) {
         case QSL_FP64: {
             dim3 g((unsigned)tiles, (n + CT<QSL_FP64>::NB - 1) / CT<QSL_FP64>::NB);
-            contract_kernel<QSL_FP64><<<g, CT_THREADS, 0, st>>>(s, spin, n, tpw, mo.ldn, R, tile_nwin, tile_win,
+            contract_kernel<QSL_FP64><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
                                                                   mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
             break;
         }
         case QSL_FP32: {
             dim3 g((unsigned)tiles, (n + CT<QSL_FP32>::NB - 1) / CT<QSL_FP32>::NB);
-            contract_kernel<QSL_FP32><<<g, CT_THREADS, 0, st>>>(s, spin, n, tpw, mo.ldn, R, tile_nwin, tile_win,
+            contract_kernel<QSL_FP32><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
                                                                   mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
             break;
         }
         default: {
             dim3 g((unsigned)tiles, (n + CT<QSL_BF16X3>::NB - 1) / CT<QSL_BF16X3>::NB);
-            contract_kernel<QSL_BF16X3><<<g, CT_THREADS, 0, st>>>(s, spin, n, tpw, mo.ldn, R, tile_nwin, tile_win,
+            contract_kernel<QSL_BF16X3><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
                                                                     mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
             break;
         }

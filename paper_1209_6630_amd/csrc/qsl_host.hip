@@ -107,9 +107,13 @@ ProfScope::~ProfScope() {
     g_prof_pending.push_back({name, a, b});
 }
 
+
+// Walkers per dA group: they share one window list (screened together).
+static int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
+
 // Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win].
 struct WsLayout {
-    size_t nwin_off[2], win_off[2], total;
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], total;
 };
 
 static WsLayout ws_layout(const DevSys& d, int64_t W) {
@@ -122,6 +126,18 @@ static WsLayout ws_layout(const DevSys& d, int64_t W) {
         off = round_up(off + tiles * sizeof(int), 256);
         L.win_off[s] = off;
         off = round_up(off + tiles * (size_t)d.n_win * sizeof(int), 256);
+    }
+    for (int s = 0; s < 2; ++s) {
+        int n = n_spin(d, s);
+        size_t groups = n ? (size_t)tiles_per_walker(n) * ((W + bw_group(W) - 1) / std::max(bw_group(W), 1)) : 0;
+        L.gnwin_off[s] = off;
+        off = round_up(off + groups * sizeof(int), 256);
+        L.gwin_off[s] = off;
+        off = round_up(off + groups * (size_t)d.n_win * sizeof(int), 256);
+    }
+    for (int s = 0; s < 2; ++s) {
+        L.dA32_off[s] = off;
+        off = round_up(off + (size_t)n_spin(d, s) * d.n_basis * sizeof(float), 256);
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -304,7 +320,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         size_t o_wat = ar.add(win_atom.data(), sizeof(int) * win_atom.size());
         size_t o_wgm = ar.add(win_gmin.data(), sizeof(double) * win_gmin.size());
         // MO copies per spin
-        size_t o_mo[2][6];
+        size_t o_mo[2][8];
         int ldn[2];
         for (int sp = 0; sp < 2; ++sp) {
             int n = sp ? d->n_dn : d->n_up;
@@ -313,6 +329,8 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             o_mo[sp][0] = ar.reserve(cells * 8);
             o_mo[sp][1] = ar.reserve(cells * 4);
             for (int k = 2; k < 6; ++k) o_mo[sp][k] = ar.reserve(cells * 2);
+            o_mo[sp][6] = ar.reserve(cells * 8);
+            o_mo[sp][7] = ar.reserve(cells * 4);
         }
         void* blk = nullptr;
         hipError_t e = hipMalloc(&blk, ar.buf.size());
@@ -346,6 +364,8 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             m.Alo = (uint16_t*)(b + o_mo[sp][3]);
             m.AThi = (uint16_t*)(b + o_mo[sp][4]);
             m.ATlo = (uint16_t*)(b + o_mo[sp][5]);
+            m.A64 = (double*)(b + o_mo[sp][6]);
+            m.A32 = (float*)(b + o_mo[sp][7]);
             m.set = (m.n == 0);
         }
         *out = S;
@@ -445,7 +465,7 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         if (n) {
             {
                 ProfScope ps("screen", st);
-                if ((e = launch_screen(d, s, a->W, a->R, nwin, win, a->status, st)) != hipSuccess)
+                if ((e = launch_screen(d, s, a->W, 1, a->R, nwin, win, a->status, st)) != hipSuccess)
                     return hip_fail(e, "screen kernel");
             }
             {
@@ -478,7 +498,7 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
     hipError_t e;
     const int N = d.n_up + d.n_dn;
     for (int s = 0; s < 2; ++s) {
-        if (a->dA[s] && !a->accumulate_dA && n_spin(d, s)) {
+        if (a->dA[s] && !a->accumulate_dA && n_spin(d, s) && a->mode == QSL_FP64) {
             if ((e = fill_f64(a->dA[s], 0.0, (int64_t)n_spin(d, s) * d.n_basis, st)) != hipSuccess)
                 return hip_fail(e, "dA clear");
         }
@@ -499,15 +519,37 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
         if (!n) continue;
         int* nwin = (int*)(ws + L.nwin_off[s]);
         int* win = (int*)(ws + L.win_off[s]);
+        float* dA32 = (float*)(ws + L.dA32_off[s]);
+        const bool f32acc = a->mode != QSL_FP64 && a->dA[s];
+        if (f32acc && (e = fill_u32((uint32_t*)dA32, 0u, (int64_t)n * d.n_basis, st)) != hipSuccess)
+            return hip_fail(e, "dA accumulator clear");
         {
             ProfScope ps("screen", st);
-            if ((e = launch_screen(d, s, a->W, a->R, nwin, win, nullptr, st)) != hipSuccess)
+            if ((e = launch_screen(d, s, a->W, 1, a->R, nwin, win, nullptr, st)) != hipSuccess)
                 return hip_fail(e, "screen kernel");
         }
-        ProfScope ps("adjoint", st);
-        if ((e = launch_backward(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->Dinv[s], a->g_logdet, a->dR,
-                                 a->dA[s], st)) != hipSuccess)
-            return hip_fail(e, "backward kernel");
+        {
+            ProfScope ps("adjoint_h", st);
+            if ((e = launch_adj_h(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->Dinv[s], a->g_logdet, a->dR,
+                                  st)) != hipSuccess)
+                return hip_fail(e, "adjoint H kernel");
+        }
+        const int gw = bw_group(a->W);
+        int* gnwin = (int*)(ws + L.gnwin_off[s]);
+        int* gwin = (int*)(ws + L.gwin_off[s]);
+        if (a->dA[s]) {
+            {
+                ProfScope ps("screen_group", st);
+                if ((e = launch_screen(d, s, a->W, gw, a->R, gnwin, gwin, nullptr, st)) != hipSuccess)
+                    return hip_fail(e, "group screen kernel");
+            }
+            ProfScope ps("adjoint_dA", st);
+            if ((e = launch_adj_da(d, s, a->mode, a->W, gw, a->R, gnwin, gwin, a->Dinv[s], a->g_logdet,
+                                   a->mode == QSL_FP64 ? a->dA[s] : nullptr, f32acc ? dA32 : nullptr, st)) != hipSuccess)
+                return hip_fail(e, "adjoint dA kernel");
+        }
+        if (f32acc && (e = launch_finalize_dA(dA32, a->dA[s], (int64_t)n * d.n_basis, a->accumulate_dA, st)) != hipSuccess)
+            return hip_fail(e, "dA finalize");
     }
     return QSL_OK;
 }

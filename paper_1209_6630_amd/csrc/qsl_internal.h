@@ -52,6 +52,8 @@ struct DevMO {
     uint16_t* Alo = nullptr;
     uint16_t* AThi = nullptr;   // [n_slots][ldn]
     uint16_t* ATlo = nullptr;
+    double* A64 = nullptr;      // [ldn][n_slots]
+    float* A32 = nullptr;       // [ldn][n_slots]
 };
 
 }  // namespace qsl
@@ -155,7 +157,9 @@ struct ProfScope {
 
 // ------------------------------------------------------------- launchers
 
-hipError_t launch_screen(const DevSys& s, int spin, int64_t W, const double* R, int* tile_nwin,
+// Screening groups: `gw` tiles of one electron range over consecutive
+// walkers; group index = t * ceil(W / gw) + walker block.
+hipError_t launch_screen(const DevSys& s, int spin, int64_t W, int gw, const double* R, int* tile_nwin,
                          int* tile_win, uint32_t* status, hipStream_t st);
 hipError_t launch_contract(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W,
                            const double* R, const int* tile_nwin, const int* tile_win, void* C,
@@ -165,10 +169,13 @@ hipError_t launch_gj(int mode, const void* C, int n, int64_t W, int spin, double
 hipError_t launch_epilogue(int mode, const void* C, const double* Dinv, int n, int64_t W, int spin,
                            int N, int e_off, double* drift, double* lap, const double* logdet,
                            uint32_t* status, hipStream_t st);
-hipError_t launch_backward(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W,
-                           const double* R, const int* tile_nwin, const int* tile_win,
-                           const double* Dinv, const double* g, double* dR, double* dA,
-                           hipStream_t st);
+hipError_t launch_adj_h(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
+                        const int* tile_nwin, const int* tile_win, const double* Dinv, const double* g, double* dR,
+                        hipStream_t st);
+hipError_t launch_adj_da(const DevSys& s, int spin, int mode, int64_t W, int gw, const double* R, const int* grp_nwin,
+                         const int* grp_win, const double* Dinv, const double* g, double* dA64, float* dA32,
+                         hipStream_t st);
+hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
 hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A_dev, int64_t ld,
                            hipStream_t st);
 hipError_t launch_scale_copy(double* dst, const double* src, int64_t n, hipStream_t st);

@@ -9,7 +9,7 @@ namespace qsl {
 // [slot][ldn]; hi = bf16(x), lo = bf16(x - hi) of the FP32 value x.
 __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restrict__ A, int64_t ld,
                                 double* AT64, float* AT32, uint16_t* Ahi, uint16_t* Alo, uint16_t* AThi,
-                                uint16_t* ATlo) {
+                                uint16_t* ATlo, double* A64, float* A32) {
     const int64_t total = (int64_t)s.n_slots * ldn;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
         const int slot = (int)(q / ldn), mo = (int)(q % ldn);
@@ -24,6 +24,8 @@ __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restri
         ATlo[q] = l;
         Ahi[(int64_t)mo * s.n_slots + slot] = h;
         Alo[(int64_t)mo * s.n_slots + slot] = l;
+        A64[(int64_t)mo * s.n_slots + slot] = v;
+        A32[(int64_t)mo * s.n_slots + slot] = f;
     }
 }
 
@@ -32,7 +34,21 @@ hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A, int64_t 
     if (!total) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
     build_mo_kernel<<<blocks, 256, 0, st>>>(s, mo.n, mo.ldn, A, ld, mo.AT64, mo.AT32, mo.Ahi, mo.Alo, mo.AThi,
-                                            mo.ATlo);
+                                            mo.ATlo, mo.A64, mo.A32);
+    return hipGetLastError();
+}
+
+// dA (caller, FP64) = [dA +] the FP32 accumulator of the adjoint kernel.
+__global__ void finalize_dA_kernel(const float* __restrict__ a32, double* __restrict__ dA, int64_t count,
+                                   int accumulate) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x)
+        dA[q] = (accumulate ? dA[q] : 0.0) + (double)a32[q];
+}
+
+hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
+    finalize_dA_kernel<<<blocks, 256, 0, st>>>(dA32, dA, count, accumulate);
     return hipGetLastError();
 }
 

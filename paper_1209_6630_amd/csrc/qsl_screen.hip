@@ -14,41 +14,65 @@ namespace qsl {
 
 constexpr int SCREEN_THREADS = 256;
 
-__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int spin, int n, int tpw,
-                                                                 const double* __restrict__ R,
+// A screening group is `gw` tiles with the same electron range over
+// consecutive walkers (gw = 1: one tile).  Groups are numbered
+// t * ngroups_w + walker-block (t = tile index within a walker).
+constexpr int SCREEN_MAXE = 2048;
+
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int spin, int n, int tpw, int64_t W,
+                                                                 int gw, const double* __restrict__ R,
                                                                  int* __restrict__ tile_nwin,
                                                                  int* __restrict__ tile_win,
                                                                  uint32_t* __restrict__ status) {
-    __shared__ double ex[TE], ey[TE], ez[TE];
+    __shared__ double ex[SCREEN_MAXE], ey[SCREEN_MAXE], ez[SCREEN_MAXE];
     __shared__ double bb[6];
+    __shared__ double bred[SCREEN_THREADS / 64][6];
     __shared__ int wave_cnt[SCREEN_THREADS / 64];
     const int tile = blockIdx.x;
-    const int w = tile / tpw;
-    const int e0 = (tile % tpw) * TE;
+    const int ngw = (int)((W + gw - 1) / gw);
+    const int t = tile / ngw, wb = tile % ngw;
+    const int w0 = wb * gw;
+    const int nw = (int)min<int64_t>(gw, W - w0);
+    const int e0 = t * TE;
     const int ne = min(TE, n - e0);
     const int N = s.n_up + s.n_dn;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int eoff = spin ? s.n_up : 0;
+    const int nall = nw * TE;  // electron slots of the group (ragged tiles padded)
+    const int w = w0;          // walker that owns a near-tie flag when gw == 1
 
-    if (tid < 64) {
+    // electron k of the group: walker w0 + k / TE, electron e0 + k % TE; the
+    // first SCREEN_MAXE positions are staged in LDS, the rest read from L2
+    auto gpos = [&](int k) -> const double* {
+        return R + ((size_t)(w0 + k / TE) * N + eoff + e0 + k % TE) * 3;
+    };
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = tid; k < nall; k += SCREEN_THREADS) {
+        const int e = k % TE;
         double x = 0, y = 0, z = 0;
-        bool ok = tid < ne;
-        if (ok) {
-            const double* r = R + ((size_t)w * N + eoff + e0 + tid) * 3;
+        if (e < ne) {
+            const double* r = gpos(k);
             x = r[0]; y = r[1]; z = r[2];
-            ex[tid] = x; ey[tid] = y; ez[tid] = z;
+            lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
+            hi[0] = fmax(hi[0], x); hi[1] = fmax(hi[1], y); hi[2] = fmax(hi[2], z);
         }
-        // bounding box of the tile's electrons
-        double lo[3] = {ok ? x : INFINITY, ok ? y : INFINITY, ok ? z : INFINITY};
-        double hi[3] = {ok ? x : -INFINITY, ok ? y : -INFINITY, ok ? z : -INFINITY};
-        for (int o = 32; o >= 1; o >>= 1)
-            for (int k = 0; k < 3; ++k) {
-                lo[k] = fmin(lo[k], __shfl_xor(lo[k], o));
-                hi[k] = fmax(hi[k], __shfl_xor(hi[k], o));
-            }
-        if (tid == 0)
-            for (int k = 0; k < 3; ++k) { bb[k] = lo[k]; bb[3 + k] = hi[k]; }
+        if (k < SCREEN_MAXE) { ex[k] = x; ey[k] = y; ez[k] = z; }
     }
+    // bounding box of the group's electrons
+    for (int o = 32; o >= 1; o >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], o));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], o));
+        }
+    if (lane == 0)
+        for (int k = 0; k < 3; ++k) { bred[wave][k] = lo[k]; bred[wave][3 + k] = hi[k]; }
+    __syncthreads();
+    if (tid == 0)
+        for (int k = 0; k < 3; ++k) {
+            double a = INFINITY, b = -INFINITY;
+            for (int v = 0; v < SCREEN_THREADS / 64; ++v) { a = fmin(a, bred[v][k]); b = fmax(b, bred[v][3 + k]); }
+            bb[k] = a; bb[3 + k] = b;
+        }
     __syncthreads();
 
     int base = 0;
@@ -66,12 +90,17 @@ __global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int sp
             double dz = fmax(fmax(bb[2] - qz, qz - bb[5]), 0.0);
             if (gm * (dx * dx + dy * dy + dz * dz) <= s.T * (1.0 + 1e-9)) {
                 bool tie = false;
-                for (int e = 0; e < ne; ++e) {
-                    const double t = __dmul_rn(gm, dist2_exact(ex[e] - qx, ey[e] - qy, ez[e] - qz));
-                    active |= t <= s.T;
+                for (int k = 0; k < nall; ++k) {
+                    if (k % TE >= ne) continue;
+                    double px, py, pz;
+                    if (k < SCREEN_MAXE) { px = ex[k]; py = ey[k]; pz = ez[k]; }
+                    else { const double* r = gpos(k); px = r[0]; py = r[1]; pz = r[2]; }
+                    const double tt = __dmul_rn(gm, dist2_exact(px - qx, py - qy, pz - qz));
+                    active |= tt <= s.T;
                     // the smallest exponent of a dropped window decides its
                     // nearest primitive to the threshold
-                    tie |= t > s.T && t - s.T <= 1e-12 * s.T;
+                    tie |= tt > s.T && tt - s.T <= 1e-12 * s.T;
+                    if (active && !status) break;
                 }
                 if (tie && status) atomicOr(status + w, QSL_STATUS_NEAR_TIE);
             }
@@ -94,13 +123,15 @@ __global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int sp
     if (tid == 0) tile_nwin[tile] = base;
 }
 
-hipError_t launch_screen(const DevSys& s, int spin, int64_t W, const double* R, int* tile_nwin, int* tile_win,
-                         uint32_t* status, hipStream_t st) {
+hipError_t launch_screen(const DevSys& s, int spin, int64_t W, int gw, const double* R, int* tile_nwin,
+                         int* tile_win, uint32_t* status, hipStream_t st) {
     const int n = n_spin(s, spin);
     const int tpw = tiles_per_walker(n);
-    const int64_t tiles = W * tpw;
-    if (tiles == 0) return hipSuccess;
-    screen_kernel<<<dim3((unsigned)tiles), SCREEN_THREADS, 0, st>>>(s, spin, n, tpw, R, tile_nwin, tile_win, status);
+    if (gw < 1 || (gw > 1 && status)) return hipErrorInvalidValue;
+    const int64_t groups = (int64_t)tpw * ((W + gw - 1) / gw);
+    if (groups == 0) return hipSuccess;
+    screen_kernel<<<dim3((unsigned)groups), SCREEN_THREADS, 0, st>>>(s, spin, n, tpw, W, gw, R, tile_nwin, tile_win,
+                                                                     status);
     return hipGetLastError();
 }
 
