@@ -150,7 +150,8 @@ __global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(DevSys s, int spin, i
     const int i0 = blockIdx.y * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     uint16_t* Gh = (uint16_t*)gbuf;
     uint16_t* Gl = Gh + TE * LDG;
     T* Gt = (T*)gbuf;
@@ -202,12 +203,14 @@ __global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(DevSys s, int spin, i
 #pragma unroll
                 for (int q = 0; q < 16; ++q) a16[q] = 0.f;
                 const int c = nb * 32 + (lane & 31);
-                const int slot = (wq[c / WIN] < 0 ? 0 : wq[c / WIN]) * WIN + (c % WIN);
+                const int qc = wq[c / WIN] < 0 ? 0 : wq[c / WIN];
+                const size_t wbase = (size_t)qc * (ldn / 8);
                 const int oct = lane >> 5;
                 for (int k0 = kb; k0 < ke; k0 += 16) {
                     const int ig = min(i0 + k0 + 8 * oct, ldn - 8);
-                    const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(AThi + (size_t)slot * ldn + ig));
-                    const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(ATlo + (size_t)slot * ldn + ig));
+                    const size_t offb = ((wbase + ig / 8) * WIN + (c % WIN)) * 8;
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(AThi + offb));
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(ATlo + offb));
                     const int off = (lane & 31) * LDG + k0 + 8 * oct;
                     const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(Gh + off));
                     const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(Gl + off));
@@ -298,7 +301,8 @@ __global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(DevSys s, int spin, 
     const int i0 = blockIdx.z * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     uint16_t* GTh = (uint16_t*)gbuf;
     uint16_t* GTl = GTh + ADJ_MB * LDGT;
     T* GTt = (T*)gbuf;

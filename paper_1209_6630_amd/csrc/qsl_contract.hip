@@ -67,7 +67,8 @@ __global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin
     const int ne = min(TE, n - e0);
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
@@ -150,9 +151,9 @@ __global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin
             const int mo = n0 + wave * 32 + (lane & 31);
             const int oct = lane >> 5;
             for (int ks = 0; ks < KC / 16; ++ks) {
-                const int slot = wq[ks * 2 + oct] * WIN;
-                const uint4 ah = *(const uint4*)(Ahi + (size_t)mo * s.n_slots + slot);
-                const uint4 al = *(const uint4*)(Alo + (size_t)mo * s.n_slots + slot);
+                const size_t off = ((size_t)wq[ks * 2 + oct] * ldn + mo) * WIN;
+                const uint4 ah = *(const uint4*)(Ahi + off);
+                const uint4 al = *(const uint4*)(Alo + off);
                 const bf16x8 bah = __builtin_bit_cast(bf16x8, ah);
                 const bf16x8 bal = __builtin_bit_cast(bf16x8, al);
                 for (int d = 0; d < 5; ++d) {

@@ -1,16 +1,13 @@
 // FP64 log|det|, sign and inverse of the Slater matrices (inversion step,
 // section "Overall performance of QMC=Chem"; Slater matrix D_ij = phi_i(r_j)).
 //
-// One workgroup inverts one n x n matrix held entirely in registers:
-// thread (pr, pc) of a PR x PC grid owns D[i][e] for i = pc + PC c (MO rows)
-// and e = pr + PR r (electron columns), loaded coalesced from C_1[e][i].
-// Gauss-Jordan elimination with partial pivoting on the rows of D: at step
-// k the pivot is the largest |D[i][k]| over rows not yet used (smallest i on
-// exact ties), found by one thread row with a wavefront shuffle reduction.
-// Pivot rows are not moved; the pivot sequence p_k is recorded and the
-// result is un-permuted on the way out: D^-1[k][p_j] = M[p_k][j].  The pivots
-// are the diagonal of U in P D = L U, so log|det| = sum log|pivot| and
-// sign = sign(permutation) prod sign(pivot).  2 n^3 flops per matrix.
+// One workgroup inverts one n x n matrix held entirely in registers, by
+// Gauss-Jordan elimination with partial pivoting on the rows of D: at step k
+// the pivot is the largest |D[i][k]| over rows not yet used (smallest i on
+// exact ties).  Pivot rows are not moved; the pivot sequence p_k is recorded
+// and the result is un-permuted on the way out: D^-1[k][p_j] = M[p_k][j].
+// The pivots are the diagonal of U in P D = L U, so log|det| = sum log|pivot|
+// and sign = sign(permutation) prod sign(pivot).  2 n^3 flops per matrix.
 #include "qsl_internal.h"
 
 namespace qsl {
@@ -23,45 +20,84 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
-// Pivot search over column k (register row RK of thread row k % PR) among
-// the rows not yet used; publishes the pivot and the column (with a zero in
-// the pivot row, which the update must leave untouched).
-template <int PC, int CPT>
-__device__ __forceinline__ void gj_search(const double (&col)[CPT], int n, int pc, uint32_t used,
-                                          double* colout, int* piv_idx, double* piv_val) {
+// Layout: wave v of NWV owns the D columns e = v + NWV c (c < CPW, electron
+// index), lane l owns the D rows i = l + 64 r (r < RPL, MO index); thread
+// (v, l) holds M[r][c] in registers, loaded coalesced from C_1[e][i].
+// Step k: the wave owning column k finds the pivot among the unused rows
+// (a wavefront argmax), publishes the column (zero in the pivot row) and
+// the pivot through LDS, one barrier; every wave then reads the pivot row
+// of its own columns from lane p % 64 with readlane (scalar registers) and
+// applies the rank-1 update.  The pivot row is left unscaled (it is divided
+// by its pivot on the way out), its column-k entry becomes 1; the other rows
+// of column k become -D[i][k]/pv through the entry 1 + 1/pv of the pivot row.
+
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& best, int& bi) {
+    const double ob = dpp_f64<CTRL>(best);
+    const int oi = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xf, 0xf, false);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+}
+
+// argmax of |col| over the unused rows of this lane, then over the wavefront
+// (largest value, smallest row index on exact ties): DPP exchanges inside
+// rows of 16 lanes (quad swaps, half-row and row mirrors), then the four row
+// results through scalar registers.  Publishes column and pivot.
+template <int RPL>
+__device__ __forceinline__ void gj_search(const double (&col)[RPL], int n, int lane, uint32_t used, double* colout,
+                                          int* piv_idx, double* piv_val) {
     double best = -1.0;
     int bi = 0x7fffffff;
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int i = pc + PC * c;
-        const double v = fabs(col[c]);
-        if (i < n && !((used >> c) & 1u) && v > best) { best = v; bi = i; }
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        const double v = fabs(col[r]);
+        if (i < n && !((used >> r) & 1u) && v > best) { best = v; bi = i; }
+    }
+    argmax_step<0xB1>(best, bi);   // quad_perm [1,0,3,2]
+    argmax_step<0x4E>(best, bi);   // quad_perm [2,3,0,1]
+    argmax_step<0x141>(best, bi);  // row_half_mirror
+    argmax_step<0x140>(best, bi);  // row_mirror
+    double sb = readlane_f64(best, 0);
+    int si = __builtin_amdgcn_readlane(bi, 0);
+#pragma unroll
+    for (int rw = 1; rw < 4; ++rw) {
+        const double ob = readlane_f64(best, 16 * rw);
+        const int oi = __builtin_amdgcn_readlane(bi, 16 * rw);
+        if (ob > sb || (ob == sb && oi < si)) { sb = ob; si = oi; }
     }
 #pragma unroll
-    for (int o = PC / 2; o >= 1; o >>= 1) {
-        const double ob = __shfl_xor(best, o);
-        const int oi = __shfl_xor(bi, o);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i < n) colout[i] = (i == si) ? 0.0 : col[r];
+        if (i == si) *piv_val = col[r];
     }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int i = pc + PC * c;
-        if (i < n) colout[i] = (i == bi) ? 0.0 : col[c];
-        if (i == bi) *piv_val = col[c];
-    }
-    if (pc == 0) *piv_idx = bi;
+    if (lane == 0) *piv_idx = si;
 }
 
-template <int PR, int PC, int RPT, int CPT, typename Tin>
-__global__ __launch_bounds__(PR* PC) void gj_kernel(const Tin* __restrict__ C, int n, int spin,
-                                                    double* __restrict__ Dinv, double* __restrict__ logdet,
-                                                    int8_t* __restrict__ sign, uint32_t* __restrict__ status) {
-    constexpr int NT = PR * PC;
-    constexpr int NR = PC * CPT;  // capacity in D rows (MO index i)
-    constexpr int NC = PR * RPT;  // capacity in D columns (electron index e)
-    constexpr int QC = 8;         // rows of D^-1 staged per output pass
+template <int NWV, int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(NWV * 64) void gj_kernel(const Tin* __restrict__ C, int n, int spin,
+                                                      double* __restrict__ Dinv, double* __restrict__ logdet,
+                                                      int8_t* __restrict__ sign, uint32_t* __restrict__ status) {
+    constexpr int NT = NWV * 64;
+    constexpr int NR = 64 * RPL;   // capacity in D rows (MO index i)
+    constexpr int NC = NWV * CPW;  // capacity in D columns (electron index e)
+    constexpr int QC = 8;          // rows of D^-1 staged per output pass
     __shared__ double colbuf[2][NR];
-    __shared__ double rowbuf[2][NC];
     __shared__ int piv_idx[2];
     __shared__ double piv_val[2];
     __shared__ int perm[NC];
@@ -71,34 +107,34 @@ __global__ __launch_bounds__(PR* PC) void gj_kernel(const Tin* __restrict__ C, i
     __shared__ int s_flag;
 
     const int w = blockIdx.x;
-    const int tid = threadIdx.x, pr = tid / PC, pc = tid % PC;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const size_t nn = (size_t)n * n;
     const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
 
-    double M[RPT][CPT];
+    double M[RPL][CPW];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r)
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int e = pr + PR * r, i = pc + PC * c;
+        for (int r = 0; r < RPL; ++r) {
+            const int e = wave + NWV * c, i = lane + 64 * r;
             M[r][c] = (e < n && i < n) ? (double)C1[(size_t)e * n + i] : 0.0;
         }
     for (int k = tid; k < NR; k += NT) { colbuf[0][k] = 0.0; colbuf[1][k] = 0.0; }
-    for (int k = tid; k < NC; k += NT) { rowbuf[0][k] = 0.0; rowbuf[1][k] = 0.0; }
     if (tid == 0) s_flag = 0;
     __syncthreads();
-    uint32_t used = 0;  // bit c: row pc + PC c already a pivot row
-    if (pr == 0) {
-        double col[CPT];
+    uint32_t used = 0;  // bit r: row lane + 64 r already a pivot row
+    if (wave == 0) {
+        double col[RPL];
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) col[c] = M[0][c];
-        gj_search<PC, CPT>(col, n, pc, used, colbuf[0], &piv_idx[0], &piv_val[0]);
+        for (int r = 0; r < RPL; ++r) col[r] = M[r][0];
+        gj_search<RPL>(col, n, lane, used, colbuf[0], &piv_idx[0], &piv_val[0]);
     }
 
     bool singular = false;
     for (int k = 0; k < n; ++k) {
         const int b = k & 1;
-        __syncthreads();  // pivot, column k and the previous update are visible
+        __syncthreads();  // pivot and column k are published, step k-1 is done
         const int p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
         const double pv = piv_val[b];
         if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
@@ -107,51 +143,65 @@ __global__ __launch_bounds__(PR* PC) void gj_kernel(const Tin* __restrict__ C, i
             break;
         }
         const double inv = 1.0 / pv;
-        const int cp = p / PC;  // wave-uniform
-        const bool own_p = pc == p % PC;
-        // the pivot row, normalised; entry k carries 1 + 1/pv so that the
-        // update turns column k into -D[i][k]/pv
+        const int lp = p & 63, rp = p >> 6;  // wave-uniform
+        const int vk = k % NWV, ck = k / NWV;
+        double colv[RPL];
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            if (c == cp) {
-                if (own_p) {
-#pragma unroll
-                    for (int r = 0; r < RPT; ++r) {
-                        const int e = pr + PR * r;
-                        if (e < n) rowbuf[b][e] = e == k ? 1.0 + inv : M[r][c] * inv;
-                    }
-                    used |= 1u << c;
-                }
-            }
-        }
+        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][lane + 64 * r];
         if (tid == 0) {
             perm[k] = p;
             rowpiv[p] = pv;
         }
-        __syncthreads();
-        // rank-1 update; the pivot row keeps its values (scaled by pv), its
-        // column-k entry becomes 1 (i.e. 1/pv after the final row scaling)
-        const int rk = k / PR, kk = k % PR;
-        const int k1 = k + 1, rk1 = k1 / PR, kk1 = k1 % PR;
-        double col[CPT];
+        // rank-1 update with the pivot row read from lane lp, register row rp.
+        // The owner of column k + 1 updates that column first and publishes
+        // its pivot before the rest of its update (look-ahead).
+        const int k1 = k + 1;
+        const bool owner1 = k1 < n && wave == k1 % NWV;
+        const int c1 = owner1 ? k1 / NWV : -1;
+        // colv / pv, so that the pivot-row value read with readlane (a
+        // scalar) feeds the FMA directly; column k uses pv + 1, which turns
+        // column k into -D[i][k]/pv.  The pivot row is untouched (colv = 0).
+        double colv_s[RPL];
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) col[c] = 0.0;
+        for (int r = 0; r < RPL; ++r) colv_s[r] = colv[r] * inv;
+        // columns in chunks: the pivot-row values come from register row rp
+        // (a scalar branch) of lane lp into scalar registers
+        constexpr int CHK = CPW % 7 == 0 ? 7 : (CPW % 4 == 0 ? 4 : 1);
+        static_for<0, CPW / CHK>([&](auto chc) __attribute__((always_inline)) {
+            constexpr int c0 = decltype(chc)::value * CHK;
+            double rv[CHK];
+            auto grab = [&](auto rr) __attribute__((always_inline)) {
+                constexpr int r = decltype(rr)::value;
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const double rv = rowbuf[b][pr + PR * r];
+                for (int j = 0; j < CHK; ++j) rv[j] = readlane_f64(M[r][c0 + j], lp);
+            };
+            if (rp == 0) grab(std::integral_constant<int, 0>{});
+            if constexpr (RPL > 1) { if (rp == 1) grab(std::integral_constant<int, 1>{}); }
+            if constexpr (RPL > 2) { if (rp == 2) grab(std::integral_constant<int, 2>{}); }
+            if constexpr (RPL > 3) { if (rp == 3) grab(std::integral_constant<int, 3>{}); }
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) M[r][c] = fma(-colbuf[b][pc + PC * c], rv, M[r][c]);
-            if (r == rk) {
+            for (int j = 0; j < CHK; ++j) {
+                const int c = c0 + j;
+                const double r_ = (wave == vk && c == ck) ? pv + 1.0 : rv[j];
 #pragma unroll
-                for (int c = 0; c < CPT; ++c)
-                    if (c == cp && pr == kk && own_p) M[r][c] = 1.0;
+                for (int r = 0; r < RPL; ++r) M[r][c] = fma(-colv_s[r], r_, M[r][c]);
             }
-            if (r == rk1) {
+        });
+        if (owner1) {
+            double col[RPL];
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) col[c] = M[r][c];
-            }
+            for (int r = 0; r < RPL; ++r) col[r] = 0.0;
+            static_for<0, CPW>([&](auto cc) __attribute__((always_inline)) {
+                constexpr int c = decltype(cc)::value;
+                if (c == c1) {
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) col[r] = M[r][c];
+                }
+            });
+            const uint32_t used1 = used | (lane == lp ? 1u << rp : 0u);
+            gj_search<RPL>(col, n, lane, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1]);
         }
-        if (k1 < n && pr == kk1) gj_search<PC, CPT>(col, n, pc, used, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1]);
+        if (lane == lp) used |= 1u << rp;
     }
     __syncthreads();
 
@@ -197,29 +247,37 @@ __global__ __launch_bounds__(PR* PC) void gj_kernel(const Tin* __restrict__ C, i
     __syncthreads();
     for (int k = tid; k < n; k += NT) invp[perm[k]] = k;
     __syncthreads();
-    // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
-    int rowi[CPT];
-    double rs[CPT];
+    // the pivot entries were left at pv during the elimination (the pivot row
+    // is never scaled); their value in the scaled representation is 1, and
+    // later updates of them only added terms: M[p_k][k] += 1 - pv_k
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int i = pc + PC * c;
-        rowi[c] = i < n ? invp[i] : -1;
-        rs[c] = i < n ? 1.0 / rowpiv[i] : 0.0;
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i >= n) continue;
+        const int kp = invp[i];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            if (wave + NWV * c == kp) M[r][c] += 1.0 - rowpiv[i];
     }
-    int cole[RPT];
+    // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
+    int rowi[RPL];
+    double rs[RPL];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int e = pr + PR * r;
-        cole[r] = e < n ? perm[e] : -1;
+    for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        rowi[r] = i < n ? invp[i] : -1;
+        rs[r] = i < n ? 1.0 / rowpiv[i] : 0.0;
     }
     for (int q0 = 0; q0 < n; q0 += QC) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int rr = rowi[c] - q0;
+        for (int r = 0; r < RPL; ++r) {
+            const int rr = rowi[r] - q0;
             if (rr >= 0 && rr < QC) {
 #pragma unroll
-                for (int r = 0; r < RPT; ++r)
-                    if (cole[r] >= 0) stage[rr][cole[r]] = M[r][c] * rs[c];
+                for (int c = 0; c < CPW; ++c) {
+                    const int e = wave + NWV * c;
+                    if (e < n) stage[rr][perm[e]] = M[r][c] * rs[r];
+                }
             }
         }
         __syncthreads();
@@ -244,10 +302,10 @@ template <typename Tin>
 static hipError_t gj_dispatch(const Tin* C, int n, int64_t W, int spin, double* Dinv, double* logdet, int8_t* sign,
                               uint32_t* status, hipStream_t st) {
     const dim3 g((unsigned)W);
-    if (n <= 32) gj_kernel<8, 32, 4, 1, Tin><<<g, 256, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else if (n <= 64) gj_kernel<16, 32, 4, 2, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else if (n <= 128) gj_kernel<16, 32, 8, 4, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else gj_kernel<16, 32, 14, 7, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
+    if (n <= 32) gj_kernel<2, 1, 16, Tin><<<g, 128, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
+    else if (n <= 64) gj_kernel<4, 1, 16, Tin><<<g, 256, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
+    else if (n <= 128) gj_kernel<8, 2, 16, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
+    else gj_kernel<8, 4, 28, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
     return hipGetLastError();
 }
 

@@ -48,9 +48,9 @@ struct DevMO {
     bool set = false;
     double* AT64 = nullptr;     // [n_slots][ldn]
     float* AT32 = nullptr;      // [n_slots][ldn]
-    uint16_t* Ahi = nullptr;    // [ldn][n_slots] bf16 bits
+    uint16_t* Ahi = nullptr;    // bf16 bits [n_win][ldn][8 slots]
     uint16_t* Alo = nullptr;
-    uint16_t* AThi = nullptr;   // [n_slots][ldn]
+    uint16_t* AThi = nullptr;   // bf16 bits [n_win][ldn/8][8 slots][8 MOs]
     uint16_t* ATlo = nullptr;
     double* A64 = nullptr;      // [ldn][n_slots]
     float* A32 = nullptr;       // [ldn][n_slots]

@@ -5,8 +5,9 @@
 namespace qsl {
 
 // A^s (n x N_b, row-major, leading dimension ld, FP64) -> the library's
-// padded copies: AT64/AT32 [slot][ldn], Ahi/Alo [ldn][slot], AThi/ATlo
-// [slot][ldn]; hi = bf16(x), lo = bf16(x - hi) of the FP32 value x.
+// padded copies: AT64/AT32 [slot][ldn], A64/A32 [ldn][slot], and hi/lo bf16
+// splits (hi = bf16(x), lo = bf16(x - hi) of the FP32 value x) packed per
+// window: Ahi/Alo [window][ldn][8], AThi/ATlo [window][ldn/8][8][8].
 __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restrict__ A, int64_t ld,
                                 double* AT64, float* AT32, uint16_t* Ahi, uint16_t* Alo, uint16_t* AThi,
                                 uint16_t* ATlo, double* A64, float* A32) {
@@ -18,12 +19,17 @@ __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restri
         const float f = (float)v;
         const uint16_t h = bf16_rne(f);
         const uint16_t l = bf16_rne(f - bf16_to_f(h));
+        const int win = slot / WIN, j = slot % WIN;
         AT64[q] = v;
         AT32[q] = f;
-        AThi[q] = h;
-        ATlo[q] = l;
-        Ahi[(int64_t)mo * s.n_slots + slot] = h;
-        Alo[(int64_t)mo * s.n_slots + slot] = l;
+        // bf16 copies packed per window: the MFMA fragments of one window
+        // (8 slots of consecutive MOs, or 8 MOs of its 8 slots) are contiguous
+        const int64_t pk = ((int64_t)win * ldn + mo) * WIN + j;                        // [win][mo][j]
+        const int64_t pt = (((int64_t)win * (ldn / 8) + mo / 8) * WIN + j) * 8 + mo % 8;  // [win][mo/8][j][mo%8]
+        Ahi[pk] = h;
+        Alo[pk] = l;
+        AThi[pt] = h;
+        ATlo[pt] = l;
         A64[(int64_t)mo * s.n_slots + slot] = v;
         A32[(int64_t)mo * s.n_slots + slot] = f;
     }

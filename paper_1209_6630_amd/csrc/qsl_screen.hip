@@ -36,7 +36,8 @@ __global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int sp
     const int e0 = t * TE;
     const int ne = min(TE, n - e0);
     const int N = s.n_up + s.n_dn;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int eoff = spin ? s.n_up : 0;
     const int nall = nw * TE;  // electron slots of the group (ragged tiles padded)
     const int w = w0;          // walker that owns a near-tie flag when gw == 1
