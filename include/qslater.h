@@ -195,6 +195,94 @@ typedef struct {
  */
 qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* args, void* stream);
 
+/* ------------------------------------------------------------------ plans
+ *
+ * A plan runs the forward and the adjoint of an uneven batch: several
+ * systems (different molecules, electron counts and walker counts) in one
+ * precision mode.  Every kernel phase (screening, contraction,
+ * inversion, drift/Laplacian, adjoint) is one launch whose blocks walk the
+ * work list of all (system, spin, electron tile, MO block) items, largest
+ * systems first, instead of one launch per system and spin.  Each Monte
+ * Carlo step treats every walker independently (subsection "Parallelizing
+ * FN-DMC"), so any mix of walkers and systems can share a launch.
+ * The adjoint reuses the forward's screening of the same coordinates.
+ */
+typedef struct qsl_plan qsl_plan;
+
+/* Plan flags. */
+#define QSL_PLAN_GRAPH 1u  /* capture the launch sequence into a HIP graph on
+                              the first qsl_plan_launch after a bind or a
+                              tuning change, and replay it afterwards       */
+
+/* Runtime tuning parameters of a plan (what qsl_autotune searches). */
+typedef struct {
+    int32_t batched;    /* 1: one launch per phase over the work list of all
+                           systems; 0: one launch per system and spin       */
+    int32_t adj_group;  /* walkers per dA group of the adjoint, 1..4096;
+                           0: min(W, 128) per system                          */
+    int32_t gj_bias;    /* 0: the smallest Gauss-Jordan block shape holding
+                           n; 1: the next larger one (when there is one)      */
+} qsl_tuning;
+
+/*
+ * Create a plan over n_sys systems with W[i] walkers each, all in `mode`.
+ * flags: QSL_PLAN_GRAPH or 0.  The plan owns its workspace (allocated on the
+ * current device at the first launch).  The systems must outlive the plan;
+ * their MO coefficients are read at launch time.
+ * Errors: INVALID_ARG (n_sys < 1, NULL, W < 0, bad mode or flags), OOM.
+ */
+qsl_status qsl_plan_create(int32_t n_sys, qsl_system* const* sys, const int64_t* W, int32_t mode,
+                           uint32_t flags, qsl_plan** out);
+
+/*
+ * Bind the device buffers of system i: `fwd` as for qsl_forward (required;
+ * its W and mode must match the plan, ws/ws_bytes are ignored), `bwd` as for
+ * qsl_backward, or NULL for a forward-only system (its W and mode must
+ * match, bwd->R must equal fwd->R, ws/ws_bytes ignored).  Pointers must
+ * stay valid and fixed while the plan is launched (a graph replays them);
+ * binding again invalidates a captured graph.  Nothing is enqueued.
+ * Errors: INVALID_ARG, SHAPE (W or mode differ from the plan),
+ * UNSUPPORTED (a spin with more electrons than the inversion supports).
+ */
+qsl_status qsl_plan_bind(qsl_plan* plan, int32_t i, const qsl_fwd_args* fwd, const qsl_bwd_args* bwd);
+
+/*
+ * Set / read the tuning.  Setting invalidates a captured graph.
+ * Errors: INVALID_ARG (NULL, a value out of range).
+ */
+qsl_status qsl_plan_set_tuning(qsl_plan* plan, const qsl_tuning* t);
+qsl_status qsl_plan_get_tuning(const qsl_plan* plan, qsl_tuning* t);
+
+/*
+ * Enqueue the forward of every system, then the adjoint of every system
+ * bound with `bwd`, on `stream`.  Results equal those of qsl_forward /
+ * qsl_backward per system with the same tuning (bit for bit, except dA,
+ * whose atomic sums over walker groups may round in any order).  The first
+ * launch after a bind or a tuning change synchronises `stream`, uploads the
+ * work lists and (QSL_PLAN_GRAPH) captures the graph; later launches only
+ * enqueue.  Launches of one plan must not overlap.
+ * Errors: INVALID_ARG (a system never bound), OOM, HIP.
+ */
+qsl_status qsl_plan_launch(qsl_plan* plan, void* stream);
+
+/* Free a plan, its workspace and graph.  NULL is accepted. */
+qsl_status qsl_plan_destroy(qsl_plan* plan);
+
+/*
+ * Autotune: time every candidate tuning (batched 0/1 x adj_group in
+ * {16, 32, 64, 128, 256} x gj_bias 0/1) on the bound buffers, keep the
+ * fastest whose outputs pass a parity self-check against the default
+ * tuning (logdet, sign, D^-1, drift, Laplacian and dR of the first and last
+ * walkers of every system within 1e-9 relative, dA within 1e-10 (FP64) or
+ * 1e-4 (other modes) of its largest entry), and set it on the plan.  With
+ * cache_path, a JSON file keyed by device, mode and the shapes of the
+ * batch: a hit sets the cached tuning without running anything; a miss
+ * tunes and writes the entry.  Overwrites the bound outputs; synchronises
+ * `stream`.  `chosen` (may be NULL) receives the tuning.
+ * Errors: INVALID_ARG, HIP, OOM; UNSUPPORTED if no candidate passes.
+ */
+qsl_status qsl_autotune(qsl_plan* plan, const char* cache_path, void* stream, qsl_tuning* chosen);
+
 /*
  * Kernel timing (for benchmarks and profilers).  While enabled, every
  * kernel the library enqueues is bracketed by two HIP events recorded on the

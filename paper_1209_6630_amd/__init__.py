@@ -10,7 +10,7 @@ from ._lib import MODES, QslError, lib  # noqa: F401
 
 def __getattr__(name):
     # torch-dependent parts are imported lazily
-    if name in ("System", "SlaterLogDet", "slater_logdet", "mode_id"):
+    if name in ("System", "Plan", "SlaterLogDet", "slater_logdet", "mode_id"):
         from . import api
         return getattr(api, name)
     raise AttributeError(name)

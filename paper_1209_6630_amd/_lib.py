@@ -42,6 +42,13 @@ class BwdArgs(ct.Structure):
                 ("ws_bytes", ct.c_size_t)]
 
 
+class Tuning(ct.Structure):
+    _fields_ = [("batched", ct.c_int32), ("adj_group", ct.c_int32), ("gj_bias", ct.c_int32)]
+
+
+PLAN_GRAPH = 1
+
+
 class KernelTime(ct.Structure):
     _fields_ = [("name", ct.c_char * 48), ("launches", ct.c_int64), ("total_ms", ct.c_double)]
 
@@ -56,6 +63,14 @@ SIGNATURES = {
     "qsl_workspace_size": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.POINTER(ct.c_size_t)]),
     "qsl_forward": (ct.c_int, [ct.c_void_p, ct.POINTER(FwdArgs), ct.c_void_p]),
     "qsl_backward": (ct.c_int, [ct.c_void_p, ct.POINTER(BwdArgs), ct.c_void_p]),
+    "qsl_plan_create": (ct.c_int, [ct.c_int32, ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_int64), ct.c_int32,
+                                   ct.c_uint32, ct.POINTER(ct.c_void_p)]),
+    "qsl_plan_bind": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.POINTER(FwdArgs), ct.POINTER(BwdArgs)]),
+    "qsl_plan_set_tuning": (ct.c_int, [ct.c_void_p, ct.POINTER(Tuning)]),
+    "qsl_plan_get_tuning": (ct.c_int, [ct.c_void_p, ct.POINTER(Tuning)]),
+    "qsl_plan_launch": (ct.c_int, [ct.c_void_p, ct.c_void_p]),
+    "qsl_plan_destroy": (ct.c_int, [ct.c_void_p]),
+    "qsl_autotune": (ct.c_int, [ct.c_void_p, ct.c_char_p, ct.c_void_p, ct.POINTER(Tuning)]),
     "qsl_profile_enable": (ct.c_int, [ct.c_int32]),
     "qsl_profile_read": (ct.c_int, [ct.POINTER(KernelTime), ct.c_int32, ct.POINTER(ct.c_int32), ct.c_int32]),
     "qsl_status_string": (ct.c_char_p, [ct.c_int]),

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BwdArgs, FwdArgs, MODES, SystemDesc, check, lib
+from ._lib import BwdArgs, FwdArgs, MODES, PLAN_GRAPH, SystemDesc, Tuning, check, lib
 
 
 def _ptr(t):
@@ -129,19 +129,7 @@ class System:
         if out is None:
             out = self.alloc_outputs(W, mode, drift)
         ws = self.workspace(W, mode)
-        a = FwdArgs()
-        a.W = W
-        a.R = R.data_ptr()
-        a.mode = mode_id(mode)
-        a.C[0] = out["C_up"].data_ptr()
-        a.C[1] = out["C_dn"].data_ptr()
-        a.logdet = out["logdet"].data_ptr()
-        a.sign = out["sign"].data_ptr()
-        a.Dinv[0] = out["Dinv_up"].data_ptr()
-        a.Dinv[1] = out["Dinv_dn"].data_ptr()
-        a.drift = out["drift"].data_ptr() if "drift" in out else None
-        a.lap = out["lap"].data_ptr() if "lap" in out else None
-        a.status = out["status"].data_ptr()
+        a = _fwd_args(self, R, mode, out)
         a.ws = ws.data_ptr()
         a.ws_bytes = ws.numel()
         check(lib().qsl_forward(self._h, ct.byref(a), _stream()))
@@ -174,6 +162,92 @@ class System:
         a.ws_bytes = ws.numel()
         check(lib().qsl_backward(self._h, ct.byref(a), _stream()))
         return dR, (dA[0] if want_dA else None), (dA[1] if want_dA else None)
+
+
+def _fwd_args(system, R, mode, out):
+    a = FwdArgs()
+    a.W = R.shape[0]
+    a.R = R.data_ptr()
+    a.mode = mode_id(mode)
+    a.C[0] = out["C_up"].data_ptr()
+    a.C[1] = out["C_dn"].data_ptr()
+    a.logdet = out["logdet"].data_ptr()
+    a.sign = out["sign"].data_ptr()
+    a.Dinv[0] = out["Dinv_up"].data_ptr()
+    a.Dinv[1] = out["Dinv_dn"].data_ptr()
+    a.drift = out["drift"].data_ptr() if "drift" in out else None
+    a.lap = out["lap"].data_ptr() if "lap" in out else None
+    a.status = out["status"].data_ptr()
+    return a
+
+
+class Plan:
+    """An uneven batch: the forward (and optionally the adjoint) of several
+    systems, one batched launch per kernel phase, optionally replayed from a
+    HIP graph.  Buffers are bound once and must stay allocated."""
+
+    def __init__(self, systems, walkers, mode="fp32", graph=True):
+        self.systems = list(systems)
+        self.W = [int(w) for w in walkers]
+        self.mode = mode
+        n = len(self.systems)
+        hs = (ct.c_void_p * n)(*[s._h.value for s in self.systems])
+        ws = (ct.c_int64 * n)(*self.W)
+        h = ct.c_void_p()
+        check(lib().qsl_plan_create(n, hs, ws, mode_id(mode), PLAN_GRAPH if graph else 0, ct.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def bind(self, i, R, out, g=None, dR=None, dA=None, accumulate=False):
+        """Bind system i: coordinates R, forward outputs `out` (from
+        System.alloc_outputs) and, with g, the adjoint buffers dR / dA."""
+        S = self.systems[i]
+        f = _fwd_args(S, R, self.mode, out)
+        b = None
+        if g is not None:
+            b = BwdArgs()
+            b.W = R.shape[0]
+            b.R = R.data_ptr()
+            b.mode = mode_id(self.mode)
+            b.Dinv[0] = out["Dinv_up"].data_ptr()
+            b.Dinv[1] = out["Dinv_dn"].data_ptr()
+            b.g_logdet = g.data_ptr()
+            b.dR = dR.data_ptr() if dR is not None else None
+            b.dA[0] = dA[0].data_ptr() if dA is not None else None
+            b.dA[1] = dA[1].data_ptr() if dA is not None else None
+            b.accumulate_dA = 1 if accumulate else 0
+        check(lib().qsl_plan_bind(self._h, i, ct.byref(f), ct.byref(b) if b is not None else None))
+        self._keep[i] = (R, out, g, dR, dA)  # keep the bound tensors alive
+
+    def launch(self):
+        check(lib().qsl_plan_launch(self._h, _stream()))
+
+    @property
+    def tuning(self):
+        t = Tuning()
+        check(lib().qsl_plan_get_tuning(self._h, ct.byref(t)))
+        return {"batched": t.batched, "adj_group": t.adj_group, "gj_bias": t.gj_bias}
+
+    @tuning.setter
+    def tuning(self, d):
+        t = Tuning(int(d.get("batched", 1)), int(d.get("adj_group", 0)), int(d.get("gj_bias", 0)))
+        check(lib().qsl_plan_set_tuning(self._h, ct.byref(t)))
+
+    def autotune(self, cache_path=None):
+        t = Tuning()
+        check(lib().qsl_autotune(self._h, cache_path.encode() if cache_path else None, _stream(), ct.byref(t)))
+        return {"batched": t.batched, "adj_group": t.adj_group, "gj_bias": t.gj_bias}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qsl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class SlaterLogDet(torch.autograd.Function):

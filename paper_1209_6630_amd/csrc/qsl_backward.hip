@@ -124,16 +124,20 @@ constexpr int AH_KW = 8;                 // windows per chunk
 constexpr int AH_KC = AH_KW * WIN;       // 64 slots
 
 template <int MODE>
-__global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(DevSys s, int spin, int n, int64_t W, int ldn,
-                                                           const double* __restrict__ R,
-                                                           const int* __restrict__ tile_nwin,
-                                                           const int* __restrict__ tile_win,
-                                                           const uint16_t* __restrict__ AThi,
-                                                           const uint16_t* __restrict__ ATlo,
-                                                           const float* __restrict__ A32,
-                                                           const double* __restrict__ A64,
-                                                           const double* __restrict__ Dinv,
-                                                           const double* __restrict__ g, double* __restrict__ dR) {
+__device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
+    const DevSys& s = j.s;
+    const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
+    const int64_t W = j.W;
+    const double* __restrict__ R = j.R;
+    const int* __restrict__ tile_nwin = j.nwin;
+    const int* __restrict__ tile_win = j.win;
+    const uint16_t* __restrict__ AThi = j.mo.AThi;
+    const uint16_t* __restrict__ ATlo = j.mo.ATlo;
+    const float* __restrict__ A32 = j.mo.A32;
+    const double* __restrict__ A64 = j.mo.A64;
+    const double* __restrict__ Dinv = j.Dinv;
+    const double* __restrict__ g = j.g;
+    double* __restrict__ dR = j.dR;
     using T = TOf<MODE>;
     constexpr bool BF = MODE == QSL_BF16X3;
     constexpr int LDG = ADJ_MB + (BF ? 8 : 1);
@@ -143,11 +147,11 @@ __global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(DevSys s, int spin, i
     __shared__ T dX[3][TE][AH_KC + 1];
     __shared__ T Hb[2][TE][AH_KC + 1];
 
-    const int tile = blockIdx.x;
+    const int tile = bx;
     const int w = (int)(tile % W);
     const int e0 = (int)(tile / W) * TE;
     const int ne = min(TE, n - e0);
-    const int i0 = blockIdx.y * ADJ_MB;
+    const int i0 = by * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -271,13 +275,17 @@ struct AdCfg {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(DevSys s, int spin, int n, int64_t W, int gw,
-                                                            const double* __restrict__ R,
-                                                            const int* __restrict__ grp_nwin,
-                                                            const int* __restrict__ grp_win,
-                                                            const double* __restrict__ Dinv,
-                                                            const double* __restrict__ g,
-                                                            double* __restrict__ dA64, float* __restrict__ dA32) {
+__device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz) {
+    const DevSys& s = j.s;
+    const int spin = j.spin, n = j.n, gw = j.gw;
+    const int64_t W = j.W;
+    const double* __restrict__ R = j.R;
+    const int* __restrict__ grp_nwin = j.gnwin;
+    const int* __restrict__ grp_win = j.gwin;
+    const double* __restrict__ Dinv = j.Dinv;
+    const double* __restrict__ g = j.g;
+    double* __restrict__ dA64 = j.dA64;
+    float* __restrict__ dA32 = j.dA32;
     using C = AdCfg<MODE>;
     using T = typename C::T;
     constexpr bool BF = C::BF;
@@ -288,17 +296,17 @@ __global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(DevSys s, int spin, 
     __shared__ __attribute__((aligned(16))) unsigned char xbuf[BF ? 2 * 2 * NS * LDX : sizeof(T) * TE * LDX];
 
     const int ngw = (int)((W + gw - 1) / gw);
-    const int grp = blockIdx.x;
+    const int grp = bx;
     const int t = grp / ngw, wb = grp % ngw;
     const int w0 = wb * gw;
     const int nw = (int)min<int64_t>(gw, W - w0);
     const int e0 = t * TE;
     const int ne = min(TE, n - e0);
     const int nwin = grp_nwin[grp];
-    const int q0 = blockIdx.y * NWB;
+    const int q0 = by * NWB;
     if (q0 >= nwin) return;
     const int nq = min(NWB, nwin - q0);
-    const int i0 = blockIdx.z * ADJ_MB;
+    const int i0 = bz * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -414,40 +422,76 @@ __global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(DevSys s, int spin, 
     }
 }
 
-hipError_t launch_adj_h(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
-                        const int* tile_nwin, const int* tile_win, const double* Dinv, const double* g, double* dR,
-                        hipStream_t st) {
-    const int n = n_spin(s, spin);
-    const int64_t tiles = W * tiles_per_walker(n);
-    if (!tiles || !dR) return hipSuccess;
-    dim3 grid((unsigned)tiles, (n + ADJ_MB - 1) / ADJ_MB);
-#define QSL_AH_ARGS s, spin, n, W, mo.ldn, R, tile_nwin, tile_win, mo.AThi, mo.ATlo, mo.A32, mo.A64, Dinv, g, dR
-    if (mode == QSL_FP64) adj_h_kernel<QSL_FP64><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
-    else if (mode == QSL_FP32) adj_h_kernel<QSL_FP32><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
-    else adj_h_kernel<QSL_BF16X3><<<grid, AH_THREADS, 0, st>>>(QSL_AH_ARGS);
-#undef QSL_AH_ARGS
+template <int MODE>
+__global__ __launch_bounds__(AH_THREADS) void adj_h_kernel(Job j) {
+    adj_h_body<MODE>(j, blockIdx.x, blockIdx.y);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(AH_THREADS) void adj_h_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { adj_h_body<MODE>(j, bx, by); });
+}
+
+template <int MODE>
+__global__ __launch_bounds__(AD_THREADS) void adj_da_kernel(Job j) {
+    adj_da_body<MODE>(j, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(AD_THREADS) void adj_da_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs,
+                    [&](const Job& j, int bx, int by, int bz) { adj_da_body<MODE>(j, bx, by, bz); });
+}
+
+void adj_h_grid(Job& j) {
+    j.gx = (int)(j.W * tiles_per_walker(j.n));
+    j.gy = (j.n + ADJ_MB - 1) / ADJ_MB;
+    j.gz = 1;
+}
+
+void adj_da_grid(Job& j) {
+    const int nwb = j.mode == QSL_FP64 ? AdCfg<QSL_FP64>::NWB : AdCfg<QSL_FP32>::NWB;
+    j.gx = tiles_per_walker(j.n) * (int)((j.W + j.gw - 1) / j.gw);
+    j.gy = (j.s.n_win + nwb - 1) / nwb;
+    j.gz = (j.n + ADJ_MB - 1) / ADJ_MB;
+}
+
+hipError_t launch_adj_h(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    adj_h_grid(j);
+    if (!j.n || !j.W || !j.dR) return hipSuccess;
+    const dim3 grid((unsigned)j.gx, j.gy);
+    if (j.mode == QSL_FP64) adj_h_kernel<QSL_FP64><<<grid, AH_THREADS, 0, st>>>(j);
+    else if (j.mode == QSL_FP32) adj_h_kernel<QSL_FP32><<<grid, AH_THREADS, 0, st>>>(j);
+    else adj_h_kernel<QSL_BF16X3><<<grid, AH_THREADS, 0, st>>>(j);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_da(const DevSys& s, int spin, int mode, int64_t W, int gw, const double* R, const int* grp_nwin,
-                         const int* grp_win, const double* Dinv, const double* g, double* dA64, float* dA32,
-                         hipStream_t st) {
-    const int n = n_spin(s, spin);
-    const int64_t groups = (int64_t)tiles_per_walker(n) * ((W + gw - 1) / gw);
-    if (!groups || (!dA64 && !dA32)) return hipSuccess;
-    const int mob = (n + ADJ_MB - 1) / ADJ_MB;
-#define QSL_AD_ARGS s, spin, n, W, gw, R, grp_nwin, grp_win, Dinv, g, dA64, dA32
-    if (mode == QSL_FP64) {
-        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_FP64>::NWB - 1) / AdCfg<QSL_FP64>::NWB, mob);
-        adj_da_kernel<QSL_FP64><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
-    } else if (mode == QSL_FP32) {
-        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_FP32>::NWB - 1) / AdCfg<QSL_FP32>::NWB, mob);
-        adj_da_kernel<QSL_FP32><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
-    } else {
-        dim3 grid((unsigned)groups, (s.n_win + AdCfg<QSL_BF16X3>::NWB - 1) / AdCfg<QSL_BF16X3>::NWB, mob);
-        adj_da_kernel<QSL_BF16X3><<<grid, AD_THREADS, 0, st>>>(QSL_AD_ARGS);
-    }
-#undef QSL_AD_ARGS
+hipError_t launch_adj_da(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    if (j.gw < 1) return hipErrorInvalidValue;
+    adj_da_grid(j);
+    if (!j.n || !j.W || (!j.dA64 && !j.dA32)) return hipSuccess;
+    const dim3 grid((unsigned)j.gx, j.gy, j.gz);
+    if (j.mode == QSL_FP64) adj_da_kernel<QSL_FP64><<<grid, AD_THREADS, 0, st>>>(j);
+    else if (j.mode == QSL_FP32) adj_da_kernel<QSL_FP32><<<grid, AD_THREADS, 0, st>>>(j);
+    else adj_da_kernel<QSL_BF16X3><<<grid, AD_THREADS, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_h_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                   hipStream_t st) {
+    if (mode == QSL_FP64) adj_h_batched<QSL_FP64><<<grid, AH_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32) adj_h_batched<QSL_FP32><<<grid, AH_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else adj_h_batched<QSL_BF16X3><<<grid, AH_THREADS, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                    hipStream_t st) {
+    if (mode == QSL_FP64) adj_da_batched<QSL_FP64><<<grid, AD_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32) adj_da_batched<QSL_FP32><<<grid, AD_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else adj_da_batched<QSL_BF16X3><<<grid, AD_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

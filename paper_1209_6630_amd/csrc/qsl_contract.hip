@@ -38,16 +38,19 @@ struct CT {
 };
 
 template <int MODE>
-__global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin, int n, int64_t W, int ldn,
-                                                              const double* __restrict__ R,
-                                                              const int* __restrict__ tile_nwin,
-                                                              const int* __restrict__ tile_win,
-                                                              const double* __restrict__ AT64,
-                                                              const float* __restrict__ AT32,
-                                                              const uint16_t* __restrict__ Ahi,
-                                                              const uint16_t* __restrict__ Alo,
-                                                              void* __restrict__ Cout,
-                                                              uint32_t* __restrict__ status) {
+__device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
+    const DevSys& s = j.s;
+    const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
+    const int64_t W = j.W;
+    const double* __restrict__ R = j.R;
+    const int* __restrict__ tile_nwin = j.nwin;
+    const int* __restrict__ tile_win = j.win;
+    const double* __restrict__ AT64 = j.mo.AT64;
+    const float* __restrict__ AT32 = j.mo.AT32;
+    const uint16_t* __restrict__ Ahi = j.mo.Ahi;
+    const uint16_t* __restrict__ Alo = j.mo.Alo;
+    void* __restrict__ Cout = j.C;
+    uint32_t* __restrict__ status = j.status;
     using P = CT<MODE>;
     using T = typename P::T;
     constexpr int KW = P::KW, KC = P::KC, LD = P::LD;
@@ -60,8 +63,8 @@ __global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin
 
     // tiles are numbered t * W + w (electron range t of walker w), so that
     // concurrently resident workgroups share the same AO windows of A
-    const int tile = blockIdx.x;
-    const int n0 = blockIdx.y * P::NB;
+    const int tile = bx;
+    const int n0 = by * P::NB;
     const int w = (int)(tile % W);
     const int e0 = (int)(tile / W) * TE;
     const int ne = min(TE, n - e0);
@@ -223,32 +226,40 @@ __global__ __launch_bounds__(CT_THREADS) void contract_kernel(DevSys s, int spin
     }
 }
 
-hipError_t launch_contract(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
-                           const int* tile_nwin, const int* tile_win, void* C, uint32_t* status, hipStream_t st) {
-    const int n = n_spin(s, spin);
-    const int tpw = tiles_per_walker(n);
-    const int64_t tiles = W * tpw;
-    if (!tiles) return hipSuccess;
-    switch (mode) {
-        case QSL_FP64: {
-            dim3 g((unsigned)tiles, (n + CT<QSL_FP64>::NB - 1) / CT<QSL_FP64>::NB);
-            contract_kernel<QSL_FP64><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
-                                                                  mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
-            break;
-        }
-        case QSL_FP32: {
-            dim3 g((unsigned)tiles, (n + CT<QSL_FP32>::NB - 1) / CT<QSL_FP32>::NB);
-            contract_kernel<QSL_FP32><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
-                                                                  mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
-            break;
-        }
-        default: {
-            dim3 g((unsigned)tiles, (n + CT<QSL_BF16X3>::NB - 1) / CT<QSL_BF16X3>::NB);
-            contract_kernel<QSL_BF16X3><<<g, CT_THREADS, 0, st>>>(s, spin, n, W, mo.ldn, R, tile_nwin, tile_win,
-                                                                    mo.AT64, mo.AT32, mo.Ahi, mo.Alo, C, status);
-            break;
-        }
-    }
+template <int MODE>
+__global__ __launch_bounds__(CT_THREADS) void contract_kernel(Job j) {
+    contract_body<MODE>(j, blockIdx.x, blockIdx.y);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(CT_THREADS) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { contract_body<MODE>(j, bx, by); });
+}
+
+// Grid of the contraction phase of a Job: tiles x MO blocks.
+void contract_grid(Job& j) {
+    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : CT<QSL_FP32>::NB;
+    j.gx = (int)(j.W * tiles_per_walker(j.n));
+    j.gy = (j.n + nb - 1) / nb;
+    j.gz = 1;
+}
+
+hipError_t launch_contract(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    contract_grid(j);
+    if (!j.n || !j.W) return hipSuccess;
+    const dim3 g((unsigned)j.gx, j.gy);
+    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64><<<g, CT_THREADS, 0, st>>>(j);
+    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32><<<g, CT_THREADS, 0, st>>>(j);
+    else contract_kernel<QSL_BF16X3><<<g, CT_THREADS, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                      hipStream_t st) {
+    if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else contract_batched<QSL_BF16X3><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 // and the result is un-permuted on the way out: D^-1[k][p_j] = M[p_k][j].
 // The pivots are the diagonal of U in P D = L U, so log|det| = sum log|pivot|
 // and sign = sign(permutation) prod sign(pivot).  2 n^3 flops per matrix.
+#include <algorithm>
+
 #include "qsl_internal.h"
 
 namespace qsl {
@@ -90,9 +92,13 @@ __device__ __forceinline__ void gj_search(const double (&col)[RPL], int n, int l
 }
 
 template <int NWV, int RPL, int CPW, typename Tin>
-__global__ __launch_bounds__(NWV * 64) void gj_kernel(const Tin* __restrict__ C, int n, int spin,
-                                                      double* __restrict__ Dinv, double* __restrict__ logdet,
-                                                      int8_t* __restrict__ sign, uint32_t* __restrict__ status) {
+__device__ __forceinline__ void gj_body(const Job& j, int bx) {
+    const Tin* __restrict__ C = (const Tin*)j.C;
+    const int n = j.n, spin = j.spin;
+    double* __restrict__ Dinv = j.Dinv;
+    double* __restrict__ logdet = j.logdet;
+    int8_t* __restrict__ sign = j.sign;
+    uint32_t* __restrict__ status = j.status;
     constexpr int NT = NWV * 64;
     constexpr int NR = 64 * RPL;   // capacity in D rows (MO index i)
     constexpr int NC = NWV * CPW;  // capacity in D columns (electron index e)
@@ -106,7 +112,7 @@ __global__ __launch_bounds__(NWV * 64) void gj_kernel(const Tin* __restrict__ C,
     __shared__ double stage[QC][NC > NR ? NC : NR];
     __shared__ int s_flag;
 
-    const int w = blockIdx.x;
+    const int w = bx;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const size_t nn = (size_t)n * n;
@@ -290,6 +296,16 @@ __global__ __launch_bounds__(NWV * 64) void gj_kernel(const Tin* __restrict__ C,
     }
 }
 
+template <int NWV, int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(NWV * 64) void gj_kernel(Job j) {
+    gj_body<NWV, RPL, CPW, Tin>(j, blockIdx.x);
+}
+
+template <int NWV, int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(NWV * 64) void gj_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gj_body<NWV, RPL, CPW, Tin>(j, bx); });
+}
+
 __global__ void empty_spin_kernel(int64_t W, int spin, double* logdet, int8_t* sign) {
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w < W) {
@@ -298,27 +314,53 @@ __global__ void empty_spin_kernel(int64_t W, int spin, double* logdet, int8_t* s
     }
 }
 
+// Register-resident variants by matrix size: 0: n <= 32, 1: <= 64, 2: <= 128, 3: <= 224.
+int gj_variant(int n) { return n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : 3; }
+int gj_threads(int v) { return v == 0 ? 128 : v == 1 ? 256 : 512; }
+int gj_job_variant(const Job& j) { return std::min(3, gj_variant(j.n) + std::max(0, j.gj_bias)); }
+
 template <typename Tin>
-static hipError_t gj_dispatch(const Tin* C, int n, int64_t W, int spin, double* Dinv, double* logdet, int8_t* sign,
-                              uint32_t* status, hipStream_t st) {
-    const dim3 g((unsigned)W);
-    if (n <= 32) gj_kernel<2, 1, 16, Tin><<<g, 128, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else if (n <= 64) gj_kernel<4, 1, 16, Tin><<<g, 256, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else if (n <= 128) gj_kernel<8, 2, 16, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
-    else gj_kernel<8, 4, 28, Tin><<<g, 512, 0, st>>>(C, n, spin, Dinv, logdet, sign, status);
+static hipError_t gj_dispatch(const Job& j, int v, bool batched, const Job* jobs, const int* prefix, int njobs,
+                              int grid, hipStream_t st) {
+    const dim3 g((unsigned)(batched ? grid : j.W));
+#define QSL_GJ(NWV, RPL, CPW)                                                                                   \
+    do {                                                                                                        \
+        if (batched) gj_batched<NWV, RPL, CPW, Tin><<<g, NWV * 64, 0, st>>>(jobs, prefix, njobs);         \
+        else gj_kernel<NWV, RPL, CPW, Tin><<<g, NWV * 64, 0, st>>>(j);                                          \
+    } while (0)
+    switch (v) {
+        case 0: QSL_GJ(2, 1, 16); break;
+        case 1: QSL_GJ(4, 1, 16); break;
+        case 2: QSL_GJ(8, 2, 16); break;
+        default: QSL_GJ(8, 4, 28); break;
+    }
+#undef QSL_GJ
     return hipGetLastError();
 }
 
-hipError_t launch_gj(int mode, const void* C, int n, int64_t W, int spin, double* Dinv, double* logdet,
-                     int8_t* sign, uint32_t* status, hipStream_t st) {
-    if (W <= 0) return hipSuccess;
-    if (n == 0) {
-        empty_spin_kernel<<<(unsigned)((W + 255) / 256), 256, 0, st>>>(W, spin, logdet, sign);
+hipError_t launch_gj(const Job& j0, hipStream_t st) {
+    if (j0.W <= 0) return hipSuccess;
+    Job j = j0;
+    j.gx = (int)j.W; j.gy = 1; j.gz = 1;
+    if (j.n == 0) {
+        empty_spin_kernel<<<(unsigned)((j.W + 255) / 256), 256, 0, st>>>(j.W, j.spin, j.logdet, j.sign);
         return hipGetLastError();
     }
-    if (n > GJ_NMAX) return hipErrorInvalidValue;
-    if (mode == QSL_FP64) return gj_dispatch<double>((const double*)C, n, W, spin, Dinv, logdet, sign, status, st);
-    return gj_dispatch<float>((const float*)C, n, W, spin, Dinv, logdet, sign, status, st);
+    if (j.n > GJ_NMAX) return hipErrorInvalidValue;
+    const int v = gj_job_variant(j);
+    if (j.mode == QSL_FP64) return gj_dispatch<double>(j, v, false, nullptr, nullptr, 0, 0, st);
+    return gj_dispatch<float>(j, v, false, nullptr, nullptr, 0, 0, st);
+}
+
+// One batched launch of GJ variant v over Jobs whose n all fit it (the
+// plan launches each variant present in its batch once).
+hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix, int njobs, int grid,
+                             hipStream_t st) {
+    if (v < 0 || v > 3) return hipErrorInvalidValue;
+    if (grid <= 0) return hipSuccess;
+    Job dummy{};
+    if (mode == QSL_FP64) return gj_dispatch<double>(dummy, v, true, jobs, prefix, njobs, grid, st);
+    return gj_dispatch<float>(dummy, v, true, jobs, prefix, njobs, grid, st);
 }
 
 }  // namespace qsl

@@ -18,12 +18,12 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-static qsl_status hip_fail(hipError_t e, const char* what) {
+qsl_status hip_fail(hipError_t e, const char* what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
     return QSL_ERR_HIP;
 }
 
-static qsl_status bad(qsl_status code, const std::string& msg) {
+qsl_status bad(qsl_status code, const std::string& msg) {
     set_error(msg);
     return code;
 }
@@ -54,7 +54,7 @@ struct Arena {
     }
 };
 
-static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,13 +68,13 @@ __global__ void fill_f64_kernel(double* p, double v, int64_t n) {
 
 // Kernels instead of hipMemsetAsync so that callers may capture the
 // sequence into a graph.
-static hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     fill_u32_kernel<<<blocks, 256, 0, st>>>(p, v, n);
     return hipGetLastError();
 }
-static hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t st) {
+hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     fill_f64_kernel<<<blocks, 256, 0, st>>>(p, v, n);
@@ -97,6 +97,8 @@ static std::vector<ProfAgg> g_prof_agg;
 
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // no events in graphs
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
     hipEventRecord(a, st);
 }
@@ -109,14 +111,11 @@ ProfScope::~ProfScope() {
 
 
 // Walkers per dA group: they share one window list (screened together).
-static int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
+int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
 
-// Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win].
-struct WsLayout {
-    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], total;
-};
-
-static WsLayout ws_layout(const DevSys& d, int64_t W) {
+// Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win],
+// the same per walker group of gw walkers, and the FP32 dA accumulator.
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
     WsLayout L{};
     size_t off = 0;
     for (int s = 0; s < 2; ++s) {
@@ -129,7 +128,7 @@ static WsLayout ws_layout(const DevSys& d, int64_t W) {
     }
     for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
-        size_t groups = n ? (size_t)tiles_per_walker(n) * ((W + bw_group(W) - 1) / std::max(bw_group(W), 1)) : 0;
+        size_t groups = n ? (size_t)tiles_per_walker(n) * ((W + gw - 1) / std::max(gw, 1)) : 0;
         L.gnwin_off[s] = off;
         off = round_up(off + groups * sizeof(int), 256);
         L.gwin_off[s] = off;
@@ -141,6 +140,54 @@ static WsLayout ws_layout(const DevSys& d, int64_t W) {
     }
     L.total = std::max<size_t>(off, 256);
     return L;
+}
+
+// The Job of one spin of a forward call: inputs, workspace lists, outputs.
+Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s) {
+    Job j{};
+    j.s = sys->d;
+    j.mo = sys->mo[s];
+    j.spin = s;
+    j.n = n_spin(sys->d, s);
+    j.mode = a->mode;
+    j.gw = 1;
+    j.W = a->W;
+    j.R = a->R;
+    j.nwin = (int*)(ws + L.nwin_off[s]);
+    j.win = (int*)(ws + L.win_off[s]);
+    j.C = a->C[s];
+    j.logdet = a->logdet;
+    j.sign = a->sign;
+    j.Dinv = a->Dinv[s];
+    j.drift = a->drift;
+    j.lap = a->lap;
+    j.status = a->status;
+    return j;
+}
+
+// The Job of one spin of an adjoint call.
+Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw) {
+    Job j{};
+    j.s = sys->d;
+    j.mo = sys->mo[s];
+    j.spin = s;
+    j.n = n_spin(sys->d, s);
+    j.mode = a->mode;
+    j.gw = gw;
+    j.W = a->W;
+    j.R = a->R;
+    j.nwin = (int*)(ws + L.nwin_off[s]);
+    j.win = (int*)(ws + L.win_off[s]);
+    j.gnwin = (int*)(ws + L.gnwin_off[s]);
+    j.gwin = (int*)(ws + L.gwin_off[s]);
+    j.Dinv = const_cast<double*>(a->Dinv[s]);
+    j.g = a->g_logdet;
+    j.dR = a->dR;
+    if (a->dA[s]) {
+        if (a->mode == QSL_FP64) j.dA64 = a->dA[s];
+        else j.dA32 = (float*)(ws + L.dA32_off[s]);
+    }
+    return j;
 }
 
 }  // namespace qsl
@@ -433,7 +480,7 @@ qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, si
     if (!sys || !bytes) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
     if (W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
     if (mode < QSL_FP64 || mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
-    *bytes = ws_layout(sys->d, W).total;
+    *bytes = ws_layout(sys->d, W, bw_group(W)).total;
     return QSL_OK;
 }
 
@@ -451,39 +498,31 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         if (!a->C[s] || !a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "C and Dinv outputs are required");
         if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
     }
-    WsLayout L = ws_layout(d, a->W);
+    WsLayout L = ws_layout(d, a->W, bw_group(a->W));
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)a->ws;
     hipError_t e;
     if (a->status && (e = fill_u32(a->status, 0u, a->W, st)) != hipSuccess) return hip_fail(e, "status clear");
-    const int N = d.n_up + d.n_dn;
     for (int s = 0; s < 2; ++s) {
-        int n = n_spin(d, s);
-        int* nwin = (int*)(ws + L.nwin_off[s]);
-        int* win = (int*)(ws + L.win_off[s]);
-        if (n) {
+        Job j = fwd_job(sys, a, L, ws, s);
+        if (j.n) {
             {
                 ProfScope ps("screen", st);
-                if ((e = launch_screen(d, s, a->W, 1, a->R, nwin, win, a->status, st)) != hipSuccess)
-                    return hip_fail(e, "screen kernel");
+                if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
             }
             {
                 ProfScope ps(a->mode == QSL_FP64 ? "contract_fp64" : a->mode == QSL_FP32 ? "contract_fp32" : "contract_bf16x3", st);
-                if ((e = launch_contract(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->C[s], a->status, st)) != hipSuccess)
-                    return hip_fail(e, "contraction kernel");
+                if ((e = launch_contract(j, st)) != hipSuccess) return hip_fail(e, "contraction kernel");
             }
         }
         {
             ProfScope ps("gauss_jordan", st);
-            if ((e = launch_gj(a->mode, a->C[s], n, a->W, s, a->Dinv[s], a->logdet, a->sign, a->status, st)) != hipSuccess)
-                return hip_fail(e, "inversion kernel");
+            if ((e = launch_gj(j, st)) != hipSuccess) return hip_fail(e, "inversion kernel");
         }
-        if (n && (a->drift || a->lap)) {
+        if (j.n && (a->drift || a->lap)) {
             ProfScope ps("drift_lap", st);
-            if ((e = launch_epilogue(a->mode, a->C[s], a->Dinv[s], n, a->W, s, N, s ? d.n_up : 0, a->drift, a->lap,
-                                     a->logdet, a->status, st)) != hipSuccess)
-                return hip_fail(e, "epilogue kernel");
+            if ((e = launch_epilogue(j, st)) != hipSuccess) return hip_fail(e, "epilogue kernel");
         }
     }
     return QSL_OK;
@@ -498,7 +537,8 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
     hipError_t e;
     const int N = d.n_up + d.n_dn;
     for (int s = 0; s < 2; ++s) {
-        if (a->dA[s] && !a->accumulate_dA && n_spin(d, s) && a->mode == QSL_FP64) {
+        // FP64 accumulates into dA directly; with no walkers, dA = 0 in every mode
+        if (a->dA[s] && !a->accumulate_dA && n_spin(d, s) && (a->mode == QSL_FP64 || a->W == 0)) {
             if ((e = fill_f64(a->dA[s], 0.0, (int64_t)n_spin(d, s) * d.n_basis, st)) != hipSuccess)
                 return hip_fail(e, "dA clear");
         }
@@ -510,45 +550,33 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
         if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
         if (!a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "NULL Dinv");
     }
-    WsLayout L = ws_layout(d, a->W);
+    WsLayout L = ws_layout(d, a->W, bw_group(a->W));
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     char* ws = (char*)a->ws;
     if (a->dR && (e = fill_f64(a->dR, 0.0, a->W * N * 3, st)) != hipSuccess) return hip_fail(e, "dR clear");
     for (int s = 0; s < 2; ++s) {
-        int n = n_spin(d, s);
-        if (!n) continue;
-        int* nwin = (int*)(ws + L.nwin_off[s]);
-        int* win = (int*)(ws + L.win_off[s]);
-        float* dA32 = (float*)(ws + L.dA32_off[s]);
-        const bool f32acc = a->mode != QSL_FP64 && a->dA[s];
-        if (f32acc && (e = fill_u32((uint32_t*)dA32, 0u, (int64_t)n * d.n_basis, st)) != hipSuccess)
+        Job j = bwd_job(sys, a, L, ws, s, bw_group(a->W));
+        if (!j.n) continue;
+        const bool f32acc = j.dA32 != nullptr;
+        if (f32acc && (e = fill_u32((uint32_t*)j.dA32, 0u, (int64_t)j.n * d.n_basis, st)) != hipSuccess)
             return hip_fail(e, "dA accumulator clear");
         {
             ProfScope ps("screen", st);
-            if ((e = launch_screen(d, s, a->W, 1, a->R, nwin, win, nullptr, st)) != hipSuccess)
-                return hip_fail(e, "screen kernel");
+            if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
         }
         {
             ProfScope ps("adjoint_h", st);
-            if ((e = launch_adj_h(d, sys->mo[s], s, a->mode, a->W, a->R, nwin, win, a->Dinv[s], a->g_logdet, a->dR,
-                                  st)) != hipSuccess)
-                return hip_fail(e, "adjoint H kernel");
+            if ((e = launch_adj_h(j, st)) != hipSuccess) return hip_fail(e, "adjoint H kernel");
         }
-        const int gw = bw_group(a->W);
-        int* gnwin = (int*)(ws + L.gnwin_off[s]);
-        int* gwin = (int*)(ws + L.gwin_off[s]);
         if (a->dA[s]) {
             {
                 ProfScope ps("screen_group", st);
-                if ((e = launch_screen(d, s, a->W, gw, a->R, gnwin, gwin, nullptr, st)) != hipSuccess)
-                    return hip_fail(e, "group screen kernel");
+                if ((e = launch_screen(j, 1, st)) != hipSuccess) return hip_fail(e, "group screen kernel");
             }
             ProfScope ps("adjoint_dA", st);
-            if ((e = launch_adj_da(d, s, a->mode, a->W, gw, a->R, gnwin, gwin, a->Dinv[s], a->g_logdet,
-                                   a->mode == QSL_FP64 ? a->dA[s] : nullptr, f32acc ? dA32 : nullptr, st)) != hipSuccess)
-                return hip_fail(e, "adjoint dA kernel");
+            if ((e = launch_adj_da(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");
         }
-        if (f32acc && (e = launch_finalize_dA(dA32, a->dA[s], (int64_t)n * d.n_basis, a->accumulate_dA, st)) != hipSuccess)
+        if (f32acc && (e = launch_finalize_dA(j.dA32, a->dA[s], (int64_t)j.n * d.n_basis, a->accumulate_dA, st)) != hipSuccess)
             return hip_fail(e, "dA finalize");
     }
     return QSL_OK;

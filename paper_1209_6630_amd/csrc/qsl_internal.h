@@ -146,6 +146,61 @@ __device__ __forceinline__ uint16_t bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// One (system, spin) unit of work of a kernel phase: everything the kernel
+// bodies read.  A per-system launch passes one Job by value; a batched
+// launch walks the blocks of several Jobs (an uneven batch of systems) with
+// one deterministic schedule, so both compute the same values.
+struct Job {
+    DevSys s;
+    DevMO mo;
+    int spin, n, mode, gw;
+    int gj_bias;             // Gauss-Jordan block shape: the smallest holding n, + gj_bias
+    int64_t W;
+    const double* R;
+    int* nwin;               // per tile (gw = 1) surviving-window counts and lists
+    int* win;
+    int* gnwin;              // per walker group (gw walkers) counts and lists
+    int* gwin;
+    void* C;
+    double* logdet;
+    int8_t* sign;
+    double* Dinv;
+    double* drift;
+    double* lap;
+    uint32_t* status;
+    const double* g;
+    double* dR;
+    double* dA64;
+    float* dA32;
+    int gx, gy, gz;          // the Job's grid in the current phase
+};
+
+// Block b of a batched launch -> (Job, block coordinates within the Job).
+__device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int b) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Block blockIdx.x of a batched launch (grid = prefix[njobs] blocks)
+// -> body(job, bx, by, bz).  The hardware dispatcher hands out blocks in
+// index order, so the work list is the queue: the plan orders Jobs by
+// falling cost per block and the long blocks start first.
+template <typename F>
+__device__ __forceinline__ void batch_block(const Job* __restrict__ jobs, const int* __restrict__ prefix,
+                                            int njobs, F body) {
+    const int b = blockIdx.x;
+    if (b >= prefix[njobs]) return;
+    const int ji = __builtin_amdgcn_readfirstlane(find_job(prefix, njobs, b));
+    const Job& j = jobs[ji];
+    const int lb = b - prefix[ji];
+    body(j, lb % j.gx, (lb / j.gx) % j.gy, lb / (j.gx * j.gy));
+}
+
 // Timing of kernel launches with HIP events (enabled by qsl_profile_enable).
 struct ProfScope {
     ProfScope(const char* name, hipStream_t st);
@@ -155,29 +210,68 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
 };
 
+// ------------------------------------------------------------ host helpers
+qsl_status hip_fail(hipError_t e, const char* what);
+qsl_status bad(qsl_status code, const std::string& msg);
+size_t round_up(size_t x, size_t a);
+hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t st);
+// Default walkers per dA group: they share one window list.
+int bw_group(int64_t W);
+
+// Workspace of one system: byte offsets of the per-spin tile and group
+// window lists and of the FP32 dA accumulator.
+struct WsLayout {
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], total;
+};
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw);
+// The Job of spin s of a forward / adjoint call on workspace ws.
+Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s);
+Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw);
+
 // ------------------------------------------------------------- launchers
 
-// Screening groups: `gw` tiles of one electron range over consecutive
-// walkers; group index = t * ceil(W / gw) + walker block.
-hipError_t launch_screen(const DevSys& s, int spin, int64_t W, int gw, const double* R, int* tile_nwin,
-                         int* tile_win, uint32_t* status, hipStream_t st);
-hipError_t launch_contract(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W,
-                           const double* R, const int* tile_nwin, const int* tile_win, void* C,
-                           uint32_t* status, hipStream_t st);
-hipError_t launch_gj(int mode, const void* C, int n, int64_t W, int spin, double* Dinv,
-                     double* logdet, int8_t* sign, uint32_t* status, hipStream_t st);
-hipError_t launch_epilogue(int mode, const void* C, const double* Dinv, int n, int64_t W, int spin,
-                           int N, int e_off, double* drift, double* lap, const double* logdet,
-                           uint32_t* status, hipStream_t st);
-hipError_t launch_adj_h(const DevSys& s, const DevMO& mo, int spin, int mode, int64_t W, const double* R,
-                        const int* tile_nwin, const int* tile_win, const double* Dinv, const double* g, double* dR,
-                        hipStream_t st);
-hipError_t launch_adj_da(const DevSys& s, int spin, int mode, int64_t W, int gw, const double* R, const int* grp_nwin,
-                         const int* grp_win, const double* Dinv, const double* g, double* dA64, float* dA32,
-                         hipStream_t st);
+// Every phase has a per-Job launcher (grid = the Job's own blocks) and a
+// batched launcher whose grid covers the blocks of jobs[0..njobs) given the
+// block prefix sums `prefix` (device memory, njobs + 1 entries; grid =
+// prefix[njobs]) of the Job grids that the *_grid / *_blocks helpers define.
+
+// Screening: group = 0 gives per-tile window lists (nwin/win, near-tie
+// status), group = 1 per walker-group lists (gnwin/gwin, gw walkers);
+// group index = t * ceil(W / gw) + walker block.
+int screen_blocks(const Job& j, int group);
+hipError_t launch_screen(const Job& j, int group, hipStream_t st);
+hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
+                                    hipStream_t st);
+// Fused AO evaluation + the five AO->MO products C_n = A B_n.
+void contract_grid(Job& j);
+hipError_t launch_contract(const Job& j, hipStream_t st);
+hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                      hipStream_t st);
+// Gauss-Jordan inversion, log|det| and sign (one block per matrix; the
+// block shape depends on n, so a batched launch serves one variant).
+int gj_variant(int n);
+int gj_threads(int v);
+int gj_job_variant(const Job& j);  // gj_variant(n) + gj_bias, clamped
+hipError_t launch_gj(const Job& j, hipStream_t st);
+hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix, int njobs, int grid,
+                             hipStream_t st);
+// Drift and Laplacian (four electrons per block).
+int epilogue_blocks(const Job& j);
+hipError_t launch_epilogue(const Job& j, hipStream_t st);
+hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                      hipStream_t st);
+// Adjoint: H = G A and dR per tile; dA per walker group.
+void adj_h_grid(Job& j);
+void adj_da_grid(Job& j);
+hipError_t launch_adj_h(const Job& j, hipStream_t st);
+hipError_t launch_adj_da(const Job& j, hipStream_t st);
+hipError_t launch_adj_h_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                   hipStream_t st);
+hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                    hipStream_t st);
 hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
 hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A_dev, int64_t ld,
                            hipStream_t st);
-hipError_t launch_scale_copy(double* dst, const double* src, int64_t n, hipStream_t st);
 
 }  // namespace qsl

@@ -61,13 +61,17 @@ hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int 
 // drift[e] = sum_i Dinv[e][i] C_{2..4}[e][i], lap[e] = sum_i Dinv[e][i] C_5[e][i]
 // (the determinant's "vector products"), one wavefront per electron.
 template <typename Tc>
-__global__ __launch_bounds__(256) void epilogue_kernel(const Tc* __restrict__ C, const double* __restrict__ Dinv,
-                                                       int n, int64_t W, int spin, int N, int e_off,
-                                                       double* __restrict__ drift, double* __restrict__ lap,
-                                                       const double* __restrict__ logdet,
-                                                       uint32_t* __restrict__ status) {
+__device__ __forceinline__ void epilogue_body(const Job& j, int bx) {
+    const Tc* __restrict__ C = (const Tc*)j.C;
+    const double* __restrict__ Dinv = j.Dinv;
+    const int n = j.n, spin = j.spin, N = j.s.n_up + j.s.n_dn, e_off = j.spin ? j.s.n_up : 0;
+    const int64_t W = j.W;
+    double* __restrict__ drift = j.drift;
+    double* __restrict__ lap = j.lap;
+    const double* __restrict__ logdet = j.logdet;
+    uint32_t* __restrict__ status = j.status;
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t row = (int64_t)bx * 4 + (threadIdx.x >> 6);
     if (row >= W * n) return;
     const int64_t w = row / n;
     const int e = (int)(row % n);
@@ -95,17 +99,31 @@ __global__ __launch_bounds__(256) void epilogue_kernel(const Tc* __restrict__ C,
     }
 }
 
-hipError_t launch_epilogue(int mode, const void* C, const double* Dinv, int n, int64_t W, int spin, int N, int e_off,
-                           double* drift, double* lap, const double* logdet, uint32_t* status, hipStream_t st) {
-    const int64_t rows = W * n;
-    if (!rows) return hipSuccess;
-    const unsigned blocks = (unsigned)((rows + 3) / 4);
-    if (mode == QSL_FP64)
-        epilogue_kernel<double><<<blocks, 256, 0, st>>>((const double*)C, Dinv, n, W, spin, N, e_off, drift, lap,
-                                                        logdet, status);
-    else
-        epilogue_kernel<float><<<blocks, 256, 0, st>>>((const float*)C, Dinv, n, W, spin, N, e_off, drift, lap,
-                                                       logdet, status);
+template <typename Tc>
+__global__ __launch_bounds__(256) void epilogue_kernel(Job j) {
+    epilogue_body<Tc>(j, blockIdx.x);
+}
+
+template <typename Tc>
+__global__ __launch_bounds__(256) void epilogue_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { epilogue_body<Tc>(j, bx); });
+}
+
+int epilogue_blocks(const Job& j) { return (int)((j.W * j.n + 3) / 4); }
+
+hipError_t launch_epilogue(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    j.gx = epilogue_blocks(j); j.gy = 1; j.gz = 1;
+    if (!j.gx) return hipSuccess;
+    if (j.mode == QSL_FP64) epilogue_kernel<double><<<(unsigned)j.gx, 256, 0, st>>>(j);
+    else epilogue_kernel<float><<<(unsigned)j.gx, 256, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
+                                      hipStream_t st) {
+    if (mode == QSL_FP64) epilogue_batched<double><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    else epilogue_batched<float><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

@@ -19,16 +19,17 @@ constexpr int SCREEN_THREADS = 256;
 // t * ngroups_w + walker-block (t = tile index within a walker).
 constexpr int SCREEN_MAXE = 2048;
 
-__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int spin, int n, int tpw, int64_t W,
-                                                                 int gw, const double* __restrict__ R,
-                                                                 int* __restrict__ tile_nwin,
-                                                                 int* __restrict__ tile_win,
-                                                                 uint32_t* __restrict__ status) {
+__device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restrict__ tile_nwin,
+                                            int* __restrict__ tile_win, uint32_t* __restrict__ status, int bx) {
+    const DevSys& s = j.s;
+    const int spin = j.spin, n = j.n;
+    const int64_t W = j.W;
+    const double* __restrict__ R = j.R;
     __shared__ double ex[SCREEN_MAXE], ey[SCREEN_MAXE], ez[SCREEN_MAXE];
     __shared__ double bb[6];
     __shared__ double bred[SCREEN_THREADS / 64][6];
     __shared__ int wave_cnt[SCREEN_THREADS / 64];
-    const int tile = blockIdx.x;
+    const int tile = bx;
     const int ngw = (int)((W + gw - 1) / gw);
     const int t = tile / ngw, wb = tile % ngw;
     const int w0 = wb * gw;
@@ -124,15 +125,38 @@ __global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(DevSys s, int sp
     if (tid == 0) tile_nwin[tile] = base;
 }
 
-hipError_t launch_screen(const DevSys& s, int spin, int64_t W, int gw, const double* R, int* tile_nwin,
-                         int* tile_win, uint32_t* status, hipStream_t st) {
-    const int n = n_spin(s, spin);
-    const int tpw = tiles_per_walker(n);
-    if (gw < 1 || (gw > 1 && status)) return hipErrorInvalidValue;
-    const int64_t groups = (int64_t)tpw * ((W + gw - 1) / gw);
-    if (groups == 0) return hipSuccess;
-    screen_kernel<<<dim3((unsigned)groups), SCREEN_THREADS, 0, st>>>(s, spin, n, tpw, W, gw, R, tile_nwin, tile_win,
-                                                                     status);
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(Job j, int group) {
+    if (group) screen_body(j, j.gw, j.gnwin, j.gwin, nullptr, blockIdx.x);
+    else screen_body(j, 1, j.nwin, j.win, j.status, blockIdx.x);
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_batched(const Job* jobs, const int* prefix, int njobs,
+                                                                     int group) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) {
+        if (group) screen_body(j, j.gw, j.gnwin, j.gwin, nullptr, bx);
+        else screen_body(j, 1, j.nwin, j.win, j.status, bx);
+    });
+}
+
+// Blocks of the screening phase of a Job (groups of gw walkers, or tiles).
+int screen_blocks(const Job& j, int group) {
+    const int gw = group ? j.gw : 1;
+    return j.n ? tiles_per_walker(j.n) * (int)((j.W + gw - 1) / gw) : 0;
+}
+
+hipError_t launch_screen(const Job& j, int group, hipStream_t st) {
+    if (group && j.gw < 1) return hipErrorInvalidValue;
+    const int blocks = screen_blocks(j, group);
+    if (!blocks) return hipSuccess;
+    Job jj = j;
+    jj.gx = blocks; jj.gy = 1; jj.gz = 1;
+    screen_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj, group);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
+                                    hipStream_t st) {
+    screen_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs, group);
     return hipGetLastError();
 }
 

@@ -84,6 +84,23 @@ def test_null_arguments():
     assert lib().qsl_system_destroy(None) == 0
 
 
+def test_plan_argument_checks():
+    """Plan entry points reject NULL / out-of-range arguments on the host."""
+    from paper_1209_6630_amd._lib import Tuning, lib
+    L = lib()
+    h = ct.c_void_p()
+    W = (ct.c_int64 * 1)(4)
+    assert L.qsl_plan_create(0, None, W, 0, 0, ct.byref(h)) == 1
+    assert L.qsl_plan_create(1, None, W, 0, 0, ct.byref(h)) == 1
+    assert L.qsl_plan_launch(None, None) == 1
+    assert L.qsl_plan_bind(None, 0, None, None) == 1
+    t = Tuning(1, 0, 0)
+    assert L.qsl_plan_set_tuning(None, ct.byref(t)) == 1
+    assert L.qsl_plan_get_tuning(None, ct.byref(t)) == 1
+    assert L.qsl_autotune(None, None, None, None) == 1
+    assert L.qsl_plan_destroy(None) == 0
+
+
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     from paper_1209_6630_amd import _lib
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
