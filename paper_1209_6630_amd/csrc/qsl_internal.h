@@ -18,7 +18,8 @@ constexpr int TE = 32;
 // a bf16 MFMA operand.
 constexpr int WIN = 8;
 // Largest Slater matrix inverted in registers by one workgroup.
-constexpr int GJ_NMAX = 224;
+constexpr int GJ_REG_NMAX = 224;   // largest n of the register-resident inversion
+constexpr int GJ_NMAX = 1024;      // largest n of the blocked inversion
 
 // Device view of a system, passed to kernels by value.
 struct DevSys {
@@ -172,6 +173,7 @@ struct Job {
     double* dR;
     double* dA64;
     float* dA32;
+    double* gjws;            // blocked inversion (n > GJ_REG_NMAX): [W][n][n] copy of D
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 
@@ -222,7 +224,7 @@ int bw_group(int64_t W);
 // Workspace of one system: byte offsets of the per-spin tile and group
 // window lists and of the FP32 dA accumulator.
 struct WsLayout {
-    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], total;
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], total;
 };
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw);
 // The Job of spin s of a forward / adjoint call on workspace ws.

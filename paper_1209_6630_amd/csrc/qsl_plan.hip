@@ -25,6 +25,7 @@ enum Phase {
     PH_GJ1,
     PH_GJ2,
     PH_GJ3,
+    PH_GJ4,          // blocked (n > 224)
     PH_EPILOGUE,     // drift and Laplacian
     PH_ADJ_H,        // H = G A, dR
     PH_SCREEN_G,     // per walker-group window lists
@@ -248,7 +249,7 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                              (int)C.jobs.size(), C.blocks(), st)) != hipSuccess)
                 return hip_fail(e, "contraction kernel");
         }
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v <= 4; ++v) {
             auto& G = p->ph[PH_GJ0 + v];
             if (!G.blocks()) continue;
             ProfScope ps("gauss_jordan", st);
@@ -265,7 +266,7 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             ProfScope ps(contract_name(mode), st);
             if ((e = launch_contract(j, st)) != hipSuccess) return hip_fail(e, "contraction kernel");
         }
-        for (int v = 0; v < 4; ++v)
+        for (int v = 0; v <= 4; ++v)
             for (const Job& j : p->ph[PH_GJ0 + v].jobs) {
                 ProfScope ps("gauss_jordan", st);
                 if ((e = launch_gj(j, st)) != hipSuccess) return hip_fail(e, "inversion kernel");
@@ -682,7 +683,7 @@ qsl_status qsl_autotune(qsl_plan* p, const char* cache_path, void* stream, qsl_t
     std::vector<qsl_tuning> cands;
     for (int bt = 1; bt >= 0; --bt)
         for (int gb = 0; gb <= 1; ++gb) {
-            if (gb && gj_variant(nmax) == 3) continue;  // no larger block shape
+            if (gb && gj_variant(nmax) >= 3) continue;  // no larger block shape
             const int groups[] = {0, 16, 32, 64, 128, 256};
             for (int g : groups) {
                 if (!any_bwd && g) continue;

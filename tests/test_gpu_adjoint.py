@@ -44,7 +44,7 @@ def _run(sysm, A_up, A_dn, R, mode, seed=0):
     return g, dR.cpu().numpy(), dAu.cpu().numpy(), dAd.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("name,W", [("44e", 8), ("158e", 4), ("434e", 2)])
+@pytest.mark.parametrize("name,W", [("44e", 8), ("158e", 4), ("434e", 2), ("1731e", 1)])
 @pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
 def test_backward_configs(name, W, mode):
     print(f"[case] backward {name} W={W} mode={mode}", flush=True)

@@ -16,7 +16,7 @@ def _cfg(name, W):
     return sysm, A_up, A_dn, R
 
 
-@pytest.mark.parametrize("name,W", [("44e", 16), ("158e", 6), ("434e", 3)])
+@pytest.mark.parametrize("name,W", [("44e", 16), ("158e", 6), ("434e", 3), ("1731e", 2)])
 @pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
 def test_forward_configs(name, W, mode):
     print(f"[case] forward {name} W={W} mode={mode}", flush=True)
@@ -27,10 +27,12 @@ def test_forward_configs(name, W, mode):
 
 
 @pytest.mark.parametrize("n_up,n_dn", [(1, 0), (1, 1), (3, 2), (32, 31), (33, 33), (64, 63), (65, 64),
-                                       (128, 127), (129, 100)])
+                                       (128, 127), (129, 100), (224, 223), (225, 224), (480, 479),
+                                       (1024, 1000)])
 def test_forward_tile_and_inversion_boundaries(n_up, n_dn):
     """Electron counts at the 32-electron tile and at every inversion
-    variant boundary (32, 64, 128), with s, p and d shells."""
+    variant boundary (32, 64, 128, 224 register-resident, then blocked up to
+    the 1024 maximum), with s, p and d shells."""
     print(f"[case] boundaries n_up={n_up} n_dn={n_dn}", flush=True)
     nat = max(2, (n_up + n_dn) // 6 + 1)
     sysm, A_up, A_dn = random_tiny(n_atoms=nat, n_up=n_up, n_dn=n_dn, seed=n_up * 7 + n_dn)
@@ -42,6 +44,33 @@ def test_forward_tile_and_inversion_boundaries(n_up, n_dn):
     for mode in ("fp64", "fp32"):
         gpu = run_gpu_forward(S, R, mode)
         compare_forward(sysm, A_up, A_dn, R, gpu, mode)
+
+
+def test_more_electrons_than_supported_is_an_error():
+    print("[case] n above the inversion maximum", flush=True)
+    from paper_1209_6630_amd import QslError
+    sysm, A_up, A_dn = random_tiny(n_atoms=180, n_up=1025, n_dn=2, seed=3)
+    R = walkers_near(sysm, 1, seed=1)
+    S = make_gpu_system(sysm, A_up, A_dn)
+    with pytest.raises(QslError) as ei:
+        run_gpu_forward(S, R, "fp32")
+    assert ei.value.code == 2  # QSL_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n_up", [40, 300])
+def test_singular_walker_blocked_and_register(n_up):
+    """A walker whose electron lies beyond every atomic radius has a zero
+    column: log|det| = -inf, sign 0, status bit, in both inversion forms."""
+    print(f"[case] singular n_up={n_up}", flush=True)
+    nat = max(3, (2 * n_up) // 6 + 1)
+    sysm, A_up, A_dn = random_tiny(n_atoms=nat, n_up=n_up, n_dn=n_up - 1, seed=11)
+    R = walkers_near(sysm, 2, seed=5)
+    R[0, n_up - 1] = [900.0, -700.0, 650.0]
+    S = make_gpu_system(sysm, A_up, A_dn)
+    gpu = run_gpu_forward(S, R, "fp64")
+    assert gpu["sign"][0, 0] == 0 and np.isneginf(gpu["logdet"][0, 0]) and gpu["status"][0] & 1
+    assert gpu["sign"][1, 0] != 0 and not (gpu["status"][1] & 1)
+    compare_forward(sysm, A_up, A_dn, R, gpu, "fp64")
 
 
 def test_singular_walker():
