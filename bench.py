@@ -4,10 +4,16 @@
 A step is one pass of the whole hot path over one batch of walkers:
 screening, fused AO evaluation + AO->MO products (split BF16 on MFMA with
 FP32 accumulation), FP64 Gauss-Jordan log|det| / sign / inverse, drift and
-Laplacian, then the adjoint (AO recomputation, dA and dR).  The workload is
-the synthetic 434-electron peptide-shaped system (134 atoms, 1270 AOs,
-217 x 1270 MO coefficients per spin) with 4096 walkers.  Inputs are resident
-in HBM before the timed region.
+Laplacian, then the adjoint (AO recomputation, dR and dA).  The headline
+workload is the synthetic 434-electron peptide-shaped system (134 atoms,
+1270 AOs, 217 x 1270 MO coefficients per spin) with 4096 walkers; the step
+is one replay of the plan's HIP graph, inputs resident in HBM.
+
+Beside it (in "also"): the same system in plain FP64, and the 1731-electron
+system (531 atoms, 5055 AOs, 866/865 MOs, 512 walkers) in FP32 and FP64,
+each with the mixed-precision error against the FP64 run on the same walkers.
+Per-kernel times come from a second, eager pass of the same steps with HIP
+events around every launch on the launch stream.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -26,9 +32,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "walker Slater-builds/sec fwd+adjoint at 434e/1731e; mixed-prec vs FP64 at stated err"
 PEAK = {"bf16x3": ("mfma", 2500.0), "fp32": ("mfma", 157.3), "fp64": ("mfma", 78.6)}
-PEAK_FP64_VALU = 78.6
-PEAK_FP32_VALU = 157.3
+PEAK_FP64 = 78.6
 HBM_PEAK = 8000.0  # GB/s
+DTYPE = {"bf16x3": "bf16x3+f32acc/f64", "fp32": "f32/f64", "fp64": "f64"}
 
 
 def log(*a):
@@ -36,7 +42,7 @@ def log(*a):
 
 
 def survivors_per_electron(sysm, R, max_walkers=64):
-    """Mean surviving AOs per electron (cost model for the flop counts):
+    """Mean surviving AOs per electron (the cost model of the flop counts):
     a shell survives when its smallest exponent times r^2 is <= T."""
     Rs = R[:max_walkers].reshape(-1, 3)
     off = np.concatenate([[0], np.cumsum(sysm.shell_nprim)])
@@ -49,6 +55,123 @@ def survivors_per_electron(sysm, R, max_walkers=64):
         r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
         tot += int(((gmin[None] * r2 <= sysm.screen_T) * nao[None]).sum())
     return tot / Rs.shape[0]
+
+
+def work_per_step(sysm, nnz, W, mode):
+    """Algorithmic work of one step per kernel kind: (amount, bound, peak, unit)."""
+    ns = [sysm.n_up, sysm.n_dn]
+    contract = sum(10.0 * n * n * nnz * W for n in ns)   # 5 products x 2 flops x MOs x survivors
+    gj = sum(2.0 * n ** 3 * W for n in ns)                 # 2 n^3 per matrix
+    adjoint = sum(2.0 * n * n * nnz * W for n in ns)       # H or dA: 2 flops per (electron, survivor, MO)
+    cb = 8 if mode == "fp64" else 4
+    epi = sum((8.0 * n * n + 4 * cb * n * n + 32.0 * n) * W for n in ns)  # Dinv + 4 C blocks read, drift/lap
+    return {
+        f"contract_{mode}": (contract, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
+        "gauss_jordan": (gj, "mfma", PEAK_FP64, "TFLOP/s"),
+        "adjoint_h": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
+        "adjoint_dA": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
+        "drift_lap": (epi, "hbm", HBM_PEAK, "GB/s"),
+    }
+
+
+class Workload:
+    """One system, W walkers, one mode: a graph plan and an eager plan bound
+    to the same device buffers (forward + adjoint)."""
+
+    def __init__(self, config, W, mode):
+        import torch
+        import qsl_synth as q
+        from paper_1209_6630_amd.api import Plan, System
+        self.config, self.W, self.mode = config, W, mode
+        self.sysm, A_up, A_dn, self.R_np = q.make_config(config, W=W)
+        self.A = (A_up, A_dn)
+        S = System.from_synth(self.sysm)
+        S.set_mo(0, A_up)
+        S.set_mo(1, A_dn)
+        self.S = S
+        dev = "cuda"
+        self.R = torch.from_numpy(self.R_np).to(dev)
+        self.out = S.alloc_outputs(W, mode)
+        self.g = torch.ones((W, 2), dtype=torch.float64, device=dev)
+        self.dR = torch.empty((W, S.n_elec, 3), dtype=torch.float64, device=dev)
+        self.dA = (torch.empty((S.n_up, S.n_basis), dtype=torch.float64, device=dev),
+                   torch.empty((S.n_dn, S.n_basis), dtype=torch.float64, device=dev))
+        self.plans = {}
+        for graph in (True, False):
+            P = Plan([S], [W], mode, graph=graph)
+            P.bind(0, self.R, self.out, g=self.g, dR=self.dR, dA=self.dA)
+            self.plans[graph] = P
+        torch.cuda.synchronize()
+
+    def time(self, steps, warmup):
+        """K graph replays bracketed by synchronisations -> ms per step;
+        then K eager launches with kernel timing -> per-kernel totals."""
+        import torch
+        from paper_1209_6630_amd import _lib
+        Pg, Pe = self.plans[True], self.plans[False]
+        for _ in range(warmup):
+            Pg.launch()
+        Pe.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            Pg.launch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        _lib.profile_enable(True)
+        _lib.profile_read(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            Pe.launch()
+        torch.cuda.synchronize()
+        ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+        prof = _lib.profile_read(reset=True)
+        _lib.profile_enable(False)
+        return ms, ms_eager, prof
+
+    def close(self):
+        for P in self.plans.values():
+            P.close()
+        self.plans = {}
+
+
+def kernel_table(prof, steps, kinds):
+    kernels = {}
+    for name, (launches, tot) in prof.items():
+        e = {"launches": launches, "avg_ms": tot / max(launches, 1), "ms_per_step": tot / steps}
+        if name in kinds:
+            work, bound, peak, unit = kinds[name]
+            achieved = work / (tot / steps * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
+            e.update(bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak)
+        kernels[name] = e
+    return kernels
+
+
+def err_vs_fp64(mixed, ref):
+    """Mixed precision against the FP64 run on the same walkers: |d logdet|
+    and the normwise relative D^-1 difference per (walker, spin) as median /
+    p99 / max, and sign disagreements.  Ill-conditioned walkers amplify the
+    product error by the condition number of D, hence the long tail."""
+    import torch
+    ok = torch.isfinite(ref["logdet"]) & torch.isfinite(mixed["logdet"])
+    ld = (mixed["logdet"] - ref["logdet"]).abs()[ok].double()
+    rels = []
+    for k in ("Dinv_up", "Dinv_dn"):
+        if ref[k].numel() == 0:
+            continue
+        for c0 in range(0, ref[k].shape[0], 256):
+            a, b = mixed[k][c0:c0 + 256], ref[k][c0:c0 + 256]
+            r = torch.linalg.matrix_norm(a - b) / torch.linalg.matrix_norm(b)
+            rels.append(r[torch.isfinite(r)])
+    rel = torch.cat(rels) if rels else torch.zeros(1, dtype=torch.float64, device=ld.device)
+
+    def q3(x):
+        if x.numel() == 0:
+            return [0.0, 0.0, 0.0]
+        return [float(torch.quantile(x, 0.5)), float(torch.quantile(x, 0.99)), float(x.max())]
+
+    return {"logdet_abs_median_p99_max": q3(ld), "Dinv_normwise_rel_median_p99_max": q3(rel),
+            "sign_mismatch": int((mixed["sign"] != ref["sign"]).sum())}
 
 
 def cpu_baseline(sysm, A_up, A_dn, R, target_s=12.0):
@@ -85,107 +208,87 @@ def main():
     ap.add_argument("--config", default="434e")
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-also", action="store_true", help="skip the FP64 and 1731e companion runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the walker batch of one "
-              "GPU is the unit of work; see the design notes for how walkers shard across GPUs.",
+              "GPU is the unit of work; the design notes describe how walkers shard across GPUs.",
               file=sys.stderr)
         sys.exit(2)
 
     import torch
     import qsl_synth as q
-    from paper_1209_6630_amd import _lib
-    from paper_1209_6630_amd.api import System
+    torch.cuda.set_device(0)
 
     cfg = q.CONFIGS[args.config]
     W = args.walkers or cfg["W"]
     mode = args.mode
     log(f"workload {args.config} W={W} mode={mode}: generating inputs")
-    sysm, A_up, A_dn, R_np = q.make_config(args.config, W=W)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    S = System.from_synth(sysm)
-    S.set_mo(0, A_up)
-    S.set_mo(1, A_dn)
-    R = torch.from_numpy(R_np).to(dev)
-    out = S.alloc_outputs(W, mode)
-    g = torch.ones((W, 2), dtype=torch.float64, device=dev)
-    N, nb = sysm.n_elec, sysm.n_basis
-    dR = torch.empty((W, N, 3), dtype=torch.float64, device=dev)
-    dA = (torch.empty((sysm.n_up, nb), dtype=torch.float64, device=dev),
-          torch.empty((sysm.n_dn, nb), dtype=torch.float64, device=dev))
-    torch.cuda.synchronize()
-
-    def step():
-        S.forward(R, mode, out=out)
-        S.backward(R, out["Dinv_up"], out["Dinv_dn"], g, mode, dR=dR, dA=dA)
-
-    log(f"warmup {args.warmup} steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    st = out["status"].cpu().numpy()
-    n_sing = int(((st & 1) != 0).sum())
-    _lib.profile_enable(True)
-    _lib.profile_read(reset=True)
-    log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = _lib.profile_read(reset=True)
-    _lib.profile_enable(False)
-    ms = (t1 - t0) * 1e3 / args.steps
+    main_wl = Workload(args.config, W, mode)
+    log(f"timing {args.steps} graph replays after {args.warmup} warm-up")
+    ms, ms_eager, prof = main_wl.time(args.steps, args.warmup)
     value = W / (ms * 1e-3)
-    log(f"{ms:.3f} ms/step, {value:.1f} walkers/s; kernels {prof}")
-
-    # algorithmic work per launch (one launch = one spin over all W walkers)
-    nnz = survivors_per_electron(sysm, R_np)
-    ns = [sysm.n_up, sysm.n_dn]
-    contract_flops = [10.0 * n * n * nnz * W for n in ns]          # 5 products x 2 flops x MOs x survivors
-    gj_flops = [2.0 * n ** 3 * W for n in ns]                        # 2 n^3 per matrix
-    adjoint_flops = [2.0 * n * n * nnz * W for n in ns]              # H or dA: 2 flops per (electron, survivor, MO)
-    cbytes = 8 if mode == "fp64" else 4
-    epi_bytes = [(8.0 * n * n + 4 * cbytes * n * n + 32.0 * n) * W for n in ns]
-    kinds = {
-        f"contract_{mode}": (sum(contract_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
-        "gauss_jordan": (sum(gj_flops), "alu", PEAK_FP64_VALU, "TFLOP/s"),
-        "adjoint_h": (sum(adjoint_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
-        "adjoint_dA": (sum(adjoint_flops), PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
-        "drift_lap": (sum(epi_bytes), "hbm", HBM_PEAK, "GB/s"),
-    }
-    kernels = {}
-    for name, (launches, tot) in prof.items():
-        per_launch_ms = tot / max(launches, 1)
-        entry = {"launches": launches, "avg_ms": per_launch_ms, "ms_per_step": tot / args.steps}
-        if name in kinds:
-            work, bound, peak, unit = kinds[name]
-            per_step_work = work  # summed over both spins = the launches of one step
-            achieved = per_step_work / (tot / args.steps * 1e-3) / (1e12 if unit == "TFLOP/s" else 1e9)
-            entry.update(bound=bound, achieved=achieved, peak=peak, unit=unit, frac=achieved / peak)
-        kernels[name] = entry
+    log(f"{ms:.3f} ms/step (eager {ms_eager:.3f}), {value:.1f} walkers/s; kernels {prof}")
+    sysm = main_wl.sysm
+    nnz = survivors_per_electron(sysm, main_wl.R_np)
+    kinds = work_per_step(sysm, nnz, W, mode)
+    kernels = kernel_table(prof, args.steps, kinds)
     dom = max((k for k in kernels if k in kinds), key=lambda k: kernels[k]["ms_per_step"])
     d = kernels[dom]
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
                 "unit": d["unit"], "frac": d["frac"], "traffic": None}
-
+    st = main_wl.out["status"].cpu().numpy()
     res = {
         "metric": METRIC, "value": value, "unit": "walker Slater-builds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16x3+f32acc/f64", "fp32": "f32/f64", "fp64": "f64"}[mode],
-        "data": "synthetic",
-        "config": {"workload": f"{args.config}-W{W}-{mode}-fwd+adjoint", "electrons": N, "n_basis": nb,
-                   "walkers": W, "mode": mode, "survivors_per_electron": round(nnz, 1),
-                   "singular_walkers": n_sing},
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[mode], "data": "synthetic",
+        "config": {"workload": f"{args.config}-W{W}-{mode}-fwd+adjoint", "electrons": sysm.n_elec,
+                   "n_basis": sysm.n_basis, "walkers": W, "mode": mode, "survivors_per_electron": round(nnz, 1),
+                   "singular_walkers": int(((st & 1) != 0).sum()), "timed": "HIP graph replays of the plan",
+                   "eager_ms_per_step": ms_eager},
         "roofline": roofline,
         "kernels": kernels,
     }
+
+    also = []
+    if not args.no_also:
+        steps2 = max(3, args.steps // 2)
+        pairs = [(args.config, W, mode, "fp64"), ("1731e", q.CONFIGS["1731e"]["W"], "fp32", "fp64")]
+        mixed_keep = main_wl
+        for name, Wx, mmode, fmode in pairs:
+            runs = {}
+            for m in (mmode, fmode):
+                if name == args.config and m == mode and mixed_keep is not None:
+                    wl, msx, prx = mixed_keep, ms, prof
+                else:
+                    log(f"companion {name} W={Wx} mode={m}")
+                    wl = Workload(name, Wx, m)
+                    msx, _, prx = wl.time(steps2, 2)
+                    nnz_x = survivors_per_electron(wl.sysm, wl.R_np)
+                    ktab = kernel_table(prx, steps2, work_per_step(wl.sysm, nnz_x, Wx, m))
+                    also.append({"workload": f"{name}-W{Wx}-{m}-fwd+adjoint", "value": Wx / (msx * 1e-3),
+                                 "unit": "walker Slater-builds/s", "ms_per_step": msx, "steps": steps2,
+                                 "dtype": DTYPE[m],
+                                 "kernels_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in ktab.items()},
+                                 "kernel_frac": {k: round(v["frac"], 4) for k, v in ktab.items() if "frac" in v}})
+                runs[m] = wl
+            e = err_vs_fp64(runs[mmode].out, runs[fmode].out)
+            for a in also:
+                if a["workload"] == f"{name}-W{Wx}-{mmode}-fwd+adjoint":
+                    a["err_vs_fp64"] = e
+            if name == args.config:
+                res["config"]["err_vs_fp64"] = e
+            for m, wl in runs.items():
+                if wl is not main_wl:
+                    wl.close()
+            runs.clear()
+            torch.cuda.empty_cache()
+    res["also"] = also
+    main_wl.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(sysm, A_up, A_dn, R_np)
+        sysm_b, A_up, A_dn, R_b = q.make_config(args.config, W=W)
+        res["cpu_baseline"] = cpu_baseline(sysm_b, A_up, A_dn, R_b)
     print(json.dumps(res), flush=True)
 
 
