@@ -14,15 +14,6 @@
 
 namespace qsl {
 
-typedef __attribute__((ext_vector_type(4))) double f64x4;
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (I < N) {
-        f(std::integral_constant<int, I>{});
-        static_for<I + 1, N>(f);
-    }
-}
 
 // Layout: wave v of NWV owns the D columns e = v + NWV c (c < CPW, electron
 // index), lane l owns the D rows i = l + 64 r (r < RPL, MO index); thread
@@ -34,28 +25,6 @@ __device__ __forceinline__ void static_for(F&& f) {
 // applies the rank-1 update.  The pivot row is left unscaled (it is divided
 // by its pivot on the way out), its column-k entry becomes 1; the other rows
 // of column k become -D[i][k]/pv through the entry 1 + 1/pv of the pivot row.
-
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-    const uint64_t u = __double_as_longlong(x);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
-    return __longlong_as_double(((uint64_t)hi << 32) | lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
-    const uint64_t u = __double_as_longlong(x);
-    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)u, CTRL, 0xf, 0xf, false);
-    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((uint64_t)hi << 32) | lo);
-}
-
-template <int CTRL>
-__device__ __forceinline__ void argmax_step(double& best, int& bi) {
-    const double ob = dpp_f64<CTRL>(best);
-    const int oi = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xf, 0xf, false);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-}
 
 // argmax of |col| over the unused rows of this lane, then over the wavefront
 // (largest value, smallest row index on exact ties): DPP exchanges inside
@@ -308,273 +277,6 @@ __global__ __launch_bounds__(NWV * 64) void gj_batched(const Job* jobs, const in
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gj_body<NWV, RPL, CPW, Tin>(j, bx); });
 }
 
-// ---------------------------------------------------------------- blocked
-//
-// 224 < n <= 1024: blocked Gauss-Jordan on a copy of D in the workspace,
-// one 512-thread workgroup per matrix.  The copy is stored by D column
-// (M[a][b] = D[b][a], row a = electron slot, b = MO row), which is the
-// layout of C_1, so it is filled by a contiguous FP64 promotion.
-//
-// Panel of GJB_NB columns a in [k0, k0 + NB): thread t holds D rows t and
-// t + 512 of the panel in registers and the panel is reduced column by
-// column exactly as in the unblocked method (pivot = largest |D[b][k]| over
-// unused rows, smallest b on ties; one barrier per column: every wave
-// publishes its best row, all threads pick the winner from LDS).  After the
-// panel, the composite of its NB elementary steps acts on any other column v
-// through its pivot rows only: v <- (v with the panel's pivot rows set to 0)
-// + L v_P, where L (n x NB) is the reduced panel itself.  That rank-NB
-// update of the whole matrix runs on v_mfma_f64_16x16x4f64: output tiles of
-// 16 columns a x 16 rows b, L from registers (each wave owns eight 16-row
-// strips of b), v_P gathered into LDS per tile of 16 columns.  Pivot rows
-// are never moved; the inverse is un-permuted on the way out.  Traffic: the
-// matrix is read and written once per panel (n^3 / NB x 16 bytes); flops
-// 2 n^3.
-constexpr int GJB_THREADS = 512;
-constexpr int GJB_RPT = 2;                       // D rows per thread in a panel
-constexpr int GJB_NB = 32;
-constexpr int GJB_WAVES = GJB_THREADS / 64;
-constexpr int GJB_SPW = GJ_NMAX / 16 / GJB_WAVES;  // 16-row strips per wave
-
-// (|value|, row) argmax over the wavefront, smallest row on exact ties;
-// uniform result.
-__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
-    argmax_step<0xB1>(best, bi);
-    argmax_step<0x4E>(best, bi);
-    argmax_step<0x141>(best, bi);
-    argmax_step<0x140>(best, bi);
-    double sb = readlane_f64(best, 0);
-    int si = __builtin_amdgcn_readlane(bi, 0);
-#pragma unroll
-    for (int rw = 1; rw < 4; ++rw) {
-        const double ob = readlane_f64(best, 16 * rw);
-        const int oi = __builtin_amdgcn_readlane(bi, 16 * rw);
-        if (ob > sb || (ob == sb && oi < si)) { sb = ob; si = oi; }
-    }
-    best = sb;
-    bi = si;
-}
-
-template <typename Tin>
-__device__ __forceinline__ void gjb_body(const Job& j, int bx) {
-    constexpr int NB = GJB_NB, RPT = GJB_RPT;
-    const int n = j.n, spin = j.spin, w = bx;
-    const size_t nn = (size_t)n * n;
-    const Tin* __restrict__ C1 = (const Tin*)j.C + (size_t)w * 5 * nn;
-    double* __restrict__ M = j.gjws + (size_t)w * nn;
-    double* __restrict__ Dw = j.Dinv + (size_t)w * nn;
-    __shared__ double cand_a[2][GJB_WAVES];
-    __shared__ int cand_i[2][GJB_WAVES];
-    __shared__ double cand_row[2][GJB_WAVES][NB];
-    __shared__ double Tt[2][16][NB + 1];
-    __shared__ int perm[GJ_NMAX];
-    __shared__ int invp[GJ_NMAX];
-    __shared__ unsigned char curpiv[GJ_NMAX];
-    __shared__ int s_flag;
-
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    // element q of M addressed as a uniform base plus a 32-bit byte offset
-    // (n^2 * 8 < 2^32), so that no 64-bit per-lane addresses are kept
-    char* const Mb = (char*)M;
-    auto Mq = [&](uint32_t q) -> double& { return *(double*)(Mb + q * 8u); };
-    for (size_t q = tid; q < nn; q += GJB_THREADS) M[q] = (double)C1[q];
-    for (int q = tid; q < GJ_NMAX; q += GJB_THREADS) curpiv[q] = 0;
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-
-    bool used[RPT] = {};
-    bool singular = false;
-    double ld = 0.0;
-    int neg = 0;
-    const int ns = (n + 15) >> 4;  // 16-row strips of b
-    for (int k0 = 0; k0 < n && !singular; k0 += NB) {
-        const int kn = min(NB, n - k0);
-        // n through an empty asm: the row addresses below are recomputed per
-        // panel instead of being hoisted (64 bits each) out of the loop
-        int nv = n;
-        asm volatile("" : "+s"(nv));
-        double P[RPT][NB];
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int b = tid + GJB_THREADS * r;
-            const int bl = min(b, n - 1);  // loads at clamped (valid) addresses, then select
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                const double v = Mq((uint32_t)((k0 + min(k, kn - 1)) * nv + bl));
-                P[r][k] = (b < n && k < kn) ? v : 0.0;
-            }
-        }
-#pragma unroll 1
-        for (int k = 0; k < kn; ++k) {
-            const int buf = (k0 + k) & 1;
-            double x[RPT];  // P[r][k] (k is not a compile-time index: select)
-            double best = -1.0;
-            int bi = 0x7fffffff;
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                x[r] = 0.0;
-#pragma unroll
-                for (int q = 0; q < NB; ++q) x[r] = q == k ? P[r][q] : x[r];
-                const int b = tid + GJB_THREADS * r;
-                const double v = fabs(x[r]);
-                if (b < n && !used[r] && v > best) { best = v; bi = b; }  // NaN never wins
-            }
-            wave_argmax(best, bi);
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-                if (tid + GJB_THREADS * r == bi) {
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) cand_row[buf][wave][q] = P[r][q];
-                }
-            if (lane == 0) {
-                cand_a[buf][wave] = best;
-                cand_i[buf][wave] = bi;
-            }
-            __syncthreads();
-            double top = -1.0;
-            int p = 0x7fffffff, pw = 0;
-#pragma unroll
-            for (int q = 0; q < GJB_WAVES; ++q) {
-                const double av = cand_a[buf][q];
-                const int i = cand_i[buf][q];
-                if (av > top || (av == top && i < p)) { top = av; p = i; pw = q; }
-            }
-            if (!(top > 0.0) || !isfinite(top)) {  // uniform
-                singular = true;
-                if (tid == 0) s_flag = (top > 0.0) ? 2 : 1;  // infinite or zero pivot
-                break;
-            }
-            const double pv = cand_row[buf][pw][k];
-            const double inv = 1.0 / pv;
-            ld += log(fabs(pv));
-            neg += pv < 0.0;
-            if (tid == 0) perm[k0 + k] = p;
-            // pivot row: P *= 1/pv, P[k] = 1/pv; other rows: P -= f * (pivot
-            // row), P[k] = -f with f = P[k]/pv (branch-free)
-#pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                const bool piv = tid + GJB_THREADS * r == p;
-                const double f = piv ? 0.0 : x[r] * inv;
-                const double m = piv ? inv : 1.0;
-                const double pk = piv ? inv : -f;
-#pragma unroll
-                for (int q = 0; q < NB; ++q) P[r][q] = q == k ? pk : fma(-f, cand_row[buf][pw][q], P[r][q] * m);
-                if (piv) {
-                    used[r] = true;
-                    curpiv[p] = 1;
-                }
-            }
-        }
-        if (singular) break;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int b = tid + GJB_THREADS * r;
-#pragma unroll
-            for (int k = 0; k < NB; ++k)
-                if (b < n && k < kn) Mq((uint32_t)((k0 + k) * nv + b)) = P[r][k];
-        }
-        __syncthreads();
-        // rank-NB update of every other column a: M[a][b] = (b pivot of this
-        // panel ? 0 : M[a][b]) + sum_k L[b][k] M[a][p_k]
-        double Lr[GJB_SPW][NB / 4];
-#pragma unroll
-        for (int t = 0; t < GJB_SPW; ++t) {
-            const int bc = 16 * (wave + GJB_WAVES * t) + (lane & 15);
-            const int bl = min(bc, n - 1);
-#pragma unroll
-            for (int ks = 0; ks < NB / 4; ++ks) {
-                const int k = 4 * ks + (lane >> 4);
-                const double v = Mq((uint32_t)((k0 + min(k, kn - 1)) * nv + bl));
-                Lr[t][ks] = (bc < n && k < kn) ? v : 0.0;
-            }
-        }
-        int tb = 0;
-#pragma unroll 1
-        for (int jt = 0; jt < ns; ++jt) {
-            const int a0 = 16 * jt;
-            if (a0 >= k0 && a0 < k0 + NB) continue;  // the panel itself
-            int nt = nv;
-            asm volatile("" : "+s"(nt));
-            for (int q = tid; q < 16 * NB; q += GJB_THREADS) {
-                const int jj = q / NB, k = q % NB;
-                const int a = a0 + jj;
-                const double v = Mq((uint32_t)(min(a, n - 1) * nt + perm[k0 + min(k, kn - 1)]));
-                Tt[tb][jj][k] = (a < n && k < kn) ? v : 0.0;
-            }
-            __syncthreads();
-            double aop[NB / 4];
-#pragma unroll
-            for (int ks = 0; ks < NB / 4; ++ks) aop[ks] = Tt[tb][lane & 15][4 * ks + (lane >> 4)];
-#pragma unroll
-            for (int t = 0; t < GJB_SPW; ++t) {
-                const int st = wave + GJB_WAVES * t;
-                if (st >= ns) continue;
-                const int bc = 16 * st + (lane & 15);
-                const int bl = min(bc, n - 1);
-                const bool keep = bc < n && !curpiv[bl];
-                f64x4 acc;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int a = a0 + (lane >> 4) + 4 * r;
-                    const double v = Mq((uint32_t)(min(a, n - 1) * nt + bl));
-                    acc[r] = (a < n && keep) ? v : 0.0;
-                }
-#pragma unroll
-                for (int ks = 0; ks < NB / 4; ++ks)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[ks], Lr[t][ks], acc, 0, 0, 0);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int a = a0 + (lane >> 4) + 4 * r;
-                    if (a < n && bc < n) Mq((uint32_t)(a * nt + bc)) = acc[r];
-                }
-            }
-            tb ^= 1;
-        }
-        __syncthreads();
-        for (int q = tid; q < GJ_NMAX; q += GJB_THREADS) curpiv[q] = 0;
-    }
-    __syncthreads();
-    if (singular) {
-        for (size_t q = tid; q < nn; q += GJB_THREADS) Dw[q] = __longlong_as_double(0x7ff8000000000000ll);
-        if (tid == 0) {
-            if (j.logdet) j.logdet[2 * w + spin] = s_flag == 1 ? -INFINITY : __longlong_as_double(0x7ff8000000000000ll);
-            if (j.sign) j.sign[2 * w + spin] = 0;
-            if (j.status) atomicOr(j.status + w, s_flag == 1 ? QSL_STATUS_SINGULAR : QSL_STATUS_NONFINITE);
-        }
-        return;
-    }
-    for (int q = tid; q < n; q += GJB_THREADS) invp[perm[q]] = q;
-    __syncthreads();
-    if (tid == 0) {
-        // parity of the pivot permutation by cycle counting (curpiv as marks)
-        int cycles = 0;
-        for (int i = 0; i < n; ++i) {
-            if (curpiv[i]) continue;
-            ++cycles;
-            for (int q = i; !curpiv[q]; q = perm[q]) curpiv[q] = 1;
-        }
-        const int sg = ((neg + n - cycles) & 1) ? -1 : 1;
-        if (j.logdet) j.logdet[2 * w + spin] = ld;
-        if (j.sign) j.sign[2 * w + spin] = (int8_t)sg;
-        if (j.status && !isfinite(ld)) atomicOr(j.status + w, QSL_STATUS_NONFINITE);
-    }
-    // D^-1[e][i] = M[invp(i)][p_e], i.e. D^-1[invp(b)][p_a] = M[a][b]
-    for (size_t q = tid; q < nn; q += GJB_THREADS) {
-        const int a = (int)(q / n), bb = (int)(q % n);
-        Dw[(size_t)invp[bb] * n + perm[a]] = M[q];
-    }
-}
-
-template <typename Tin>
-__global__ __launch_bounds__(GJB_THREADS) void gjb_kernel(Job j) {
-    gjb_body<Tin>(j, blockIdx.x);
-}
-
-template <typename Tin>
-__global__ __launch_bounds__(GJB_THREADS) void gjb_batched(const Job* jobs, const int* prefix, int njobs) {
-    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gjb_body<Tin>(j, bx); });
-}
-
 __global__ void empty_spin_kernel(int64_t W, int spin, double* logdet, int8_t* sign) {
     int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w < W) {
@@ -586,7 +288,7 @@ __global__ void empty_spin_kernel(int64_t W, int spin, double* logdet, int8_t* s
 // Variants by matrix size: register-resident 0: n <= 32, 1: <= 64,
 // 2: <= 128, 3: <= 224; 4: blocked, n <= 1024.
 int gj_variant(int n) { return n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : n <= GJ_REG_NMAX ? 3 : 4; }
-int gj_threads(int v) { return v == 0 ? 128 : v == 1 ? 256 : v < 4 ? 512 : GJB_THREADS; }
+int gj_threads(int v) { return v == 0 ? 128 : v == 1 ? 256 : 512; }
 int gj_job_variant(const Job& j) {
     const int v = gj_variant(j.n);
     return v == 4 ? 4 : std::min(3, v + std::max(0, j.gj_bias));
@@ -605,11 +307,7 @@ static hipError_t gj_dispatch(const Job& j, int v, bool batched, const Job* jobs
         case 0: QSL_GJ(2, 1, 16); break;
         case 1: QSL_GJ(4, 1, 16); break;
         case 2: QSL_GJ(8, 2, 16); break;
-        case 3: QSL_GJ(8, 4, 28); break;
-        default:
-            if (batched) gjb_batched<Tin><<<g, GJB_THREADS, 0, st>>>(jobs, prefix, njobs);
-            else gjb_kernel<Tin><<<g, GJB_THREADS, 0, st>>>(j);
-            break;
+        default: QSL_GJ(8, 4, 28); break;
     }
 #undef QSL_GJ
     return hipGetLastError();
@@ -625,15 +323,17 @@ hipError_t launch_gj(const Job& j0, hipStream_t st) {
     }
     if (j.n > GJ_NMAX) return hipErrorInvalidValue;
     const int v = gj_job_variant(j);
+    if (v == 4) return launch_gjb(j, st);
     if (j.mode == QSL_FP64) return gj_dispatch<double>(j, v, false, nullptr, nullptr, 0, 0, st);
     return gj_dispatch<float>(j, v, false, nullptr, nullptr, 0, 0, st);
 }
 
 // One batched launch of GJ variant v over Jobs whose n all fit it (the
-// plan launches each variant present in its batch once).
+// plan launches each variant present in its batch once; the blocked
+// variant 4 is a sequence of launches over panels, see qsl_gjb.hip).
 hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix, int njobs, int grid,
                              hipStream_t st) {
-    if (v < 0 || v > 4) return hipErrorInvalidValue;
+    if (v < 0 || v > 3) return hipErrorInvalidValue;
     if (grid <= 0) return hipSuccess;
     Job dummy{};
     if (mode == QSL_FP64) return gj_dispatch<double>(dummy, v, true, jobs, prefix, njobs, grid, st);

@@ -141,7 +141,7 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
     for (int s = 0; s < 2; ++s) {
         const size_t n = (size_t)n_spin(d, s);
         L.gj_off[s] = off;
-        if (n > (size_t)GJ_REG_NMAX) off = round_up(off + (size_t)W * n * n * sizeof(double), 256);
+        if (n > (size_t)GJ_REG_NMAX) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
     }
     L.total = std::max<size_t>(off, 256);
     return L;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/qslater.h"
@@ -20,6 +21,15 @@ constexpr int WIN = 8;
 // Largest Slater matrix inverted in registers by one workgroup.
 constexpr int GJ_REG_NMAX = 224;   // largest n of the register-resident inversion
 constexpr int GJ_NMAX = 1024;      // largest n of the blocked inversion
+constexpr int GJ_PANEL = 32;       // panel width of the blocked inversion
+// Blocked inversion workspace per matrix: the copy of D with rows padded to
+// gj_ld(n) doubles (128-byte aligned rows), the pivot rows of one panel,
+// the pivot order, row flags and state; a multiple of 16 doubles.
+__host__ __device__ inline int gj_ld(int n) { return (n + 15) & ~15; }
+__host__ __device__ inline size_t gj_ws_doubles(int n) {
+    const size_t ld = (size_t)gj_ld(n);
+    return (ld * n + ld * GJ_PANEL + ((size_t)5 * n + 40) / 8 + 15) & ~(size_t)15;
+}
 
 // Device view of a system, passed to kernels by value.
 struct DevSys {
@@ -173,7 +183,7 @@ struct Job {
     double* dR;
     double* dA64;
     float* dA32;
-    double* gjws;            // blocked inversion (n > GJ_REG_NMAX): [W][n][n] copy of D
+    double* gjws;            // blocked inversion (n > GJ_REG_NMAX): W x gj_ws_doubles(n)
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 
@@ -201,6 +211,38 @@ __device__ __forceinline__ void batch_block(const Job* __restrict__ jobs, const 
     const Job& j = jobs[ji];
     const int lb = b - prefix[ji];
     body(j, lb % j.gx, (lb / j.gx) % j.gy, lb / (j.gx * j.gy));
+}
+
+// Compile-time loop: f(integral_constant<int, I>) for I in [I0, N).
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+// Wavefront helpers of the pivot searches.
+__device__ __forceinline__ double readlane_f64(double x, int lane) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_update_dpp(0u, (uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = __builtin_amdgcn_update_dpp(0u, (uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((uint64_t)hi << 32) | lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double& best, int& bi) {
+    const double ob = dpp_f64<CTRL>(best);
+    const int oi = __builtin_amdgcn_update_dpp(0, bi, CTRL, 0xf, 0xf, false);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
 }
 
 // Timing of kernel launches with HIP events (enabled by qsl_profile_enable).
@@ -254,7 +296,12 @@ hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix,
 // block shape depends on n, so a batched launch serves one variant).
 int gj_variant(int n);
 int gj_threads(int v);
-int gj_job_variant(const Job& j);  // gj_variant(n) + gj_bias, clamped
+int gj_job_variant(const Job& j);  // gj_variant(n) + gj_bias, clamped; 4 = blocked
+// Blocked inversion (variant 4, 224 < n <= 1024): the launch sequence of one
+// Job, or of the Jobs of a plan (prefix counts matrices, nmax = largest n).
+hipError_t launch_gjb(const Job& j, hipStream_t st);
+hipError_t launch_gjb_batched(int mode, const Job* jobs, const int* prefix, int njobs, int matrices, int nmax,
+                              hipStream_t st);
 hipError_t launch_gj(const Job& j, hipStream_t st);
 hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix, int njobs, int grid,
                              hipStream_t st);

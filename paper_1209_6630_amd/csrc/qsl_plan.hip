@@ -253,9 +253,16 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             auto& G = p->ph[PH_GJ0 + v];
             if (!G.blocks()) continue;
             ProfScope ps("gauss_jordan", st);
-            if ((e = launch_gj_batched(mode, v, dev_jobs(p, PH_GJ0 + v), dev_prefix(p, PH_GJ0 + v),
-                                       (int)G.jobs.size(), G.blocks(), st)) != hipSuccess)
-                return hip_fail(e, "inversion kernel");
+            if (v == 4) {
+                int nmax = 0;
+                for (const Job& j : G.jobs) nmax = std::max(nmax, j.n);
+                e = launch_gjb_batched(mode, dev_jobs(p, PH_GJ4), dev_prefix(p, PH_GJ4), (int)G.jobs.size(),
+                                       G.blocks(), nmax, st);
+            } else {
+                e = launch_gj_batched(mode, v, dev_jobs(p, PH_GJ0 + v), dev_prefix(p, PH_GJ0 + v),
+                                      (int)G.jobs.size(), G.blocks(), st);
+            }
+            if (e != hipSuccess) return hip_fail(e, "inversion kernel");
         }
     } else {
         for (const Job& j : p->ph[PH_SCREEN].jobs) {
