@@ -62,11 +62,20 @@ __device__ __forceinline__ void mma_f(Blk<MODE>& acc, int k0, int k1, int lane, 
         f32x16 a16;
 #pragma unroll
         for (int q = 0; q < 16; ++q) a16[q] = acc.v[q];
+        // two interleaved accumulators: consecutive MFMAs are independent
+        f32x16 b16;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) b16[q] = 0.f;
         const int kk = lane >> 5, rc = lane & 31;
-        for (int k = k0; k < k1; k += 2)
+        int k = k0;
+        for (; k + 2 < k1; k += 4) {
+            a16 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa(rc, k + kk), fb(k + kk, rc), a16, 0, 0, 0);
+            b16 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa(rc, k + 2 + kk), fb(k + 2 + kk, rc), b16, 0, 0, 0);
+        }
+        for (; k < k1; k += 2)
             a16 = __builtin_amdgcn_mfma_f32_32x32x2f32(fa(rc, k + kk), fb(k + kk, rc), a16, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc.v[q] = a16[q];
+        for (int q = 0; q < 16; ++q) acc.v[q] = a16[q] + b16[q];
     } else {
         f64x4 a4[2][2];
 #pragma unroll
@@ -114,6 +123,49 @@ __device__ __forceinline__ void window_values(const DevSys& s, int q, const doub
         slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, gg, g1, g2, v);
 #pragma unroll
         for (int d = 0; d < 4; ++d) vals[d][j] = v[d];
+    }
+}
+
+// AO values only (no derivatives) of one electron at the 8 slots of window
+// q: the radial sum over the kept primitives times the Cartesian monomial.
+template <typename T>
+__device__ __forceinline__ void window_values0(const DevSys& s, int q, const double r[3], T vals[WIN]) {
+#pragma unroll
+    for (int j = 0; j < WIN; ++j) vals[j] = T(0);
+    if (q < 0) return;
+    const int at = s.win_atom[q];
+    const double dx = r[0] - s.atom_xyz[3 * at];
+    const double dy = r[1] - s.atom_xyz[3 * at + 1];
+    const double dz = r[2] - s.atom_xyz[3 * at + 2];
+    const double r2 = dist2_exact(dx, dy, dz);
+    const T X = (T)dx, Y = (T)dy, Z = (T)dz;
+    int prev = -1;
+    T gg = 0;
+#pragma unroll
+    for (int j = 0; j < WIN; ++j) {
+        const int slot = q * WIN + j;
+        const int sh = s.slot_shell[slot];
+        if (sh < 0) continue;
+        if (sh != prev) {
+            const int p0 = s.shell_p0[sh], np = s.shell_np[sh];
+            gg = T(0);
+            for (int k = 0; k < np; ++k) {
+                const double t = __dmul_rn(s.prim_exp[p0 + k], r2);
+                if (t <= s.T) {
+                    T c;
+                    if constexpr (sizeof(T) == 8) c = (T)s.prim_c64[p0 + k];
+                    else c = s.prim_c32[p0 + k];
+                    gg += c * exp_t(-(T)t);
+                }
+            }
+            prev = sh;
+        }
+        const int pw = s.slot_pow[slot];
+        const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
+        const T px = a == 0 ? T(1) : (a == 1 ? X : X * X);
+        const T py = b == 0 ? T(1) : (b == 1 ? Y : Y * Y);
+        const T pz = c == 0 ? T(1) : (c == 1 ? Z : Z * Z);
+        vals[j] = (T)s.slot_f[slot] * px * py * pz * gg;
     }
 }
 
@@ -180,7 +232,9 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
     }
     const int nwin = tile_nwin[tile];
     const int* wins = tile_win + (size_t)tile * s.n_win;
-    T dr = 0;  // tid < 96: (electron tid % 32, component tid / 32)
+    // dR partial sums: thread (electron tid % 32, slot group tid / 32 of 8
+    // slots per chunk), three components; reduced over the groups at the end
+    T dr[3] = {0, 0, 0};
 
     for (int c0 = 0; c0 < nwin; c0 += AH_KW) {
         __syncthreads();
@@ -203,9 +257,10 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
             Blk<MODE> acc;
             acc.zero();
             if constexpr (BF) {
-                f32x16 a16;
+                // the three products in three accumulators (independent chains)
+                f32x16 a16, b16, c16;
 #pragma unroll
-                for (int q = 0; q < 16; ++q) a16[q] = 0.f;
+                for (int q = 0; q < 16; ++q) a16[q] = b16[q] = c16[q] = 0.f;
                 const int c = nb * 32 + (lane & 31);
                 const int qc = wq[c / WIN] < 0 ? 0 : wq[c / WIN];
                 const size_t wbase = (size_t)qc * (ldn / 8);
@@ -219,11 +274,11 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
                     const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(Gh + off));
                     const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(Gl + off));
                     a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a16, 0, 0, 0);
-                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, a16, 0, 0, 0);
-                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, a16, 0, 0, 0);
+                    b16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, b16, 0, 0, 0);
+                    c16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c16, 0, 0, 0);
                 }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) acc.v[q] = a16[q];
+                for (int q = 0; q < 16; ++q) acc.v[q] = a16[q] + (b16[q] + c16[q]);
             } else {
                 int slotc[2];
 #pragma unroll
@@ -243,17 +298,31 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
             for (int q = 0; q < 16; ++q) Hb[kh][Blk<MODE>::row(q, lane)][nb * 32 + Blk<MODE>::col(q, lane)] = acc.v[q];
         }
         __syncthreads();
-        if (tid < 96) {
-            const int e = tid & (TE - 1), comp = tid >> 5;
-            T acc = 0;
-#pragma unroll 8
-            for (int c = 0; c < AH_KC; ++c) acc += (Hb[0][e][c] + Hb[1][e][c]) * dX[comp][e][c];
-            dr += acc;
+        {
+            const int e = tid & (TE - 1), cb = (tid >> 5) * (AH_KC / (AH_THREADS / TE));
+#pragma unroll
+            for (int c = cb; c < cb + AH_KC / (AH_THREADS / TE); ++c) {
+                const T h = Hb[0][e][c] + Hb[1][e][c];
+#pragma unroll
+                for (int comp = 0; comp < 3; ++comp) dr[comp] += h * dX[comp][e][c];
+            }
         }
     }
-    if (tid < 96 && dR) {
+    // reduce the slot groups (dX is free now) and add to dR
+    __syncthreads();
+    T* red = &dX[0][0][0];  // [3][groups][TE]
+    {
+        const int e = tid & (TE - 1), grp = tid >> 5;
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) red[(comp * (AH_THREADS / TE) + grp) * TE + e] = dr[comp];
+    }
+    __syncthreads();
+    if (tid < 3 * TE && dR) {
         const int e = tid & (TE - 1), comp = tid >> 5;
-        if (e < ne) atomicAdd(dR + ((size_t)w * N + eoff + e0 + e) * 3 + comp, (double)dr);
+        T acc = 0;
+#pragma unroll
+        for (int grp = 0; grp < AH_THREADS / TE; ++grp) acc += red[(comp * (AH_THREADS / TE) + grp) * TE + e];
+        if (e < ne) atomicAdd(dR + ((size_t)w * N + eoff + e0 + e) * 3 + comp, (double)acc);
     }
 }
 
@@ -319,10 +388,107 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     T* Xt = (T*)xbuf;
 
     if (tid < NWB) wq[tid] = tid < nq ? grp_win[(size_t)grp * s.n_win + q0 + tid] : -1;
+    // the block's windows are the same for every walker of the group: stage
+    // their atom positions, slot monomials and shell primitives in LDS once
+    constexpr int SPW = WIN;  // local shells per window (shells are consecutive slots)
+    __shared__ double lw_pos[NWB][3];
+    __shared__ int lw_pow[NWB][WIN];     // a | b<<4 | c<<8, -1 for padding
+    __shared__ T lw_f[NWB][WIN];
+    __shared__ int8_t lw_sh[NWB][WIN];   // local shell of the slot
+    __shared__ int8_t lw_np[NWB][SPW];
+    __shared__ double lw_exp[NWB][SPW][QSL_PMAX];
+    __shared__ T lw_c[NWB][SPW][QSL_PMAX];
+    __syncthreads();
+    for (int p = tid; p < NWB * WIN; p += AD_THREADS) {
+        const int wli = p / WIN, jj = p % WIN;
+        const int q = wq[wli];
+        int pw = -1, lsh = 0;
+        T f = T(0);
+        if (q >= 0) {
+            const int slot = q * WIN + jj;
+            const int sh = s.slot_shell[slot];
+            if (sh >= 0) {
+                pw = s.slot_pow[slot] & 0xfff;
+                f = (T)s.slot_f[slot];
+                lsh = sh - s.slot_shell[q * WIN];
+            }
+            if (jj == 0) {
+                const int at = s.win_atom[q];
+                for (int k = 0; k < 3; ++k) lw_pos[wli][k] = s.atom_xyz[3 * at + k];
+            }
+            // local shell jj of the window (if it exists)
+            const int shl = s.slot_shell[q * WIN] + jj;
+            int np = 0;
+            if (shl < s.n_shells && s.win_atom[q] == s.shell_atom[shl]) {
+                np = s.shell_np[shl];
+                const int p0 = s.shell_p0[shl];
+                for (int k = 0; k < np; ++k) {
+                    lw_exp[wli][jj][k] = s.prim_exp[p0 + k];
+                    if constexpr (sizeof(T) == 8) lw_c[wli][jj][k] = (T)s.prim_c64[p0 + k];
+                    else lw_c[wli][jj][k] = s.prim_c32[p0 + k];
+                }
+            }
+            lw_np[wli][jj] = (int8_t)np;
+        }
+        lw_pow[wli][jj] = pw;
+        lw_f[wli][jj] = f;
+        lw_sh[wli][jj] = (int8_t)lsh;
+    }
+    // AO values of one electron at the 8 slots of block window wli, from LDS
+    auto win_vals = [&](int wli, const double r[3], T vals[WIN]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
+        if (wq[wli] < 0) return;
+        const double dx = r[0] - lw_pos[wli][0], dy = r[1] - lw_pos[wli][1], dz = r[2] - lw_pos[wli][2];
+        const double r2 = dist2_exact(dx, dy, dz);
+        const T X = (T)dx, Y = (T)dy, Z = (T)dz;
+        int prev = -1;
+        T gg = 0;
+#pragma unroll
+        for (int jj = 0; jj < WIN; ++jj) {
+            const int pw = lw_pow[wli][jj];
+            if (pw < 0) continue;
+            const int ls = lw_sh[wli][jj];
+            if (ls != prev) {
+                gg = T(0);
+                const int np = lw_np[wli][ls];
+                for (int k = 0; k < np; ++k) {
+                    const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
+                    if (t <= s.T) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
+                }
+                prev = ls;
+            }
+            const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
+            const T px = a == 0 ? T(1) : (a == 1 ? X : X * X);
+            const T py = b == 0 ? T(1) : (b == 1 ? Y : Y * Y);
+            const T pz = c == 0 ? T(1) : (c == 1 ? Z : Z * Z);
+            vals[jj] = lw_f[wli][jj] * px * py * pz * gg;
+        }
+    };
     Blk<MODE> acc[PB];
 #pragma unroll
     for (int k = 0; k < PB; ++k) acc[k].zero();
 
+    // D^-1 block of the next walker, loaded while the current one is used
+    constexpr int GPT = (TE * ADJ_MB + AD_THREADS - 1) / AD_THREADS;
+    double gpre[GPT];
+    double gnext = 0.0;
+    auto load_g = [&](int w) {
+        gnext = g[2 * w + spin];
+        // uniform base + 32-bit byte offsets (the block spans < 2^32 bytes)
+        const char* Db = (const char*)(Dinv + ((size_t)w * n + e0) * n + i0);
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) {
+            const int q = tid + k * AD_THREADS;
+            const int e = q / ADJ_MB, ii = q % ADJ_MB;
+            const bool ok = q < TE * ADJ_MB && e < ne && i0 + ii < n;
+            const uint32_t off = ok ? (uint32_t)(e * n + ii) * 8u : 0u;
+            const double x = *(const double*)(Db + off);
+            gpre[k] = ok ? x : 0.0;
+        }
+    };
+    constexpr bool PF = MODE != QSL_FP64;  // FP64: no registers to spare for the prefetch
+    if constexpr (PF) load_g(w0);
     for (int wl = 0; wl < nw; ++wl) {
         const int w = w0 + wl;
         __syncthreads();  // previous walker's operands are consumed
@@ -330,11 +496,14 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const int e = tid / 3, k = tid % 3;
             epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
         }
-        const double gwv = g[2 * w + spin];
-        for (int q = tid; q < TE * ADJ_MB; q += AD_THREADS) {
+        if constexpr (!PF) load_g(w);
+        const double gwv = gnext;
+#pragma unroll
+        for (int k = 0; k < GPT; ++k) {
+            const int q = tid + k * AD_THREADS;
+            if (q >= TE * ADJ_MB) continue;
             const int e = q / ADJ_MB, ii = q % ADJ_MB;
-            double v = 0.0;
-            if (gwv != 0.0 && e < ne && i0 + ii < n) v = gwv * Dinv[((size_t)w * n + e0 + e) * n + i0 + ii];
+            const double v = gwv != 0.0 ? gwv * gpre[k] : 0.0;
             if constexpr (BF) {
                 const float f = (float)v;
                 const uint16_t h = bf16_rne(f);
@@ -344,22 +513,29 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                 GTt[ii * LDGT + e] = (T)v;
             }
         }
+        if constexpr (PF) {
+            if (wl + 1 < nw) load_g(w + 1);
+        }
         __syncthreads();
         // AO values of (electron, window) into LDS
         for (int p = tid; p < TE * NWB; p += AD_THREADS) {
             const int e = p & (TE - 1), wli = p / TE;
-            T vals[4][WIN];
+            T vals[WIN];
             const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-            window_values<T>(s, e < ne ? wq[wli] : -1, r, vals);
+            if (e < ne) win_vals(wli, r, vals);
+            else {
+#pragma unroll
+                for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
+            }
 #pragma unroll
             for (int j = 0; j < WIN; ++j) {
                 const int c = wli * WIN + j;
                 if constexpr (BF) {
-                    const uint16_t h = bf16_rne(vals[0][j]);
+                    const uint16_t h = bf16_rne(vals[j]);
                     Xh[c * LDX + e] = h;
-                    Xl[c * LDX + e] = bf16_rne(vals[0][j] - bf16_to_f(h));
+                    Xl[c * LDX + e] = bf16_rne(vals[j] - bf16_to_f(h));
                 } else {
-                    Xt[e * LDX + c] = vals[0][j];
+                    Xt[e * LDX + c] = vals[j];
                 }
             }
         }
@@ -371,9 +547,12 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const int ib = b / SB, sb = b % SB;
             if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
             if constexpr (BF) {
-                f32x16 a16;
+                f32x16 a16, b16, c16;  // three independent chains
 #pragma unroll
-                for (int q = 0; q < 16; ++q) a16[q] = acc[k].v[q];
+                for (int q = 0; q < 16; ++q) {
+                    a16[q] = acc[k].v[q];
+                    b16[q] = c16[q] = 0.f;
+                }
                 const int oct = lane >> 5;
 #pragma unroll
                 for (int k0 = 0; k0 < TE; k0 += 16) {
@@ -384,11 +563,11 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                     const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(Xh + offb));
                     const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(Xl + offb));
                     a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a16, 0, 0, 0);
-                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, a16, 0, 0, 0);
-                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, a16, 0, 0, 0);
+                    b16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, b16, 0, 0, 0);
+                    c16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c16, 0, 0, 0);
                 }
 #pragma unroll
-                for (int q = 0; q < 16; ++q) acc[k].v[q] = a16[q];
+                for (int q = 0; q < 16; ++q) acc[k].v[q] = a16[q] + (b16[q] + c16[q]);
             } else {
                 auto fa = [&](int r, int kk) -> T { return GTt[(ib * 32 + r) * LDGT + kk]; };
                 auto fb = [&](int kk, int cc) -> T { return Xt[kk * LDX + sb * 32 + cc]; };

@@ -23,21 +23,23 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
-constexpr int CT_THREADS = 256;
-
-template <int MODE>
+template <int MODE, int NWAVE>
 struct CT {
-    // windows per chunk, MO columns per wave
+    // windows per chunk, MO columns per wave, MO columns per workgroup
     static constexpr int KW = MODE == QSL_FP64 ? 4 : 8;
     static constexpr int KC = KW * WIN;
     static constexpr int NBW = MODE == QSL_FP64 ? 16 : 32;
-    static constexpr int NB = 4 * NBW;
+    static constexpr int NB = NWAVE * NBW;
+    static constexpr int THREADS = NWAVE * 64;
+    // AO evaluation: slots of one window per thread (8, or 4 when the
+    // workgroup has twice as many threads as (electron, window) pairs)
+    static constexpr int SPT = THREADS >= 2 * TE * KW ? WIN / 2 : WIN;
     using T = typename std::conditional<MODE == QSL_FP64, double, float>::type;
     // LDS row stride (elements) of one electron's chunk of B
     static constexpr int LD = MODE == QSL_BF16X3 ? KC + 8 : (MODE == QSL_FP32 ? KC + 4 : KC + 2);
 };
 
-template <int MODE>
+template <int MODE, int NWAVE>
 __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
@@ -51,9 +53,9 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const uint16_t* __restrict__ Alo = j.mo.Alo;
     void* __restrict__ Cout = j.C;
     uint32_t* __restrict__ status = j.status;
-    using P = CT<MODE>;
+    using P = CT<MODE, NWAVE>;
     using T = typename P::T;
-    constexpr int KW = P::KW, KC = P::KC, LD = P::LD;
+    constexpr int KW = P::KW, KC = P::KC, LD = P::LD, SPT = P::SPT;
 
     __shared__ double epos[TE][3];
     __shared__ int wq[KW];
@@ -93,14 +95,17 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     __syncthreads();
 
     for (int c0 = 0; c0 < nwin; c0 += KW) {
-        // ---- phase R: AO values of (electron e, window wl) into LDS
-        if (tid < TE * KW) {
-            const int e = tid & (TE - 1), wl = tid / TE;
+        // ---- phase R: AO values of (electron e, window wl, slots js..js+SPT)
+        // into LDS
+        if (tid < TE * KW * (WIN / SPT)) {
+            const int e = tid & (TE - 1), wl = (tid / TE) % KW, js = (tid / (TE * KW)) * SPT;
             const int q = c0 + wl < nwin ? wins[c0 + wl] : -1;
-            if (e == 0) wq[wl] = q < 0 ? 0 : q;
-            T vals[5][WIN];
+            if (e == 0 && js == 0) wq[wl] = q < 0 ? 0 : q;
+            T vals[5][SPT];
+#pragma unroll
             for (int d = 0; d < 5; ++d)
-                for (int j = 0; j < WIN; ++j) vals[d][j] = T(0);
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) vals[d][j] = T(0);
             if (q >= 0 && e < ne) {
                 const int at = s.win_atom[q];
                 const double dx = epos[e][0] - s.atom_xyz[3 * at];
@@ -109,8 +114,9 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 const double r2 = dist2_exact(dx, dy, dz);
                 int prev = -1;
                 T g = 0, g1 = 0, g2 = 0;
-                for (int j = 0; j < WIN; ++j) {
-                    const int slot = q * WIN + j;
+#pragma unroll
+                for (int j = 0; j < SPT; ++j) {
+                    const int slot = q * WIN + js + j;
                     const int sh = s.slot_shell[slot];
                     if (sh < 0) continue;
                     if (sh != prev) {
@@ -119,30 +125,34 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                     }
                     T v[5];
                     slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, g, g1, g2, v);
+#pragma unroll
                     for (int d = 0; d < 5; ++d) vals[d][j] = v[d];
                 }
             }
             if constexpr (MODE == QSL_BF16X3) {
                 uint16_t* bh = (uint16_t*)bbuf;
                 uint16_t* bl = bh + BELEMS;
+#pragma unroll
                 for (int d = 0; d < 5; ++d) {
-                    uint16_t h[WIN], lo[WIN];
-                    for (int j = 0; j < WIN; ++j) {
-                        h[j] = bf16_rne(vals[d][j]);
-                        lo[j] = bf16_rne(vals[d][j] - bf16_to_f(h[j]));
+                    uint32_t hv[SPT / 2], lv[SPT / 2];
+#pragma unroll
+                    for (int p = 0; p < SPT / 2; ++p) bf16_split2(vals[d][2 * p], vals[d][2 * p + 1], hv[p], lv[p]);
+                    uint16_t* ph = bh + (d * TE + e) * LD + wl * WIN + js;
+                    uint16_t* pl = bl + (d * TE + e) * LD + wl * WIN + js;
+                    if constexpr (SPT == WIN) {
+                        *(uint4*)ph = uint4{hv[0], hv[1], hv[2], hv[3]};
+                        *(uint4*)pl = uint4{lv[0], lv[1], lv[2], lv[3]};
+                    } else {
+                        *(uint2*)ph = uint2{hv[0], hv[1]};
+                        *(uint2*)pl = uint2{lv[0], lv[1]};
                     }
-                    uint4 hv, lv;
-                    hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
-                    hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
-                    lv.x = lo[0] | ((uint32_t)lo[1] << 16); lv.y = lo[2] | ((uint32_t)lo[3] << 16);
-                    lv.z = lo[4] | ((uint32_t)lo[5] << 16); lv.w = lo[6] | ((uint32_t)lo[7] << 16);
-                    *(uint4*)(bh + (d * TE + e) * LD + wl * WIN) = hv;
-                    *(uint4*)(bl + (d * TE + e) * LD + wl * WIN) = lv;
                 }
             } else {
                 T* bt = (T*)bbuf;
+#pragma unroll
                 for (int d = 0; d < 5; ++d)
-                    for (int j = 0; j < WIN; ++j) bt[(d * TE + e) * LD + wl * WIN + j] = vals[d][j];
+#pragma unroll
+                    for (int j = 0; j < SPT; ++j) bt[(d * TE + e) * LD + wl * WIN + js + j] = vals[d][j];
             }
         }
         __syncthreads();
@@ -159,14 +169,21 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 const uint4 al = *(const uint4*)(Alo + off);
                 const bf16x8 bah = __builtin_bit_cast(bf16x8, ah);
                 const bf16x8 bal = __builtin_bit_cast(bf16x8, al);
+                bf16x8 xh[5], xl[5];
+#pragma unroll
                 for (int d = 0; d < 5; ++d) {
                     const int off = (d * TE + (lane & 31)) * LD + ks * 16 + oct * 8;
-                    const bf16x8 xh = __builtin_bit_cast(bf16x8, *(const uint4*)(bh + off));
-                    const bf16x8 xl = __builtin_bit_cast(bf16x8, *(const uint4*)(bl + off));
-                    acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bah, acc32[d], 0, 0, 0);
-                    acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh, bal, acc32[d], 0, 0, 0);
-                    acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl, bah, acc32[d], 0, 0, 0);
+                    xh[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bh + off));
+                    xl[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bl + off));
                 }
+                // the three products of one accumulator are dependent: issue
+                // them five accumulators apart
+#pragma unroll
+                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bah, acc32[d], 0, 0, 0);
+#pragma unroll
+                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bal, acc32[d], 0, 0, 0);
+#pragma unroll
+                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[d], bah, acc32[d], 0, 0, 0);
             }
         } else if constexpr (MODE == QSL_FP32) {
             const float* bt = (const float*)bbuf;
@@ -226,19 +243,24 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(CT_THREADS) void contract_kernel(Job j) {
-    contract_body<MODE>(j, blockIdx.x, blockIdx.y);
+template <int MODE, int NWAVE>
+__global__ __launch_bounds__(NWAVE * 64) void contract_kernel(Job j) {
+    contract_body<MODE, NWAVE>(j, blockIdx.x, blockIdx.y);
 }
 
-template <int MODE>
-__global__ __launch_bounds__(CT_THREADS) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
-    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { contract_body<MODE>(j, bx, by); });
+template <int MODE, int NWAVE>
+__global__ __launch_bounds__(NWAVE * 64) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs,
+                [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE, NWAVE>(j, bx, by); });
 }
+
+// Waves per workgroup: 8 (256 MO columns, one AO evaluation for twice the
+// products) for the FP32 and split-BF16 modes when n > 128, else 4.
+int contract_waves(int mode, int n) { return mode != QSL_FP64 && n > 128 ? 8 : 4; }
 
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
-    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : CT<QSL_FP32>::NB;
+    const int nb = (j.mode == QSL_FP64 ? 16 : 32) * contract_waves(j.mode, j.n);
     j.gx = (int)(j.W * tiles_per_walker(j.n));
     j.gy = (j.n + nb - 1) / nb;
     j.gz = 1;
@@ -249,17 +271,22 @@ hipError_t launch_contract(const Job& j0, hipStream_t st) {
     contract_grid(j);
     if (!j.n || !j.W) return hipSuccess;
     const dim3 g((unsigned)j.gx, j.gy);
-    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64><<<g, CT_THREADS, 0, st>>>(j);
-    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32><<<g, CT_THREADS, 0, st>>>(j);
-    else contract_kernel<QSL_BF16X3><<<g, CT_THREADS, 0, st>>>(j);
+    const bool wide = contract_waves(j.mode, j.n) == 8;
+    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64, 4><<<g, 256, 0, st>>>(j);
+    else if (j.mode == QSL_FP32 && wide) contract_kernel<QSL_FP32, 8><<<g, 512, 0, st>>>(j);
+    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32, 4><<<g, 256, 0, st>>>(j);
+    else if (wide) contract_kernel<QSL_BF16X3, 8><<<g, 512, 0, st>>>(j);
+    else contract_kernel<QSL_BF16X3, 4><<<g, 256, 0, st>>>(j);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
-                                      hipStream_t st) {
-    if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
-    else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
-    else contract_batched<QSL_BF16X3><<<grid, CT_THREADS, 0, st>>>(jobs, prefix, njobs);
+hipError_t launch_contract_batched(int mode, int nwave, const Job* jobs, const int* prefix, int njobs, int grid,
+                                   hipStream_t st) {
+    if (mode == QSL_FP64) contract_batched<QSL_FP64, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32 && nwave == 8) contract_batched<QSL_FP32, 8><<<grid, 512, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32) contract_batched<QSL_FP32, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    else if (nwave == 8) contract_batched<QSL_BF16X3, 8><<<grid, 512, 0, st>>>(jobs, prefix, njobs);
+    else contract_batched<QSL_BF16X3, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

@@ -125,6 +125,14 @@ __device__ __forceinline__ void shell_radial(const DevSys& s, int sh, double r2,
     }
 }
 
+// x^a, a x^(a-1) and a (a-1) x^(a-2) of one Cartesian axis, a <= 2.
+template <typename T>
+__device__ __forceinline__ void axis_pow(int a, T x, T& p, T& dp, T& d2) {
+    p = a == 0 ? T(1) : (a == 1 ? x : x * x);
+    dp = a == 0 ? T(0) : (a == 1 ? T(1) : T(2) * x);
+    d2 = a == 2 ? T(2) : T(0);
+}
+
 // Value, d/dx, d/dy, d/dz and Laplacian of the Cartesian AO in `slot`,
 // given its shell's radial sums and the displacement from its atom.
 template <typename T>
@@ -133,29 +141,39 @@ __device__ __forceinline__ void slot_values(const DevSys& s, int slot, T X, T Y,
     const int pw = s.slot_pow[slot];
     const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
     const T f = (T)s.slot_f[slot];
-    const T px[3] = {T(1), X, X * X}, py[3] = {T(1), Y, Y * Y}, pz[3] = {T(1), Z, Z * Z};
-    const T P = f * px[a] * py[b] * pz[c];
-    const T Px = a ? f * T(a) * px[a - 1] * py[b] * pz[c] : T(0);
-    const T Py = b ? f * T(b) * px[a] * py[b - 1] * pz[c] : T(0);
-    const T Pz = c ? f * T(c) * px[a] * py[b] * pz[c - 1] : T(0);
-    // l <= 2, so a second derivative of x^a is 2 when a == 2 and 0 otherwise
-    const T L = (a == 2 ? T(2) * f * py[b] * pz[c] : T(0)) + (b == 2 ? T(2) * f * px[a] * pz[c] : T(0)) +
-                (c == 2 ? T(2) * f * px[a] * py[b] : T(0));
+    T px, dx, d2x, py, dy, d2y, pz, dz, d2z;
+    axis_pow(a, X, px, dx, d2x);
+    axis_pow(b, Y, py, dy, d2y);
+    axis_pow(c, Z, pz, dz, d2z);
+    const T fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
+    const T P = fyz * px;
+    const T Px = fyz * dx, Py = fxz * dy, Pz = fxy * dz;
+    // l <= 2: at most one axis has a non-zero second derivative factor
+    const T L = d2x * fyz + d2y * fxz + d2z * fxy;
+    const T pg1 = P * g1;
     out[0] = P * g;
-    out[1] = Px * g + P * g1 * X;
-    out[2] = Py * g + P * g1 * Y;
-    out[3] = Pz * g + P * g1 * Z;
+    out[1] = Px * g + pg1 * X;
+    out[2] = Py * g + pg1 * Y;
+    out[3] = Pz * g + pg1 * Z;
     // Delta . grad P = l P for a homogeneous polynomial of degree l
-    out[4] = L * g + T(2 * l) * g1 * P + P * g2;
+    out[4] = L * g + T(2 * l) * pg1 + P * g2;
 }
 
-// bf16 round-to-nearest-even of a float, as raw bits (finite inputs).
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(r >> 16);
-}
+// bf16 round-to-nearest-even of a float, as raw bits (the gfx950 hardware
+// conversion v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint16_t bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// Split of two floats x = hi + lo with hi = bf16(x), lo = bf16(x - hi), as
+// packed bf16 pairs (first value in the low half): two packed conversions.
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
+__device__ __forceinline__ void bf16_split2(float a, float b, uint32_t& hi, uint32_t& lo) {
+    const uint32_t h = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)a, (__bf16)b});
+    const float ra = a - __uint_as_float(h << 16);
+    const float rb = b - __uint_as_float(h & 0xffff0000u);
+    hi = h;
+    lo = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)ra, (__bf16)rb});
+}
 
 // One (system, spin) unit of work of a kernel phase: everything the kernel
 // bodies read.  A per-system launch passes one Job by value; a batched
@@ -288,10 +306,13 @@ hipError_t launch_screen(const Job& j, int group, hipStream_t st);
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st);
 // Fused AO evaluation + the five AO->MO products C_n = A B_n.
+// Waves per workgroup (4 or 8) of a Job's contraction; a batched launch
+// serves Jobs of one width.
+int contract_waves(int mode, int n);
 void contract_grid(Job& j);
 hipError_t launch_contract(const Job& j, hipStream_t st);
-hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
-                                      hipStream_t st);
+hipError_t launch_contract_batched(int mode, int nwave, const Job* jobs, const int* prefix, int njobs, int grid,
+                                   hipStream_t st);
 // Gauss-Jordan inversion, log|det| and sign (one block per matrix; the
 // block shape depends on n, so a batched launch serves one variant).
 int gj_variant(int n);
