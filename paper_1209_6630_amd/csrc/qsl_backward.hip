@@ -96,79 +96,6 @@ __device__ __forceinline__ void mma_f(Blk<MODE>& acc, int k0, int k1, int lane, 
     }
 }
 
-// AO value (d = 0) and gradient (d = 1..3) of one electron at the 8 slots of
-// window q (zeros for padding slots and for q < 0).
-template <typename T>
-__device__ __forceinline__ void window_values(const DevSys& s, int q, const double r[3], T vals[4][WIN]) {
-#pragma unroll
-    for (int d = 0; d < 4; ++d)
-#pragma unroll
-        for (int j = 0; j < WIN; ++j) vals[d][j] = T(0);
-    if (q < 0) return;
-    const int at = s.win_atom[q];
-    const double dx = r[0] - s.atom_xyz[3 * at];
-    const double dy = r[1] - s.atom_xyz[3 * at + 1];
-    const double dz = r[2] - s.atom_xyz[3 * at + 2];
-    const double r2 = dist2_exact(dx, dy, dz);
-    int prev = -1;
-    T gg = 0, g1 = 0, g2 = 0;
-    bool tie = false;
-#pragma unroll
-    for (int j = 0; j < WIN; ++j) {
-        const int slot = q * WIN + j;
-        const int sh = s.slot_shell[slot];
-        if (sh < 0) continue;
-        if (sh != prev) { shell_radial<T>(s, sh, r2, gg, g1, g2, tie); prev = sh; }
-        T v[5];
-        slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, gg, g1, g2, v);
-#pragma unroll
-        for (int d = 0; d < 4; ++d) vals[d][j] = v[d];
-    }
-}
-
-// AO values only (no derivatives) of one electron at the 8 slots of window
-// q: the radial sum over the kept primitives times the Cartesian monomial.
-template <typename T>
-__device__ __forceinline__ void window_values0(const DevSys& s, int q, const double r[3], T vals[WIN]) {
-#pragma unroll
-    for (int j = 0; j < WIN; ++j) vals[j] = T(0);
-    if (q < 0) return;
-    const int at = s.win_atom[q];
-    const double dx = r[0] - s.atom_xyz[3 * at];
-    const double dy = r[1] - s.atom_xyz[3 * at + 1];
-    const double dz = r[2] - s.atom_xyz[3 * at + 2];
-    const double r2 = dist2_exact(dx, dy, dz);
-    const T X = (T)dx, Y = (T)dy, Z = (T)dz;
-    int prev = -1;
-    T gg = 0;
-#pragma unroll
-    for (int j = 0; j < WIN; ++j) {
-        const int slot = q * WIN + j;
-        const int sh = s.slot_shell[slot];
-        if (sh < 0) continue;
-        if (sh != prev) {
-            const int p0 = s.shell_p0[sh], np = s.shell_np[sh];
-            gg = T(0);
-            for (int k = 0; k < np; ++k) {
-                const double t = __dmul_rn(s.prim_exp[p0 + k], r2);
-                if (t <= s.T) {
-                    T c;
-                    if constexpr (sizeof(T) == 8) c = (T)s.prim_c64[p0 + k];
-                    else c = s.prim_c32[p0 + k];
-                    gg += c * exp_t(-(T)t);
-                }
-            }
-            prev = sh;
-        }
-        const int pw = s.slot_pow[slot];
-        const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
-        const T px = a == 0 ? T(1) : (a == 1 ? X : X * X);
-        const T py = b == 0 ? T(1) : (b == 1 ? Y : Y * Y);
-        const T pz = c == 0 ? T(1) : (c == 1 ? Z : Z * Z);
-        vals[j] = (T)s.slot_f[slot] * px * py * pz * gg;
-    }
-}
-
 // ---------------------------------------------------------------- adj_h
 
 constexpr int AH_THREADS = 256;
@@ -198,6 +125,8 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
     __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? 2 * 2 * TE * LDG : sizeof(T) * TE * LDG];
     __shared__ T dX[3][TE][AH_KC + 1];
     __shared__ T Hb[2][TE][AH_KC + 1];
+    __shared__ int wqs[AH_KW];
+    __shared__ WinStage<T, AH_KW> wst;
 
     const int tile = bx;
     const int w = (int)(tile % W);
@@ -238,13 +167,27 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
 
     for (int c0 = 0; c0 < nwin; c0 += AH_KW) {
         __syncthreads();
+        if (tid < AH_KW) {
+            const int q = c0 + tid < nwin ? wins[c0 + tid] : -1;
+            wqs[tid] = q;
+            wq[tid] = q;
+        }
+        __syncthreads();
+        stage_windows<T, AH_KW>(s, wqs, wst, tid, AH_THREADS);
+        __syncthreads();
         {
             const int e = tid & (TE - 1), wl = tid / TE;
-            const int q = c0 + wl < nwin ? wins[c0 + wl] : -1;
-            if (e == 0) wq[wl] = q;
-            T vals[4][WIN];
-            const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-            window_values<T>(s, e < ne ? q : -1, r, vals);
+            T vals[5][WIN];
+            bool tie = false;
+            if (wqs[wl] >= 0 && e < ne) {
+                const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+                staged_values<T, AH_KW, WIN>(s, wst, wl, 0, r, vals, tie);
+            } else {
+#pragma unroll
+                for (int d = 0; d < 5; ++d)
+#pragma unroll
+                    for (int j = 0; j < WIN; ++j) vals[d][j] = T(0);
+            }
 #pragma unroll
             for (int j = 0; j < WIN; ++j)
 #pragma unroll

@@ -159,6 +159,120 @@ __device__ __forceinline__ void slot_values(const DevSys& s, int slot, T X, T Y,
     out[4] = L * g + T(2 * l) * pg1 + P * g2;
 }
 
+// The tables of NW AO windows staged in LDS by a workgroup (atom position,
+// slot monomials and factors, local shells and their primitives), so that
+// the evaluation of every (electron, window) reads LDS instead of chains of
+// dependent global loads.  Shells are consecutive slots, so a window holds
+// at most WIN of them, numbered from the shell of its first slot.
+template <typename T, int NW>
+struct WinStage {
+    double pos[NW][3];
+    double ex[NW][WIN][QSL_PMAX];
+    T c[NW][WIN][QSL_PMAX];
+    T f[NW][WIN];
+    int pow[NW][WIN];       // a | b<<4 | c<<8 | l<<12, -1 for padding slots
+    int8_t sh[NW][WIN];     // local shell of the slot
+    int8_t np[NW][WIN];     // primitives of local shell
+};
+
+// Cooperative fill for windows wq[0..NW) (wq < 0: empty); all threads of the
+// workgroup call it; the caller synchronises before reading.
+template <typename T, int NW>
+__device__ __forceinline__ void stage_windows(const DevSys& s, const int* wq, WinStage<T, NW>& st, int tid,
+                                              int nthreads) {
+    for (int p = tid; p < NW * WIN; p += nthreads) {
+        const int wl = p / WIN, jj = p % WIN;
+        const int q = wq[wl];
+        int pw = -1, lsh = 0, np = 0;
+        T f = T(0);
+        if (q >= 0) {
+            const int slot = q * WIN + jj;
+            const int sh0 = s.slot_shell[q * WIN];
+            const int sh = s.slot_shell[slot];
+            if (sh >= 0) {
+                pw = s.slot_pow[slot];
+                f = (T)s.slot_f[slot];
+                lsh = sh - sh0;
+            }
+            const int at = s.win_atom[q];
+            if (jj < 3) st.pos[wl][jj] = s.atom_xyz[3 * at + jj];
+            const int shl = sh0 + jj;  // local shell jj, if it is on the same atom
+            if (shl < s.n_shells && s.shell_atom[shl] == at) {
+                np = s.shell_np[shl];
+                const int p0 = s.shell_p0[shl];
+                for (int k = 0; k < np; ++k) {
+                    st.ex[wl][jj][k] = s.prim_exp[p0 + k];
+                    if constexpr (sizeof(T) == 8) st.c[wl][jj][k] = (T)s.prim_c64[p0 + k];
+                    else st.c[wl][jj][k] = s.prim_c32[p0 + k];
+                }
+            }
+        }
+        st.pow[wl][jj] = pw;
+        st.f[wl][jj] = f;
+        st.sh[wl][jj] = (int8_t)lsh;
+        st.np[wl][jj] = (int8_t)np;
+    }
+}
+
+// Radial sums of local shell ls of staged window wl (as shell_radial).
+template <typename T, int NW>
+__device__ __forceinline__ void staged_radial(const DevSys& s, const WinStage<T, NW>& st, int wl, int ls, double r2,
+                                              T& g, T& g1, T& g2, bool& tie) {
+    g = T(0); g1 = T(0); g2 = T(0);
+    const double tieb = 1e-12 * s.T;
+    const int np = st.np[wl][ls];
+    for (int k = 0; k < np; ++k) {
+        const double gk = st.ex[wl][ls][k];
+        const double t = __dmul_rn(gk, r2);
+        tie |= fabs(t - s.T) <= tieb;
+        if (t <= s.T) {
+            const T ek = st.c[wl][ls][k] * exp_t(-(T)t);
+            const T gT = (T)gk;
+            g += ek;
+            g1 += T(-2) * gT * ek;
+            g2 += ek * (T(4) * gT * gT * (T)r2 - T(6) * gT);
+        }
+    }
+}
+
+// Value, gradient and Laplacian (out[0..4]) of the CNT slots js.. of staged
+// window wl for one electron at r (zeros for padding slots).
+template <typename T, int NW, int CNT>
+__device__ __forceinline__ void staged_values(const DevSys& s, const WinStage<T, NW>& st, int wl, int js,
+                                              const double r[3], T vals[5][CNT], bool& tie) {
+    const double dx = r[0] - st.pos[wl][0], dy = r[1] - st.pos[wl][1], dz = r[2] - st.pos[wl][2];
+    const double r2 = dist2_exact(dx, dy, dz);
+    const T X = (T)dx, Y = (T)dy, Z = (T)dz;
+    int prev = -1;
+    T g = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) {
+        const int pw = st.pow[wl][js + j];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) vals[d][j] = T(0);
+        if (pw < 0) continue;
+        const int ls = st.sh[wl][js + j];
+        if (ls != prev) {
+            staged_radial<T, NW>(s, st, wl, ls, r2, g, g1, g2, tie);
+            prev = ls;
+        }
+        const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
+        T px, ddx, d2x, py, ddy, d2y, pz, ddz, d2z;
+        axis_pow(a, X, px, ddx, d2x);
+        axis_pow(b, Y, py, ddy, d2y);
+        axis_pow(c, Z, pz, ddz, d2z);
+        const T f = st.f[wl][js + j];
+        const T fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
+        const T P = fyz * px;
+        const T pg1 = P * g1;
+        vals[0][j] = P * g;
+        vals[1][j] = fyz * ddx * g + pg1 * X;
+        vals[2][j] = fxz * ddy * g + pg1 * Y;
+        vals[3][j] = fxy * ddz * g + pg1 * Z;
+        vals[4][j] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + T(2 * l) * pg1 + P * g2;
+    }
+}
+
 // bf16 round-to-nearest-even of a float, as raw bits (the gfx950 hardware
 // conversion v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint16_t bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
