@@ -8,7 +8,8 @@
 // recomputed here; the forward never stores them.
 //
 // Two kernels, both on MFMA in the forward's precision mode:
-//  adj_h   one workgroup per tile of 32 electrons (one walker): G in LDS,
+//  adj_h   one workgroup per tile (one electron index in 32 walkers, as in
+//          the forward's contraction): G in LDS,
 //          gradients of the tile's surviving AOs into LDS chunk by chunk,
 //          H = G A (M = 32 electrons, N = 64 slots, K = MOs), dR = H . grad chi.
 //  adj_dA  one workgroup per (electron range t, block of walkers, block of
@@ -128,10 +129,12 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
     __shared__ int wqs[AH_KW];
     __shared__ WinStage<T, AH_KW> wst;
 
+    // row r of the tile is electron eidx of walker w0 + r (ne valid rows)
     const int tile = bx;
-    const int w = (int)(tile % W);
-    const int e0 = (int)(tile / W) * TE;
-    const int ne = min(TE, n - e0);
+    const int wbk = walker_blocks(W);
+    const int eidx = tile / wbk;
+    const int w0 = (tile % wbk) * TE;
+    const int ne = (int)min<int64_t>(TE, W - w0);
     const int i0 = by * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
@@ -143,13 +146,15 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
-        epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
+        epos[e][k] = e < ne ? R[((size_t)(w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
     }
-    const double gw = g[2 * w + spin];
     for (int q = tid; q < TE * ADJ_MB; q += AH_THREADS) {
         const int e = q / ADJ_MB, ii = q % ADJ_MB;
         double v = 0.0;
-        if (gw != 0.0 && e < ne && i0 + ii < n) v = gw * Dinv[((size_t)w * n + e0 + e) * n + i0 + ii];
+        if (e < ne && i0 + ii < n) {
+            const double gw = g[2 * (w0 + e) + spin];
+            if (gw != 0.0) v = gw * Dinv[((size_t)(w0 + e) * n + eidx) * n + i0 + ii];
+        }
         if constexpr (BF) {
             const float f = (float)v;
             const uint16_t h = bf16_rne(f);
@@ -265,7 +270,7 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
         T acc = 0;
 #pragma unroll
         for (int grp = 0; grp < AH_THREADS / TE; ++grp) acc += red[(comp * (AH_THREADS / TE) + grp) * TE + e];
-        if (e < ne) atomicAdd(dR + ((size_t)w * N + eoff + e0 + e) * 3 + comp, (double)acc);
+        if (e < ne) atomicAdd(dR + ((size_t)(w0 + e) * N + eoff + eidx) * 3 + comp, (double)acc);
     }
 }
 
@@ -566,7 +571,7 @@ __global__ __launch_bounds__(AD_THREADS) void adj_da_batched(const Job* jobs, co
 }
 
 void adj_h_grid(Job& j) {
-    j.gx = (int)(j.W * tiles_per_walker(j.n));
+    j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.n + ADJ_MB - 1) / ADJ_MB;
     j.gz = 1;
 }

@@ -1,6 +1,8 @@
 // Fused AO evaluation + AO->MO products C_n = A B_n, n = 1..5 (equation (abc)).
 //
-// One workgroup owns a tile of 32 electrons of one walker and spin and a
+// One workgroup owns a tile (one electron index of one spin in 32
+// consecutive walkers: positions that share their neighbourhood, so the
+// tile's union of surviving windows stays close to one electron's) and a
 // block of MO columns.  It walks the tile's surviving AO windows in chunks:
 // each thread evaluates the five AO quantities (value, gradient, Laplacian;
 // AO equations for chi and g) of one electron at the 8 slots of one window
@@ -63,13 +65,15 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     constexpr int BELEMS = 5 * TE * LD;
     __shared__ __attribute__((aligned(16))) unsigned char bbuf[MODE == QSL_BF16X3 ? 2 * BELEMS * 2 : BELEMS * sizeof(T)];
 
-    // tiles are numbered t * W + w (electron range t of walker w), so that
-    // concurrently resident workgroups share the same AO windows of A
+    // tiles are numbered e * walker_blocks(W) + walker block, so that
+    // concurrently resident workgroups share the same AO windows of A; row r
+    // of the tile is walker w0 + r (ne valid rows)
     const int tile = bx;
     const int n0 = by * P::NB;
-    const int w = (int)(tile % W);
-    const int e0 = (int)(tile / W) * TE;
-    const int ne = min(TE, n - e0);
+    const int wbk = walker_blocks(W);
+    const int eidx = tile / wbk;
+    const int w0 = (tile % wbk) * TE;
+    const int ne = (int)min<int64_t>(TE, W - w0);
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -77,7 +81,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
-        epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
+        epos[e][k] = e < ne ? R[((size_t)(w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
     }
     const int nwin = tile_nwin[tile];
     const int* wins = tile_win + (size_t)tile * s.n_win;
@@ -216,7 +220,8 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         __syncthreads();
     }
 
-    if (tie && status) atomicOr(status + w, QSL_STATUS_NEAR_TIE);
+    // a near tie of a kept primitive flags the walker of the thread's row
+    if (tie && status) atomicOr(status + w0 + (tid & (TE - 1)), QSL_STATUS_NEAR_TIE);
     // ---- store C[w][d][e][mo]
     if constexpr (MODE == QSL_FP64) {
         double* C = (double*)Cout;
@@ -227,7 +232,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                     for (int r = 0; r < 4; ++r) {
                         // v_mfma_f64_16x16x4f64 result: row (lane / 16) + 4 r, column lane % 16
                         const int el = h * 16 + (lane >> 4) + 4 * r;
-                        if (el < ne) C[(((size_t)w * 5 + d) * n + e0 + el) * n + mo] = acc64[d][h][r];
+                        if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[d][h][r];
                     }
         }
     } else {
@@ -237,7 +242,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
             for (int d = 0; d < 5; ++d)
                 for (int r = 0; r < 16; ++r) {
                     const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (el < ne) C[(((size_t)w * 5 + d) * n + e0 + el) * n + mo] = acc32[d][r];
+                    if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[d][r];
                 }
         }
     }
@@ -261,7 +266,7 @@ int contract_waves(int mode, int n) { return mode != QSL_FP64 && n > 128 ? 8 : 4
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
     const int nb = (j.mode == QSL_FP64 ? 16 : 32) * contract_waves(j.mode, j.n);
-    j.gx = (int)(j.W * tiles_per_walker(j.n));
+    j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.n + nb - 1) / nb;
     j.gz = 1;
 }

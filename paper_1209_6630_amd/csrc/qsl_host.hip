@@ -120,7 +120,7 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
     size_t off = 0;
     for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
-        size_t tiles = n ? (size_t)W * tiles_per_walker(n) : 0;
+        size_t tiles = n ? (size_t)electron_tiles(n, W) : 0;
         L.nwin_off[s] = off;
         off = round_up(off + tiles * sizeof(int), 256);
         L.win_off[s] = off;

@@ -86,7 +86,12 @@ namespace qsl {
 void set_error(const std::string& msg);
 
 inline int n_spin(const DevSys& s, int spin) { return spin ? s.n_dn : s.n_up; }
-inline int tiles_per_walker(int n) { return (n + TE - 1) / TE; }
+__host__ __device__ inline int tiles_per_walker(int n) { return (n + TE - 1) / TE; }
+// Forward (and adjoint-H) tiles: one electron index across TE consecutive
+// walkers; tile = e * walker_blocks(W) + walker block.  Electron e of every
+// walker sits near the same atoms, so the tile's surviving windows are few.
+__host__ __device__ inline int walker_blocks(int64_t W) { return (int)((W + TE - 1) / TE); }
+__host__ __device__ inline int64_t electron_tiles(int n, int64_t W) { return (int64_t)n * walker_blocks(W); }
 
 // ------------------------------------------------------------------ device
 

@@ -1,25 +1,27 @@
-// Screening and compaction (per tile of 32 electrons of one walker and spin).
+// Screening and compaction of AO windows for a set of electron positions.
 //
-// An AO window (8 padded slots of one atom) survives for a tile iff some
-// electron of the tile keeps some primitive of some shell meeting the window:
+// An AO window (8 padded slots of one atom) survives for a set iff some
+// electron of the set keeps some primitive of some shell meeting the window:
 // min_k(gamma_k) r^2 <= T, decided in FP64 exactly as the AO evaluation does
 // (threshold on the Gaussian part and atomic radius, section "Exploiting the
 // highly localized character of atomic basis functions").  Surviving windows
 // are written in ascending order with a wavefront ballot + block prefix,
-// giving the tile's list of AO indices (the paper's `indices` array, here at
-// window granularity and shared by the tile).
+// giving the set's list of AO indices (the paper's `indices` array, here at
+// window granularity and shared by the set).
+//
+// Two kinds of sets:
+//  electron tiles (forward, adjoint H): electron e of TE consecutive walkers,
+//      tile = e * walker_blocks(W) + walker block;
+//  walker groups (adjoint dA): electrons [32 t, 32 t + 32) of gw consecutive
+//      walkers, group = t * ceil(W / gw) + walker block.
 #include "qsl_internal.h"
 
 namespace qsl {
 
 constexpr int SCREEN_THREADS = 256;
+constexpr int SCREEN_MAXE = 2048;  // positions staged in LDS (the rest are read from L2)
 
-// A screening group is `gw` tiles with the same electron range over
-// consecutive walkers (gw = 1: one tile).  Groups are numbered
-// t * ngroups_w + walker-block (t = tile index within a walker).
-constexpr int SCREEN_MAXE = 2048;
-
-__device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restrict__ tile_nwin,
+__device__ __forceinline__ void screen_body(const Job& j, bool group, int* __restrict__ tile_nwin,
                                             int* __restrict__ tile_win, uint32_t* __restrict__ status, int bx) {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n;
@@ -30,29 +32,39 @@ __device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restric
     __shared__ double bred[SCREEN_THREADS / 64][6];
     __shared__ int wave_cnt[SCREEN_THREADS / 64];
     const int tile = bx;
-    const int ngw = (int)((W + gw - 1) / gw);
-    const int t = tile / ngw, wb = tile % ngw;
-    const int w0 = wb * gw;
-    const int nw = (int)min<int64_t>(gw, W - w0);
-    const int e0 = t * TE;
-    const int ne = min(TE, n - e0);
     const int N = s.n_up + s.n_dn;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const int eoff = spin ? s.n_up : 0;
-    const int nall = nw * TE;  // electron slots of the group (ragged tiles padded)
-    const int w = w0;          // walker that owns a near-tie flag when gw == 1
-
-    // electron k of the group: walker w0 + k / TE, electron e0 + k % TE; the
-    // first SCREEN_MAXE positions are staged in LDS, the rest read from L2
-    auto gpos = [&](int k) -> const double* {
-        return R + ((size_t)(w0 + k / TE) * N + eoff + e0 + k % TE) * 3;
-    };
+    // position k of the set -> (walker, electron); `valid` drops the ragged
+    // electrons of the last 32-electron range of a walker group
+    int nall, w0, e0, ne, kstride;
+    if (group) {
+        const int gw = j.gw;
+        const int ngw = (int)((W + gw - 1) / gw);
+        const int t = tile / ngw, wb = tile % ngw;
+        w0 = wb * gw;
+        e0 = t * TE;
+        ne = min(TE, n - e0);
+        nall = (int)min<int64_t>(gw, W - w0) * TE;
+        kstride = TE;
+    } else {
+        const int wbk = walker_blocks(W);
+        const int e = tile / wbk, wb = tile % wbk;
+        w0 = wb * TE;
+        e0 = e;
+        ne = 1;
+        nall = (int)min<int64_t>(TE, W - w0);
+        kstride = 1;
+    }
+    auto kw = [&](int k) { return w0 + k / kstride; };
+    auto ke = [&](int k) { return e0 + k % kstride; };
+    auto valid = [&](int k) { return k % kstride < ne; };
+    auto gpos = [&](int k) -> const double* { return R + ((size_t)kw(k) * N + eoff + ke(k)) * 3; };
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int k = tid; k < nall; k += SCREEN_THREADS) {
-        const int e = k % TE;
         double x = 0, y = 0, z = 0;
-        if (e < ne) {
+        if (valid(k)) {
             const double* r = gpos(k);
             x = r[0]; y = r[1]; z = r[2];
             lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
@@ -60,7 +72,7 @@ __device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restric
         }
         if (k < SCREEN_MAXE) { ex[k] = x; ey[k] = y; ez[k] = z; }
     }
-    // bounding box of the group's electrons
+    // bounding box of the set's electrons
     for (int o = 32; o >= 1; o >>= 1)
         for (int k = 0; k < 3; ++k) {
             lo[k] = fmin(lo[k], __shfl_xor(lo[k], o));
@@ -86,25 +98,23 @@ __device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restric
             const int at = s.win_atom[q];
             const double gm = s.win_gmin[q];
             const double qx = s.atom_xyz[3 * at], qy = s.atom_xyz[3 * at + 1], qz = s.atom_xyz[3 * at + 2];
-            // conservative prefilter: distance from the atom to the tile's box
+            // conservative prefilter: distance from the atom to the set's box
             double dx = fmax(fmax(bb[0] - qx, qx - bb[3]), 0.0);
             double dy = fmax(fmax(bb[1] - qy, qy - bb[4]), 0.0);
             double dz = fmax(fmax(bb[2] - qz, qz - bb[5]), 0.0);
             if (gm * (dx * dx + dy * dy + dz * dz) <= s.T * (1.0 + 1e-9)) {
-                bool tie = false;
                 for (int k = 0; k < nall; ++k) {
-                    if (k % TE >= ne) continue;
+                    if (!valid(k)) continue;
                     double px, py, pz;
                     if (k < SCREEN_MAXE) { px = ex[k]; py = ey[k]; pz = ez[k]; }
                     else { const double* r = gpos(k); px = r[0]; py = r[1]; pz = r[2]; }
                     const double tt = __dmul_rn(gm, dist2_exact(px - qx, py - qy, pz - qz));
                     active |= tt <= s.T;
                     // the smallest exponent of a dropped window decides its
-                    // nearest primitive to the threshold
-                    tie |= tt > s.T && tt - s.T <= 1e-12 * s.T;
+                    // nearest primitive to the threshold: flag that walker
+                    if (status && tt > s.T && tt - s.T <= 1e-12 * s.T) atomicOr(status + kw(k), QSL_STATUS_NEAR_TIE);
                     if (active && !status) break;
                 }
-                if (tie && status) atomicOr(status + w, QSL_STATUS_NEAR_TIE);
             }
         }
         const uint64_t m = __ballot(active);
@@ -126,22 +136,23 @@ __device__ __forceinline__ void screen_body(const Job& j, int gw, int* __restric
 }
 
 __global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(Job j, int group) {
-    if (group) screen_body(j, j.gw, j.gnwin, j.gwin, nullptr, blockIdx.x);
-    else screen_body(j, 1, j.nwin, j.win, j.status, blockIdx.x);
+    if (group) screen_body(j, true, j.gnwin, j.gwin, nullptr, blockIdx.x);
+    else screen_body(j, false, j.nwin, j.win, j.status, blockIdx.x);
 }
 
 __global__ __launch_bounds__(SCREEN_THREADS) void screen_batched(const Job* jobs, const int* prefix, int njobs,
                                                                      int group) {
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) {
-        if (group) screen_body(j, j.gw, j.gnwin, j.gwin, nullptr, bx);
-        else screen_body(j, 1, j.nwin, j.win, j.status, bx);
+        if (group) screen_body(j, true, j.gnwin, j.gwin, nullptr, bx);
+        else screen_body(j, false, j.nwin, j.win, j.status, bx);
     });
 }
 
 // Blocks of the screening phase of a Job (groups of gw walkers, or tiles).
 int screen_blocks(const Job& j, int group) {
-    const int gw = group ? j.gw : 1;
-    return j.n ? tiles_per_walker(j.n) * (int)((j.W + gw - 1) / gw) : 0;
+    if (!j.n || !j.W) return 0;
+    if (!group) return (int)electron_tiles(j.n, j.W);
+    return tiles_per_walker(j.n) * (int)((j.W + j.gw - 1) / j.gw);
 }
 
 hipError_t launch_screen(const Job& j, int group, hipStream_t st) {
