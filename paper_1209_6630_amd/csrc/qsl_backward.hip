@@ -126,8 +126,6 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
     __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? 2 * 2 * TE * LDG : sizeof(T) * TE * LDG];
     __shared__ T dX[3][TE][AH_KC + 1];
     __shared__ T Hb[2][TE][AH_KC + 1];
-    __shared__ int wqs[AH_KW];
-    __shared__ WinStage<T, AH_KW> wst;
 
     // row r of the tile is electron eidx of walker w0 + r (ne valid rows)
     const int tile = bx;
@@ -172,21 +170,15 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
 
     for (int c0 = 0; c0 < nwin; c0 += AH_KW) {
         __syncthreads();
-        if (tid < AH_KW) {
-            const int q = c0 + tid < nwin ? wins[c0 + tid] : -1;
-            wqs[tid] = q;
-            wq[tid] = q;
-        }
-        __syncthreads();
-        stage_windows<T, AH_KW>(s, wqs, wst, tid, AH_THREADS);
-        __syncthreads();
         {
             const int e = tid & (TE - 1), wl = tid / TE;
+            const int q = c0 + wl < nwin ? wins[c0 + wl] : -1;
+            if (e == 0) wq[wl] = q;
             T vals[5][WIN];
             bool tie = false;
-            if (wqs[wl] >= 0 && e < ne) {
+            if (q >= 0 && e < ne) {
                 const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-                staged_values<T, AH_KW, WIN>(s, wst, wl, 0, r, vals, tie);
+                rec_values<T, WIN>(s.win_rec[q], s.T, 0, r, vals, tie);
             } else {
 #pragma unroll
                 for (int d = 0; d < 5; ++d)

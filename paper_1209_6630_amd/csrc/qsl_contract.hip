@@ -25,14 +25,16 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
-template <int MODE, int NWAVE>
+constexpr int CT_WAVES = 4;
+
+template <int MODE>
 struct CT {
     // windows per chunk, MO columns per wave, MO columns per workgroup
     static constexpr int KW = MODE == QSL_FP64 ? 4 : 8;
     static constexpr int KC = KW * WIN;
     static constexpr int NBW = MODE == QSL_FP64 ? 16 : 32;
-    static constexpr int NB = NWAVE * NBW;
-    static constexpr int THREADS = NWAVE * 64;
+    static constexpr int NB = CT_WAVES * NBW;
+    static constexpr int THREADS = CT_WAVES * 64;
     // AO evaluation: slots of one window per thread (8, or 4 when the
     // workgroup has twice as many threads as (electron, window) pairs)
     static constexpr int SPT = THREADS >= 2 * TE * KW ? WIN / 2 : WIN;
@@ -41,7 +43,7 @@ struct CT {
     static constexpr int LD = MODE == QSL_BF16X3 ? KC + 8 : (MODE == QSL_FP32 ? KC + 4 : KC + 2);
 };
 
-template <int MODE, int NWAVE>
+template <int MODE>
 __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
@@ -55,7 +57,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const uint16_t* __restrict__ Alo = j.mo.Alo;
     void* __restrict__ Cout = j.C;
     uint32_t* __restrict__ status = j.status;
-    using P = CT<MODE, NWAVE>;
+    using P = CT<MODE>;
     using T = typename P::T;
     constexpr int KW = P::KW, KC = P::KC, LD = P::LD, SPT = P::SPT;
 
@@ -111,27 +113,8 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
 #pragma unroll
                 for (int j = 0; j < SPT; ++j) vals[d][j] = T(0);
             if (q >= 0 && e < ne) {
-                const int at = s.win_atom[q];
-                const double dx = epos[e][0] - s.atom_xyz[3 * at];
-                const double dy = epos[e][1] - s.atom_xyz[3 * at + 1];
-                const double dz = epos[e][2] - s.atom_xyz[3 * at + 2];
-                const double r2 = dist2_exact(dx, dy, dz);
-                int prev = -1;
-                T g = 0, g1 = 0, g2 = 0;
-#pragma unroll
-                for (int j = 0; j < SPT; ++j) {
-                    const int slot = q * WIN + js + j;
-                    const int sh = s.slot_shell[slot];
-                    if (sh < 0) continue;
-                    if (sh != prev) {
-                        shell_radial<T>(s, sh, r2, g, g1, g2, tie);
-                        prev = sh;
-                    }
-                    T v[5];
-                    slot_values<T>(s, slot, (T)dx, (T)dy, (T)dz, g, g1, g2, v);
-#pragma unroll
-                    for (int d = 0; d < 5; ++d) vals[d][j] = v[d];
-                }
+                const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+                rec_values<T, SPT>(s.win_rec[q], s.T, js, r, vals, tie);
             }
             if constexpr (MODE == QSL_BF16X3) {
                 uint16_t* bh = (uint16_t*)bbuf;
@@ -248,24 +231,20 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     }
 }
 
-template <int MODE, int NWAVE>
-__global__ __launch_bounds__(NWAVE * 64) void contract_kernel(Job j) {
-    contract_body<MODE, NWAVE>(j, blockIdx.x, blockIdx.y);
+template <int MODE>
+__global__ __launch_bounds__(CT_WAVES * 64) void contract_kernel(Job j) {
+    contract_body<MODE>(j, blockIdx.x, blockIdx.y);
 }
 
-template <int MODE, int NWAVE>
-__global__ __launch_bounds__(NWAVE * 64) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+template <int MODE>
+__global__ __launch_bounds__(CT_WAVES * 64) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
     batch_block(jobs, prefix, njobs,
-                [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE, NWAVE>(j, bx, by); });
+                [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE>(j, bx, by); });
 }
-
-// Waves per workgroup: 8 (256 MO columns, one AO evaluation for twice the
-// products) for the FP32 and split-BF16 modes when n > 128, else 4.
-int contract_waves(int mode, int n) { return mode != QSL_FP64 && n > 128 ? 8 : 4; }
 
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
-    const int nb = (j.mode == QSL_FP64 ? 16 : 32) * contract_waves(j.mode, j.n);
+    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : CT<QSL_FP32>::NB;
     j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.n + nb - 1) / nb;
     j.gz = 1;
@@ -276,22 +255,19 @@ hipError_t launch_contract(const Job& j0, hipStream_t st) {
     contract_grid(j);
     if (!j.n || !j.W) return hipSuccess;
     const dim3 g((unsigned)j.gx, j.gy);
-    const bool wide = contract_waves(j.mode, j.n) == 8;
-    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64, 4><<<g, 256, 0, st>>>(j);
-    else if (j.mode == QSL_FP32 && wide) contract_kernel<QSL_FP32, 8><<<g, 512, 0, st>>>(j);
-    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32, 4><<<g, 256, 0, st>>>(j);
-    else if (wide) contract_kernel<QSL_BF16X3, 8><<<g, 512, 0, st>>>(j);
-    else contract_kernel<QSL_BF16X3, 4><<<g, 256, 0, st>>>(j);
+    constexpr int T = CT_WAVES * 64;
+    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64><<<g, T, 0, st>>>(j);
+    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32><<<g, T, 0, st>>>(j);
+    else contract_kernel<QSL_BF16X3><<<g, T, 0, st>>>(j);
     return hipGetLastError();
 }
 
-hipError_t launch_contract_batched(int mode, int nwave, const Job* jobs, const int* prefix, int njobs, int grid,
+hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                    hipStream_t st) {
-    if (mode == QSL_FP64) contract_batched<QSL_FP64, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
-    else if (mode == QSL_FP32 && nwave == 8) contract_batched<QSL_FP32, 8><<<grid, 512, 0, st>>>(jobs, prefix, njobs);
-    else if (mode == QSL_FP32) contract_batched<QSL_FP32, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
-    else if (nwave == 8) contract_batched<QSL_BF16X3, 8><<<grid, 512, 0, st>>>(jobs, prefix, njobs);
-    else contract_batched<QSL_BF16X3, 4><<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    constexpr int T = CT_WAVES * 64;
+    if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+    else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+    else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

@@ -354,6 +354,27 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             }
         }
         S->slot_ao = slot_ao;
+        std::vector<WinRec> win_rec(std::max(n_win, 1));
+        for (int q = 0; q < n_win; ++q) {
+            WinRec& r = win_rec[q];
+            memset(&r, 0, sizeof r);
+            const int at = win_atom[q];
+            for (int k = 0; k < 3; ++k) r.pos[k] = d->atom_xyz[3 * at + k];
+            const int sh0 = slot_shell[q * WIN];
+            for (int j = 0; j < WIN; ++j) {
+                const int sh = slot_shell[q * WIN + j];
+                if (sh < 0) { r.pw[j] = -1; continue; }
+                r.pw[j] = (slot_pow[q * WIN + j] & 0xffff) | ((sh - sh0) << 16);
+                r.f32[j] = (float)slot_f[q * WIN + j];
+                r.f64[j] = slot_f[q * WIN + j];
+                r.np[j] = sh_np[sh];
+                for (int k = 0; k < sh_np[sh]; ++k) {
+                    r.ex[j][k] = ex[p0[sh] + k];
+                    r.c32[j][k] = c32[p0[sh] + k];
+                    r.c64[j][k] = c64[p0[sh] + k];
+                }
+            }
+        }
 
         // device tables in one allocation
         Arena ar;
@@ -372,6 +393,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         size_t o_sao = ar.add(slot_ao.data(), sizeof(int) * slot_ao.size());
         size_t o_wat = ar.add(win_atom.data(), sizeof(int) * win_atom.size());
         size_t o_wgm = ar.add(win_gmin.data(), sizeof(double) * win_gmin.size());
+        size_t o_wrec = ar.add(win_rec.data(), sizeof(WinRec) * win_rec.size());
         // MO copies per spin
         size_t o_mo[2][8];
         int ldn[2];
@@ -407,6 +429,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         D.slot_shell = (const int*)(b + o_ssh); D.slot_pow = (const int*)(b + o_spw);
         D.slot_f = (const double*)(b + o_sf); D.slot_ao = (const int*)(b + o_sao);
         D.win_atom = (const int*)(b + o_wat); D.win_gmin = (const double*)(b + o_wgm);
+        D.win_rec = (const WinRec*)(b + o_wrec);
         for (int sp = 0; sp < 2; ++sp) {
             DevMO& m = S->mo[sp];
             m.n = sp ? d->n_dn : d->n_up;

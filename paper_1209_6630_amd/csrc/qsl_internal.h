@@ -31,6 +31,23 @@ __host__ __device__ inline size_t gj_ws_doubles(int n) {
     return (ld * n + ld * GJ_PANEL + ((size_t)5 * n + 40) / 8 + 15) & ~(size_t)15;
 }
 
+// Everything the AO evaluation of one window needs, in one record (built
+// once per system), so that an evaluation is one level of loads after the
+// window index instead of a chain through slot, shell and primitive tables.
+// Slot j: pw = a | b<<4 | c<<8 | l<<12 | (its shell's index within the
+// window)<<16, -1 for padding; the shell's primitives are repeated per slot.
+struct WinRec {
+    double pos[3];
+    double pad0;
+    int pw[WIN];
+    int np[WIN];
+    float f32[WIN];
+    double f64[WIN];
+    double ex[WIN][QSL_PMAX];
+    float c32[WIN][QSL_PMAX];
+    double c64[WIN][QSL_PMAX];
+};
+
 // Device view of a system, passed to kernels by value.
 struct DevSys {
     int n_atoms, n_shells, n_slots, n_win, n_basis;
@@ -49,6 +66,7 @@ struct DevSys {
     const int* slot_pow;      // [n_slots] a | b<<4 | c<<8 | l<<12
     const double* slot_f;     // [n_slots] Cartesian factor
     const int* slot_ao;       // [n_slots] ABI AO index, -1 for padding
+    const WinRec* win_rec;    // [n_win]
     const int* win_atom;      // [n_win]
     const double* win_gmin;   // [n_win] min exponent over shells meeting the window
 };
@@ -105,31 +123,6 @@ __device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
 __device__ __forceinline__ double exp_t(double x) { return exp(x); }
 __device__ __forceinline__ float exp_t(float x) { return expf(x); }
 
-// Radial part of a contracted shell over its kept primitives:
-// g = sum c_k e_k, g1 = sum -2 gamma_k c_k e_k, g2 = sum c_k e_k (4 gamma_k^2 r^2 - 6 gamma_k)
-template <typename T>
-__device__ __forceinline__ void shell_radial(const DevSys& s, int sh, double r2, T& g, T& g1, T& g2,
-                                             bool& tie) {
-    const int p0 = s.shell_p0[sh], np = s.shell_np[sh];
-    g = T(0); g1 = T(0); g2 = T(0);
-    const double tieb = 1e-12 * s.T;
-    for (int k = 0; k < np; ++k) {
-        const double gk = s.prim_exp[p0 + k];
-        const double t = __dmul_rn(gk, r2);
-        tie |= fabs(t - s.T) <= tieb;
-        if (t <= s.T) {
-            T c;
-            if constexpr (sizeof(T) == 8) c = (T)s.prim_c64[p0 + k];
-            else c = s.prim_c32[p0 + k];
-            const T ek = c * exp_t(-(T)t);
-            const T gT = (T)gk;
-            g += ek;
-            g1 += T(-2) * gT * ek;
-            g2 += ek * (T(4) * gT * gT * (T)r2 - T(6) * gT);
-        }
-    }
-}
-
 // x^a, a x^(a-1) and a (a-1) x^(a-2) of one Cartesian axis, a <= 2.
 template <typename T>
 __device__ __forceinline__ void axis_pow(int a, T x, T& p, T& dp, T& d2) {
@@ -138,127 +131,43 @@ __device__ __forceinline__ void axis_pow(int a, T x, T& p, T& dp, T& d2) {
     d2 = a == 2 ? T(2) : T(0);
 }
 
-// Value, d/dx, d/dy, d/dz and Laplacian of the Cartesian AO in `slot`,
-// given its shell's radial sums and the displacement from its atom.
-template <typename T>
-__device__ __forceinline__ void slot_values(const DevSys& s, int slot, T X, T Y, T Z, T g, T g1,
-                                            T g2, T out[5]) {
-    const int pw = s.slot_pow[slot];
-    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
-    const T f = (T)s.slot_f[slot];
-    T px, dx, d2x, py, dy, d2y, pz, dz, d2z;
-    axis_pow(a, X, px, dx, d2x);
-    axis_pow(b, Y, py, dy, d2y);
-    axis_pow(c, Z, pz, dz, d2z);
-    const T fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
-    const T P = fyz * px;
-    const T Px = fyz * dx, Py = fxz * dy, Pz = fxy * dz;
-    // l <= 2: at most one axis has a non-zero second derivative factor
-    const T L = d2x * fyz + d2y * fxz + d2z * fxy;
-    const T pg1 = P * g1;
-    out[0] = P * g;
-    out[1] = Px * g + pg1 * X;
-    out[2] = Py * g + pg1 * Y;
-    out[3] = Pz * g + pg1 * Z;
-    // Delta . grad P = l P for a homogeneous polynomial of degree l
-    out[4] = L * g + T(2 * l) * pg1 + P * g2;
-}
-
-// The tables of NW AO windows staged in LDS by a workgroup (atom position,
-// slot monomials and factors, local shells and their primitives), so that
-// the evaluation of every (electron, window) reads LDS instead of chains of
-// dependent global loads.  Shells are consecutive slots, so a window holds
-// at most WIN of them, numbered from the shell of its first slot.
-template <typename T, int NW>
-struct WinStage {
-    double pos[NW][3];
-    double ex[NW][WIN][QSL_PMAX];
-    T c[NW][WIN][QSL_PMAX];
-    T f[NW][WIN];
-    int pow[NW][WIN];       // a | b<<4 | c<<8 | l<<12, -1 for padding slots
-    int8_t sh[NW][WIN];     // local shell of the slot
-    int8_t np[NW][WIN];     // primitives of local shell
-};
-
-// Cooperative fill for windows wq[0..NW) (wq < 0: empty); all threads of the
-// workgroup call it; the caller synchronises before reading.
-template <typename T, int NW>
-__device__ __forceinline__ void stage_windows(const DevSys& s, const int* wq, WinStage<T, NW>& st, int tid,
-                                              int nthreads) {
-    for (int p = tid; p < NW * WIN; p += nthreads) {
-        const int wl = p / WIN, jj = p % WIN;
-        const int q = wq[wl];
-        int pw = -1, lsh = 0, np = 0;
-        T f = T(0);
-        if (q >= 0) {
-            const int slot = q * WIN + jj;
-            const int sh0 = s.slot_shell[q * WIN];
-            const int sh = s.slot_shell[slot];
-            if (sh >= 0) {
-                pw = s.slot_pow[slot];
-                f = (T)s.slot_f[slot];
-                lsh = sh - sh0;
-            }
-            const int at = s.win_atom[q];
-            if (jj < 3) st.pos[wl][jj] = s.atom_xyz[3 * at + jj];
-            const int shl = sh0 + jj;  // local shell jj, if it is on the same atom
-            if (shl < s.n_shells && s.shell_atom[shl] == at) {
-                np = s.shell_np[shl];
-                const int p0 = s.shell_p0[shl];
-                for (int k = 0; k < np; ++k) {
-                    st.ex[wl][jj][k] = s.prim_exp[p0 + k];
-                    if constexpr (sizeof(T) == 8) st.c[wl][jj][k] = (T)s.prim_c64[p0 + k];
-                    else st.c[wl][jj][k] = s.prim_c32[p0 + k];
-                }
-            }
-        }
-        st.pow[wl][jj] = pw;
-        st.f[wl][jj] = f;
-        st.sh[wl][jj] = (int8_t)lsh;
-        st.np[wl][jj] = (int8_t)np;
-    }
-}
-
-// Radial sums of local shell ls of staged window wl (as shell_radial).
-template <typename T, int NW>
-__device__ __forceinline__ void staged_radial(const DevSys& s, const WinStage<T, NW>& st, int wl, int ls, double r2,
-                                              T& g, T& g1, T& g2, bool& tie) {
-    g = T(0); g1 = T(0); g2 = T(0);
-    const double tieb = 1e-12 * s.T;
-    const int np = st.np[wl][ls];
-    for (int k = 0; k < np; ++k) {
-        const double gk = st.ex[wl][ls][k];
-        const double t = __dmul_rn(gk, r2);
-        tie |= fabs(t - s.T) <= tieb;
-        if (t <= s.T) {
-            const T ek = st.c[wl][ls][k] * exp_t(-(T)t);
-            const T gT = (T)gk;
-            g += ek;
-            g1 += T(-2) * gT * ek;
-            g2 += ek * (T(4) * gT * gT * (T)r2 - T(6) * gT);
-        }
-    }
-}
-
-// Value, gradient and Laplacian (out[0..4]) of the CNT slots js.. of staged
-// window wl for one electron at r (zeros for padding slots).
-template <typename T, int NW, int CNT>
-__device__ __forceinline__ void staged_values(const DevSys& s, const WinStage<T, NW>& st, int wl, int js,
-                                              const double r[3], T vals[5][CNT], bool& tie) {
-    const double dx = r[0] - st.pos[wl][0], dy = r[1] - st.pos[wl][1], dz = r[2] - st.pos[wl][2];
+// Value, gradient and Laplacian (out[0..4]) of the CNT slots js.. of window
+// record r for one electron at p (zeros for padding slots), with the near-tie
+// flag of the kept-primitive tests.
+template <typename T, int CNT>
+__device__ __forceinline__ void rec_values(const WinRec& r, double T_thr, int js, const double p[3],
+                                           T vals[5][CNT], bool& tie) {
+    const double dx = p[0] - r.pos[0], dy = p[1] - r.pos[1], dz = p[2] - r.pos[2];
     const double r2 = dist2_exact(dx, dy, dz);
     const T X = (T)dx, Y = (T)dy, Z = (T)dz;
+    const double tieb = 1e-12 * T_thr;
     int prev = -1;
     T g = 0, g1 = 0, g2 = 0;
 #pragma unroll
     for (int j = 0; j < CNT; ++j) {
-        const int pw = st.pow[wl][js + j];
+        const int pw = r.pw[js + j];
 #pragma unroll
         for (int d = 0; d < 5; ++d) vals[d][j] = T(0);
         if (pw < 0) continue;
-        const int ls = st.sh[wl][js + j];
+        const int ls = pw >> 16;
         if (ls != prev) {
-            staged_radial<T, NW>(s, st, wl, ls, r2, g, g1, g2, tie);
+            g = T(0); g1 = T(0); g2 = T(0);
+            const int np = r.np[js + j];
+            for (int k = 0; k < np; ++k) {
+                const double gk = r.ex[js + j][k];
+                const double t = __dmul_rn(gk, r2);
+                tie |= fabs(t - T_thr) <= tieb;
+                if (t <= T_thr) {
+                    T c;
+                    if constexpr (sizeof(T) == 8) c = (T)r.c64[js + j][k];
+                    else c = r.c32[js + j][k];
+                    const T ek = c * exp_t(-(T)t);
+                    const T gT = (T)gk;
+                    g += ek;
+                    g1 += T(-2) * gT * ek;
+                    g2 += ek * (T(4) * gT * gT * (T)r2 - T(6) * gT);
+                }
+            }
             prev = ls;
         }
         const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
@@ -266,7 +175,9 @@ __device__ __forceinline__ void staged_values(const DevSys& s, const WinStage<T,
         axis_pow(a, X, px, ddx, d2x);
         axis_pow(b, Y, py, ddy, d2y);
         axis_pow(c, Z, pz, ddz, d2z);
-        const T f = st.f[wl][js + j];
+        T f;
+        if constexpr (sizeof(T) == 8) f = (T)r.f64[js + j];
+        else f = r.f32[js + j];
         const T fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
         const T P = fyz * px;
         const T pg1 = P * g1;
@@ -425,12 +336,9 @@ hipError_t launch_screen(const Job& j, int group, hipStream_t st);
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st);
 // Fused AO evaluation + the five AO->MO products C_n = A B_n.
-// Waves per workgroup (4 or 8) of a Job's contraction; a batched launch
-// serves Jobs of one width.
-int contract_waves(int mode, int n);
 void contract_grid(Job& j);
 hipError_t launch_contract(const Job& j, hipStream_t st);
-hipError_t launch_contract_batched(int mode, int nwave, const Job* jobs, const int* prefix, int njobs, int grid,
+hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                    hipStream_t st);
 // Gauss-Jordan inversion, log|det| and sign (one block per matrix; the
 // block shape depends on n, so a batched launch serves one variant).

@@ -20,8 +20,7 @@ namespace qsl {
 // Kernel phases of a launch, in order.
 enum Phase {
     PH_SCREEN = 0,   // per-tile window lists (forward; reused by the adjoint)
-    PH_CONTRACT,     // AO evaluation + the five products (4-wave workgroups)
-    PH_CONTRACT_W,   // the same with 8-wave workgroups (n > 128)
+    PH_CONTRACT,     // AO evaluation + the five products
     PH_GJ0,          // Gauss-Jordan, one phase per block shape
     PH_GJ1,
     PH_GJ2,
@@ -144,7 +143,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
         p->ph[PH_SCREEN].jobs.push_back(j);
         j = f;
         contract_grid(j);
-        p->ph[contract_waves(j.mode, j.n) == 8 ? PH_CONTRACT_W : PH_CONTRACT].jobs.push_back(j);
+        p->ph[PH_CONTRACT].jobs.push_back(j);
         j = f;
         j.gx = (int)j.W; j.gy = 1; j.gz = 1;
         p->ph[PH_GJ0 + gj_job_variant(j)].jobs.push_back(j);
@@ -243,11 +242,10 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                            S.blocks(), 0, st)) != hipSuccess)
                 return hip_fail(e, "screen kernel");
         }
-        for (int ph = PH_CONTRACT; ph <= PH_CONTRACT_W; ++ph) {
-            auto& C = p->ph[ph];
-            if (!C.blocks()) continue;
+        auto& C = p->ph[PH_CONTRACT];
+        if (C.blocks()) {
             ProfScope ps(contract_name(mode), st);
-            if ((e = launch_contract_batched(mode, ph == PH_CONTRACT_W ? 8 : 4, dev_jobs(p, ph), dev_prefix(p, ph),
+            if ((e = launch_contract_batched(mode, dev_jobs(p, PH_CONTRACT), dev_prefix(p, PH_CONTRACT),
                                              (int)C.jobs.size(), C.blocks(), st)) != hipSuccess)
                 return hip_fail(e, "contraction kernel");
         }
@@ -271,11 +269,10 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             ProfScope ps("screen", st);
             if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
         }
-        for (int ph = PH_CONTRACT; ph <= PH_CONTRACT_W; ++ph)
-            for (const Job& j : p->ph[ph].jobs) {
-                ProfScope ps(contract_name(mode), st);
-                if ((e = launch_contract(j, st)) != hipSuccess) return hip_fail(e, "contraction kernel");
-            }
+        for (const Job& j : p->ph[PH_CONTRACT].jobs) {
+            ProfScope ps(contract_name(mode), st);
+            if ((e = launch_contract(j, st)) != hipSuccess) return hip_fail(e, "contraction kernel");
+        }
         for (int v = 0; v <= 4; ++v)
             for (const Job& j : p->ph[PH_GJ0 + v].jobs) {
                 ProfScope ps("gauss_jordan", st);
