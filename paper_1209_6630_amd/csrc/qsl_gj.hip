@@ -129,9 +129,9 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
             perm[k] = p;
             rowpiv[p] = pv;
         }
-        // rank-1 update with the pivot row read from lane lp, register row rp.
-        // The owner of column k + 1 updates that column first and publishes
-        // its pivot before the rest of its update (look-ahead).
+        // rank-1 update with the pivot row read from lane lp, register row rp;
+        // then the owner of column k + 1 searches that column's pivot and
+        // publishes it for the next step.
         const int k1 = k + 1;
         const bool owner1 = k1 < n && wave == k1 % NWV;
         const int c1 = owner1 ? k1 / NWV : -1;
