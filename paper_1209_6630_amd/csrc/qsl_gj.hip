@@ -287,7 +287,7 @@ __global__ void empty_spin_kernel(int64_t W, int spin, double* logdet, int8_t* s
 
 // Variants by matrix size: register-resident 0: n <= 32, 1: <= 64,
 // 2: <= 128, 3: <= 224; 4: blocked, n <= 1024.
-int gj_variant(int n) { return n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : n <= GJ_REG_NMAX ? 3 : 4; }
+int gj_variant(int n) { return gj_blocked(n) ? 4 : n <= 32 ? 0 : n <= 64 ? 1 : n <= 128 ? 2 : 3; }
 int gj_threads(int v) { return v == 0 ? 128 : v == 1 ? 256 : 512; }
 int gj_job_variant(const Job& j) {
     const int v = gj_variant(j.n);

@@ -37,16 +37,25 @@ namespace qsl {
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
 constexpr int GJB_NB = GJ_PANEL;
-constexpr int GJB_PT = 512;                                 // panel / finish threads
-constexpr int GJB_PWAVES = GJB_PT / 64;
-constexpr int GJB_RPT = GJ_NMAX / GJB_PT;                   // panel rows per thread
-constexpr int GJB_UT = 512;                                 // update threads
-constexpr int GJB_UWAVES = GJB_UT / 64;
-constexpr int GJB_HALVES = 2;                               // row halves per matrix
-constexpr int GJB_SPW = GJ_NMAX / 16 / GJB_UWAVES / GJB_HALVES;  // 16-row strips per wave
-constexpr int GJB_CHUNKS = 4;                               // column-tile sets per matrix
-constexpr int GJB_UPD_BLOCKS = GJB_HALVES * GJB_CHUNKS;     // update blocks per matrix
-constexpr int GJB_COPY_BLOCKS = 8;                          // init / finish blocks per matrix
+constexpr int GJB_COPY_BLOCKS = 8;  // init / finish blocks per matrix
+
+// Launch shapes by the largest n served (NMX = 256 or GJ_NMAX): threads of
+// the panel / init / finish workgroups and of the update workgroups, rows
+// per panel thread, 16-row strips per update wave, row halves and column
+// ranges per matrix in the update.
+template <int NMX>
+struct GjbCfg {
+    static constexpr int PT = NMX >= 512 ? 512 : 256;
+    static constexpr int PWAVES = PT / 64;
+    static constexpr int RPT = NMX / PT;
+    static constexpr int UT = PT;
+    static constexpr int UWAVES = UT / 64;
+    static constexpr int SPW = 4;
+    static constexpr int HALVES = NMX / 16 / UWAVES / SPW;
+    static constexpr int CHUNKS = 4;
+    static constexpr int UPD_BLOCKS = HALVES * CHUNKS;
+    static_assert(HALVES >= 1 && RPT >= 1, "launch shape");
+};
 
 struct GjbState {
     double ld;  // sum log|pivot|
@@ -115,8 +124,9 @@ __device__ __forceinline__ void wave_argmax(double& best, int& bi) {
 // M[b][a] = D[b][a] = C_1[a][b] promoted to FP64 (32 x 32 tiles through
 // LDS: coalesced reads of C_1 rows, coalesced writes of M rows); row flags
 // and state reset.
-template <typename Tin>
+template <int NMX, typename Tin>
 __device__ __forceinline__ void gjb_init_body(const Job& j, int w, int sub) {
+    constexpr int GJB_PT = GjbCfg<NMX>::PT;
     const int n = j.n;
     const size_t nn = (size_t)n * n;
     const GjbView v = gjb_view(j, w);
@@ -124,19 +134,20 @@ __device__ __forceinline__ void gjb_init_body(const Job& j, int w, int sub) {
     __shared__ double tile[32][33];
     const int tid = threadIdx.x;
     const int nt = (n + 31) >> 5;
-    const int tx = tid & 31, ty = tid >> 5;  // 32 x 16
+    constexpr int RP = GJB_PT / 32;  // tile rows per pass
+    const int tx = tid & 31, ty = tid >> 5;
     for (int t = sub; t < nt * nt; t += GJB_COPY_BLOCKS) {
         const int ta = t / nt, tb = t % nt;  // source rows a (C_1), columns b
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int a = 32 * ta + ty + 16 * h, b = 32 * tb + tx;
-            tile[ty + 16 * h][tx] = (a < n && b < n) ? (double)C1[(size_t)a * n + b] : 0.0;
+        for (int h = 0; h < 32 / RP; ++h) {
+            const int a = 32 * ta + ty + RP * h, b = 32 * tb + tx;
+            tile[ty + RP * h][tx] = (a < n && b < n) ? (double)C1[(size_t)a * n + b] : 0.0;
         }
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int b = 32 * tb + ty + 16 * h, a = 32 * ta + tx;
-            if (a < n && b < n) v.M[(size_t)b * v.ld + a] = tile[tx][ty + 16 * h];
+        for (int h = 0; h < 32 / RP; ++h) {
+            const int b = 32 * tb + ty + RP * h, a = 32 * ta + tx;
+            if (a < n && b < n) v.M[(size_t)b * v.ld + a] = tile[tx][ty + RP * h];
         }
         __syncthreads();
     }
@@ -150,16 +161,18 @@ __device__ __forceinline__ void gjb_init_body(const Job& j, int w, int sub) {
     }
 }
 
-template <bool BATCHED, typename Tin>
-__global__ __launch_bounds__(GJB_PT) void gjb_init_kernel(Job single, const Job* jobs, const int* prefix,
-                                                           int njobs) {
+template <int NMX, bool BATCHED, typename Tin>
+__global__ __launch_bounds__(GjbCfg<NMX>::PT) void gjb_init_kernel(Job single, const Job* jobs, const int* prefix,
+                                                                    int njobs) {
     gjb_block<BATCHED>(single, jobs, prefix, njobs, GJB_COPY_BLOCKS,
-                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_init_body<Tin>(j, w, sub); });
+                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_init_body<NMX, Tin>(j, w, sub); });
 }
 
 // ----------------------------------------------------------------- panel
+template <int NMX>
 __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
-    constexpr int NB = GJB_NB, RPT = GJB_RPT;
+    using C = GjbCfg<NMX>;
+    constexpr int NB = GJB_NB, RPT = C::RPT, GJB_PT = C::PT, GJB_PWAVES = C::PWAVES;
     const int n = j.n;
     if (k0 >= n) return;
     const GjbView v = gjb_view(j, w);
@@ -286,16 +299,19 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(GJB_PT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
-                                                            int njobs, int k0) {
+template <int NMX, bool BATCHED>
+__global__ __launch_bounds__(GjbCfg<NMX>::PT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
+                                                                     int njobs, int k0) {
     gjb_block<BATCHED>(single, jobs, prefix, njobs, 1,
-                       [&](const Job& j, int w, int) __attribute__((always_inline)) { gjb_panel_body(j, w, k0); });
+                       [&](const Job& j, int w, int) __attribute__((always_inline)) { gjb_panel_body<NMX>(j, w, k0); });
 }
 
 // ---------------------------------------------------------------- update
+template <int NMX>
 __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, int k0) {
-    constexpr int NB = GJB_NB, HS = GJB_SPW;
+    using C = GjbCfg<NMX>;
+    constexpr int NB = GJB_NB, HS = C::SPW, GJB_SPW = C::SPW, GJB_UT = C::UT, GJB_UWAVES = C::UWAVES;
+    constexpr int GJB_HALVES = C::HALVES, GJB_CHUNKS = C::CHUNKS;
     const int n = j.n;
     if (k0 >= n) return;
     const GjbView v = gjb_view(j, w);
@@ -401,18 +417,20 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(GJB_UT) void gjb_update_kernel(Job single, const Job* jobs, const int* prefix,
-                                                             int njobs, int k0) {
-    gjb_block<BATCHED>(single, jobs, prefix, njobs, GJB_UPD_BLOCKS,
-                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_update_body(j, w, sub, k0); });
+template <int NMX, bool BATCHED>
+__global__ __launch_bounds__(GjbCfg<NMX>::UT) void gjb_update_kernel(Job single, const Job* jobs, const int* prefix,
+                                                                      int njobs, int k0) {
+    gjb_block<BATCHED>(single, jobs, prefix, njobs, GjbCfg<NMX>::UPD_BLOCKS,
+                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_update_body<NMX>(j, w, sub, k0); });
 }
 
 // ---------------------------------------------------------------- finish
 // D^-1[e][i] = M[p_e][invp(i)]: row p_e of M staged in LDS and written out
 // permuted (both sides coalesced); log|det| = sum log|pivot|, sign =
 // sign(permutation) prod sign(pivot).
+template <int NMX>
 __device__ __forceinline__ void gjb_finish_body(const Job& j, int w, int sub) {
+    constexpr int GJB_PT = GjbCfg<NMX>::PT;
     const int n = j.n, spin = j.spin;
     const size_t nn = (size_t)n * n;
     const GjbView v = gjb_view(j, w);
@@ -465,39 +483,47 @@ __device__ __forceinline__ void gjb_finish_body(const Job& j, int w, int sub) {
     }
 }
 
-template <bool BATCHED>
-__global__ __launch_bounds__(GJB_PT) void gjb_finish_kernel(Job single, const Job* jobs, const int* prefix,
-                                                             int njobs) {
+template <int NMX, bool BATCHED>
+__global__ __launch_bounds__(GjbCfg<NMX>::PT) void gjb_finish_kernel(Job single, const Job* jobs, const int* prefix,
+                                                                      int njobs) {
     gjb_block<BATCHED>(single, jobs, prefix, njobs, GJB_COPY_BLOCKS,
-                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_finish_body(j, w, sub); });
+                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_finish_body<NMX>(j, w, sub); });
 }
 
 // ------------------------------------------------------------- launchers
+
+template <int NMX, bool BATCHED>
+static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, const int* prefix, int njobs,
+                                 int matrices, int nmax, hipStream_t st) {
+    using C = GjbCfg<NMX>;
+    const unsigned m = (unsigned)matrices;
+    if (mode == QSL_FP64)
+        gjb_init_kernel<NMX, BATCHED, double><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
+    else
+        gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
+    hipError_t e = hipGetLastError();
+    for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += GJB_NB) {
+        gjb_panel_kernel<NMX, BATCHED><<<m, C::PT, 0, st>>>(single, jobs, prefix, njobs, k0);
+        gjb_update_kernel<NMX, BATCHED><<<m * C::UPD_BLOCKS, C::UT, 0, st>>>(single, jobs, prefix, njobs, k0);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return e;
+    gjb_finish_kernel<NMX, BATCHED><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
+    return hipGetLastError();
+}
 
 template <bool BATCHED>
 static hipError_t gjb_sequence(int mode, const Job& single, const Job* jobs, const int* prefix, int njobs,
                                int matrices, int nmax, hipStream_t st) {
     if (matrices <= 0 || nmax <= 0) return hipSuccess;
     if (nmax > GJ_NMAX) return hipErrorInvalidValue;
-    const unsigned m = (unsigned)matrices;
-    if (mode == QSL_FP64)
-        gjb_init_kernel<BATCHED, double><<<m * GJB_COPY_BLOCKS, GJB_PT, 0, st>>>(single, jobs, prefix, njobs);
-    else
-        gjb_init_kernel<BATCHED, float><<<m * GJB_COPY_BLOCKS, GJB_PT, 0, st>>>(single, jobs, prefix, njobs);
-    hipError_t e = hipGetLastError();
-    for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += GJB_NB) {
-        gjb_panel_kernel<BATCHED><<<m, GJB_PT, 0, st>>>(single, jobs, prefix, njobs, k0);
-        gjb_update_kernel<BATCHED><<<m * GJB_UPD_BLOCKS, GJB_UT, 0, st>>>(single, jobs, prefix, njobs, k0);
-        e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    gjb_finish_kernel<BATCHED><<<m * GJB_COPY_BLOCKS, GJB_PT, 0, st>>>(single, jobs, prefix, njobs);
-    return hipGetLastError();
+    if (nmax <= 256) return gjb_sequence_n<256, BATCHED>(mode, single, jobs, prefix, njobs, matrices, nmax, st);
+    return gjb_sequence_n<GJ_NMAX, BATCHED>(mode, single, jobs, prefix, njobs, matrices, nmax, st);
 }
 
 hipError_t launch_gjb(const Job& j, hipStream_t st) {
-    if (j.n <= GJ_REG_NMAX || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
-    if (j.W > (int64_t)(0x7fffffff / GJB_UPD_BLOCKS)) return hipErrorInvalidValue;
+    if (!gj_blocked(j.n) || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
+    if (j.W > (int64_t)(0x7fffffff / GjbCfg<GJ_NMAX>::UPD_BLOCKS)) return hipErrorInvalidValue;
     return gjb_sequence<false>(j.mode, j, nullptr, nullptr, 0, (int)j.W, j.n, st);
 }
 

@@ -141,7 +141,7 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
     for (int s = 0; s < 2; ++s) {
         const size_t n = (size_t)n_spin(d, s);
         L.gj_off[s] = off;
-        if (n > (size_t)GJ_REG_NMAX) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
+        if (gj_blocked((int)n)) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -161,7 +161,7 @@ Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws,
     j.nwin = (int*)(ws + L.nwin_off[s]);
     j.win = (int*)(ws + L.win_off[s]);
     j.C = a->C[s];
-    if (j.n > GJ_REG_NMAX) j.gjws = (double*)(ws + L.gj_off[s]);
+    if (gj_blocked(j.n)) j.gjws = (double*)(ws + L.gj_off[s]);
     j.logdet = a->logdet;
     j.sign = a->sign;
     j.Dinv = a->Dinv[s];

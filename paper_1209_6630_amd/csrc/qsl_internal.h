@@ -20,6 +20,8 @@ constexpr int TE = 32;
 constexpr int WIN = 8;
 // Largest Slater matrix inverted in registers by one workgroup.
 constexpr int GJ_REG_NMAX = 224;   // largest n of the register-resident inversion
+constexpr int GJ_BLOCKED_FROM = GJ_REG_NMAX + 1;  // n from which the blocked inversion is used
+__host__ __device__ inline bool gj_blocked(int n) { return n >= GJ_BLOCKED_FROM; }
 constexpr int GJ_NMAX = 1024;      // largest n of the blocked inversion
 constexpr int GJ_PANEL = 32;       // panel width of the blocked inversion
 // Blocked inversion workspace per matrix: the copy of D with rows padded to
@@ -231,7 +233,7 @@ struct Job {
     double* dR;
     double* dA64;
     float* dA32;
-    double* gjws;            // blocked inversion (n > GJ_REG_NMAX): W x gj_ws_doubles(n)
+    double* gjws;            // blocked inversion (gj_blocked(n)): W x gj_ws_doubles(n)
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 
