@@ -267,6 +267,281 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
     }
 }
 
+// Half-wave layout for 128 < n <= 224 (eight waves).  Half h of wave v is
+// column group g = 2 v + h of 16; lane li (< 32) of the half owns the D rows
+// i = li + 32 r (r < RPL) and holds M[r][c] for the D columns e = g + 16 c
+// (c < CPW): 7 x 14 values per lane cover 224 x 224 with little padding.
+// Step k: every half writes its segment of the pivot row (lane p % 32,
+// register row p / 32) to LDS and reads it back broadcast, the owner of
+// column k substituting pv + 1 in its slot; the rank-1 update then takes
+// the published column k, already scaled by -1/pv.  Before that update the
+// owner of column k + 1 applies the step to that one column, searches its
+// pivot and publishes column and pivot for step k + 1, so the search
+// overlaps the other waves' updates.  One barrier per step.
+// A wave's register columns rotate by one after its second half's step
+// (k = 16 c + 2 v + 1), so the column a half searches next is always its
+// register column 0; after R rotations register column c holds the D
+// column e = g + 16 ((c + R) mod CPW).
+template <int RPL>
+__device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int li, int half, uint32_t used,
+                                           double* colout, int* piv_idx, double* piv_val) {
+    // |a| over the candidate rows (unused, i < n), -1 elsewhere; NaN never wins
+    double a[RPL];
+    double best = -1.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        a[r] = (i < n && !((used >> r) & 1u)) ? fabs(col[r]) : -1.0;
+        best = fmax(best, a[r]);
+    }
+    // largest value: inside rows of 16 lanes by DPP (quad swaps, half-row
+    // and row mirrors), then the owning half's two rows
+    best = fmax(best, dpp_f64<0xB1>(best));
+    best = fmax(best, dpp_f64<0x4E>(best));
+    best = fmax(best, dpp_f64<0x141>(best));
+    best = fmax(best, dpp_f64<0x140>(best));
+    const int l0 = 32 * half;
+    const double gmax = fmax(readlane_f64(best, l0), readlane_f64(best, l0 + 16));
+    // smallest row attaining it: the first register row r with a hit in the
+    // owning half, its lowest lane; the sign comes from the same ballot row
+    int si = 0x7fffffff;
+    bool neg = false;
+#pragma unroll
+    for (int r = RPL - 1; r >= 0; --r) {
+        const uint32_t hit = (uint32_t)(__ballot(a[r] == gmax) >> l0);
+        const uint32_t ng = (uint32_t)(__ballot(col[r] < 0.0) >> l0);
+        if (hit) {
+            const int lw = __builtin_ctz(hit);
+            si = 32 * r + lw;
+            neg = (ng >> lw) & 1u;
+        }
+    }
+    if (!(gmax >= 0.0)) si = 0x7fffffff;  // no candidate row
+    const double pv = neg ? -gmax : gmax;
+    const double inv = 1.0 / pv;
+    if ((threadIdx.x & 63) >> 5 == half) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = li + 32 * r;
+            if (i < n) colout[i] = i == si ? 0.0 : -col[r] * inv;
+        }
+    }
+    if ((threadIdx.x & 63) == 0) { *piv_idx = si; *piv_val = pv; }
+}
+
+template <int RPL, int CPW, typename Tin>
+__device__ __forceinline__ void gjh_body(const Job& j, int bx) {
+    const Tin* __restrict__ C = (const Tin*)j.C;
+    const int n = j.n, spin = j.spin;
+    double* __restrict__ Dinv = j.Dinv;
+    double* __restrict__ logdet = j.logdet;
+    int8_t* __restrict__ sign = j.sign;
+    uint32_t* __restrict__ status = j.status;
+    constexpr int NG = 16, NT = 512;
+    constexpr int NR = 32 * RPL;  // capacity in D rows (MO index i)
+    constexpr int NC = NG * CPW;  // capacity in D columns (electron index e)
+    constexpr int QC = 8;         // rows of D^-1 staged per output pass
+    __shared__ double colbuf[2][NR];
+    __shared__ int piv_idx[2];
+    __shared__ double piv_val[2];
+    __shared__ __align__(16) double prow[NG][CPW];
+    __shared__ int perm[NC];
+    __shared__ int invp[NR];
+    __shared__ double rowpiv[NR];
+    __shared__ double stage[QC][NC > NR ? NC : NR];
+    __shared__ int s_flag;
+
+    const int w = bx;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const int g = 2 * wave + h;                                  // column group of this half
+    const size_t nn = (size_t)n * n;
+    const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
+
+    double M[RPL][CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int e = g + NG * c, i = li + 32 * r;
+            M[r][c] = (e < n && i < n) ? (double)C1[(size_t)e * n + i] : 0.0;
+        }
+    for (int k = tid; k < NR; k += NT) { colbuf[0][k] = 0.0; colbuf[1][k] = 0.0; }
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    uint32_t used = 0;  // bit r: row li + 32 r already a pivot row
+    int rot = 0;        // rotations of this wave's register columns (mod CPW)
+    if (wave == 0) {
+        double col[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) col[r] = M[r][0];
+        gjh_search<RPL>(col, n, li, 0, used, colbuf[0], &piv_idx[0], &piv_val[0]);
+    }
+
+    bool singular = false;
+    for (int k = 0; k < n; ++k) {
+        const int b = k & 1;
+        __syncthreads();  // pivot and column k are published, step k-1 is done
+        const int p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
+        const double pv = readlane_f64(piv_val[b], 0);
+        if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
+            singular = true;
+            if (tid == 0) s_flag = isfinite(pv) || p >= n ? 1 : 2;
+            break;
+        }
+        const int lp = p & 31, rp = p >> 5;  // wave-uniform
+        const int gk = k % NG;
+        double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
+        if (tid == 0) {
+            perm[k] = p;
+            rowpiv[p] = pv;
+        }
+        // this half's segment of the pivot row; column k takes pv + 1, which
+        // turns it into -D[i][k]/pv (the pivot row itself is untouched)
+        if (li == lp) {
+            static_for<0, RPL>([&](auto rr) __attribute__((always_inline)) {
+                constexpr int r = decltype(rr)::value;
+                if (rp == r) {
+#pragma unroll
+                    for (int c = 0; c < CPW; ++c) prow[g][c] = M[r][c];
+                    // keeps the RPL branches apart: merged, they would index
+                    // M through a pointer and move it out of registers
+                    asm volatile("; pivot row %0" ::"n"(r));
+                }
+            });
+        }
+        if (wave == (gk >> 1) && lane == 0) prow[gk][0] = pv + 1.0;
+        const int k1 = k + 1;
+        const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
+        if (k1 < n && wave == ((k1 % NG) >> 1)) {
+            // look-ahead: column k + 1 (register column 0 of its half) after
+            // this step, its pivot, published
+            const double x = prow[g][0];
+            double col[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
+            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1]);
+        }
+        double pr[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) pr[c] = prow[g][c];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) M[r][c] = fma(colv[r], pr[c], M[r][c]);
+        used = used1;
+        if ((k & 1) && wave == (gk >> 1)) {  // both halves done with column 0
+            double t[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) t[r] = M[r][0];
+#pragma unroll
+            for (int c = 0; c + 1 < CPW; ++c)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][c] = M[r][c + 1];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) M[r][CPW - 1] = t[r];
+            rot = rot + 1 == CPW ? 0 : rot + 1;
+        }
+    }
+    __syncthreads();
+
+    double* Dw = Dinv + (size_t)w * nn;
+    if (singular) {
+        // undefined inverse: NaN, log|det| = -inf, sign = 0
+        for (size_t q = tid; q < nn; q += NT) Dw[q] = __longlong_as_double(0x7ff8000000000000ll);
+        if (tid == 0) {
+            if (logdet) logdet[2 * w + spin] = s_flag == 1 ? -INFINITY : __longlong_as_double(0x7ff8000000000000ll);
+            if (sign) sign[2 * w + spin] = 0;
+            if (status) atomicOr(status + w, s_flag == 1 ? QSL_STATUS_SINGULAR : QSL_STATUS_NONFINITE);
+        }
+        return;
+    }
+    if (tid < 64) {
+        // log|det| = sum log|pivot|, sign = sign(permutation) prod sign(pivot)
+        double ld = 0.0;
+        int neg = 0;
+        for (int i = tid; i < n; i += 64) {
+            ld += log(fabs(rowpiv[i]));
+            neg += rowpiv[i] < 0.0;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            ld += __shfl_xor(ld, o);
+            neg += __shfl_xor(neg, o);
+        }
+        if (tid == 0) {
+            // parity of the pivot permutation by cycle counting (invp as scratch)
+            for (int i = 0; i < n; ++i) invp[i] = 0;
+            int cycles = 0;
+            for (int i = 0; i < n; ++i) {
+                if (invp[i]) continue;
+                ++cycles;
+                for (int jj = i; !invp[jj]; jj = perm[jj]) invp[jj] = 1;
+            }
+            const int sg = ((neg + n - cycles) & 1) ? -1 : 1;
+            if (logdet) logdet[2 * w + spin] = ld;
+            if (sign) sign[2 * w + spin] = (int8_t)sg;
+            if (status && !isfinite(ld)) atomicOr(status + w, QSL_STATUS_NONFINITE);
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < n; k += NT) invp[perm[k]] = k;
+    __syncthreads();
+    // the pivot entries were left at pv during the elimination (the pivot row
+    // is never scaled); their value in the scaled representation is 1, and
+    // later updates of them only added terms: M[p_k][k] += 1 - pv_k
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        if (i >= n) continue;
+        const int kp = invp[i];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            if (g + NG * (c + rot < CPW ? c + rot : c + rot - CPW) == kp) M[r][c] += 1.0 - rowpiv[i];
+    }
+    // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
+    int rowi[RPL];
+    double rs[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        rowi[r] = i < n ? invp[i] : -1;
+        rs[r] = i < n ? 1.0 / rowpiv[i] : 0.0;
+    }
+    for (int q0 = 0; q0 < n; q0 += QC) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int rr = rowi[r] - q0;
+            if (rr >= 0 && rr < QC) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c) {
+                    const int e = g + NG * (c + rot < CPW ? c + rot : c + rot - CPW);
+                    if (e < n) stage[rr][perm[e]] = M[r][c] * rs[r];
+                }
+            }
+        }
+        __syncthreads();
+        const int rows = min(QC, n - q0);
+        for (int q = tid; q < rows * n; q += NT) {
+            const int rr = q / n, cc = q % n;
+            Dw[(size_t)(q0 + rr) * n + cc] = stage[rr][cc];
+        }
+        __syncthreads();
+    }
+}
+
+template <int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(512) void gjh_kernel(Job j) {
+    gjh_body<RPL, CPW, Tin>(j, blockIdx.x);
+}
+
+template <int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(512) void gjh_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gjh_body<RPL, CPW, Tin>(j, bx); });
+}
+
 template <int NWV, int RPL, int CPW, typename Tin>
 __global__ __launch_bounds__(NWV * 64) void gj_kernel(Job j) {
     gj_body<NWV, RPL, CPW, Tin>(j, blockIdx.x);
@@ -307,7 +582,10 @@ static hipError_t gj_dispatch(const Job& j, int v, bool batched, const Job* jobs
         case 0: QSL_GJ(2, 1, 16); break;
         case 1: QSL_GJ(4, 1, 16); break;
         case 2: QSL_GJ(8, 2, 16); break;
-        default: QSL_GJ(8, 4, 28); break;
+        default:
+            if (batched) gjh_batched<7, 14, Tin><<<g, 512, 0, st>>>(jobs, prefix, njobs);
+            else gjh_kernel<7, 14, Tin><<<g, 512, 0, st>>>(j);
+            break;
     }
 #undef QSL_GJ
     return hipGetLastError();
