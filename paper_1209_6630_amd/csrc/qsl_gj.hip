@@ -340,7 +340,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     constexpr int NG = 16, NT = 512;
     constexpr int NR = 32 * RPL;  // capacity in D rows (MO index i)
     constexpr int NC = NG * CPW;  // capacity in D columns (electron index e)
-    constexpr int QC = 8;         // rows of D^-1 staged per output pass
+    constexpr int QC = 32;        // rows of D^-1 staged per output pass
     __shared__ double colbuf[2][NR];
     __shared__ int piv_idx[2];
     __shared__ double piv_val[2];
@@ -349,6 +349,8 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     __shared__ int invp[NR];
     __shared__ double rowpiv[NR];
     __shared__ double stage[QC][NC > NR ? NC : NR];
+    __shared__ double red_ld[NT / 64];
+    __shared__ int red_neg[NT / 64];
     __shared__ int s_flag;
 
     const int w = bx;
@@ -358,13 +360,16 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     const size_t nn = (size_t)n * n;
     const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
 
+    // every load unconditional (clamped address, padding zeroed after), so
+    // that all of them are in flight together
     double M[RPL][CPW];
 #pragma unroll
     for (int c = 0; c < CPW; ++c)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int e = g + NG * c, i = li + 32 * r;
-            M[r][c] = (e < n && i < n) ? (double)C1[(size_t)e * n + i] : 0.0;
+            const Tin v = C1[min(e, n - 1) * n + min(i, n - 1)];
+            M[r][c] = (e < n && i < n) ? (double)v : 0.0;
         }
     for (int k = tid; k < NR; k += NT) { colbuf[0][k] = 0.0; colbuf[1][k] = 0.0; }
     if (tid == 0) s_flag = 0;
@@ -458,40 +463,40 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         }
         return;
     }
-    if (tid < 64) {
-        // log|det| = sum log|pivot|, sign = sign(permutation) prod sign(pivot)
+    // log|det| = sum log|pivot|; sign = sign(permutation) prod sign(pivot),
+    // the permutation's sign from the parity of its inversions
+    {
         double ld = 0.0;
         int neg = 0;
-        for (int i = tid; i < n; i += 64) {
-            ld += log(fabs(rowpiv[i]));
-            neg += rowpiv[i] < 0.0;
+        if (tid < n) {
+            ld = log(fabs(rowpiv[tid]));
+            neg = rowpiv[tid] < 0.0;
+            const int pa = perm[tid];
+            for (int b2 = tid + 1; b2 < n; ++b2) neg += perm[b2] < pa;
         }
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) {
             ld += __shfl_xor(ld, o);
             neg += __shfl_xor(neg, o);
         }
-        if (tid == 0) {
-            // parity of the pivot permutation by cycle counting (invp as scratch)
-            for (int i = 0; i < n; ++i) invp[i] = 0;
-            int cycles = 0;
-            for (int i = 0; i < n; ++i) {
-                if (invp[i]) continue;
-                ++cycles;
-                for (int jj = i; !invp[jj]; jj = perm[jj]) invp[jj] = 1;
-            }
-            const int sg = ((neg + n - cycles) & 1) ? -1 : 1;
-            if (logdet) logdet[2 * w + spin] = ld;
-            if (sign) sign[2 * w + spin] = (int8_t)sg;
-            if (status && !isfinite(ld)) atomicOr(status + w, QSL_STATUS_NONFINITE);
-        }
+        if (lane == 0) { red_ld[wave] = ld; red_neg[wave] = neg; }
     }
-    __syncthreads();
     for (int k = tid; k < n; k += NT) invp[perm[k]] = k;
     __syncthreads();
+    if (tid == 0) {
+        double ld = 0.0;
+        int neg = 0;
+        for (int v = 0; v < NT / 64; ++v) { ld += red_ld[v]; neg += red_neg[v]; }
+        if (logdet) logdet[2 * w + spin] = ld;
+        if (sign) sign[2 * w + spin] = (neg & 1) ? -1 : 1;
+        if (status && !isfinite(ld)) atomicOr(status + w, QSL_STATUS_NONFINITE);
+    }
     // the pivot entries were left at pv during the elimination (the pivot row
     // is never scaled); their value in the scaled representation is 1, and
     // later updates of them only added terms: M[p_k][k] += 1 - pv_k
+    int ec[CPW];  // D column of each register column
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) ec[c] = g + NG * (c + rot < CPW ? c + rot : c + rot - CPW);
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = li + 32 * r;
@@ -499,7 +504,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         const int kp = invp[i];
 #pragma unroll
         for (int c = 0; c < CPW; ++c)
-            if (g + NG * (c + rot < CPW ? c + rot : c + rot - CPW) == kp) M[r][c] += 1.0 - rowpiv[i];
+            if (ec[c] == kp) M[r][c] += 1.0 - rowpiv[i];
     }
     // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
     int rowi[RPL];
@@ -510,16 +515,16 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         rowi[r] = i < n ? invp[i] : -1;
         rs[r] = i < n ? 1.0 / rowpiv[i] : 0.0;
     }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) ec[c] = ec[c] < n ? perm[ec[c]] : -1;  // destination column
     for (int q0 = 0; q0 < n; q0 += QC) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int rr = rowi[r] - q0;
             if (rr >= 0 && rr < QC) {
 #pragma unroll
-                for (int c = 0; c < CPW; ++c) {
-                    const int e = g + NG * (c + rot < CPW ? c + rot : c + rot - CPW);
-                    if (e < n) stage[rr][perm[e]] = M[r][c] * rs[r];
-                }
+                for (int c = 0; c < CPW; ++c)
+                    if (ec[c] >= 0) stage[rr][ec[c]] = M[r][c] * rs[r];
             }
         }
         __syncthreads();
