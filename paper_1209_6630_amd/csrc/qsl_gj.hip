@@ -422,12 +422,18 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
         if (k1 < n && wave == ((k1 % NG) >> 1)) {
             // look-ahead: column k + 1 (register column 0 of its half) after
-            // this step, its pivot, published
-            const double x = prow[g][0];
+            // this step, its pivot, published.  It is the step's critical
+            // path: the wave runs it at raised priority over its SIMD mate.
+            __builtin_amdgcn_s_setprio(3);
+            double xr = M[0][0];
+#pragma unroll
+            for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
+            const double x = readlane_f64(xr, 32 * (k1 & 1) + lp);  // pivot row, column k + 1
             double col[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
             gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1]);
+            __builtin_amdgcn_s_setprio(0);
         }
         double pr[CPW];
 #pragma unroll
