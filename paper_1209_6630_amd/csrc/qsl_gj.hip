@@ -277,14 +277,18 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 // the published column k, already scaled by -1/pv.  Before that update the
 // owner of column k + 1 applies the step to that one column, searches its
 // pivot and publishes column and pivot for step k + 1, so the search
-// overlaps the other waves' updates.  One barrier per step.
+// overlaps the other waves' updates.  No barrier per step: the publisher
+// raises a flag in LDS, each wave records the last step whose inputs it has
+// read, and a publisher overwrites a buffer (two, by step parity) only once
+// every wave has read it; the waves run up to two steps apart, so one
+// wave's latencies hide behind another's FMAs.
 // A wave's register columns rotate by one after its second half's step
 // (k = 16 c + 2 v + 1), so the column a half searches next is always its
 // register column 0; after R rotations register column c holds the D
 // column e = g + 16 ((c + R) mod CPW).
-template <int RPL>
+template <int RPL, typename Before>
 __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int li, int half, uint32_t used,
-                                           double* colout, int* piv_idx, double* piv_val) {
+                                           double* colout, int* piv_idx, double* piv_val, Before&& before) {
     // |a| over the candidate rows (unused, i < n), -1 elsewhere; NaN never wins
     double a[RPL];
     double best = -1.0;
@@ -319,6 +323,7 @@ __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int 
     if (!(gmax >= 0.0)) si = 0x7fffffff;  // no candidate row
     const double pv = neg ? -gmax : gmax;
     const double inv = 1.0 / pv;
+    before();  // the buffers may be overwritten from here on
     if ((threadIdx.x & 63) >> 5 == half) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
@@ -327,6 +332,15 @@ __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int 
         }
     }
     if ((threadIdx.x & 63) == 0) { *piv_idx = si; *piv_val = pv; }
+}
+
+// Workgroup-scope flag accesses in LDS (acquire / release order the data
+// accesses of the issuing wave around them).
+__device__ __forceinline__ int flag_load(int* f) {
+    return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void flag_store(int* f, int v) {
+    __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int RPL, int CPW, typename Tin>
@@ -352,6 +366,9 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     __shared__ double red_ld[NT / 64];
     __shared__ int red_neg[NT / 64];
     __shared__ int s_flag;
+    __shared__ int pub;           // last step whose pivot and column are published
+    __shared__ int prog[NT / 64]; // last step each wave has read its inputs of
+    __shared__ int s_abort;       // a wait ran over its bound
 
     const int w = bx;
     const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
@@ -372,23 +389,52 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             M[r][c] = (e < n && i < n) ? (double)v : 0.0;
         }
     for (int k = tid; k < NR; k += NT) { colbuf[0][k] = 0.0; colbuf[1][k] = 0.0; }
-    if (tid == 0) s_flag = 0;
+    if (tid == 0) { s_flag = 0; pub = -1; s_abort = 0; }
+    if (tid < NT / 64) prog[tid] = -1;
     __syncthreads();
+    // Waits on the flags, bounded: past SPIN_LIMIT polls (or once another
+    // wave gave up) the wave sets s_abort and leaves the elimination, so
+    // every wave reaches the end of the kernel.
+    constexpr int SPIN_LIMIT = 1 << 22;
+    auto give_up = [&]() {
+        if (lane == 0) flag_store(&s_abort, 1);
+        return false;
+    };
+    auto wait_published = [&](int step) -> bool {  // pivot and column of step published
+        for (int it = 0;; ++it) {
+            if (__builtin_amdgcn_readfirstlane(flag_load(&pub)) >= step) return true;
+            if (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort))) return give_up();
+            __builtin_amdgcn_s_sleep(1);
+        }
+    };
+    auto wait_consumed = [&](int step) -> bool {  // every wave has read the inputs of step
+        for (int it = 0;; ++it) {
+            const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
+            if (__ballot(pg < step) == 0) return true;
+            if (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort))) return give_up();
+            __builtin_amdgcn_s_sleep(1);
+        }
+    };
     uint32_t used = 0;  // bit r: row li + 32 r already a pivot row
     int rot = 0;        // rotations of this wave's register columns (mod CPW)
     if (wave == 0) {
         double col[RPL];
 #pragma unroll
         for (int r = 0; r < RPL; ++r) col[r] = M[r][0];
-        gjh_search<RPL>(col, n, li, 0, used, colbuf[0], &piv_idx[0], &piv_val[0]);
+        gjh_search<RPL>(col, n, li, 0, used, colbuf[0], &piv_idx[0], &piv_val[0], [] {});
+        if (lane == 0) flag_store(&pub, 0);
     }
 
     bool singular = false;
     for (int k = 0; k < n; ++k) {
         const int b = k & 1;
-        __syncthreads();  // pivot and column k are published, step k-1 is done
+        if (!wait_published(k)) break;
         const int p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
         const double pv = readlane_f64(piv_val[b], 0);
+        double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
+        if (lane == 0) flag_store(&prog[wave], k);  // after the reads above
         if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
             singular = true;
             if (tid == 0) s_flag = isfinite(pv) || p >= n ? 1 : 2;
@@ -396,9 +442,6 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         }
         const int lp = p & 31, rp = p >> 5;  // wave-uniform
         const int gk = k % NG;
-        double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
         if (tid == 0) {
             perm[k] = p;
             rowpiv[p] = pv;
@@ -432,8 +475,13 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             double col[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
-            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1]);
+            // buffer b ^ 1 last held step k - 1: written once every wave read it
+            bool ok = true;
+            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1],
+                            [&] { ok = wait_consumed(k - 1); });
             __builtin_amdgcn_s_setprio(0);
+            if (!ok) break;
+            if (lane == 0) flag_store(&pub, k1);
         }
         double pr[CPW];
 #pragma unroll
@@ -457,6 +505,10 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         }
     }
     __syncthreads();
+    if (s_abort) {  // reported as a non-finite result
+        singular = true;
+        if (tid == 0) s_flag = 2;
+    }
 
     double* Dw = Dinv + (size_t)w * nn;
     if (singular) {
