@@ -279,8 +279,8 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 // pivot and publishes column and pivot for step k + 1, so the search
 // overlaps the other waves' updates.  No barrier per step: the publisher
 // raises a flag in LDS, each wave records the last step whose inputs it has
-// read, and a publisher overwrites a buffer (two, by step parity) only once
-// every wave has read it; the waves run up to two steps apart, so one
+// read, and a publisher overwrites a buffer (four, by step mod 4) only once
+// every wave has read it; the waves run a few steps apart, so one
 // wave's latencies hide behind another's FMAs.
 // A wave's register columns rotate by one after its second half's step
 // (k = 16 c + 2 v + 1), so the column a half searches next is always its
@@ -355,9 +355,10 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     constexpr int NR = 32 * RPL;  // capacity in D rows (MO index i)
     constexpr int NC = NG * CPW;  // capacity in D columns (electron index e)
     constexpr int QC = 32;        // rows of D^-1 staged per output pass
-    __shared__ double colbuf[2][NR];
-    __shared__ int piv_idx[2];
-    __shared__ double piv_val[2];
+    constexpr int NB = 4;         // publication buffers, by step mod NB
+    __shared__ double colbuf[NB][NR];
+    __shared__ int piv_idx[NB];
+    __shared__ double piv_val[NB];
     __shared__ __align__(16) double prow[NG][CPW];
     __shared__ int perm[NC];
     __shared__ int invp[NR];
@@ -388,7 +389,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             const Tin v = C1[min(e, n - 1) * n + min(i, n - 1)];
             M[r][c] = (e < n && i < n) ? (double)v : 0.0;
         }
-    for (int k = tid; k < NR; k += NT) { colbuf[0][k] = 0.0; colbuf[1][k] = 0.0; }
+    for (int k = tid; k < NB * NR; k += NT) colbuf[k / NR][k % NR] = 0.0;
     if (tid == 0) { s_flag = 0; pub = -1; s_abort = 0; }
     if (tid < NT / 64) prog[tid] = -1;
     __syncthreads();
@@ -427,7 +428,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
 
     bool singular = false;
     for (int k = 0; k < n; ++k) {
-        const int b = k & 1;
+        const int b = k % NB, b1 = (k + 1) % NB;
         if (!wait_published(k)) break;
         const int p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
         const double pv = readlane_f64(piv_val[b], 0);
@@ -446,6 +447,29 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             perm[k] = p;
             rowpiv[p] = pv;
         }
+        const int k1 = k + 1;
+        const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
+        if (k1 < n && wave == ((k1 % NG) >> 1)) {
+            // look-ahead: column k + 1 (register column 0 of its half) after
+            // this step, its pivot, published.  It is the step's critical
+            // path: first thing after the inputs, at raised priority over
+            // the SIMD mate.
+            __builtin_amdgcn_s_setprio(3);
+            double xr = M[0][0];
+#pragma unroll
+            for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
+            const double x = readlane_f64(xr, 32 * (k1 & 1) + lp);  // pivot row, column k + 1
+            double col[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
+            // buffer b1 last held step k + 1 - NB: written once every wave read it
+            bool ok = true;
+            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1],
+                            [&] { ok = wait_consumed(k1 - NB); });
+            if (ok && lane == 0) flag_store(&pub, k1);
+            __builtin_amdgcn_s_setprio(0);
+            if (!ok) break;
+        }
         // this half's segment of the pivot row; column k takes pv + 1, which
         // turns it into -D[i][k]/pv (the pivot row itself is untouched)
         if (li == lp) {
@@ -461,28 +485,6 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             });
         }
         if (wave == (gk >> 1) && lane == 0) prow[gk][0] = pv + 1.0;
-        const int k1 = k + 1;
-        const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
-        if (k1 < n && wave == ((k1 % NG) >> 1)) {
-            // look-ahead: column k + 1 (register column 0 of its half) after
-            // this step, its pivot, published.  It is the step's critical
-            // path: the wave runs it at raised priority over its SIMD mate.
-            __builtin_amdgcn_s_setprio(3);
-            double xr = M[0][0];
-#pragma unroll
-            for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
-            const double x = readlane_f64(xr, 32 * (k1 & 1) + lp);  // pivot row, column k + 1
-            double col[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
-            // buffer b ^ 1 last held step k - 1: written once every wave read it
-            bool ok = true;
-            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b ^ 1], &piv_idx[b ^ 1], &piv_val[b ^ 1],
-                            [&] { ok = wait_consumed(k - 1); });
-            __builtin_amdgcn_s_setprio(0);
-            if (!ok) break;
-            if (lane == 0) flag_store(&pub, k1);
-        }
         double pr[CPW];
 #pragma unroll
         for (int c = 0; c < CPW; ++c) pr[c] = prow[g][c];
