@@ -268,7 +268,8 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 }
 
 // Half-wave layout for 128 < n <= 224 (eight waves).  Half h of wave v is
-// column group g = 2 v + h of 16; lane li (< 32) of the half owns the D rows
+// column group g = v + 8 h of 16, so that consecutive columns belong to
+// different waves; lane li (< 32) of the half owns the D rows
 // i = li + 32 r (r < RPL) and holds M[r][c] for the D columns e = g + 16 c
 // (c < CPW): 7 x 14 values per lane cover 224 x 224 with little padding.
 // Step k: every half writes its segment of the pivot row (lane p % 32,
@@ -283,7 +284,7 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 // every wave has read it; the waves run a few steps apart, so one
 // wave's latencies hide behind another's FMAs.
 // A wave's register columns rotate by one after its second half's step
-// (k = 16 c + 2 v + 1), so the column a half searches next is always its
+// (k = 16 c + v + 8), so the column a half searches next is always its
 // register column 0; after R rotations register column c holds the D
 // column e = g + 16 ((c + R) mod CPW).
 template <int RPL, typename Before>
@@ -334,13 +335,19 @@ __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int 
     if ((threadIdx.x & 63) == 0) { *piv_idx = si; *piv_val = pv; }
 }
 
-// Workgroup-scope flag accesses in LDS (acquire / release order the data
-// accesses of the issuing wave around them).
+// Flag accesses in LDS.  The LDS executes the DS instructions of one wave in
+// program order, so a flag written after a wave's data writes is seen only
+// once they are done, and data read after a flag was seen is the data
+// published before it; only the compiler has to keep the order (the
+// signal fences), no wait is needed.
 __device__ __forceinline__ int flag_load(int* f) {
-    return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int v = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return v;
 }
 __device__ __forceinline__ void flag_store(int* f, int v) {
-    __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int RPL, int CPW, typename Tin>
@@ -374,7 +381,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     const int w = bx;
     const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-    const int g = 2 * wave + h;                                  // column group of this half
+    const int g = wave + 8 * h;                                  // column group of this half
     const size_t nn = (size_t)n * n;
     const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
 
@@ -401,19 +408,22 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         if (lane == 0) flag_store(&s_abort, 1);
         return false;
     };
+    auto stop = [&](int it) {  // the abort flag is polled every 64th time
+        return (it & 63) == 63 && (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort)));
+    };
     auto wait_published = [&](int step) -> bool {  // pivot and column of step published
         for (int it = 0;; ++it) {
             if (__builtin_amdgcn_readfirstlane(flag_load(&pub)) >= step) return true;
-            if (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort))) return give_up();
-            __builtin_amdgcn_s_sleep(1);
+            if (stop(it)) return give_up();
+            if (it >= 4) __builtin_amdgcn_s_sleep(1);
         }
     };
     auto wait_consumed = [&](int step) -> bool {  // every wave has read the inputs of step
         for (int it = 0;; ++it) {
             const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
             if (__ballot(pg < step) == 0) return true;
-            if (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort))) return give_up();
-            __builtin_amdgcn_s_sleep(1);
+            if (stop(it)) return give_up();
+            if (it >= 4) __builtin_amdgcn_s_sleep(1);
         }
     };
     uint32_t used = 0;  // bit r: row li + 32 r already a pivot row
@@ -449,7 +459,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         }
         const int k1 = k + 1;
         const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
-        if (k1 < n && wave == ((k1 % NG) >> 1)) {
+        if (k1 < n && wave == (k1 & 7)) {
             // look-ahead: column k + 1 (register column 0 of its half) after
             // this step, its pivot, published.  It is the step's critical
             // path: first thing after the inputs, at raised priority over
@@ -458,13 +468,14 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             double xr = M[0][0];
 #pragma unroll
             for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
-            const double x = readlane_f64(xr, 32 * (k1 & 1) + lp);  // pivot row, column k + 1
+            const int h1 = (k1 % NG) >> 3;  // half owning column k + 1
+            const double x = readlane_f64(xr, 32 * h1 + lp);  // pivot row, column k + 1
             double col[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
             // buffer b1 last held step k + 1 - NB: written once every wave read it
             bool ok = true;
-            gjh_search<RPL>(col, n, li, k1 & 1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1],
+            gjh_search<RPL>(col, n, li, h1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1],
                             [&] { ok = wait_consumed(k1 - NB); });
             if (ok && lane == 0) flag_store(&pub, k1);
             __builtin_amdgcn_s_setprio(0);
@@ -484,7 +495,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
                 }
             });
         }
-        if (wave == (gk >> 1) && lane == 0) prow[gk][0] = pv + 1.0;
+        if (wave == (gk & 7) && lane == 0) prow[gk][0] = pv + 1.0;
         double pr[CPW];
 #pragma unroll
         for (int c = 0; c < CPW; ++c) pr[c] = prow[g][c];
@@ -493,7 +504,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
 #pragma unroll
             for (int r = 0; r < RPL; ++r) M[r][c] = fma(colv[r], pr[c], M[r][c]);
         used = used1;
-        if ((k & 1) && wave == (gk >> 1)) {  // both halves done with column 0
+        if (gk >= 8 && wave == (gk & 7)) {  // both halves done with column 0
             double t[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) t[r] = M[r][0];
