@@ -9,11 +9,13 @@
 // straight into LDS, so B never reaches HBM, then the four waves run the
 // contraction on MFMA with the 5 x 32 rows (derivative, electron) as the M
 // dimension and MOs as N.  Zero rows/columns of the screened B cost MFMA
-// work but no memory traffic.
+// work but no memory traffic.  In the f32 modes each wave holds two MO
+// sub-blocks, so one evaluation of the AOs serves 256 MOs; a sub-block past
+// n is skipped.
 //
 // Precision modes:
 //   FP64   AO eval FP64, v_mfma_f64_16x16x4f64, 64 MOs per workgroup.
-//   FP32   AO eval FP32, v_mfma_f32_32x32x2f32, 128 MOs per workgroup.
+//   FP32   AO eval FP32, v_mfma_f32_32x32x2f32, 256 MOs per workgroup.
 //   BF16X3 AO eval FP32, each operand split x = hi + lo (bf16, round to
 //          nearest even), C += Bhi Ahi + Bhi Alo + Blo Ahi on
 //          v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
@@ -33,7 +35,9 @@ struct CT {
     static constexpr int KW = MODE == QSL_FP64 ? 4 : 8;
     static constexpr int KC = KW * WIN;
     static constexpr int NBW = MODE == QSL_FP64 ? 16 : 32;
-    static constexpr int NB = CT_WAVES * NBW;
+    static constexpr int MSUB = MODE == QSL_FP64 ? 1 : 2;  // MO sub-blocks per wave
+    static constexpr int NSB = CT_WAVES * NBW;      // MOs per sub-block
+    static constexpr int NB = MSUB * NSB;
     static constexpr int THREADS = CT_WAVES * 64;
     // AO evaluation: slots of one window per thread (8, or 4 when the
     // workgroup has twice as many threads as (electron, window) pairs)
@@ -88,14 +92,19 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const int nwin = tile_nwin[tile];
     const int* wins = tile_win + (size_t)tile * s.n_win;
 
-    f32x16 acc32[5];
-    f64x4 acc64[5][2];
-    if constexpr (MODE == QSL_FP64) {
-        for (int d = 0; d < 5; ++d)
-            for (int h = 0; h < 2; ++h) acc64[d][h] = f64x4{0, 0, 0, 0};
-    } else {
-        for (int d = 0; d < 5; ++d)
-            for (int r = 0; r < 16; ++r) acc32[d][r] = 0.f;
+    constexpr int MSUB = P::MSUB, NSB = P::NSB;
+    const int nsub = min(MSUB, (n - n0 + NSB - 1) / NSB);  // sub-blocks below n (uniform)
+    f32x16 acc32[MSUB][5];
+    f64x4 acc64[MSUB][5][2];
+#pragma unroll
+    for (int sb = 0; sb < MSUB; ++sb) {
+        if constexpr (MODE == QSL_FP64) {
+            for (int d = 0; d < 5; ++d)
+                for (int h = 0; h < 2; ++h) acc64[sb][d][h] = f64x4{0, 0, 0, 0};
+        } else {
+            for (int d = 0; d < 5; ++d)
+                for (int r = 0; r < 16; ++r) acc32[sb][d][r] = 0.f;
+        }
     }
     bool tie = false;
     __syncthreads();
@@ -148,14 +157,8 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         if constexpr (MODE == QSL_BF16X3) {
             const uint16_t* bh = (const uint16_t*)bbuf;
             const uint16_t* bl = bh + BELEMS;
-            const int mo = n0 + wave * 32 + (lane & 31);
             const int oct = lane >> 5;
             for (int ks = 0; ks < KC / 16; ++ks) {
-                const size_t off = ((size_t)wq[ks * 2 + oct] * ldn + mo) * WIN;
-                const uint4 ah = *(const uint4*)(Ahi + off);
-                const uint4 al = *(const uint4*)(Alo + off);
-                const bf16x8 bah = __builtin_bit_cast(bf16x8, ah);
-                const bf16x8 bal = __builtin_bit_cast(bf16x8, al);
                 bf16x8 xh[5], xl[5];
 #pragma unroll
                 for (int d = 0; d < 5; ++d) {
@@ -163,41 +166,63 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                     xh[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bh + off));
                     xl[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bl + off));
                 }
-                // the three products of one accumulator are dependent: issue
-                // them five accumulators apart
+                const size_t wbase = (size_t)wq[ks * 2 + oct] * ldn;
 #pragma unroll
-                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bah, acc32[d], 0, 0, 0);
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    if (sb >= nsub) break;
+                    const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
+                    const size_t off = (wbase + mo) * WIN;
+                    const bf16x8 bah = __builtin_bit_cast(bf16x8, *(const uint4*)(Ahi + off));
+                    const bf16x8 bal = __builtin_bit_cast(bf16x8, *(const uint4*)(Alo + off));
+                    // the three products of one accumulator are dependent:
+                    // issue them five accumulators apart
 #pragma unroll
-                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bal, acc32[d], 0, 0, 0);
+                    for (int d = 0; d < 5; ++d)
+                        acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bah, acc32[sb][d], 0, 0, 0);
 #pragma unroll
-                for (int d = 0; d < 5; ++d) acc32[d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[d], bah, acc32[d], 0, 0, 0);
+                    for (int d = 0; d < 5; ++d)
+                        acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[d], bal, acc32[sb][d], 0, 0, 0);
+#pragma unroll
+                    for (int d = 0; d < 5; ++d)
+                        acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[d], bah, acc32[sb][d], 0, 0, 0);
+                }
             }
         } else if constexpr (MODE == QSL_FP32) {
             const float* bt = (const float*)bbuf;
-            const int mo = n0 + wave * 32 + (lane & 31);
             const int kk = lane >> 5;
             for (int ks = 0; ks < KC / 2; ++ks) {
                 const int c = ks * 2 + kk;
                 const int slot = wq[c / WIN] * WIN + (c % WIN);
-                const float b = AT32[(size_t)slot * ldn + mo];
-                for (int d = 0; d < 5; ++d) {
-                    const float a = bt[(d * TE + (lane & 31)) * LD + c];
-                    acc32[d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc32[d], 0, 0, 0);
+                float a[5];
+#pragma unroll
+                for (int d = 0; d < 5; ++d) a[d] = bt[(d * TE + (lane & 31)) * LD + c];
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    if (sb >= nsub) break;
+                    const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
+                    const float b = AT32[(size_t)slot * ldn + mo];
+#pragma unroll
+                    for (int d = 0; d < 5; ++d)
+                        acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[d], b, acc32[sb][d], 0, 0, 0);
                 }
             }
         } else {
             const double* bt = (const double*)bbuf;
-            const int mo = n0 + wave * 16 + (lane & 15);
             const int kk = lane >> 4;
             for (int ks = 0; ks < KC / 4; ++ks) {
                 const int c = ks * 4 + kk;
                 const int slot = wq[c / WIN] * WIN + (c % WIN);
-                const double b = AT64[(size_t)slot * ldn + mo];
-                for (int d = 0; d < 5; ++d)
-                    for (int h = 0; h < 2; ++h) {
-                        const double a = bt[(d * TE + h * 16 + (lane & 15)) * LD + c];
-                        acc64[d][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[d][h], 0, 0, 0);
-                    }
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    if (sb >= nsub) break;
+                    const int mo = n0 + sb * NSB + wave * 16 + (lane & 15);
+                    const double b = AT64[(size_t)slot * ldn + mo];
+                    for (int d = 0; d < 5; ++d)
+                        for (int h = 0; h < 2; ++h) {
+                            const double a = bt[(d * TE + h * 16 + (lane & 15)) * LD + c];
+                            acc64[sb][d][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc64[sb][d][h], 0, 0, 0);
+                        }
+                }
             }
         }
         __syncthreads();
@@ -206,38 +231,41 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     // a near tie of a kept primitive flags the walker of the thread's row
     if (tie && status) atomicOr(status + w0 + (tid & (TE - 1)), QSL_STATUS_NEAR_TIE);
     // ---- store C[w][d][e][mo]
-    if constexpr (MODE == QSL_FP64) {
-        double* C = (double*)Cout;
-        const int mo = n0 + wave * 16 + (lane & 15);
-        if (mo < n) {
-            for (int d = 0; d < 5; ++d)
-                for (int h = 0; h < 2; ++h)
-                    for (int r = 0; r < 4; ++r) {
-                        // v_mfma_f64_16x16x4f64 result: row (lane / 16) + 4 r, column lane % 16
-                        const int el = h * 16 + (lane >> 4) + 4 * r;
-                        if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[d][h][r];
+#pragma unroll
+    for (int sb = 0; sb < MSUB; ++sb) {
+        if constexpr (MODE == QSL_FP64) {
+            double* C = (double*)Cout;
+            const int mo = n0 + sb * NSB + wave * 16 + (lane & 15);
+            if (mo < n) {
+                for (int d = 0; d < 5; ++d)
+                    for (int h = 0; h < 2; ++h)
+                        for (int r = 0; r < 4; ++r) {
+                            // v_mfma_f64_16x16x4f64 result: row (lane / 16) + 4 r, column lane % 16
+                            const int el = h * 16 + (lane >> 4) + 4 * r;
+                            if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[sb][d][h][r];
+                        }
+            }
+        } else {
+            float* C = (float*)Cout;
+            const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
+            if (mo < n) {
+                for (int d = 0; d < 5; ++d)
+                    for (int r = 0; r < 16; ++r) {
+                        const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                        if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[sb][d][r];
                     }
-        }
-    } else {
-        float* C = (float*)Cout;
-        const int mo = n0 + wave * 32 + (lane & 31);
-        if (mo < n) {
-            for (int d = 0; d < 5; ++d)
-                for (int r = 0; r < 16; ++r) {
-                    const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[d][r];
-                }
+            }
         }
     }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CT_WAVES * 64) void contract_kernel(Job j) {
+__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_kernel(Job j) {
     contract_body<MODE>(j, blockIdx.x, blockIdx.y);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CT_WAVES * 64) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
     batch_block(jobs, prefix, njobs,
                 [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE>(j, bx, by); });
 }
