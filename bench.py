@@ -73,6 +73,8 @@ def work_per_step(sysm, nnz, W, mode):
         "adjoint_h": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         "adjoint_dA": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         "drift_lap": (epi, "hbm", HBM_PEAK, "GB/s"),
+        # dR = g drift: drift read, dR written, g read per component
+        "dR_drift": (sum(56.0 * n * W for n in ns), "hbm", HBM_PEAK, "GB/s"),
     }
 
 

@@ -184,13 +184,18 @@ typedef struct {
     int32_t accumulate_dA;    /* 1: dA += ..., 0: dA = ...                        */
     void* ws;
     size_t ws_bytes;
+    const double* drift;      /* optional [W][N][3] device: the forward's drift on
+                                 the same R; then dR = g drift (see below)       */
 } qsl_bwd_args;
 
 /*
- * Backward: recomputes the AO values and gradients (never stored by the
- * forward), forms G = g D^-1, H = A^T G at the surviving AOs for dR, and
- * accumulates dA over walkers.  Derivatives hold the screened survivor sets
- * fixed.  Walkers flagged singular must have g = 0.  Enqueued on `stream`.
+ * Backward: recomputes the AO values (never stored by the forward) and
+ * accumulates dA = sum_w G chi over walkers, G = g D^-1.  dR: with drift
+ * given, dR[w][e] = g[w][s(e)] drift[w][e] (0 where g = 0), since
+ * d log|det D^s| / dr_e = sum_i D^-1[e][i] grad phi_i(r_e) is the drift
+ * ("vector products" equations); without it, G A at the recomputed AO
+ * gradients.  Derivatives hold the screened survivor sets fixed.  Walkers
+ * flagged singular must have g = 0.  Enqueued on `stream`.
  * Errors: INVALID_ARG, WORKSPACE, HIP.
  */
 qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* args, void* stream);
@@ -238,7 +243,8 @@ qsl_status qsl_plan_create(int32_t n_sys, qsl_system* const* sys, const int64_t*
  * Bind the device buffers of system i: `fwd` as for qsl_forward (required;
  * its W and mode must match the plan, ws/ws_bytes are ignored), `bwd` as for
  * qsl_backward, or NULL for a forward-only system (its W and mode must
- * match, bwd->R must equal fwd->R, ws/ws_bytes ignored).  Pointers must
+ * match, bwd->R must equal fwd->R, ws/ws_bytes ignored; with bwd->drift
+ * NULL the forward's drift, if bound, serves for dR).  Pointers must
  * stay valid and fixed while the plan is launched (a graph replays them);
  * binding again invalidates a captured graph.  Nothing is enqueued.
  * Errors: INVALID_ARG, SHAPE (W or mode differ from the plan),

@@ -39,7 +39,7 @@ class BwdArgs(ct.Structure):
     _fields_ = [("W", ct.c_int64), ("R", ct.c_void_p), ("mode", ct.c_int32),
                 ("Dinv", ct.c_void_p * 2), ("g_logdet", ct.c_void_p), ("dR", ct.c_void_p),
                 ("dA", ct.c_void_p * 2), ("accumulate_dA", ct.c_int32), ("ws", ct.c_void_p),
-                ("ws_bytes", ct.c_size_t)]
+                ("ws_bytes", ct.c_size_t), ("drift", ct.c_void_p)]
 
 
 class Tuning(ct.Structure):

@@ -136,8 +136,10 @@ class System:
         return out
 
     def backward(self, R, Dinv_up, Dinv_dn, g, mode="fp64", dR=None, dA=None, accumulate=False,
-                 want_dR=True, want_dA=True):
-        """Adjoint of sum g[w,s] logdet[w,s].  Returns (dR, dA_up, dA_dn)."""
+                 want_dR=True, want_dA=True, drift=None):
+        """Adjoint of sum g[w,s] logdet[w,s].  Returns (dR, dA_up, dA_dn).
+        drift: the forward's drift on the same R (then dR = g drift);
+        None recomputes the AO gradients for dR."""
         W = R.shape[0]
         dev = "cuda"
         if want_dR and dR is None:
@@ -160,6 +162,7 @@ class System:
         a.accumulate_dA = 1 if accumulate else 0
         a.ws = ws.data_ptr()
         a.ws_bytes = ws.numel()
+        a.drift = drift.data_ptr() if drift is not None else None
         check(lib().qsl_backward(self._h, ct.byref(a), _stream()))
         return dR, (dA[0] if want_dA else None), (dA[1] if want_dA else None)
 
@@ -260,14 +263,14 @@ class SlaterLogDet(torch.autograd.Function):
         system.set_mo(1, A_dn.detach())
         out = system.forward(R.detach().contiguous(), mode)
         ctx.system, ctx.mode = system, mode
-        ctx.save_for_backward(R.detach(), out["Dinv_up"], out["Dinv_dn"])
+        ctx.save_for_backward(R.detach(), out["Dinv_up"], out["Dinv_dn"], out["drift"])
         ctx.mark_non_differentiable(out["sign"])
         return out["logdet"], out["sign"]
 
     @staticmethod
     def backward(ctx, g_logdet, _g_sign):
-        R, Di_up, Di_dn = ctx.saved_tensors
-        dR, dA_up, dA_dn = ctx.system.backward(R, Di_up, Di_dn, g_logdet, ctx.mode)
+        R, Di_up, Di_dn, drift = ctx.saved_tensors
+        dR, dA_up, dA_dn = ctx.system.backward(R, Di_up, Di_dn, g_logdet, ctx.mode, drift=drift)
         return dR, dA_up, dA_dn, None, None
 
 

@@ -189,6 +189,7 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
     j.Dinv = const_cast<double*>(a->Dinv[s]);
     j.g = a->g_logdet;
     j.dR = a->dR;
+    j.drift = const_cast<double*>(a->drift);  // read only by the backward
     if (a->dA[s]) {
         if (a->mode == QSL_FP64) j.dA64 = a->dA[s];
         else j.dA32 = (float*)(ws + L.dA32_off[s]);
@@ -582,18 +583,23 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
     WsLayout L = ws_layout(d, a->W, bw_group(a->W));
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     char* ws = (char*)a->ws;
-    if (a->dR && (e = fill_f64(a->dR, 0.0, a->W * N * 3, st)) != hipSuccess) return hip_fail(e, "dR clear");
+    // with the drift, dR is written whole (every electron of both spins)
+    if (a->dR && !a->drift && (e = fill_f64(a->dR, 0.0, a->W * N * 3, st)) != hipSuccess)
+        return hip_fail(e, "dR clear");
     for (int s = 0; s < 2; ++s) {
         Job j = bwd_job(sys, a, L, ws, s, bw_group(a->W));
         if (!j.n) continue;
         const bool f32acc = j.dA32 != nullptr;
         if (f32acc && (e = fill_u32((uint32_t*)j.dA32, 0u, (int64_t)j.n * d.n_basis, st)) != hipSuccess)
             return hip_fail(e, "dA accumulator clear");
-        {
-            ProfScope ps("screen", st);
-            if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
-        }
-        {
+        if (a->dR && a->drift) {
+            ProfScope ps("dR_drift", st);
+            if ((e = launch_dr_drift(j, st)) != hipSuccess) return hip_fail(e, "dR kernel");
+        } else if (a->dR) {
+            {
+                ProfScope ps("screen", st);
+                if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
+            }
             ProfScope ps("adjoint_h", st);
             if ((e = launch_adj_h(j, st)) != hipSuccess) return hip_fail(e, "adjoint H kernel");
         }

@@ -357,6 +357,10 @@ hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix
                              hipStream_t st);
 // Drift and Laplacian (four electrons per block).
 int epilogue_blocks(const Job& j);
+// dR of one spin from the forward's drift: dR[w][e] = g[w][s] drift[w][e].
+int dr_drift_blocks(const Job& j);
+hipError_t launch_dr_drift(const Job& j, hipStream_t st);
+hipError_t launch_dr_drift_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_epilogue(const Job& j, hipStream_t st);
 hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                       hipStream_t st);

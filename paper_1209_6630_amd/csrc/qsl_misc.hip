@@ -127,4 +127,43 @@ hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix,
     return hipGetLastError();
 }
 
+// dR through the forward's drift.  By Jacobi's formula the derivative of
+// log|det D^s| in r_e is sum_i D^-1[e][i] grad phi_i(r_e), the drift of the
+// "vector products" equations, so dR[w][e] = g[w][s] drift[w][e] for the
+// electrons e of spin s (exactly 0 where g = 0: a singular walker's drift is
+// NaN).  One thread per component.
+__device__ __forceinline__ void dr_drift_body(const Job& j, int bx) {
+    const int64_t q = (int64_t)bx * 256 + threadIdx.x;
+    const int64_t per_w = (int64_t)j.n * 3;
+    if (q >= j.W * per_w) return;
+    const int64_t w = q / per_w;
+    const int64_t r = q - w * per_w;  // e * 3 + component within the spin
+    const int N = j.s.n_up + j.s.n_dn;
+    const int64_t at = w * N * 3 + (j.spin ? (int64_t)j.s.n_up * 3 : 0) + r;
+    const double gw = j.g[2 * w + j.spin];
+    j.dR[at] = gw != 0.0 ? gw * j.drift[at] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void dr_drift_kernel(Job j) { dr_drift_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void dr_drift_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { dr_drift_body(j, bx); });
+}
+
+int dr_drift_blocks(const Job& j) { return (int)((j.W * j.n * 3 + 255) / 256); }
+
+hipError_t launch_dr_drift(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    j.gx = dr_drift_blocks(j); j.gy = 1; j.gz = 1;
+    if (!j.gx || !j.dR || !j.drift) return hipSuccess;
+    dr_drift_kernel<<<(unsigned)j.gx, 256, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_dr_drift_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    dr_drift_batched<<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
 }  // namespace qsl

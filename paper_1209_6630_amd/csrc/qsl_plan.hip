@@ -27,7 +27,8 @@ enum Phase {
     PH_GJ3,
     PH_GJ4,          // blocked (n > 224)
     PH_EPILOGUE,     // drift and Laplacian
-    PH_ADJ_H,        // H = G A, dR
+    PH_DR,           // dR = g drift (drift bound)
+    PH_ADJ_H,        // H = G A, dR (no drift bound)
     PH_SCREEN_G,     // per walker-group window lists
     PH_ADJ_DA,       // dA
     PH_COUNT
@@ -156,7 +157,10 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     for (const Job& b : p->bjobs) {
         if (!b.n || !b.W) continue;
         Job j = b;
-        if (j.dR) {
+        if (j.dR && j.drift) {
+            j.gx = dr_drift_blocks(j); j.gy = 1; j.gz = 1;
+            p->ph[PH_DR].jobs.push_back(j);
+        } else if (j.dR) {
             adj_h_grid(j);
             p->ph[PH_ADJ_H].jobs.push_back(j);
         }
@@ -220,7 +224,8 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         if (!p->has_bwd[i]) continue;
         const qsl_bwd_args& b = p->bwd[i];
         const DevSys& d = p->sys[i]->d;
-        if (b.dR && b.W && (e = fill_f64(b.dR, 0.0, b.W * (d.n_up + d.n_dn) * 3, st)) != hipSuccess)
+        // with the drift, dR is written whole
+        if (b.dR && !b.drift && b.W && (e = fill_f64(b.dR, 0.0, b.W * (d.n_up + d.n_dn) * 3, st)) != hipSuccess)
             return hip_fail(e, "dR clear");
     }
     for (int i = 0, k = 0; i < p->n_sys; ++i) {
@@ -295,6 +300,18 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         }
     }
     // adjoint (the tile lists of the forward's screening are reused)
+    auto& DRp = p->ph[PH_DR];
+    if (batched && DRp.blocks()) {
+        ProfScope ps("dR_drift", st);
+        if ((e = launch_dr_drift_batched(dev_jobs(p, PH_DR), dev_prefix(p, PH_DR), (int)DRp.jobs.size(), DRp.blocks(),
+                                         st)) != hipSuccess)
+            return hip_fail(e, "dR kernel");
+    } else if (!batched) {
+        for (const Job& j : DRp.jobs) {
+            ProfScope ps("dR_drift", st);
+            if ((e = launch_dr_drift(j, st)) != hipSuccess) return hip_fail(e, "dR kernel");
+        }
+    }
     auto& H = p->ph[PH_ADJ_H];
     auto& SG = p->ph[PH_SCREEN_G];
     auto& DA = p->ph[PH_ADJ_DA];
@@ -618,6 +635,8 @@ qsl_status qsl_plan_bind(qsl_plan* p, int32_t i, const qsl_fwd_args* f, const qs
         p->bwd[i] = *b;
         p->bwd[i].ws = nullptr;
         p->bwd[i].ws_bytes = 0;
+        // the adjoint runs after the forward: its drift gives dR
+        if (!p->bwd[i].drift) p->bwd[i].drift = f->drift;
     }
     p->bound[i] = 1;
     p->dirty = true;

@@ -32,24 +32,30 @@ def _abs_bounds(sysm, A_up, A_dn, R, ref, g):
     return bA, bR
 
 
-def _run(sysm, A_up, A_dn, R, mode, seed=0):
+def _run(sysm, A_up, A_dn, R, mode, seed=0, use_drift=False):
     import torch
     S = make_gpu_system(sysm, A_up, A_dn)
     Rt = torch.from_numpy(R).cuda()
     out = S.forward(Rt, mode)
     g = np.random.default_rng(seed).normal(size=(R.shape[0], 2))
     gt = torch.from_numpy(g).cuda()
-    dR, dAu, dAd = S.backward(Rt, out["Dinv_up"], out["Dinv_dn"], gt, mode)
+    dR, dAu, dAd = S.backward(Rt, out["Dinv_up"], out["Dinv_dn"], gt, mode,
+                              drift=out["drift"] if use_drift else None)
     torch.cuda.synchronize()
     return g, dR.cpu().numpy(), dAu.cpu().numpy(), dAd.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
 
 
-@pytest.mark.parametrize("name,W", [("44e", 8), ("158e", 4), ("434e", 2), ("1731e", 1)])
+@pytest.mark.parametrize("name,W,use_drift", [("44e", 8, False), ("158e", 4, False), ("434e", 2, False),
+                                              ("1731e", 1, False), ("44e", 8, True), ("158e", 4, True),
+                                              ("434e", 2, True)])
 @pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
-def test_backward_configs(name, W, mode):
-    print(f"[case] backward {name} W={W} mode={mode}", flush=True)
+def test_backward_configs(name, W, use_drift, mode):
+    """dR from recomputed AO gradients, or from the forward's drift: both
+    within the same bound (the drift's C_2..C_4 carry the forward's
+    product error, which that bound covers)."""
+    print(f"[case] backward {name} W={W} mode={mode} drift={use_drift}", flush=True)
     sysm, A_up, A_dn, R = q.make_config(name, W=W)
-    g, dR, dAu, dAd, out = _run(sysm, A_up, A_dn, R, mode)
+    g, dR, dAu, dAd, out = _run(sysm, A_up, A_dn, R, mode, use_drift=use_drift)
     # the adjoint arithmetic: the oracle adjoint from the GPU's own inverse
     # (same G; the forward tests bound the inverse itself)
     ref = {"Dinv_up": out["Dinv_up"], "Dinv_dn": out["Dinv_dn"]}
@@ -118,3 +124,29 @@ def test_backward_accumulate_and_finite_difference():
         Am = A_up.copy(); Am[i, j] -= h
         fd = (L(Ap) - L(Am)) / (2 * h)
         assert dAu.cpu().numpy()[i, j] == pytest.approx(fd, rel=1e-5, abs=1e-7)
+
+
+@pytest.mark.parametrize("use_drift", [False, True])
+def test_singular_walker_zero_weight_gives_zero_dR(use_drift):
+    """A singular walker (NaN inverse and drift) with g = 0 contributes
+    exactly nothing: its dR rows are 0 and dA stays finite, on both dR paths;
+    the other walkers' dR equal g times their drift."""
+    print(f"[case] singular walker adjoint drift={use_drift}", flush=True)
+    import torch
+    sysm, A_up, A_dn = random_tiny(n_atoms=3, n_up=4, n_dn=3, seed=5)
+    R = walkers_near(sysm, 3, seed=2)
+    R[1, 2] = [400.0, -300.0, 250.0]   # beyond every atomic radius
+    S = make_gpu_system(sysm, A_up, A_dn)
+    Rt = torch.from_numpy(R).cuda()
+    out = S.forward(Rt, "fp64")
+    assert int(out["status"][1].item()) & 1
+    g = np.array([[0.7, -1.1], [0.0, 0.0], [1.3, 0.4]])
+    dR, dAu, dAd = S.backward(Rt, out["Dinv_up"], out["Dinv_dn"], torch.from_numpy(g).cuda(), "fp64",
+                              drift=out["drift"] if use_drift else None)
+    dR = dR.cpu().numpy()
+    assert np.all(dR[1] == 0.0)
+    assert np.all(np.isfinite(dAu.cpu().numpy())) and np.all(np.isfinite(dAd.cpu().numpy()))
+    drift = out["drift"].cpu().numpy()
+    for w in (0, 2):
+        gg = np.concatenate([np.full(sysm.n_up, g[w, 0]), np.full(sysm.n_dn, g[w, 1])])
+        np.testing.assert_allclose(dR[w], gg[:, None] * drift[w], rtol=1e-9, atol=1e-12)

@@ -41,7 +41,8 @@ def _per_system(it, mode):
     import torch
     S = it["S"]
     out = S.forward(it["Rt"], mode)
-    dR, dAu, dAd = S.backward(it["Rt"], out["Dinv_up"], out["Dinv_dn"], it["gt"], mode)
+    # the plan's adjoint takes dR from the forward's drift
+    dR, dAu, dAd = S.backward(it["Rt"], out["Dinv_up"], out["Dinv_dn"], it["gt"], mode, drift=out["drift"])
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items()}
     res.update(dR=dR.cpu().numpy(), dA_up=dAu.cpu().numpy(), dA_dn=dAd.cpu().numpy())
