@@ -203,6 +203,41 @@ def cpu_baseline(sysm, A_up, A_dn, R, target_s=12.0):
                       f"OpenMP over walkers on {nthr} threads, {t:.1f} s"}
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "traffic_434e_W4096_bf16x3.md")
+KERNEL_SOURCES = {
+    "contract": ["qsl_contract.hip", "qsl_internal.h"],
+    "gauss_jordan": ["qsl_gj.hip", "qsl_internal.h"],
+    "adjoint_dA": ["qsl_backward.hip", "qsl_internal.h"],
+}
+
+
+def sources_digest(kind):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1209_6630_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (its `traffic-json:` line), scaled by the
+    copy-kernel calibration there; None when there is no entry for this
+    workload and kernel, or the kernel's sources changed since."""
+    kind = "contract" if kernel.startswith("contract_") else kernel
+    if kind not in KERNEL_SOURCES or not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("traffic-json:"):
+            doc = json.loads(line.split(":", 1)[1])
+            e = doc.get("kernels", {}).get(kernel)
+            if doc.get("workload") == workload and e and e.get("sources_sha256") == sources_digest(kind):
+                return e["hbm_bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +248,8 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the FP64 and 1731e companion runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after timing, run one plain copy kernel over MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the walker batch of one "
@@ -240,7 +277,16 @@ def main():
     dom = max((k for k in kernels if k in kinds), key=lambda k: kernels[k]["ms_per_step"])
     d = kernels[dom]
     roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                "unit": d["unit"], "frac": d["frac"], "traffic": None}
+                "unit": d["unit"], "frac": d["frac"],
+                "traffic": measured_traffic(f"{args.config}-W{W}-{mode}-fwd+adjoint", dom)}
+    if args.copy_calibration > 0:
+        # a plain copy of known size: reads and writes MIB MiB once (its HBM
+        # counter readings scale the other kernels' readings)
+        src = torch.ones(args.copy_calibration << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     st = main_wl.out["status"].cpu().numpy()
     res = {
         "metric": METRIC, "value": value, "unit": "walker Slater-builds/s", "n_gpus": 1,
