@@ -123,7 +123,18 @@ __device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
 }
 
 __device__ __forceinline__ double exp_t(double x) { return exp(x); }
-__device__ __forceinline__ float exp_t(float x) { return expf(x); }
+// e^x for the FP32 AO evaluation (x = -gamma r^2 in [-T, 0]): 2^(x log2 e)
+// with the product split exactly into h + l by an FMA remainder (log2 e
+// itself as a float pair), the hardware 2^h (v_exp_f32) and the first-order
+// factor 1 + l ln 2 for the small rest (|l| < 2^-17 here, so l^2 is below
+// the float rounding).  A few ulp, against about 20 instructions of expf.
+__device__ __forceinline__ float exp_t(float x) {
+    constexpr float L2E = 1.44269502f;         // log2(e) rounded to float
+    constexpr float L2E_LO = 1.92596299e-8f;   // log2(e) - L2E
+    const float h = x * L2E;
+    const float l = fmaf(x, L2E_LO, fmaf(x, L2E, -h));
+    return __builtin_amdgcn_exp2f(h) * fmaf(l, 0.693147181f, 1.0f);
+}
 
 // x^a, a x^(a-1) and a (a-1) x^(a-2) of one Cartesian axis, a <= 2.
 template <typename T>
