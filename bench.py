@@ -75,6 +75,9 @@ def work_per_step(sysm, nnz, W, mode):
         "drift_lap": (epi, "hbm", HBM_PEAK, "GB/s"),
         # dR = g drift: drift read, dR written, g read per component
         "dR_drift": (sum(56.0 * n * W for n in ns), "hbm", HBM_PEAK, "GB/s"),
+        # split-BF16 G^T: D^-1 read, hi + lo written over the padded tiles
+        "g_split": (sum((8.0 * n * n + 4.0 * -(-n // 32) * 32 * -(-n // 224) * 224) * W for n in ns),
+                    "hbm", HBM_PEAK, "GB/s"),
     }
 
 

@@ -28,8 +28,6 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
-constexpr int ADJ_MB = 224;             // MOs per workgroup (7 blocks of 32)
-constexpr int ADJ_NIB = ADJ_MB / 32;
 
 template <int MODE>
 using TOf = typename std::conditional<MODE == QSL_FP64, double, float>::type;
@@ -410,10 +408,34 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     for (int k = 0; k < PB; ++k) acc[k].zero();
 
     // D^-1 block of the next walker, loaded while the current one is used
-    constexpr int GPT = (TE * ADJ_MB + AD_THREADS - 1) / AD_THREADS;
+    // (FP32 / FP64); in BF16X3 the rows of the split G^T (g_split), copied
+    // to LDS as they are
+    constexpr int GPT = BF ? 1 : (TE * ADJ_MB + AD_THREADS - 1) / AD_THREADS;
+    constexpr int GQ = 2 * ADJ_MB * TE / 8;                      // uint4 of G^T hi + lo
+    constexpr int GQT = BF ? (GQ + AD_THREADS - 1) / AD_THREADS : 1;
+    static_assert(!BF || GQT == 4, "split-G staging is written for 4 rows of 16 bytes per thread");
     double gpre[GPT];
+    uint4 gq0{}, gq1{}, gq2{}, gq3{};  // scalars: an array would be moved to LDS
     double gnext = 0.0;
-    auto load_g = [&](int w) {
+    auto load_gs = [&](int w) __attribute__((always_inline)) {
+        const int NIP = (n + ADJ_MB - 1) / ADJ_MB * ADJ_MB;
+        const uint16_t* gh = j.gsplit + (((int64_t)w * tiles_per_walker(n) + t) * NIP + i0) * TE;
+        const int64_t lo = j.W * gsplit_elems(n);
+        auto at = [&](int k) -> const uint4* {
+            const int q = tid + k * AD_THREADS;
+            const int half = q >= GQ / 2, r = q - half * (GQ / 2);
+            return (const uint4*)(gh + (q < GQ ? half * lo + (r >> 2) * TE + (r & 3) * 8 : 0));
+        };
+        gq0 = *at(0);
+        gq1 = *at(1);
+        gq2 = *at(2);
+        gq3 = *at(3);
+    };
+    auto load_g = [&](int w) __attribute__((always_inline)) {
+        if constexpr (BF) {
+            load_gs(w);
+            return;
+        }
         gnext = g[2 * w + spin];
         // uniform base + 32-bit byte offsets (the block spans < 2^32 bytes)
         const char* Db = (const char*)(Dinv + ((size_t)w * n + e0) * n + i0);
@@ -437,20 +459,25 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
         }
         if constexpr (!PF) load_g(w);
-        const double gwv = gnext;
+        if constexpr (BF) {
+            auto put = [&](int k, const uint4& v) {
+                const int q = tid + k * AD_THREADS;
+                if (q >= GQ) return;
+                const int half = q >= GQ / 2, r = q - half * (GQ / 2);
+                *(uint4*)((half ? GTl : GTh) + (r >> 2) * LDGT + (r & 3) * 8) = v;
+            };
+            put(0, gq0);
+            put(1, gq1);
+            put(2, gq2);
+            put(3, gq3);
+        } else {
+            const double gwv = gnext;
 #pragma unroll
-        for (int k = 0; k < GPT; ++k) {
-            const int q = tid + k * AD_THREADS;
-            if (q >= TE * ADJ_MB) continue;
-            const int e = q / ADJ_MB, ii = q % ADJ_MB;
-            const double v = gwv != 0.0 ? gwv * gpre[k] : 0.0;
-            if constexpr (BF) {
-                const float f = (float)v;
-                const uint16_t h = bf16_rne(f);
-                GTh[ii * LDGT + e] = h;
-                GTl[ii * LDGT + e] = bf16_rne(f - bf16_to_f(h));
-            } else {
-                GTt[ii * LDGT + e] = (T)v;
+            for (int k = 0; k < GPT; ++k) {
+                const int q = tid + k * AD_THREADS;
+                if (q >= TE * ADJ_MB) continue;
+                const int e = q / ADJ_MB, ii = q % ADJ_MB;
+                GTt[ii * LDGT + e] = (T)(gwv != 0.0 ? gwv * gpre[k] : 0.0);
             }
         }
         if constexpr (PF) {
@@ -539,6 +566,68 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- G split
+// G = g D^-1 (0 where g = 0) rounded to FP32 and split hi = bf16(G),
+// lo = bf16(G - hi) (the arithmetic the dA kernel applied per window block
+// before), stored transposed per electron tile: [w][t][i][32 electrons],
+// i < round_up(n, ADJ_MB), hi array then lo array.  One thread per 8
+// electrons of one (walker, tile, MO).
+__device__ __forceinline__ void gsplit_body(const Job& j, int bx) {
+    const int n = j.n;
+    const int T = (n + TE - 1) / TE, NIP = (n + ADJ_MB - 1) / ADJ_MB * ADJ_MB;
+    const int64_t q = (int64_t)bx * 256 + threadIdx.x;
+    if (q >= j.W * T * NIP * 4) return;
+    // four consecutive lanes fill one 64-byte row (32 electrons) of one MO
+    const int e8 = (int)(q & 3);
+    const int64_t rest = q >> 2;
+    const int ii = (int)(rest % NIP);
+    const int64_t wt = rest / NIP;
+    const int64_t w = wt / T;
+    const int t = (int)(wt % T);
+    const double gw = j.g[2 * w + j.spin];
+    uint32_t hv[4], lv[4];
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+        float f[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int e = t * TE + e8 * 8 + u + k;
+            double v = 0.0;
+            if (e < n && ii < n && gw != 0.0) v = gw * j.Dinv[((size_t)w * n + e) * n + ii];
+            f[k] = (float)v;
+        }
+        bf16_split2(f[0], f[1], hv[u / 2], lv[u / 2]);
+    }
+    uint16_t* gh = j.gsplit + (wt * NIP + ii) * TE + e8 * 8;
+    uint16_t* gl = gh + j.W * gsplit_elems(n);
+    *(uint4*)gh = uint4{hv[0], hv[1], hv[2], hv[3]};
+    *(uint4*)gl = uint4{lv[0], lv[1], lv[2], lv[3]};
+}
+
+__global__ __launch_bounds__(256) void gsplit_kernel(Job j) { gsplit_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void gsplit_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gsplit_body(j, bx); });
+}
+
+int gsplit_blocks(const Job& j) {
+    return (int)((j.W * (int64_t)tiles_per_walker(j.n) * ((j.n + ADJ_MB - 1) / ADJ_MB * ADJ_MB) * 4 + 255) / 256);
+}
+
+hipError_t launch_gsplit(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    j.gx = gsplit_blocks(j); j.gy = 1; j.gz = 1;
+    if (!j.gx || !j.gsplit) return hipSuccess;
+    gsplit_kernel<<<(unsigned)j.gx, 256, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_gsplit_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    gsplit_batched<<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
 }
 
 template <int MODE>

@@ -115,7 +115,7 @@ int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
 
 // Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win],
 // the same per walker group of gw walkers, and the FP32 dA accumulator.
-WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
     WsLayout L{};
     size_t off = 0;
     for (int s = 0; s < 2; ++s) {
@@ -142,6 +142,11 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw) {
         const size_t n = (size_t)n_spin(d, s);
         L.gj_off[s] = off;
         if (gj_blocked((int)n)) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
+    }
+    for (int s = 0; s < 2; ++s) {
+        const int n = n_spin(d, s);
+        L.gs_off[s] = off;
+        if (mode == QSL_BF16X3 && n) off = round_up(off + (size_t)W * gsplit_elems(n) * 2 * sizeof(uint16_t), 256);
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -193,6 +198,7 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
     if (a->dA[s]) {
         if (a->mode == QSL_FP64) j.dA64 = a->dA[s];
         else j.dA32 = (float*)(ws + L.dA32_off[s]);
+        if (a->mode == QSL_BF16X3) j.gsplit = (uint16_t*)(ws + L.gs_off[s]);
     }
     return j;
 }
@@ -510,7 +516,7 @@ qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, si
     if (!sys || !bytes) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
     if (W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
     if (mode < QSL_FP64 || mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
-    *bytes = ws_layout(sys->d, W, bw_group(W)).total;
+    *bytes = ws_layout(sys->d, W, bw_group(W), mode).total;
     return QSL_OK;
 }
 
@@ -528,7 +534,7 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         if (!a->C[s] || !a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "C and Dinv outputs are required");
         if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
     }
-    WsLayout L = ws_layout(d, a->W, bw_group(a->W));
+    WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)a->ws;
@@ -580,7 +586,7 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
         if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
         if (!a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "NULL Dinv");
     }
-    WsLayout L = ws_layout(d, a->W, bw_group(a->W));
+    WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     char* ws = (char*)a->ws;
     // with the drift, dR is written whole (every electron of both spins)
@@ -607,6 +613,10 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
             {
                 ProfScope ps("screen_group", st);
                 if ((e = launch_screen(j, 1, st)) != hipSuccess) return hip_fail(e, "group screen kernel");
+            }
+            if (j.gsplit) {
+                ProfScope ps("g_split", st);
+                if ((e = launch_gsplit(j, st)) != hipSuccess) return hip_fail(e, "G split kernel");
             }
             ProfScope ps("adjoint_dA", st);
             if ((e = launch_adj_da(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");

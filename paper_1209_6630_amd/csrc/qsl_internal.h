@@ -245,6 +245,7 @@ struct Job {
     double* dA64;
     float* dA32;
     double* gjws;            // blocked inversion (gj_blocked(n)): W x gj_ws_doubles(n)
+    uint16_t* gsplit;        // BF16X3 adjoint: W x gsplit_elems(n) hi, then as many lo
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 
@@ -326,10 +327,20 @@ int bw_group(int64_t W);
 
 // Workspace of one system: byte offsets of the per-spin tile and group
 // window lists and of the FP32 dA accumulator.
+// MOs per workgroup of the adjoint kernels (7 blocks of 32).
+constexpr int ADJ_MB = 224;
+constexpr int ADJ_NIB = ADJ_MB / 32;
+// Split-BF16 G^T of the dA adjoint, per walker and spin: for each electron
+// tile t (32 electrons) and MO i < round_up(n, ADJ_MB), 32 values (one per
+// electron of the tile), hi array then lo array.
+__host__ __device__ inline int64_t gsplit_elems(int n) {
+    return (int64_t)((n + TE - 1) / TE) * ((n + ADJ_MB - 1) / ADJ_MB * ADJ_MB) * TE;
+}
+
 struct WsLayout {
-    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], total;
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2], total;
 };
-WsLayout ws_layout(const DevSys& d, int64_t W, int gw);
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode);
 // The Job of spin s of a forward / adjoint call on workspace ws.
 Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s);
 Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw);
@@ -378,6 +389,11 @@ hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix,
 // Adjoint: H = G A and dR per tile; dA per walker group.
 void adj_h_grid(Job& j);
 void adj_da_grid(Job& j);
+// G = g D^-1 of the dA adjoint as its BF16 hi/lo pair, transposed per
+// electron tile (Job.gsplit); BF16X3 mode.
+int gsplit_blocks(const Job& j);
+hipError_t launch_gsplit(const Job& j, hipStream_t st);
+hipError_t launch_gsplit_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_adj_h(const Job& j, hipStream_t st);
 hipError_t launch_adj_da(const Job& j, hipStream_t st);
 hipError_t launch_adj_h_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,

@@ -30,6 +30,7 @@ enum Phase {
     PH_DR,           // dR = g drift (drift bound)
     PH_ADJ_H,        // H = G A, dR (no drift bound)
     PH_SCREEN_G,     // per walker-group window lists
+    PH_GSPLIT,       // split-BF16 G^T for dA (BF16X3)
     PH_ADJ_DA,       // dA
     PH_COUNT
 };
@@ -112,7 +113,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     size_t total = 0;
     for (int i = 0; i < p->n_sys; ++i) {
         p->gw[i] = plan_gw(p, i);
-        p->lay[i] = ws_layout(p->sys[i]->d, p->W[i], p->gw[i]);
+        p->lay[i] = ws_layout(p->sys[i]->d, p->W[i], p->gw[i], p->mode);
         p->ws_off[i] = total;
         total = round_up(total + p->lay[i].total, 256);
     }
@@ -168,6 +169,11 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
             j = b;
             j.gx = screen_blocks(j, 1); j.gy = 1; j.gz = 1;
             p->ph[PH_SCREEN_G].jobs.push_back(j);
+            if (b.gsplit) {
+                j = b;
+                j.gx = gsplit_blocks(j); j.gy = 1; j.gz = 1;
+                p->ph[PH_GSPLIT].jobs.push_back(j);
+            }
             j = b;
             adj_da_grid(j);
             p->ph[PH_ADJ_DA].jobs.push_back(j);
@@ -328,6 +334,13 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                            SG.blocks(), 1, st)) != hipSuccess)
                 return hip_fail(e, "group screen kernel");
         }
+        auto& GS = p->ph[PH_GSPLIT];
+        if (GS.blocks()) {
+            ProfScope ps("g_split", st);
+            if ((e = launch_gsplit_batched(dev_jobs(p, PH_GSPLIT), dev_prefix(p, PH_GSPLIT), (int)GS.jobs.size(),
+                                           GS.blocks(), st)) != hipSuccess)
+                return hip_fail(e, "G split kernel");
+        }
         if (DA.blocks()) {
             ProfScope ps("adjoint_dA", st);
             if ((e = launch_adj_da_batched(mode, dev_jobs(p, PH_ADJ_DA), dev_prefix(p, PH_ADJ_DA),
@@ -342,6 +355,10 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         for (const Job& j : SG.jobs) {
             ProfScope ps("screen_group", st);
             if ((e = launch_screen(j, 1, st)) != hipSuccess) return hip_fail(e, "group screen kernel");
+        }
+        for (const Job& j : p->ph[PH_GSPLIT].jobs) {
+            ProfScope ps("g_split", st);
+            if ((e = launch_gsplit(j, st)) != hipSuccess) return hip_fail(e, "G split kernel");
         }
         for (const Job& j : DA.jobs) {
             ProfScope ps("adjoint_dA", st);
