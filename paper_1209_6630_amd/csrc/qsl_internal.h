@@ -356,6 +356,11 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
 // status), group = 1 per walker-group lists (gnwin/gwin, gw walkers);
 // group index = t * ceil(W / gw) + walker block.
 int screen_blocks(const Job& j, int group);
+// Walker-group lists as the union of the tile lists (same blocks as group
+// screening); for systems of at most UNION_MAXWIN windows.
+constexpr int UNION_MAXWIN = 8192;
+hipError_t launch_group_union(const Job& j, hipStream_t st);
+hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_screen(const Job& j, int group, hipStream_t st);
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st);

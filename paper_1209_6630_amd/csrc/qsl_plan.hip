@@ -328,11 +328,18 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                           H.blocks(), st)) != hipSuccess)
                 return hip_fail(e, "adjoint H kernel");
         }
+        // the adjoint's walker-group lists: the union of the forward's tile
+        // lists (same positions), or a screening of their own for systems
+        // with more windows than the union bitmap holds
+        bool small = true;
+        for (const Job& j : SG.jobs) small = small && j.s.n_win <= UNION_MAXWIN;
         if (SG.blocks()) {
             ProfScope ps("screen_group", st);
-            if ((e = launch_screen_batched(dev_jobs(p, PH_SCREEN_G), dev_prefix(p, PH_SCREEN_G), (int)SG.jobs.size(),
-                                           SG.blocks(), 1, st)) != hipSuccess)
-                return hip_fail(e, "group screen kernel");
+            e = small ? launch_group_union_batched(dev_jobs(p, PH_SCREEN_G), dev_prefix(p, PH_SCREEN_G),
+                                                   (int)SG.jobs.size(), SG.blocks(), st)
+                      : launch_screen_batched(dev_jobs(p, PH_SCREEN_G), dev_prefix(p, PH_SCREEN_G), (int)SG.jobs.size(),
+                                              SG.blocks(), 1, st);
+            if (e != hipSuccess) return hip_fail(e, "group screen kernel");
         }
         auto& GS = p->ph[PH_GSPLIT];
         if (GS.blocks()) {
@@ -354,7 +361,8 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         }
         for (const Job& j : SG.jobs) {
             ProfScope ps("screen_group", st);
-            if ((e = launch_screen(j, 1, st)) != hipSuccess) return hip_fail(e, "group screen kernel");
+            e = j.s.n_win <= UNION_MAXWIN ? launch_group_union(j, st) : launch_screen(j, 1, st);
+            if (e != hipSuccess) return hip_fail(e, "group screen kernel");
         }
         for (const Job& j : p->ph[PH_GSPLIT].jobs) {
             ProfScope ps("g_split", st);

@@ -19,6 +19,7 @@
 namespace qsl {
 
 constexpr int SCREEN_THREADS = 256;
+static_assert(UNION_MAXWIN / 32 <= SCREEN_THREADS, "one bitmap word per thread");
 constexpr int SCREEN_MAXE = 2048;  // positions staged in LDS (the rest are read from L2)
 
 __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __restrict__ tile_nwin,
@@ -168,6 +169,79 @@ hipError_t launch_screen(const Job& j, int group, hipStream_t st) {
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st) {
     screen_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs, group);
+    return hipGetLastError();
+}
+
+// Walker-group lists as the union of tile lists already built on the same
+// positions: electrons [32 t, 32 t + 32) of walkers [w0, w0 + gw) are
+// covered by the tiles of those electrons in walker blocks w0 / TE ..
+// (w0 + gw - 1) / TE, whose survivors follow the same rule.  The union is
+// the group's own list, or a superset when gw is not a multiple of TE (the
+// extra windows only carry AO values screened to zero).  One bit per window
+// in LDS, compacted in ascending order.
+__device__ __forceinline__ void group_union_body(const Job& j, int bx) {
+    __shared__ uint32_t bits[UNION_MAXWIN / 32];
+    __shared__ int wtot[SCREEN_THREADS / 64];
+    const int n = j.n, nwin_all = j.s.n_win;
+    const int64_t W = j.W;
+    const int gw = j.gw;
+    const int ngw = (int)((W + gw - 1) / gw);
+    const int t = bx / ngw, wb = bx % ngw;
+    const int64_t w0 = (int64_t)wb * gw, wend = min<int64_t>(W, w0 + gw);
+    const int e0 = t * TE, ne = min(TE, n - e0);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwords = (nwin_all + 31) / 32;  // <= SCREEN_THREADS
+    if (tid < nwords) bits[tid] = 0u;
+    __syncthreads();
+    const int wbk = walker_blocks(W);
+    const int b0 = (int)(w0 / TE), nb = (int)((wend - 1) / TE) - b0 + 1;
+    for (int tt = wave; tt < ne * nb; tt += SCREEN_THREADS / 64) {  // one wave per tile
+        const int tile = (e0 + tt / nb) * wbk + b0 + tt % nb;
+        const int cnt = j.nwin[tile];
+        const int* lst = j.win + (size_t)tile * nwin_all;
+        for (int q = lane; q < cnt; q += 64) {
+            const int wd = lst[q];
+            atomicOr(&bits[wd >> 5], 1u << (wd & 31));
+        }
+    }
+    __syncthreads();
+    const uint32_t word = tid < nwords ? bits[tid] : 0u;
+    const int c = __popc(word);
+    int x = c;  // inclusive prefix inside the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    int off = 0;
+    for (int v = 0; v < wave; ++v) off += wtot[v];
+    int pos = off + x - c;
+    int* out = j.gwin + (size_t)bx * nwin_all;
+    for (uint32_t wd = word; wd; wd &= wd - 1) out[pos++] = tid * 32 + __builtin_ctz(wd);
+    if (tid == SCREEN_THREADS - 1) j.gnwin[bx] = off + x;
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void group_union_kernel(Job j) { group_union_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(SCREEN_THREADS) void group_union_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { group_union_body(j, bx); });
+}
+
+hipError_t launch_group_union(const Job& j, hipStream_t st) {
+    if (j.gw < 1 || j.s.n_win > UNION_MAXWIN) return hipErrorInvalidValue;
+    const int blocks = screen_blocks(j, 1);
+    if (!blocks) return hipSuccess;
+    Job jj = j;
+    jj.gx = blocks; jj.gy = 1; jj.gz = 1;
+    group_union_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    group_union_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 
