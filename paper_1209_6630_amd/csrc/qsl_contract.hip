@@ -107,9 +107,24 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         }
     }
     bool tie = false;
+    // the records of a chunk's windows in LDS (two buffers, by chunk parity):
+    // the AO evaluation reads them many times per thread, from LDS rather
+    // than through dependent global loads; chunk c + 1 is copied during the
+    // products of chunk c
+    constexpr int RQ = MODE == QSL_FP64 ? WINREC_Q64 : WINREC_Q32;
+    __shared__ __attribute__((aligned(16))) WinRec wrec[2][KW];
+    auto stage_recs = [&](int buf, int c0) __attribute__((always_inline)) {
+        for (int q = tid; q < KW * RQ; q += P::THREADS) {
+            const int wl = q / RQ, part = q % RQ;
+            if (c0 + wl < nwin)
+                ((uint4*)&wrec[buf][wl])[part] = ((const uint4*)&s.win_rec[wins[c0 + wl]])[part];
+        }
+    };
+    stage_recs(0, 0);
     __syncthreads();
 
     for (int c0 = 0; c0 < nwin; c0 += KW) {
+        const int buf = (c0 / KW) & 1;
         // ---- phase R: AO values of (electron e, window wl, slots js..js+SPT)
         // into LDS
         if (tid < TE * KW * (WIN / SPT)) {
@@ -123,7 +138,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 for (int j = 0; j < SPT; ++j) vals[d][j] = T(0);
             if (q >= 0 && e < ne) {
                 const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-                rec_values<T, SPT>(s.win_rec[q], s.T, js, r, vals, tie);
+                rec_values<T, SPT>(wrec[buf][wl], s.T, js, r, vals, tie);
             }
             if constexpr (MODE == QSL_BF16X3) {
                 uint16_t* bh = (uint16_t*)bbuf;
@@ -154,6 +169,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         __syncthreads();
 
         // ---- phase M: MFMA over the chunk
+        stage_recs(buf ^ 1, c0 + KW);
         if constexpr (MODE == QSL_BF16X3) {
             const uint16_t* bh = (const uint16_t*)bbuf;
             const uint16_t* bl = bh + BELEMS;

@@ -44,11 +44,16 @@ struct WinRec {
     int pw[WIN];
     int np[WIN];
     float f32[WIN];
-    double f64[WIN];
     double ex[WIN][QSL_PMAX];
     float c32[WIN][QSL_PMAX];
+    // FP64-only fields last: the f32 modes read a prefix of the record
+    double f64[WIN];
     double c64[WIN][QSL_PMAX];
 };
+// 16-byte pieces of a record read in FP32 / split-BF16 (prefix) or FP64 mode
+constexpr int WINREC_Q32 = (int)(offsetof(WinRec, f64) / 16);
+constexpr int WINREC_Q64 = (int)(sizeof(WinRec) / 16);
+static_assert(offsetof(WinRec, f64) % 16 == 0 && sizeof(WinRec) % 16 == 0, "records are copied in 16-byte pieces");
 
 // Device view of a system, passed to kernels by value.
 struct DevSys {
