@@ -159,11 +159,15 @@ __device__ __forceinline__ void rec_values(const WinRec& r, double T_thr, int js
     const double r2 = dist2_exact(dx, dy, dz);
     const T X = (T)dx, Y = (T)dy, Z = (T)dz;
     const double tieb = 1e-12 * T_thr;
+    // the slot fields first, all loads issued together
+    int pws[CNT];
+#pragma unroll
+    for (int j = 0; j < CNT; ++j) pws[j] = r.pw[js + j];
     int prev = -1;
     T g = 0, g1 = 0, g2 = 0;
 #pragma unroll
     for (int j = 0; j < CNT; ++j) {
-        const int pw = r.pw[js + j];
+        const int pw = pws[j];
 #pragma unroll
         for (int d = 0; d < 5; ++d) vals[d][j] = T(0);
         if (pw < 0) continue;
@@ -171,14 +175,23 @@ __device__ __forceinline__ void rec_values(const WinRec& r, double T_thr, int js
         if (ls != prev) {
             g = T(0); g1 = T(0); g2 = T(0);
             const int np = r.np[js + j];
-            for (int k = 0; k < np; ++k) {
-                const double gk = r.ex[js + j][k];
+            // every primitive slot of the shell loaded at once (np <= QSL_PMAX)
+            double exs[QSL_PMAX];
+            T cs[QSL_PMAX];
+#pragma unroll
+            for (int k = 0; k < QSL_PMAX; ++k) {
+                exs[k] = r.ex[js + j][k];
+                if constexpr (sizeof(T) == 8) cs[k] = (T)r.c64[js + j][k];
+                else cs[k] = r.c32[js + j][k];
+            }
+#pragma unroll
+            for (int k = 0; k < QSL_PMAX; ++k) {
+                if (k >= np) break;
+                const double gk = exs[k];
                 const double t = __dmul_rn(gk, r2);
                 tie |= fabs(t - T_thr) <= tieb;
                 if (t <= T_thr) {
-                    T c;
-                    if constexpr (sizeof(T) == 8) c = (T)r.c64[js + j][k];
-                    else c = r.c32[js + j][k];
+                    const T c = cs[k];
                     const T ek = c * exp_t(-(T)t);
                     const T gT = (T)gk;
                     g += ek;
