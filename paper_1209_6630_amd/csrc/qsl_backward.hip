@@ -382,17 +382,40 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         const T X = (T)dx, Y = (T)dy, Z = (T)dz;
         int prev = -1;
         T gg = 0;
+        // slot fields loaded together, then each shell's primitives at once
+        int pws[WIN], lss[WIN];
 #pragma unroll
         for (int jj = 0; jj < WIN; ++jj) {
-            const int pw = lw_pow[wli][jj];
+            pws[jj] = lw_pow[wli][jj];
+            lss[jj] = lw_sh[wli][jj];
+        }
+#pragma unroll
+        for (int jj = 0; jj < WIN; ++jj) {
+            const int pw = pws[jj];
             if (pw < 0) continue;
-            const int ls = lw_sh[wli][jj];
+            const int ls = lss[jj];
             if (ls != prev) {
                 gg = T(0);
                 const int np = lw_np[wli][ls];
-                for (int k = 0; k < np; ++k) {
-                    const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
-                    if (t <= s.T) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
+                if constexpr (BF) {
+                    double exs[QSL_PMAX];
+                    T cs[QSL_PMAX];
+#pragma unroll
+                    for (int k = 0; k < QSL_PMAX; ++k) {
+                        exs[k] = lw_exp[wli][ls][k];
+                        cs[k] = lw_c[wli][ls][k];
+                    }
+#pragma unroll
+                    for (int k = 0; k < QSL_PMAX; ++k) {
+                        if (k >= np) break;
+                        const double t = __dmul_rn(exs[k], r2);
+                        if (t <= s.T) gg += cs[k] * exp_t(-(T)t);
+                    }
+                } else {  // no registers to spare for the batch of loads
+                    for (int k = 0; k < np; ++k) {
+                        const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
+                        if (t <= s.T) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
+                    }
                 }
                 prev = ls;
             }
