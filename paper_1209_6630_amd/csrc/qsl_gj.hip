@@ -411,13 +411,6 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     auto stop = [&](int it) {  // the abort flag is polled every 64th time
         return (it & 63) == 63 && (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort)));
     };
-    auto wait_published = [&](int step) -> bool {  // pivot and column of step published
-        for (int it = 0;; ++it) {
-            if (__builtin_amdgcn_readfirstlane(flag_load(&pub)) >= step) return true;
-            if (stop(it)) return give_up();
-            if (it >= 4) __builtin_amdgcn_s_sleep(1);
-        }
-    };
     auto wait_consumed = [&](int step) -> bool {  // every wave has read the inputs of step
         for (int it = 0;; ++it) {
             const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
@@ -439,12 +432,24 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     bool singular = false;
     for (int k = 0; k < n; ++k) {
         const int b = k % NB, b1 = (k + 1) % NB;
-        if (!wait_published(k)) break;
-        const int p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
-        const double pv = readlane_f64(piv_val[b], 0);
+        // pivot and column of step k, read in one batch with the
+        // publication flag: the LDS serves a wave's reads in order, so what
+        // is read after a flag value >= k is the published data
+        int p;
+        double pv;
         double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
+        bool live = true;
+        for (int it = 0;; ++it) {
+            const int fv = flag_load(&pub);
+            p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
+            pv = readlane_f64(piv_val[b], 0);
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
+            for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
+            if (__builtin_amdgcn_readfirstlane(fv) >= k) break;
+            if (stop(it)) { live = give_up(); break; }
+            if (it >= 4) __builtin_amdgcn_s_sleep(1);
+        }
+        if (!live) break;
         if (lane == 0) flag_store(&prog[wave], k);  // after the reads above
         if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
             singular = true;
@@ -470,13 +475,16 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
             const int h1 = (k1 % NG) >> 3;  // half owning column k + 1
             const double x = readlane_f64(xr, 32 * h1 + lp);  // pivot row, column k + 1
+            // buffer b1 last held step k + 1 - NB: written once every wave
+            // read it (the counters are read now, checked after the search)
+            const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
             double col[RPL];
 #pragma unroll
             for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
-            // buffer b1 last held step k + 1 - NB: written once every wave read it
             bool ok = true;
-            gjh_search<RPL>(col, n, li, h1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1],
-                            [&] { ok = wait_consumed(k1 - NB); });
+            gjh_search<RPL>(col, n, li, h1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1], [&] {
+                if (__ballot(pg < k1 - NB) != 0) ok = wait_consumed(k1 - NB);
+            });
             if (ok && lane == 0) flag_store(&pub, k1);
             __builtin_amdgcn_s_setprio(0);
             if (!ok) break;
