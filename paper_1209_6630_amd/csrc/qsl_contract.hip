@@ -111,16 +111,27 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     // the AO evaluation reads them many times per thread, from LDS rather
     // than through dependent global loads; chunk c + 1 is copied during the
     // products of chunk c
+    // (the f32 modes keep the record prefix they read, RQ pieces of 16 bytes,
+    // back to back; a wave's direct global-to-LDS load fills 64 consecutive
+    // pieces, no registers involved)
     constexpr int RQ = MODE == QSL_FP64 ? WINREC_Q64 : WINREC_Q32;
-    __shared__ __attribute__((aligned(16))) WinRec wrec[2][KW];
-    auto stage_recs = [&](int buf, int c0) __attribute__((always_inline)) {
-        for (int q = tid; q < KW * RQ; q += P::THREADS) {
-            const int wl = q / RQ, part = q % RQ;
-            if (c0 + wl < nwin)
-                ((uint4*)&wrec[buf][wl])[part] = ((const uint4*)&s.win_rec[wins[c0 + wl]])[part];
+    constexpr int NPASS = (KW * RQ + P::THREADS - 1) / P::THREADS;
+    __shared__ __attribute__((aligned(16))) uint4 wrecq[2][NPASS * P::THREADS];
+    auto rec = [&](int buf, int wl) -> const WinRec& { return *(const WinRec*)&wrecq[buf][wl * RQ]; };
+    auto fetch_recs = [&](int buf, int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ps = 0; ps < NPASS; ++ps) {
+            const int q = ps * P::THREADS + tid;
+            const int wl = q / RQ;
+            const int wi = q < KW * RQ && c0 + wl < nwin ? wins[c0 + wl] : wins[0];
+            // lane l of wave v writes piece ps * THREADS + 64 v + l
+            __builtin_amdgcn_global_load_lds((const void*)((const uint4*)&s.win_rec[wi] + q % RQ),
+                                             (__attribute__((address_space(3))) void*)&wrecq[buf][ps * P::THREADS + wave * 64],
+                                             16, 0, 0);
         }
     };
-    stage_recs(0, 0);
+    if (nwin > 0) fetch_recs(0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the direct loads into LDS are done
     __syncthreads();
 
     for (int c0 = 0; c0 < nwin; c0 += KW) {
@@ -138,7 +149,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 for (int j = 0; j < SPT; ++j) vals[d][j] = T(0);
             if (q >= 0 && e < ne) {
                 const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-                rec_values<T, SPT>(wrec[buf][wl], s.T, js, r, vals, tie);
+                rec_values<T, SPT>(rec(buf, wl), s.T, js, r, vals, tie);
             }
             if constexpr (MODE == QSL_BF16X3) {
                 uint16_t* bh = (uint16_t*)bbuf;
@@ -168,8 +179,9 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         }
         __syncthreads();
 
-        // ---- phase M: MFMA over the chunk
-        stage_recs(buf ^ 1, c0 + KW);
+        // ---- phase M: MFMA over the chunk (the next chunk's records load
+        // meanwhile; pieces of windows past the list are never read)
+        if (c0 + KW < nwin) fetch_recs(buf ^ 1, c0 + KW);
         if constexpr (MODE == QSL_BF16X3) {
             const uint16_t* bh = (const uint16_t*)bbuf;
             const uint16_t* bl = bh + BELEMS;
@@ -241,6 +253,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 }
             }
         }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the next chunk's records are in LDS
         __syncthreads();
     }
 
