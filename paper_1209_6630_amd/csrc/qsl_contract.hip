@@ -198,6 +198,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
+                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
                     const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
                     const size_t off = (wbase + mo) * WIN;
                     const bf16x8 bah = __builtin_bit_cast(bf16x8, *(const uint4*)(Ahi + off));
@@ -227,6 +228,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
+                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
                     const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
                     const float b = AT32[(size_t)slot * ldn + mo];
 #pragma unroll

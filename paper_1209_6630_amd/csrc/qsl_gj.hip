@@ -290,15 +290,22 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 template <int RPL, typename Before>
 __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int li, int half, uint32_t used,
                                            double* colout, int* piv_idx, double* piv_val, Before&& before) {
-    // |a| over the candidate rows (unused, i < n), -1 elsewhere; NaN never wins
+    // |a| over the candidate rows (unused, i < n), -1 elsewhere; NaN never
+    // wins; the lane's maximum by a tree
     double a[RPL];
-    double best = -1.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = li + 32 * r;
         a[r] = (i < n && !((used >> r) & 1u)) ? fabs(col[r]) : -1.0;
-        best = fmax(best, a[r]);
     }
+    double m[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) m[r] = a[r];
+#pragma unroll
+    for (int w = 1; w < RPL; w *= 2)
+#pragma unroll
+        for (int r = 0; r + w < RPL; r += 2 * w) m[r] = fmax(m[r], m[r + w]);
+    double best = fmax(m[0], -1.0);
     // largest value: inside rows of 16 lanes by DPP (quad swaps, half-row
     // and row mirrors), then the owning half's two rows
     best = fmax(best, dpp_f64<0xB1>(best));
@@ -323,7 +330,11 @@ __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int 
     }
     if (!(gmax >= 0.0)) si = 0x7fffffff;  // no candidate row
     const double pv = neg ? -gmax : gmax;
-    const double inv = 1.0 / pv;
+    // 1/pv: hardware reciprocal and two Newton steps (the error squares each
+    // step), shorter than the general division on this step's critical path
+    double inv = __builtin_amdgcn_rcp(pv);
+    inv = fma(inv, fma(-pv, inv, 1.0), inv);
+    inv = fma(inv, fma(-pv, inv, 1.0), inv);
     before();  // the buffers may be overwritten from here on
     if ((threadIdx.x & 63) >> 5 == half) {
 #pragma unroll
