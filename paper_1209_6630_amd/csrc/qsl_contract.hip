@@ -195,14 +195,22 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                     xl[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bl + off));
                 }
                 const size_t wbase = (size_t)wq[ks * 2 + oct] * ldn;
+                // the A fragments of every sub-block first: one memory wait
+                // per k-step (a sub-block wholly past n reads a valid row
+                // and is skipped below)
+                bf16x8 ah[MSUB], al[MSUB];
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    const int mo = min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
+                    const size_t off = (wbase + mo) * WIN;
+                    ah[sb] = __builtin_bit_cast(bf16x8, *(const uint4*)(Ahi + off));
+                    al[sb] = __builtin_bit_cast(bf16x8, *(const uint4*)(Alo + off));
+                }
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
                     if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
-                    const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
-                    const size_t off = (wbase + mo) * WIN;
-                    const bf16x8 bah = __builtin_bit_cast(bf16x8, *(const uint4*)(Ahi + off));
-                    const bf16x8 bal = __builtin_bit_cast(bf16x8, *(const uint4*)(Alo + off));
+                    const bf16x8 bah = ah[sb], bal = al[sb];
                     // the three products of one accumulator are dependent:
                     // issue them five accumulators apart
 #pragma unroll
