@@ -449,10 +449,10 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const int half = q >= GQ / 2, r = q - half * (GQ / 2);
             return (const uint4*)(gh + (q < GQ ? half * lo + (r >> 2) * TE + (r & 3) * 8 : 0));
         };
-        gq0 = *at(0);
-        gq1 = *at(1);
-        gq2 = *at(2);
-        gq3 = *at(3);
+        gq0 = __builtin_bit_cast(uint4, *gmem(at(0)));
+        gq1 = __builtin_bit_cast(uint4, *gmem(at(1)));
+        gq2 = __builtin_bit_cast(uint4, *gmem(at(2)));
+        gq3 = __builtin_bit_cast(uint4, *gmem(at(3)));
     };
     auto load_g = [&](int w) __attribute__((always_inline)) {
         if constexpr (BF) {
@@ -618,15 +618,16 @@ __device__ __forceinline__ void gsplit_body(const Job& j, int bx) {
         for (int k = 0; k < 2; ++k) {
             const int e = t * TE + e8 * 8 + u + k;
             double v = 0.0;
-            if (e < n && ii < n && gw != 0.0) v = gw * j.Dinv[((size_t)w * n + e) * n + ii];
+            if (e < n && ii < n && gw != 0.0) v = gw * gmem(j.Dinv)[((size_t)w * n + e) * n + ii];
             f[k] = (float)v;
         }
         bf16_split2(f[0], f[1], hv[u / 2], lv[u / 2]);
     }
     uint16_t* gh = j.gsplit + (wt * NIP + ii) * TE + e8 * 8;
     uint16_t* gl = gh + j.W * gsplit_elems(n);
-    *(uint4*)gh = uint4{hv[0], hv[1], hv[2], hv[3]};
-    *(uint4*)gl = uint4{lv[0], lv[1], lv[2], lv[3]};
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    *gmem((u32x4*)gh) = u32x4{hv[0], hv[1], hv[2], hv[3]};
+    *gmem((u32x4*)gl) = u32x4{lv[0], lv[1], lv[2], lv[3]};
 }
 
 __global__ __launch_bounds__(256) void gsplit_kernel(Job j) { gsplit_body(j, blockIdx.x); }

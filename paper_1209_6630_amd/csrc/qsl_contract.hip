@@ -123,7 +123,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         for (int ps = 0; ps < NPASS; ++ps) {
             const int q = ps * P::THREADS + tid;
             const int wl = q / RQ;
-            const int wi = q < KW * RQ && c0 + wl < nwin ? wins[c0 + wl] : wins[0];
+            const int wi = gmem(wins)[q < KW * RQ && c0 + wl < nwin ? c0 + wl : 0];
             // lane l of wave v writes piece ps * THREADS + 64 v + l
             __builtin_amdgcn_global_load_lds((const void*)((const uint4*)&s.win_rec[wi] + q % RQ),
                                              (__attribute__((address_space(3))) void*)&wrecq[buf][ps * P::THREADS + wave * 64],
@@ -140,7 +140,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         // into LDS
         if (tid < TE * KW * (WIN / SPT)) {
             const int e = tid & (TE - 1), wl = (tid / TE) % KW, js = (tid / (TE * KW)) * SPT;
-            const int q = c0 + wl < nwin ? wins[c0 + wl] : -1;
+            const int q = c0 + wl < nwin ? gmem(wins)[c0 + wl] : -1;
             if (e == 0 && js == 0) wq[wl] = q < 0 ? 0 : q;
             T vals[5][SPT];
 #pragma unroll
@@ -186,6 +186,25 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
             const uint16_t* bh = (const uint16_t*)bbuf;
             const uint16_t* bl = bh + BELEMS;
             const int oct = lane >> 5;
+            // A fragments of every sub-block, one k-step ahead (software
+            // pipelined: the next k-step's loads are in flight during this
+            // k-step's products); a sub-block wholly past n reads a valid
+            // row and is skipped
+            bf16x8 ah[MSUB], al[MSUB];
+            auto load_a = [&](int ks) __attribute__((always_inline)) {
+                const size_t wbase = (size_t)wq[ks * 2 + oct] * ldn;
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    const int mo = min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
+                    const size_t off = (wbase + mo) * WIN;
+                    // global (not generic) loads: the wait before the products
+                    // can leave the next k-step's loads in flight
+                    ah[sb] = __builtin_bit_cast(bf16x8, *gmem((const uint4*)(Ahi + off)));
+                    al[sb] = __builtin_bit_cast(bf16x8, *gmem((const uint4*)(Alo + off)));
+                }
+            };
+            load_a(0);
+#pragma unroll
             for (int ks = 0; ks < KC / 16; ++ks) {
                 bf16x8 xh[5], xl[5];
 #pragma unroll
@@ -194,23 +213,15 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                     xh[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bh + off));
                     xl[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(bl + off));
                 }
-                const size_t wbase = (size_t)wq[ks * 2 + oct] * ldn;
-                // the A fragments of every sub-block first: one memory wait
-                // per k-step (a sub-block wholly past n reads a valid row
-                // and is skipped below)
-                bf16x8 ah[MSUB], al[MSUB];
+                bf16x8 cah[MSUB], cal[MSUB];
 #pragma unroll
-                for (int sb = 0; sb < MSUB; ++sb) {
-                    const int mo = min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
-                    const size_t off = (wbase + mo) * WIN;
-                    ah[sb] = __builtin_bit_cast(bf16x8, *(const uint4*)(Ahi + off));
-                    al[sb] = __builtin_bit_cast(bf16x8, *(const uint4*)(Alo + off));
-                }
+                for (int sb = 0; sb < MSUB; ++sb) { cah[sb] = ah[sb]; cal[sb] = al[sb]; }
+                if (ks + 1 < KC / 16) load_a(ks + 1);
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
                     if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
-                    const bf16x8 bah = ah[sb], bal = al[sb];
+                    const bf16x8 bah = cah[sb], bal = cal[sb];
                     // the three products of one accumulator are dependent:
                     // issue them five accumulators apart
 #pragma unroll
@@ -281,7 +292,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                         for (int r = 0; r < 4; ++r) {
                             // v_mfma_f64_16x16x4f64 result: row (lane / 16) + 4 r, column lane % 16
                             const int el = h * 16 + (lane >> 4) + 4 * r;
-                            if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[sb][d][h][r];
+                            if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[sb][d][h][r];
                         }
             }
         } else {
@@ -291,7 +302,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                 for (int d = 0; d < 5; ++d)
                     for (int r = 0; r < 16; ++r) {
                         const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        if (el < ne) C[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[sb][d][r];
+                        if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[sb][d][r];
                     }
             }
         }

@@ -404,7 +404,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
             const int e = g + NG * c, i = li + 32 * r;
-            const Tin v = C1[min(e, n - 1) * n + min(i, n - 1)];
+            const Tin v = gmem(C1)[min(e, n - 1) * n + min(i, n - 1)];
             M[r][c] = (e < n && i < n) ? (double)v : 0.0;
         }
     for (int k = tid; k < NB * NR; k += NT) colbuf[k / NR][k % NR] = 0.0;
@@ -621,7 +621,7 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         const int rows = min(QC, n - q0);
         for (int q = tid; q < rows * n; q += NT) {
             const int rr = q / n, cc = q % n;
-            Dw[(size_t)(q0 + rr) * n + cc] = stage[rr][cc];
+            gmem(Dw)[(size_t)(q0 + rr) * n + cc] = stage[rr][cc];
         }
         __syncthreads();
     }

@@ -293,6 +293,14 @@ __device__ __forceinline__ void batch_block(const Job* __restrict__ jobs, const 
     body(j, lb % j.gx, (lb / j.gx) % j.gy, lb / (j.gx * j.gy));
 }
 
+// The same pointer in the global address space: its loads and stores are
+// global (not generic) instructions, so waits for them leave LDS traffic
+// and younger loads alone.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 // Compile-time loop: f(integral_constant<int, I>) for I in [I0, N).
 template <int I, int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {

@@ -80,9 +80,9 @@ __device__ __forceinline__ void epilogue_body(const Job& j, int bx) {
     const Tc* Cw = C + (size_t)w * 5 * nn + (size_t)e * n;
     double acc[4] = {0, 0, 0, 0};
     for (int i = lane; i < n; i += 64) {
-        const double di = d[i];
+        const double di = gmem(d)[i];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = fma(di, (double)Cw[(size_t)(c + 1) * nn + i], acc[c]);
+        for (int c = 0; c < 4; ++c) acc[c] = fma(di, (double)gmem(Cw)[(size_t)(c + 1) * nn + i], acc[c]);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
