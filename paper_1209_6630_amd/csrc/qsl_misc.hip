@@ -79,10 +79,24 @@ __device__ __forceinline__ void epilogue_body(const Job& j, int bx) {
     const size_t nn = (size_t)n * n;
     const Tc* Cw = C + (size_t)w * 5 * nn + (size_t)e * n;
     double acc[4] = {0, 0, 0, 0};
-    for (int i = lane; i < n; i += 64) {
-        const double di = gmem(d)[i];
+    // four strides of 64 per pass, their loads issued together (clamped
+    // addresses; past n nothing is added)
+    for (int i0 = 0; i0 < n; i0 += 256) {
+        double di[4];
+        Tc cv[4][4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = fma(di, (double)gmem(Cw)[(size_t)(c + 1) * nn + i], acc[c]);
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(i0 + 64 * u + lane, n - 1);
+            di[u] = gmem(d)[i];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cv[u][c] = gmem(Cw)[(size_t)(c + 1) * nn + i];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + 64 * u + lane < n) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = fma(di[u], (double)cv[u][c], acc[c]);
+            }
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
