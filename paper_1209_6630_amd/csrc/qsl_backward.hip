@@ -318,6 +318,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     const int eoff = spin ? s.n_up : 0;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const double Tscr = readlane_f64(s.T, 0);                    // screening threshold, in scalar registers
     uint16_t* GTh = (uint16_t*)gbuf;
     uint16_t* GTl = GTh + ADJ_MB * LDGT;
     T* GTt = (T*)gbuf;
@@ -372,34 +373,48 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         lw_f[wli][jj] = f;
         lw_sh[wli][jj] = (int8_t)lsh;
     }
-    // AO values of one electron at the 8 slots of block window wli, from LDS
-    auto win_vals = [&](int wli, const double r[3], T vals[WIN]) __attribute__((always_inline)) {
+    // X entries that no walker writes (electrons past the tile, windows past
+    // the list, padding slots) stay zero from here on
+    for (int q = tid; q < (int)(sizeof(xbuf) / 4); q += AD_THREADS) ((uint32_t*)xbuf)[q] = 0u;
+    // AO values of electron e at the 8 slots of block window wli into X; a
+    // shell's radial factor is formed at its first slot from its primitives
+    // (a primitive past the screening threshold is skipped, by the whole wave
+    // when no lane keeps it).  BF16X3 loads the slot fields and the shell's
+    // primitives at once; FP32 / FP64 have no registers to spare for that.
+    auto win_vals = [&](int e, int wli) __attribute__((always_inline)) {
+        int pws[BF ? WIN : 1], lss[BF ? WIN : 1];
+        T fs[BF ? WIN : 1];
+        if constexpr (BF) {
 #pragma unroll
-        for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
-        if (wq[wli] < 0) return;
-        const double dx = r[0] - lw_pos[wli][0], dy = r[1] - lw_pos[wli][1], dz = r[2] - lw_pos[wli][2];
+            for (int jj = 0; jj < WIN; ++jj) {
+                pws[jj] = lw_pow[wli][jj];
+                lss[jj] = lw_sh[wli][jj];
+                fs[jj] = lw_f[wli][jj];
+            }
+        }
+        const double dx = epos[e][0] - lw_pos[wli][0], dy = epos[e][1] - lw_pos[wli][1],
+                     dz = epos[e][2] - lw_pos[wli][2];
         const double r2 = dist2_exact(dx, dy, dz);
         const T X = (T)dx, Y = (T)dy, Z = (T)dz;
         int prev = -1;
-        T gg = 0;
-        // slot fields loaded together, then each shell's primitives at once
-        int pws[WIN], lss[WIN];
+        T gg = T(0);
 #pragma unroll
         for (int jj = 0; jj < WIN; ++jj) {
-            pws[jj] = lw_pow[wli][jj];
-            lss[jj] = lw_sh[wli][jj];
-        }
-#pragma unroll
-        for (int jj = 0; jj < WIN; ++jj) {
-            const int pw = pws[jj];
+            int pw, ls;
+            if constexpr (BF) {
+                pw = pws[jj];
+                ls = lss[jj];
+            } else {
+                pw = lw_pow[wli][jj];
+                ls = lw_sh[wli][jj];
+            }
             if (pw < 0) continue;
-            const int ls = lss[jj];
             if (ls != prev) {
                 gg = T(0);
                 const int np = lw_np[wli][ls];
                 if constexpr (BF) {
                     double exs[QSL_PMAX];
-                    T cs[QSL_PMAX];
+                    float cs[QSL_PMAX];
 #pragma unroll
                     for (int k = 0; k < QSL_PMAX; ++k) {
                         exs[k] = lw_exp[wli][ls][k];
@@ -409,12 +424,12 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                     for (int k = 0; k < QSL_PMAX; ++k) {
                         if (k >= np) break;
                         const double t = __dmul_rn(exs[k], r2);
-                        if (t <= s.T) gg += cs[k] * exp_t(-(T)t);
+                        if (t <= Tscr) gg += cs[k] * exp_t(-(float)t);
                     }
-                } else {  // no registers to spare for the batch of loads
+                } else {
                     for (int k = 0; k < np; ++k) {
                         const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
-                        if (t <= s.T) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
+                        if (t <= Tscr) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
                     }
                 }
                 prev = ls;
@@ -423,12 +438,29 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const T px = a == 0 ? T(1) : (a == 1 ? X : X * X);
             const T py = b == 0 ? T(1) : (b == 1 ? Y : Y * Y);
             const T pz = c == 0 ? T(1) : (c == 1 ? Z : Z * Z);
-            vals[jj] = lw_f[wli][jj] * px * py * pz * gg;
+            const int ci = wli * WIN + jj;
+            if constexpr (BF) {
+                const float v = fs[jj] * px * py * pz * gg;
+                const uint16_t h = bf16_rne(v);
+                Xh[ci * LDX + e] = h;
+                Xl[ci * LDX + e] = bf16_rne(v - bf16_to_f(h));
+            } else {
+                Xt[e * LDX + ci] = lw_f[wli][jj] * px * py * pz * gg;
+            }
         }
     };
-    Blk<MODE> acc[PB];
+    // the dA block in the accumulators: BF16X3 keeps the MFMA operand form
+    Blk<MODE> acc[BF ? 1 : PB];
+    f32x16 accv[BF ? PB : 1];
 #pragma unroll
-    for (int k = 0; k < PB; ++k) acc[k].zero();
+    for (int k = 0; k < PB; ++k) {
+        if constexpr (BF) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) accv[k][q] = 0.f;
+        } else {
+            acc[k].zero();
+        }
+    }
 
     // D^-1 block of the next walker, loaded while the current one is used
     // (FP32 / FP64); in BF16X3 the rows of the split G^T (g_split), copied
@@ -472,15 +504,18 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             gpre[k] = ok ? x : 0.0;
         }
     };
+    // electron coordinates of the tile, also loaded one walker ahead
+    auto load_pos = [&](int w) __attribute__((always_inline)) -> double {
+        const int e = tid / 3, k = tid % 3;
+        return tid < TE * 3 && e < ne ? gmem(R)[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
+    };
+    double pnext = load_pos(w0);
     constexpr bool PF = MODE != QSL_FP64;  // FP64: no registers to spare for the prefetch
     if constexpr (PF) load_g(w0);
     for (int wl = 0; wl < nw; ++wl) {
         const int w = w0 + wl;
         __syncthreads();  // previous walker's operands are consumed
-        if (tid < TE * 3) {
-            const int e = tid / 3, k = tid % 3;
-            epos[e][k] = e < ne ? R[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
-        }
+        if (tid < TE * 3) epos[tid / 3][tid % 3] = pnext;
         if constexpr (!PF) load_g(w);
         if constexpr (BF) {
             auto put = [&](int k, const uint4& v) {
@@ -506,59 +541,73 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         if constexpr (PF) {
             if (wl + 1 < nw) load_g(w + 1);
         }
+        // after the G prefetch, so that the G stores above never wait for it
+        if (wl + 1 < nw) pnext = load_pos(w + 1);
         __syncthreads();
         // AO values of (electron, window) into LDS
         for (int p = tid; p < TE * NWB; p += AD_THREADS) {
             const int e = p & (TE - 1), wli = p / TE;
-            T vals[WIN];
-            const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
-            if (e < ne) win_vals(wli, r, vals);
-            else {
-#pragma unroll
-                for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
-            }
-#pragma unroll
-            for (int j = 0; j < WIN; ++j) {
-                const int c = wli * WIN + j;
-                if constexpr (BF) {
-                    const uint16_t h = bf16_rne(vals[j]);
-                    Xh[c * LDX + e] = h;
-                    Xl[c * LDX + e] = bf16_rne(vals[j] - bf16_to_f(h));
-                } else {
-                    Xt[e * LDX + c] = vals[j];
-                }
-            }
+            if (e < ne && wq[wli] >= 0) win_vals(e, wli);
         }
         __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PB; ++k) {
-            const int b = wave + 8 * k;
-            if (b >= NBLK) continue;
-            const int ib = b / SB, sb = b % SB;
-            if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
-            if constexpr (BF) {
-                f32x16 a16, b16, c16;  // three independent chains
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    a16[q] = acc[k].v[q];
-                    b16[q] = c16[q] = 0.f;
-                }
+        if constexpr (BF) {
+            // wave w owns slot block w and every MO block k
+            static_assert(SB == 8 && PB == ADJ_NIB && PB == 7, "one slot block per wave, seven MO blocks");
+            // Every MO block of the staged G runs, also those past n: their G
+            // rows are zeros (g_split pads to whole blocks), and a branch per
+            // block costs more registers than the MFMAs it would skip.  Blocks
+            // go in groups of two (the last group takes three): a block's
+            // products are an MFMA of its partner apart.  The operands of the
+            // next group are read while this group's MFMAs run; scheduling
+            // barriers keep that order (and the register count) as written.
+            // Every index is a compile-time constant, so the accumulators stay
+            // in registers.
+            if (wave * 32 < nq * WIN) {
+                constexpr int NG = PB / 2;
+                constexpr int GMAX = PB - 2 * (NG - 1);
+                constexpr int NST = 2 * NG;  // (k-step, group) steps
                 const int oct = lane >> 5;
+                bf16x8 bh[2], bl[2], ah[2][GMAX], al[2][GMAX];
+                static_for<0, 2>([&](auto h) {
+                    const int offb = (wave * 32 + (lane & 31)) * LDX + 16 * h + 8 * oct;
+                    bh[h] = __builtin_bit_cast(bf16x8, *(const uint4*)(Xh + offb));
+                    bl[h] = __builtin_bit_cast(bf16x8, *(const uint4*)(Xl + offb));
+                });
+                auto load = [&](auto st_c) __attribute__((always_inline)) {
+                    constexpr int st = decltype(st_c)::value;
+                    constexpr int h = st / NG, g = st % NG, kb = 2 * g, kn = g == NG - 1 ? PB - kb : 2;
+                    static_for<0, kn>([&](auto u) {
+                        const int offa = ((kb + u) * 32 + (lane & 31)) * LDGT + 16 * h + 8 * oct;
+                        ah[st & 1][u] = __builtin_bit_cast(bf16x8, *(const uint4*)(GTh + offa));
+                        al[st & 1][u] = __builtin_bit_cast(bf16x8, *(const uint4*)(GTl + offa));
+                    });
+                };
+                load(std::integral_constant<int, 0>{});
+                static_for<0, NST>([&](auto st_c) {
+                    constexpr int st = decltype(st_c)::value;
+                    if constexpr (st + 1 < NST) load(std::integral_constant<int, st + 1>{});
+                    __builtin_amdgcn_sched_barrier(0);
+                    constexpr int h = st / NG, g = st % NG, kb = 2 * g, kn = g == NG - 1 ? PB - kb : 2;
+                    constexpr int bb = st & 1;
+                    static_for<0, kn>([&](auto u) {
+                        accv[kb + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bb][u], bh[h], accv[kb + u], 0, 0, 0);
+                    });
+                    static_for<0, kn>([&](auto u) {
+                        accv[kb + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[bb][u], bl[h], accv[kb + u], 0, 0, 0);
+                    });
+                    static_for<0, kn>([&](auto u) {
+                        accv[kb + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[bb][u], bh[h], accv[kb + u], 0, 0, 0);
+                    });
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+            }
+        } else {
 #pragma unroll
-                for (int k0 = 0; k0 < TE; k0 += 16) {
-                    const int offa = (ib * 32 + (lane & 31)) * LDGT + k0 + 8 * oct;
-                    const int offb = (sb * 32 + (lane & 31)) * LDX + k0 + 8 * oct;
-                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const uint4*)(GTh + offa));
-                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const uint4*)(GTl + offa));
-                    const bf16x8 bh = __builtin_bit_cast(bf16x8, *(const uint4*)(Xh + offb));
-                    const bf16x8 bl = __builtin_bit_cast(bf16x8, *(const uint4*)(Xl + offb));
-                    a16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, a16, 0, 0, 0);
-                    b16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, b16, 0, 0, 0);
-                    c16 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c16, 0, 0, 0);
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q) acc[k].v[q] = a16[q] + (b16[q] + c16[q]);
-            } else {
+            for (int k = 0; k < PB; ++k) {
+                const int b = wave + 8 * k;
+                if (b >= NBLK) continue;
+                const int ib = b / SB, sb = b % SB;
+                if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
                 auto fa = [&](int r, int kk) -> T { return GTt[(ib * 32 + r) * LDGT + kk]; };
                 auto fb = [&](int kk, int cc) -> T { return Xt[kk * LDX + sb * 32 + cc]; };
                 mma_f<MODE>(acc[k], 0, TE, lane, fa, fb);
@@ -578,7 +627,9 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const int i = i0 + ib * 32 + Blk<MODE>::row(q, lane);
             const int c = sb * 32 + Blk<MODE>::col(q, lane);
             const int qw = wq[c / WIN];
-            const T v = acc[k].v[q];
+            T v;
+            if constexpr (BF) v = accv[k][q];
+            else v = acc[k].v[q];
             if (i >= n || qw < 0 || v == T(0)) continue;
             const int ao = s.slot_ao[qw * WIN + (c % WIN)];
             if (ao < 0) continue;
