@@ -326,7 +326,36 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     uint16_t* Xl = Xh + NS * LDX;
     T* Xt = (T*)xbuf;
 
-    if (tid < NWB) wq[tid] = tid < nq ? grp_win[(size_t)grp * s.n_win + q0 + tid] : -1;
+    // The block's windows ordered by their slot pattern (shells, slots):
+    // the two windows an AO wave takes at once then mostly share their
+    // branches.  Past-the-list entries (-1) stay last.
+    {
+        __shared__ int wraw[NWB], wkey[NWB];
+        if (tid < NWB) {
+            int q = -1, key = 1 << 30;
+            if (tid < nq) {
+                q = grp_win[(size_t)grp * s.n_win + q0 + tid];
+                const int sh0 = s.slot_shell[q * WIN];
+                int nv = 0, shl = sh0;
+                for (int jj = 0; jj < WIN; ++jj) {
+                    const int sh = s.slot_shell[q * WIN + jj];
+                    if (sh >= 0) {
+                        ++nv;
+                        shl = sh;
+                    }
+                }
+                key = (shl - sh0) * (WIN + 1) + nv;
+            }
+            wraw[tid] = q;
+            wkey[tid] = key;
+        }
+        __syncthreads();
+        if (tid < NWB) {
+            int r = 0;
+            for (int k = 0; k < NWB; ++k) r += wkey[k] < wkey[tid] || (wkey[k] == wkey[tid] && k < tid);
+            wq[r] = wraw[tid];
+        }
+    }
     // the block's windows are the same for every walker of the group: stage
     // their atom positions, slot monomials and shell primitives in LDS once
     constexpr int SPW = WIN;  // local shells per window (shells are consecutive slots)
@@ -373,35 +402,88 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         lw_f[wli][jj] = f;
         lw_sh[wli][jj] = (int8_t)lsh;
     }
-    // X entries that no walker writes (electrons past the tile, windows past
-    // the list, padding slots) stay zero from here on
-    for (int q = tid; q < (int)(sizeof(xbuf) / 4); q += AD_THREADS) ((uint32_t*)xbuf)[q] = 0u;
-    // AO values of electron e at the 8 slots of block window wli into X; a
-    // shell's radial factor is formed at its first slot from its primitives
-    // (a primitive past the screening threshold is skipped, by the whole wave
-    // when no lane keeps it).  BF16X3 loads the slot fields and the shell's
-    // primitives at once; FP32 / FP64 have no registers to spare for that.
-    auto win_vals = [&](int e, int wli) __attribute__((always_inline)) {
-        int pws[BF ? WIN : 1], lss[BF ? WIN : 1];
-        T fs[BF ? WIN : 1];
-        if constexpr (BF) {
+    // BF16X3: X entries that no walker writes (electrons past the tile,
+    // windows past the list, padding slots) stay zero from here on
+    if constexpr (BF)
+        for (int q = tid; q < (int)(sizeof(xbuf) / 4); q += AD_THREADS) ((uint32_t*)xbuf)[q] = 0u;
+    // BF16X3: AO values of electron e at the 8 slots of block window wli,
+    // written to X; a shell's radial factor is formed at its first slot from
+    // its primitives (a primitive past the screening threshold is skipped, by
+    // the whole wave when no lane keeps it).  The slot fields and the shell's
+    // primitives are loaded at once.
+    auto win_vals_bf = [&](int e, int wli) __attribute__((always_inline)) {
+        int pws[WIN], lss[WIN];
+        float fs[WIN];
 #pragma unroll
-            for (int jj = 0; jj < WIN; ++jj) {
-                pws[jj] = lw_pow[wli][jj];
-                lss[jj] = lw_sh[wli][jj];
-                fs[jj] = lw_f[wli][jj];
-            }
+        for (int jj = 0; jj < WIN; ++jj) {
+            pws[jj] = lw_pow[wli][jj];
+            lss[jj] = lw_sh[wli][jj];
+            fs[jj] = (float)lw_f[wli][jj];
         }
         const double dx = epos[e][0] - lw_pos[wli][0], dy = epos[e][1] - lw_pos[wli][1],
                      dz = epos[e][2] - lw_pos[wli][2];
         const double r2 = dist2_exact(dx, dy, dz);
+        const float X = (float)dx, Y = (float)dy, Z = (float)dz;
+        int prev = -1;
+        float gg = 0.f;
+#pragma unroll
+        for (int jj = 0; jj < WIN; ++jj) {
+            const int pw = pws[jj], ls = lss[jj];
+            if (pw < 0) continue;
+            if (ls != prev) {
+                gg = 0.f;
+                const int np = lw_np[wli][ls];
+                double exs[QSL_PMAX];
+                float cs[QSL_PMAX];
+#pragma unroll
+                for (int k = 0; k < QSL_PMAX; ++k) {
+                    exs[k] = lw_exp[wli][ls][k];
+                    cs[k] = (float)lw_c[wli][ls][k];
+                }
+#pragma unroll
+                for (int k = 0; k < QSL_PMAX; ++k) {
+                    if (k >= np) break;
+                    const double t = __dmul_rn(exs[k], r2);
+                    if (t <= Tscr) gg += cs[k] * exp_t(-(float)t);
+                }
+                prev = ls;
+            }
+            const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15;
+            const float px = a == 0 ? 1.f : (a == 1 ? X : X * X);
+            const float py = b == 0 ? 1.f : (b == 1 ? Y : Y * Y);
+            const float pz = c == 0 ? 1.f : (c == 1 ? Z : Z * Z);
+            const float v = fs[jj] * px * py * pz * gg;
+            const int ci = wli * WIN + jj;
+            const uint16_t h = bf16_rne(v);
+            Xh[ci * LDX + e] = h;
+            Xl[ci * LDX + e] = bf16_rne(v - bf16_to_f(h));
+        }
+    };
+    // FP32 / FP64: AO values of one electron at the 8 slots of block window
+    // wli (zeros where the window is past the list)
+    auto win_vals = [&](int wli, const double r[3], T vals[WIN]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
+        if (wq[wli] < 0) return;
+        const double dx = r[0] - lw_pos[wli][0], dy = r[1] - lw_pos[wli][1], dz = r[2] - lw_pos[wli][2];
+        const double r2 = dist2_exact(dx, dy, dz);
         const T X = (T)dx, Y = (T)dy, Z = (T)dz;
         int prev = -1;
-        T gg = T(0);
+        T gg = 0;
+        // FP64: slot fields loaded together (in FP32 that costs spills)
+        constexpr bool BATCH = MODE == QSL_FP64;
+        int pws[BATCH ? WIN : 1], lss[BATCH ? WIN : 1];
+        if constexpr (BATCH) {
+#pragma unroll
+            for (int jj = 0; jj < WIN; ++jj) {
+                pws[jj] = lw_pow[wli][jj];
+                lss[jj] = lw_sh[wli][jj];
+            }
+        }
 #pragma unroll
         for (int jj = 0; jj < WIN; ++jj) {
             int pw, ls;
-            if constexpr (BF) {
+            if constexpr (BATCH) {
                 pw = pws[jj];
                 ls = lss[jj];
             } else {
@@ -412,25 +494,9 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             if (ls != prev) {
                 gg = T(0);
                 const int np = lw_np[wli][ls];
-                if constexpr (BF) {
-                    double exs[QSL_PMAX];
-                    float cs[QSL_PMAX];
-#pragma unroll
-                    for (int k = 0; k < QSL_PMAX; ++k) {
-                        exs[k] = lw_exp[wli][ls][k];
-                        cs[k] = lw_c[wli][ls][k];
-                    }
-#pragma unroll
-                    for (int k = 0; k < QSL_PMAX; ++k) {
-                        if (k >= np) break;
-                        const double t = __dmul_rn(exs[k], r2);
-                        if (t <= Tscr) gg += cs[k] * exp_t(-(float)t);
-                    }
-                } else {
-                    for (int k = 0; k < np; ++k) {
-                        const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
-                        if (t <= Tscr) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
-                    }
+                for (int k = 0; k < np; ++k) {  // no registers to spare for a batch of loads
+                    const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
+                    if (t <= Tscr) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
                 }
                 prev = ls;
             }
@@ -438,15 +504,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const T px = a == 0 ? T(1) : (a == 1 ? X : X * X);
             const T py = b == 0 ? T(1) : (b == 1 ? Y : Y * Y);
             const T pz = c == 0 ? T(1) : (c == 1 ? Z : Z * Z);
-            const int ci = wli * WIN + jj;
-            if constexpr (BF) {
-                const float v = fs[jj] * px * py * pz * gg;
-                const uint16_t h = bf16_rne(v);
-                Xh[ci * LDX + e] = h;
-                Xl[ci * LDX + e] = bf16_rne(v - bf16_to_f(h));
-            } else {
-                Xt[e * LDX + ci] = lw_f[wli][jj] * px * py * pz * gg;
-            }
+            vals[jj] = lw_f[wli][jj] * px * py * pz * gg;
         }
     };
     // the dA block in the accumulators: BF16X3 keeps the MFMA operand form
@@ -504,18 +562,18 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             gpre[k] = ok ? x : 0.0;
         }
     };
-    // electron coordinates of the tile, also loaded one walker ahead
+    // electron coordinates of the tile, loaded one walker ahead with G
     auto load_pos = [&](int w) __attribute__((always_inline)) -> double {
         const int e = tid / 3, k = tid % 3;
         return tid < TE * 3 && e < ne ? gmem(R)[((size_t)w * N + eoff + e0 + e) * 3 + k] : 0.0;
     };
-    double pnext = load_pos(w0);
     constexpr bool PF = MODE != QSL_FP64;  // FP64: no registers to spare for the prefetch
+    double pnext = PF ? load_pos(w0) : 0.0;
     if constexpr (PF) load_g(w0);
     for (int wl = 0; wl < nw; ++wl) {
         const int w = w0 + wl;
         __syncthreads();  // previous walker's operands are consumed
-        if (tid < TE * 3) epos[tid / 3][tid % 3] = pnext;
+        if (tid < TE * 3) epos[tid / 3][tid % 3] = PF ? pnext : load_pos(w);
         if constexpr (!PF) load_g(w);
         if constexpr (BF) {
             auto put = [&](int k, const uint4& v) {
@@ -542,12 +600,24 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             if (wl + 1 < nw) load_g(w + 1);
         }
         // after the G prefetch, so that the G stores above never wait for it
-        if (wl + 1 < nw) pnext = load_pos(w + 1);
+        if (PF && wl + 1 < nw) pnext = load_pos(w + 1);
         __syncthreads();
         // AO values of (electron, window) into LDS
         for (int p = tid; p < TE * NWB; p += AD_THREADS) {
             const int e = p & (TE - 1), wli = p / TE;
-            if (e < ne && wq[wli] >= 0) win_vals(e, wli);
+            if constexpr (BF) {
+                if (e < ne && wq[wli] >= 0) win_vals_bf(e, wli);
+            } else {
+                T vals[WIN];
+                const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+                if (e < ne) win_vals(wli, r, vals);
+                else {
+#pragma unroll
+                    for (int jj = 0; jj < WIN; ++jj) vals[jj] = T(0);
+                }
+#pragma unroll
+                for (int j = 0; j < WIN; ++j) Xt[e * LDX + wli * WIN + j] = vals[j];
+            }
         }
         __syncthreads();
         if constexpr (BF) {
