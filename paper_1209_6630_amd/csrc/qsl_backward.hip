@@ -326,36 +326,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     uint16_t* Xl = Xh + NS * LDX;
     T* Xt = (T*)xbuf;
 
-    // The block's windows ordered by their slot pattern (shells, slots):
-    // the two windows an AO wave takes at once then mostly share their
-    // branches.  Past-the-list entries (-1) stay last.
-    {
-        __shared__ int wraw[NWB], wkey[NWB];
-        if (tid < NWB) {
-            int q = -1, key = 1 << 30;
-            if (tid < nq) {
-                q = grp_win[(size_t)grp * s.n_win + q0 + tid];
-                const int sh0 = s.slot_shell[q * WIN];
-                int nv = 0, shl = sh0;
-                for (int jj = 0; jj < WIN; ++jj) {
-                    const int sh = s.slot_shell[q * WIN + jj];
-                    if (sh >= 0) {
-                        ++nv;
-                        shl = sh;
-                    }
-                }
-                key = (shl - sh0) * (WIN + 1) + nv;
-            }
-            wraw[tid] = q;
-            wkey[tid] = key;
-        }
-        __syncthreads();
-        if (tid < NWB) {
-            int r = 0;
-            for (int k = 0; k < NWB; ++k) r += wkey[k] < wkey[tid] || (wkey[k] == wkey[tid] && k < tid);
-            wq[r] = wraw[tid];
-        }
-    }
+    if (tid < NWB) wq[tid] = tid < nq ? grp_win[(size_t)grp * s.n_win + q0 + tid] : -1;
     // the block's windows are the same for every walker of the group: stage
     // their atom positions, slot monomials and shell primitives in LDS once
     constexpr int SPW = WIN;  // local shells per window (shells are consecutive slots)

@@ -349,6 +349,35 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
                 slot_shell.push_back(-1); slot_pow.push_back(0); slot_f.push_back(0.0); slot_ao.push_back(-1);
             }
         }
+        // Windows ordered by their slot pattern (shells, valid slots), atom
+        // order within a pattern: every ascending window list (a tile's, a
+        // walker group's) then holds windows of one pattern side by side,
+        // and the AO passes, which give the two half-waves of a wave two
+        // windows, branch alike in both halves.
+        {
+            const int nw0 = (int)slot_shell.size() / WIN;
+            std::vector<int> key(nw0), perm(nw0);
+            for (int q = 0; q < nw0; ++q) {
+                int nv = 0, shl = slot_shell[q * WIN];
+                for (int j = 0; j < WIN; ++j) {
+                    if (slot_shell[q * WIN + j] < 0) continue;
+                    ++nv;
+                    shl = slot_shell[q * WIN + j];
+                }
+                key[q] = (shl - slot_shell[q * WIN]) * (WIN + 1) + nv;
+                perm[q] = q;
+            }
+            std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+            auto permute = [&](auto& v) {
+                const auto o = v;
+                for (int q = 0; q < nw0; ++q)
+                    for (int j = 0; j < WIN; ++j) v[(size_t)q * WIN + j] = o[(size_t)perm[q] * WIN + j];
+            };
+            permute(slot_shell);
+            permute(slot_pow);
+            permute(slot_f);
+            permute(slot_ao);
+        }
         const int n_slots = (int)slot_shell.size(), n_win = n_slots / WIN;
         std::vector<int> win_atom(std::max(n_win, 1));
         std::vector<double> win_gmin(std::max(n_win, 1), std::numeric_limits<double>::infinity());
