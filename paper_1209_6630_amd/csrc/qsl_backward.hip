@@ -573,12 +573,28 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         // after the G prefetch, so that the G stores above never wait for it
         if (PF && wl + 1 < nw) pnext = load_pos(w + 1);
         __syncthreads();
-        // AO values of (electron, window) into LDS
+        // AO values of (electron, window) into LDS.  BF16X3: wave w evaluates
+        // the windows of its own slot block (windows w, w + 8, w + 16,
+        // w + 24, a mix of slot patterns), which no other wave reads, so no
+        // barrier separates its evaluation from its MFMAs: the waves of a
+        // SIMD drift apart and one's MFMAs overlap the other's evaluation.
+        if constexpr (BF) {
+            static_assert(NWB == 4 * (AD_THREADS / 64), "four windows per wave");
+            const int e = lane & (TE - 1);
+#pragma unroll 1
+            for (int it = 0; it < 2; ++it) {
+                const int wli = wave + 8 * ((lane >> 5) + 2 * it);
+                if (e < ne && wq[wli] >= 0) win_vals_bf(e, wli);
+            }
+            // this wave's X rows are written before its lanes read them (one
+            // wave's LDS operations complete in order; the fence keeps the
+            // compiler from moving the reads up)
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int p = tid; p < TE * NWB; p += AD_THREADS) {
             const int e = p & (TE - 1), wli = p / TE;
-            if constexpr (BF) {
-                if (e < ne && wq[wli] >= 0) win_vals_bf(e, wli);
-            } else {
+            if constexpr (!BF) {
                 T vals[WIN];
                 const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
                 if (e < ne) win_vals(wli, r, vals);
@@ -590,9 +606,10 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                 for (int j = 0; j < WIN; ++j) Xt[e * LDX + wli * WIN + j] = vals[j];
             }
         }
-        __syncthreads();
+        if constexpr (!BF) __syncthreads();
         if constexpr (BF) {
-            // wave w owns slot block w and every MO block k
+            // wave w owns slot block w (column c: slot c % 8 of window
+            // w + 8 (c / 8)) and every MO block k
             static_assert(SB == 8 && PB == ADJ_NIB && PB == 7, "one slot block per wave, seven MO blocks");
             // Every MO block of the staged G runs, also those past n: their G
             // rows are zeros (g_split pads to whole blocks), and a branch per
@@ -603,14 +620,15 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             // barriers keep that order (and the register count) as written.
             // Every index is a compile-time constant, so the accumulators stay
             // in registers.
-            if (wave * 32 < nq * WIN) {
+            if (wave < nq) {
                 constexpr int NG = PB / 2;
                 constexpr int GMAX = PB - 2 * (NG - 1);
                 constexpr int NST = 2 * NG;  // (k-step, group) steps
                 const int oct = lane >> 5;
                 bf16x8 bh[2], bl[2], ah[2][GMAX], al[2][GMAX];
+                const int xrow = (wave + 8 * ((lane & 31) >> 3)) * WIN + (lane & 7);
                 static_for<0, 2>([&](auto h) {
-                    const int offb = (wave * 32 + (lane & 31)) * LDX + 16 * h + 8 * oct;
+                    const int offb = xrow * LDX + 16 * h + 8 * oct;
                     bh[h] = __builtin_bit_cast(bf16x8, *(const uint4*)(Xh + offb));
                     bl[h] = __builtin_bit_cast(bf16x8, *(const uint4*)(Xl + offb));
                 });
@@ -662,12 +680,15 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
         const int b = wave + 8 * k;
         if (b >= NBLK) continue;
         const int ib = b / SB, sb = b % SB;
-        if (i0 + ib * 32 >= n || sb * 32 >= nq * WIN) continue;
+        // (BF16X3: slot block sb starts with window sb)
+        if (i0 + ib * 32 >= n || (BF ? sb >= nq : sb * 32 >= nq * WIN)) continue;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const int i = i0 + ib * 32 + Blk<MODE>::row(q, lane);
             const int c = sb * 32 + Blk<MODE>::col(q, lane);
-            const int qw = wq[c / WIN];
+            // BF16X3 columns: slot c % 8 of window sb + 8 ((c % 32) / 8)
+            const int wc = BF ? sb + 8 * ((c & 31) >> 3) : c / WIN;
+            const int qw = wq[wc];
             T v;
             if constexpr (BF) v = accv[k][q];
             else v = acc[k].v[q];
