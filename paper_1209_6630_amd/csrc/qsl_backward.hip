@@ -297,9 +297,12 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     using T = typename C::T;
     constexpr bool BF = C::BF;
     constexpr int NWB = C::NWB, NS = C::NS, SB = C::SB, NBLK = C::NBLK, PB = C::PB, LDGT = C::LDGT, LDX = C::LDX;
-    __shared__ double epos[TE][3];
+    // BF16X3 double-buffers the electron positions and G: the next walker's
+    // are stored after this walker's MFMAs, one barrier per walker
+    constexpr int NBUF = BF ? 2 : 1;
+    __shared__ double epos[NBUF][TE][3];
     __shared__ int wq[NWB];
-    __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? 2 * 2 * ADJ_MB * LDGT : sizeof(T) * ADJ_MB * LDGT];
+    __shared__ __attribute__((aligned(16))) unsigned char gbuf[BF ? NBUF * 2 * 2 * ADJ_MB * LDGT : sizeof(T) * ADJ_MB * LDGT];
     __shared__ __attribute__((aligned(16))) unsigned char xbuf[BF ? 2 * 2 * NS * LDX : sizeof(T) * TE * LDX];
 
     const int ngw = (int)((W + gw - 1) / gw);
@@ -319,9 +322,10 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
     const double Tscr = readlane_f64(s.T, 0);                    // screening threshold, in scalar registers
-    uint16_t* GTh = (uint16_t*)gbuf;
+    uint16_t* GTh = (uint16_t*)gbuf;  // the current buffer (hi, then lo)
     uint16_t* GTl = GTh + ADJ_MB * LDGT;
     T* GTt = (T*)gbuf;
+    double(*ep)[3] = epos[0];
     uint16_t* Xh = (uint16_t*)xbuf;
     uint16_t* Xl = Xh + NS * LDX;
     T* Xt = (T*)xbuf;
@@ -391,8 +395,8 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             lss[jj] = lw_sh[wli][jj];
             fs[jj] = (float)lw_f[wli][jj];
         }
-        const double dx = epos[e][0] - lw_pos[wli][0], dy = epos[e][1] - lw_pos[wli][1],
-                     dz = epos[e][2] - lw_pos[wli][2];
+        const double dx = ep[e][0] - lw_pos[wli][0], dy = ep[e][1] - lw_pos[wli][1],
+                     dz = ep[e][2] - lw_pos[wli][2];
         const double r2 = dist2_exact(dx, dy, dz);
         const float X = (float)dx, Y = (float)dy, Z = (float)dz;
         int prev = -1;
@@ -541,23 +545,41 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     constexpr bool PF = MODE != QSL_FP64;  // FP64: no registers to spare for the prefetch
     double pnext = PF ? load_pos(w0) : 0.0;
     if constexpr (PF) load_g(w0);
+    // BF16X3: copy the prefetched split-G rows into buffer b
+    auto put_g = [&](int b) __attribute__((always_inline)) {
+        uint16_t* gh = (uint16_t*)gbuf + b * 2 * ADJ_MB * LDGT;
+        uint16_t* gl = gh + ADJ_MB * LDGT;
+        auto put = [&](int k, const uint4& v) {
+            const int q = tid + k * AD_THREADS;
+            if (q >= GQ) return;
+            const int half = q >= GQ / 2, r = q - half * (GQ / 2);
+            *(uint4*)((half ? gl : gh) + (r >> 2) * LDGT + (r & 3) * 8) = v;
+        };
+        put(0, gq0);
+        put(1, gq1);
+        put(2, gq2);
+        put(3, gq3);
+    };
+    if constexpr (BF) {  // walker w0 into buffer 0, walker w0 + 1 in flight
+        if (tid < TE * 3) epos[0][tid / 3][tid % 3] = pnext;
+        put_g(0);
+        if (nw > 1) {
+            load_g(w0 + 1);
+            pnext = load_pos(w0 + 1);
+        }
+        __syncthreads();
+    }
     for (int wl = 0; wl < nw; ++wl) {
         const int w = w0 + wl;
-        __syncthreads();  // previous walker's operands are consumed
-        if (tid < TE * 3) epos[tid / 3][tid % 3] = PF ? pnext : load_pos(w);
-        if constexpr (!PF) load_g(w);
         if constexpr (BF) {
-            auto put = [&](int k, const uint4& v) {
-                const int q = tid + k * AD_THREADS;
-                if (q >= GQ) return;
-                const int half = q >= GQ / 2, r = q - half * (GQ / 2);
-                *(uint4*)((half ? GTl : GTh) + (r >> 2) * LDGT + (r & 3) * 8) = v;
-            };
-            put(0, gq0);
-            put(1, gq1);
-            put(2, gq2);
-            put(3, gq3);
+            const int b = wl & 1;
+            GTh = (uint16_t*)gbuf + b * 2 * ADJ_MB * LDGT;
+            GTl = GTh + ADJ_MB * LDGT;
+            ep = epos[b];
         } else {
+            __syncthreads();  // previous walker's operands are consumed
+            if (tid < TE * 3) epos[0][tid / 3][tid % 3] = PF ? pnext : load_pos(w);
+            if constexpr (!PF) load_g(w);
             const double gwv = gnext;
 #pragma unroll
             for (int k = 0; k < GPT; ++k) {
@@ -566,13 +588,13 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                 const int e = q / ADJ_MB, ii = q % ADJ_MB;
                 GTt[ii * LDGT + e] = (T)(gwv != 0.0 ? gwv * gpre[k] : 0.0);
             }
+            if constexpr (PF) {
+                if (wl + 1 < nw) load_g(w + 1);
+            }
+            // after the G prefetch, so that the G stores above never wait for it
+            if (PF && wl + 1 < nw) pnext = load_pos(w + 1);
+            __syncthreads();
         }
-        if constexpr (PF) {
-            if (wl + 1 < nw) load_g(w + 1);
-        }
-        // after the G prefetch, so that the G stores above never wait for it
-        if (PF && wl + 1 < nw) pnext = load_pos(w + 1);
-        __syncthreads();
         // AO values of (electron, window) into LDS.  BF16X3: wave w evaluates
         // the windows of its own slot block (windows w, w + 8, w + 16,
         // w + 24, a mix of slot patterns), which no other wave reads, so no
@@ -596,7 +618,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             const int e = p & (TE - 1), wli = p / TE;
             if constexpr (!BF) {
                 T vals[WIN];
-                const double r[3] = {epos[e][0], epos[e][1], epos[e][2]};
+                const double r[3] = {ep[e][0], ep[e][1], ep[e][2]};
                 if (e < ne) win_vals(wli, r, vals);
                 else {
 #pragma unroll
@@ -660,6 +682,17 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                     __builtin_amdgcn_sched_barrier(0);
                 });
             }
+            if (wl + 1 < nw) {  // walker w + 1 into the other buffers, w + 2 in flight
+                if (tid < TE * 3) epos[(wl + 1) & 1][tid / 3][tid % 3] = pnext;
+                put_g((wl + 1) & 1);
+                if (wl + 2 < nw) {
+                    load_g(w + 2);
+                    pnext = load_pos(w + 2);
+                }
+            }
+            // the one barrier per walker: this walker's MFMAs are done with G
+            // and the next walker's positions and G are visible
+            __syncthreads();
         } else {
 #pragma unroll
             for (int k = 0; k < PB; ++k) {
