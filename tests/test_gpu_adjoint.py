@@ -78,6 +78,28 @@ def test_backward_configs(name, W, use_drift, mode):
         np.testing.assert_allclose(dR, gg[:, :, None] * out["drift"], rtol=1e-8, atol=1e-10 * np.abs(dR).max())
 
 
+@pytest.mark.parametrize("n_atoms,n_up,n_dn,W", [(2, 3, 2, 3), (5, 12, 11, 5), (12, 40, 39, 3)])
+@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
+def test_backward_few_windows(n_atoms, n_up, n_dn, W, mode):
+    """Systems with fewer windows than one dA block of 32: waves that own
+    no window, partly filled slot blocks, a single walker iteration or a
+    few; against the oracle adjoint within the bound of the full-size
+    configurations."""
+    print(f"[case] backward few windows atoms={n_atoms} n={n_up}/{n_dn} W={W} mode={mode}", flush=True)
+    sysm, A_up, A_dn = random_tiny(n_atoms=n_atoms, n_up=n_up, n_dn=n_dn, seed=21 + n_atoms)
+    R = walkers_near(sysm, W, seed=3 + n_atoms)
+    for use_drift in (False, True):
+        g, dR, dAu, dAd, out = _run(sysm, A_up, A_dn, R, mode, use_drift=use_drift)
+        ref = {"Dinv_up": out["Dinv_up"], "Dinv_dn": out["Dinv_dn"]}
+        nnz = max_survivors(sysm, R[:1])
+        tol = (64 + 64 + 2 * nnz) * U32 + (2.0 ** -16 if mode == "bf16x3" else 0.0)
+        rdR, rdAu, rdAd = oracle.backward(sysm, A_up, A_dn, R, ref["Dinv_up"], ref["Dinv_dn"], g)
+        bA, bR = _abs_bounds(sysm, A_up, A_dn, R, ref, g)
+        assert np.all(np.abs(dAu - rdAu) <= tol * bA[0] + 1e-300)
+        assert np.all(np.abs(dAd - rdAd) <= tol * bA[1] + 1e-300)
+        assert np.all(np.abs(dR - rdR) <= tol * bR + 1e-300)
+
+
 def test_autograd_function_matches_oracle():
     print("[case] autograd", flush=True)
     import torch
