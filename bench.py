@@ -65,6 +65,9 @@ def work_per_step(sysm, nnz, W, mode):
     adjoint = sum(2.0 * n * n * nnz * W for n in ns)       # H or dA: 2 flops per (electron, survivor, MO)
     cb = 8 if mode == "fp64" else 4
     epi = sum((8.0 * n * n + 4 * cb * n * n + 32.0 * n) * W for n in ns)  # Dinv + 4 C blocks read, drift/lap
+
+    def gsplit_bytes(D_read):
+        return sum(((8.0 * n * n if D_read else 0.0) + 4.0 * -(-n // 32) * 32 * -(-n // 224) * 224) * W for n in ns)
     return {
         f"contract_{mode}": (contract, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         # n <= 224: register-resident elimination on FP64 vector FMAs; larger
@@ -76,8 +79,9 @@ def work_per_step(sysm, nnz, W, mode):
         # dR = g drift: drift read, dR written, g read per component
         "dR_drift": (sum(56.0 * n * W for n in ns), "hbm", HBM_PEAK, "GB/s"),
         # split-BF16 G^T: D^-1 read, hi + lo written over the padded tiles
-        "g_split": (sum((8.0 * n * n + 4.0 * -(-n // 32) * 32 * -(-n // 224) * 224) * W for n in ns),
-                    "hbm", HBM_PEAK, "GB/s"),
+        "g_split": (gsplit_bytes(D_read=True), "hbm", HBM_PEAK, "GB/s"),
+        # drift / Laplacian that also writes the split G^T (D^-1 read once)
+        "drift_lap_g": (epi + gsplit_bytes(D_read=False), "hbm", HBM_PEAK, "GB/s"),
     }
 
 

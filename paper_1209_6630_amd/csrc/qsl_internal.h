@@ -417,6 +417,11 @@ hipError_t launch_dr_drift_batched(const Job* jobs, const int* prefix, int njobs
 hipError_t launch_epilogue(const Job& j, hipStream_t st);
 hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                       hipStream_t st);
+// Drift and Laplacian plus the split-BF16 G^T (Job.g, Job.gsplit; f32 C):
+// one block per (walker, electron tile).
+int epilogue_g_blocks(const Job& j);
+hipError_t launch_epilogue_g(const Job& j, hipStream_t st);
+hipError_t launch_epilogue_g_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 // Adjoint: H = G A and dR per tile; dA per walker group.
 void adj_h_grid(Job& j);
 void adj_da_grid(Job& j);

@@ -141,6 +141,123 @@ hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix,
     return hipGetLastError();
 }
 
+// Drift and Laplacian together with the split-BF16 G^T of the dA adjoint
+// (plans in BF16X3 that run both): one workgroup per (walker, electron tile
+// of 32) reads the tile's D^-1 rows once for both.  The drift / Laplacian
+// arithmetic is the plain epilogue's lane for lane (same sums, same order),
+// and G = g D^-1 rounded to FP32 and split like gsplit_body, so the results
+// are bit-identical to the two separate kernels.  The G^T tile [i][32] is
+// transposed through LDS in chunks of 256 MOs: wave v fills the columns of
+// its 8 electrons, then the chunk goes out as 16-byte rows.
+template <typename Tc>
+__device__ __forceinline__ void epilogue_g_body(const Job& j, int bx) {
+    const Tc* __restrict__ C = (const Tc*)j.C;
+    const double* __restrict__ Dinv = j.Dinv;
+    const int n = j.n, spin = j.spin, N = j.s.n_up + j.s.n_dn, e_off = spin ? j.s.n_up : 0;
+    const int T = tiles_per_walker(n), NIP = (n + ADJ_MB - 1) / ADJ_MB * ADJ_MB;
+    const int64_t w = bx / T;
+    const int t = bx % T;
+    if (w >= j.W) return;
+    constexpr int RW = TE / 4;      // electrons per wave (4 waves)
+    constexpr int CH = 256;         // MOs per chunk
+    constexpr int LDT = TE + 2;     // LDS row (uint16): 68 bytes, rows on distinct banks
+    __shared__ __attribute__((aligned(16))) uint16_t th[CH][LDT], tl[CH][LDT];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double gw = j.g[2 * w + spin];
+    const size_t nn = (size_t)n * n;
+    uint16_t* gh = j.gsplit + (w * T + t) * (int64_t)NIP * TE;
+    uint16_t* gl = gh + j.W * gsplit_elems(n);
+    double acc[RW][4];
+#pragma unroll
+    for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int i0 = 0; i0 < NIP; i0 += CH) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int el = wave * RW + r, e = t * TE + el;
+            const bool ev = e < n;
+            const double* d = Dinv + (w * n + (ev ? e : 0)) * n;
+            const Tc* Cw = C + (size_t)w * 5 * nn + (size_t)(ev ? e : 0) * n;
+            double di[4];
+            Tc cv[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = min(i0 + 64 * u + lane, n - 1);
+                di[u] = gmem(d)[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cv[u][c] = gmem(Cw)[(size_t)(c + 1) * nn + i];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + 64 * u + lane;
+                if (ev && i < n) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[r][c] = fma(di[u], (double)cv[u][c], acc[r][c]);
+                }
+                double v = 0.0;
+                if (ev && i < n && gw != 0.0) v = gw * di[u];
+                const float f = (float)v;
+                const uint16_t h = bf16_rne(f);
+                th[64 * u + lane][el] = h;
+                tl[64 * u + lane][el] = bf16_rne(f - bf16_to_f(h));
+            }
+        }
+        __syncthreads();
+        // rows i0 .. i0 + rows - 1 of the tile, hi then lo: 4 pieces of 16
+        // bytes per row
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        const int rows = min(CH, NIP - i0);
+        for (int q = threadIdx.x; q < rows * 8; q += 256) {
+            const int half = q >= rows * 4, qq = q - half * rows * 4;
+            const int row = qq >> 2, part = qq & 3;
+            const uint32_t* src = (const uint32_t*)((half ? tl[row] : th[row]) + part * 8);
+            const u32x4 v = u32x4{src[0], src[1], src[2], src[3]};
+            *gmem((u32x4*)((half ? gl : gh) + (int64_t)(i0 + row) * TE + part * 8)) = v;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += __shfl_xor(acc[r][c], o);
+        const int e = t * TE + wave * RW + r;
+        if (lane == 0 && e < n) {
+            const int64_t ge = w * N + e_off + e;
+            if (j.drift)
+                for (int c = 0; c < 3; ++c) j.drift[ge * 3 + c] = acc[r][c];
+            if (j.lap) j.lap[ge] = acc[r][3];
+            const bool fin = isfinite(acc[r][0]) && isfinite(acc[r][1]) && isfinite(acc[r][2]) && isfinite(acc[r][3]);
+            const bool sing = j.logdet && isinf(j.logdet[2 * w + spin]) && j.logdet[2 * w + spin] < 0;
+            if (!fin && !sing && j.status) atomicOr(j.status + w, QSL_STATUS_NONFINITE);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void epilogue_g_kernel(Job j) { epilogue_g_body<float>(j, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void epilogue_g_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { epilogue_g_body<float>(j, bx); });
+}
+
+int epilogue_g_blocks(const Job& j) { return (int)(j.W * tiles_per_walker(j.n)); }
+
+hipError_t launch_epilogue_g(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    j.gx = epilogue_g_blocks(j); j.gy = 1; j.gz = 1;
+    if (!j.gx || !j.gsplit || !j.g || j.mode == QSL_FP64) return hipErrorInvalidValue;
+    epilogue_g_kernel<<<(unsigned)j.gx, 256, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue_g_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    epilogue_g_batched<<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
 // dR through the forward's drift.  By Jacobi's formula the derivative of
 // log|det D^s| in r_e is sum_i D^-1[e][i] grad phi_i(r_e), the drift of the
 // "vector products" equations, so dR[w][e] = g[w][s] drift[w][e] for the

@@ -27,6 +27,7 @@ enum Phase {
     PH_GJ3,
     PH_GJ4,          // blocked (n > 224)
     PH_EPILOGUE,     // drift and Laplacian
+    PH_EPI_G,        // drift and Laplacian with the split-BF16 G^T (BF16X3 with dA)
     PH_DR,           // dR = g drift (drift bound)
     PH_ADJ_H,        // H = G A, dR (no drift bound)
     PH_SCREEN_G,     // per walker-group window lists
@@ -151,10 +152,30 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
         p->ph[PH_GJ0 + gj_job_variant(j)].jobs.push_back(j);
         if (f.drift || f.lap) {
             j = f;
-            j.gx = epilogue_blocks(j); j.gy = 1; j.gz = 1;
-            p->ph[PH_EPILOGUE].jobs.push_back(j);
+            // BF16X3 with dA: the epilogue also writes the adjoint's split G
+            // (it reads the same D^-1 rows), and g_split does not run
+            const Job* bg = nullptr;
+            if (f.mode == QSL_BF16X3)
+                for (const Job& b : p->bjobs)
+                    if (b.gsplit && b.g && (b.dA64 || b.dA32) && b.Dinv == f.Dinv && b.spin == f.spin && b.W == f.W &&
+                        b.n == f.n)
+                        bg = &b;
+            if (bg) {
+                j.g = bg->g;
+                j.gsplit = bg->gsplit;
+                j.gx = epilogue_g_blocks(j); j.gy = 1; j.gz = 1;
+                p->ph[PH_EPI_G].jobs.push_back(j);
+            } else {
+                j.gx = epilogue_blocks(j); j.gy = 1; j.gz = 1;
+                p->ph[PH_EPILOGUE].jobs.push_back(j);
+            }
         }
     }
+    auto g_fused = [&](const Job& b) {
+        for (const Job& e : p->ph[PH_EPI_G].jobs)
+            if (e.gsplit == b.gsplit) return true;
+        return false;
+    };
     for (const Job& b : p->bjobs) {
         if (!b.n || !b.W) continue;
         Job j = b;
@@ -169,7 +190,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
             j = b;
             j.gx = screen_blocks(j, 1); j.gy = 1; j.gz = 1;
             p->ph[PH_SCREEN_G].jobs.push_back(j);
-            if (b.gsplit) {
+            if (b.gsplit && !g_fused(b)) {
                 j = b;
                 j.gx = gsplit_blocks(j); j.gy = 1; j.gz = 1;
                 p->ph[PH_GSPLIT].jobs.push_back(j);
@@ -303,6 +324,18 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         for (const Job& j : E.jobs) {
             ProfScope ps("drift_lap", st);
             if ((e = launch_epilogue(j, st)) != hipSuccess) return hip_fail(e, "epilogue kernel");
+        }
+    }
+    auto& EG = p->ph[PH_EPI_G];
+    if (batched && EG.blocks()) {
+        ProfScope ps("drift_lap_g", st);
+        if ((e = launch_epilogue_g_batched(dev_jobs(p, PH_EPI_G), dev_prefix(p, PH_EPI_G), (int)EG.jobs.size(),
+                                           EG.blocks(), st)) != hipSuccess)
+            return hip_fail(e, "epilogue kernel");
+    } else if (!batched) {
+        for (const Job& j : EG.jobs) {
+            ProfScope ps("drift_lap_g", st);
+            if ((e = launch_epilogue_g(j, st)) != hipSuccess) return hip_fail(e, "epilogue kernel");
         }
     }
     // adjoint (the tile lists of the forward's screening are reused)
