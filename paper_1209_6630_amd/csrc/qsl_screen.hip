@@ -20,15 +20,19 @@ namespace qsl {
 
 constexpr int SCREEN_THREADS = 256;
 static_assert(UNION_MAXWIN / 32 <= SCREEN_THREADS, "one bitmap word per thread");
-constexpr int SCREEN_MAXE = 2048;  // positions staged in LDS (the rest are read from L2)
+// positions staged in LDS (the rest are read from L2): a tile has TE, a
+// walker group up to gw * TE; the tile kernels keep their LDS small, so
+// more of their workgroups share a CU
+constexpr int SCREEN_MAXE_GROUP = 2048;
 
+template <int MAXE>
 __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __restrict__ tile_nwin,
                                             int* __restrict__ tile_win, uint32_t* __restrict__ status, int bx) {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n;
     const int64_t W = j.W;
     const double* __restrict__ R = j.R;
-    __shared__ double ex[SCREEN_MAXE], ey[SCREEN_MAXE], ez[SCREEN_MAXE];
+    __shared__ double ex[MAXE], ey[MAXE], ez[MAXE];
     __shared__ double bb[6];
     __shared__ double bred[SCREEN_THREADS / 64][6];
     __shared__ int wave_cnt[SCREEN_THREADS / 64];
@@ -71,7 +75,7 @@ __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __res
             lo[0] = fmin(lo[0], x); lo[1] = fmin(lo[1], y); lo[2] = fmin(lo[2], z);
             hi[0] = fmax(hi[0], x); hi[1] = fmax(hi[1], y); hi[2] = fmax(hi[2], z);
         }
-        if (k < SCREEN_MAXE) { ex[k] = x; ey[k] = y; ez[k] = z; }
+        if (k < MAXE) { ex[k] = x; ey[k] = y; ez[k] = z; }
     }
     // bounding box of the set's electrons
     for (int o = 32; o >= 1; o >>= 1)
@@ -107,7 +111,7 @@ __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __res
                 for (int k = 0; k < nall; ++k) {
                     if (!valid(k)) continue;
                     double px, py, pz;
-                    if (k < SCREEN_MAXE) { px = ex[k]; py = ey[k]; pz = ez[k]; }
+                    if (k < MAXE) { px = ex[k]; py = ey[k]; pz = ez[k]; }
                     else { const double* r = gpos(k); px = r[0]; py = r[1]; pz = r[2]; }
                     const double tt = __dmul_rn(gm, dist2_exact(px - qx, py - qy, pz - qz));
                     active |= tt <= s.T;
@@ -136,16 +140,22 @@ __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __res
     if (tid == 0) tile_nwin[tile] = base;
 }
 
-__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(Job j, int group) {
-    if (group) screen_body(j, true, j.gnwin, j.gwin, nullptr, blockIdx.x);
-    else screen_body(j, false, j.nwin, j.win, j.status, blockIdx.x);
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_kernel(Job j) {
+    screen_body<TE>(j, false, j.nwin, j.win, j.status, blockIdx.x);
 }
 
-__global__ __launch_bounds__(SCREEN_THREADS) void screen_batched(const Job* jobs, const int* prefix, int njobs,
-                                                                     int group) {
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_group_kernel(Job j) {
+    screen_body<SCREEN_MAXE_GROUP>(j, true, j.gnwin, j.gwin, nullptr, blockIdx.x);
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs,
+                [&](const Job& j, int bx, int, int) { screen_body<TE>(j, false, j.nwin, j.win, j.status, bx); });
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void screen_group_batched(const Job* jobs, const int* prefix, int njobs) {
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) {
-        if (group) screen_body(j, true, j.gnwin, j.gwin, nullptr, bx);
-        else screen_body(j, false, j.nwin, j.win, j.status, bx);
+        screen_body<SCREEN_MAXE_GROUP>(j, true, j.gnwin, j.gwin, nullptr, bx);
     });
 }
 
@@ -162,13 +172,15 @@ hipError_t launch_screen(const Job& j, int group, hipStream_t st) {
     if (!blocks) return hipSuccess;
     Job jj = j;
     jj.gx = blocks; jj.gy = 1; jj.gz = 1;
-    screen_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj, group);
+    if (group) screen_group_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj);
+    else screen_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj);
     return hipGetLastError();
 }
 
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st) {
-    screen_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs, group);
+    if (group) screen_group_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else screen_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 
