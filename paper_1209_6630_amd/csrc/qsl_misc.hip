@@ -149,6 +149,8 @@ hipError_t launch_epilogue_batched(int mode, const Job* jobs, const int* prefix,
 // are bit-identical to the two separate kernels.  The G^T tile [i][32] is
 // transposed through LDS in chunks of 256 MOs: wave v fills the columns of
 // its 8 electrons, then the chunk goes out as 16-byte rows.
+constexpr int EPG_THREADS = 512;  // 8 waves, 4 electron rows each
+
 template <typename Tc>
 __device__ __forceinline__ void epilogue_g_body(const Job& j, int bx) {
     const Tc* __restrict__ C = (const Tc*)j.C;
@@ -158,7 +160,7 @@ __device__ __forceinline__ void epilogue_g_body(const Job& j, int bx) {
     const int64_t w = bx / T;
     const int t = bx % T;
     if (w >= j.W) return;
-    constexpr int RW = TE / 4;      // electrons per wave (4 waves)
+    constexpr int RW = TE / (EPG_THREADS / 64);  // electrons per wave
     constexpr int CH = 256;         // MOs per chunk
     constexpr int LDT = TE + 2;     // LDS row (uint16): 68 bytes, rows on distinct banks
     __shared__ __attribute__((aligned(16))) uint16_t th[CH][LDT], tl[CH][LDT];
@@ -208,7 +210,7 @@ __device__ __forceinline__ void epilogue_g_body(const Job& j, int bx) {
         // bytes per row
         typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
         const int rows = min(CH, NIP - i0);
-        for (int q = threadIdx.x; q < rows * 8; q += 256) {
+        for (int q = threadIdx.x; q < rows * 8; q += EPG_THREADS) {
             const int half = q >= rows * 4, qq = q - half * rows * 4;
             const int row = qq >> 2, part = qq & 3;
             const uint32_t* src = (const uint32_t*)((half ? tl[row] : th[row]) + part * 8);
@@ -236,9 +238,9 @@ __device__ __forceinline__ void epilogue_g_body(const Job& j, int bx) {
     }
 }
 
-__global__ __launch_bounds__(256) void epilogue_g_kernel(Job j) { epilogue_g_body<float>(j, blockIdx.x); }
+__global__ __launch_bounds__(EPG_THREADS) void epilogue_g_kernel(Job j) { epilogue_g_body<float>(j, blockIdx.x); }
 
-__global__ __launch_bounds__(256) void epilogue_g_batched(const Job* jobs, const int* prefix, int njobs) {
+__global__ __launch_bounds__(EPG_THREADS) void epilogue_g_batched(const Job* jobs, const int* prefix, int njobs) {
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { epilogue_g_body<float>(j, bx); });
 }
 
@@ -248,13 +250,13 @@ hipError_t launch_epilogue_g(const Job& j0, hipStream_t st) {
     Job j = j0;
     j.gx = epilogue_g_blocks(j); j.gy = 1; j.gz = 1;
     if (!j.gx || !j.gsplit || !j.g || j.mode == QSL_FP64) return hipErrorInvalidValue;
-    epilogue_g_kernel<<<(unsigned)j.gx, 256, 0, st>>>(j);
+    epilogue_g_kernel<<<(unsigned)j.gx, EPG_THREADS, 0, st>>>(j);
     return hipGetLastError();
 }
 
 hipError_t launch_epilogue_g_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    epilogue_g_batched<<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    epilogue_g_batched<<<grid, EPG_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 
