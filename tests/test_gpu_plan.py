@@ -114,6 +114,41 @@ def test_plan_equals_per_system_calls(mode, graph):
     P.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_plan_without_drift_splits_g_itself(graph):
+    """A BF16X3 plan bound without drift and Laplacian outputs: dR comes
+    from recomputed AO gradients and the split G from its own pre-pass (no
+    epilogue to write it); equal to the per-system calls."""
+    import torch
+    from paper_1209_6630_amd.api import Plan
+    print(f"[case] plan without drift graph={graph}", flush=True)
+    mode = "bf16x3"
+    items = _batch([("44e", 6), ("158e", 3)])
+    P = Plan([it["S"] for it in items], [it["R"].shape[0] for it in items], mode, graph=graph)
+    bufs = []
+    for i, it in enumerate(items):
+        S, W = it["S"], it["R"].shape[0]
+        out = S.alloc_outputs(W, mode, drift=False)
+        dR = torch.empty((W, S.n_elec, 3), dtype=torch.float64, device="cuda")
+        dA = (torch.empty((S.n_up, S.n_basis), dtype=torch.float64, device="cuda"),
+              torch.empty((S.n_dn, S.n_basis), dtype=torch.float64, device="cuda"))
+        P.bind(i, it["Rt"], out, g=it["gt"], dR=dR, dA=dA)
+        bufs.append((out, dR, dA))
+    P.launch()
+    got = _read(bufs)
+    for it, g_ in zip(items, got):
+        S = it["S"]
+        out = S.forward(it["Rt"], mode)
+        dR, dAu, dAd = S.backward(it["Rt"], out["Dinv_up"], out["Dinv_dn"], it["gt"], mode)
+        torch.cuda.synchronize()
+        for k in ("logdet", "sign", "Dinv_up", "Dinv_dn", "C_up", "C_dn"):
+            np.testing.assert_array_equal(g_[k], out[k].cpu().numpy(), err_msg=k)
+        np.testing.assert_array_equal(g_["dR"], dR.cpu().numpy())
+        _dA_close(dAu.cpu().numpy(), g_["dA_up"], mode)
+        _dA_close(dAd.cpu().numpy(), g_["dA_dn"], mode)
+    P.close()
+
+
 def test_graph_replays_follow_new_coordinates():
     """Replays of one captured graph, with eager work and new walker
     coordinates copied into the bound R between them, each equal the eager
