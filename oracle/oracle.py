@@ -56,7 +56,7 @@ def load():
                                     ct.POINTER(ct.c_int8), _dp, _dp, _dp, _dp,
                                     ct.POINTER(ct.c_uint32), ct.c_int32]
         lib.orc_backward.argtypes = [S, _dp, _dp, ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
-                                     _dp, ct.c_int32]
+                                     _dp, _dp, _dp, _dp, ct.c_int32]
         lib.orc_max_threads.restype = ct.c_int
         _lib = lib
     return _lib
@@ -153,8 +153,10 @@ def forward(sys, A_up, A_dn, R, want_abs=False, nthreads=0):
     return out
 
 
-def backward(sys, A_up, A_dn, R, Dinv_up, Dinv_dn, g, nthreads=0):
-    """Adjoint of log|det|: returns (dR[W,N,3], dA_up, dA_dn)."""
+def backward(sys, A_up, A_dn, R, Dinv_up, Dinv_dn, g, nthreads=0, want_abs=False):
+    """Adjoint of log|det|: returns (dR[W,N,3], dA_up, dA_dn); with want_abs
+    also (dR_abs, dA_abs_up, dA_abs_dn), the same sums over the absolute
+    values of every term."""
     o = _osys(sys)
     R = np.ascontiguousarray(R, np.float64)
     W, N = R.shape[0], R.shape[1]
@@ -166,8 +168,11 @@ def backward(sys, A_up, A_dn, R, Dinv_up, Dinv_dn, g, nthreads=0):
     dR = np.zeros((W, N, 3))
     dA_up = np.zeros_like(A_up)
     dA_dn = np.zeros_like(A_dn)
+    ab = (np.zeros((W, N, 3)), np.zeros_like(A_up), np.zeros_like(A_dn)) if want_abs else (None, None, None)
     load().orc_backward(o.ref, _p(A_up), _p(A_dn), W, _p(R), _p(Dinv_up), _p(Dinv_dn), _p(g),
-                        _p(dR), _p(dA_up), _p(dA_dn), int(nthreads))
+                        _p(dR), _p(dA_up), _p(dA_dn), _p(ab[0]), _p(ab[1]), _p(ab[2]), int(nthreads))
+    if want_abs:
+        return dR, dA_up, dA_dn, ab
     return dR, dA_up, dA_dn
 
 

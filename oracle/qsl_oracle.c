@@ -466,10 +466,15 @@ void orc_forward(const orc_system* s, const double* A_up, const double* A_dn,
  *   dR[w][e]   = sum_k (sum_i A^s[i][idx(k,e)] G[e][i]) grad chi_idx(k,e)(r_e)
  * The survivor sets are held fixed (derivative of the screened function).
  * dR is overwritten; dA is overwritten with the sum over walkers.
+ * Optional (NULL to skip): the same sums over absolute values of every term,
+ *   dA_abs^s[i][j] = sum_w sum_e |G[e][i]| |chi_j(r_e)|
+ *   dR_abs[w][e]   = sum_k (sum_i |A^s[i][idx(k,e)]| |G[e][i]|) |grad chi_idx(k,e)(r_e)|
+ * (componentwise), the scale against which rounding errors are bounded.
  */
 void orc_backward(const orc_system* s, const double* A_up, const double* A_dn,
                   int32_t W, const double* R, const double* Dinv_up, const double* Dinv_dn,
-                  const double* g, double* dR, double* dA_up, double* dA_dn, int32_t nthreads) {
+                  const double* g, double* dR, double* dA_up, double* dA_dn,
+                  double* dR_abs, double* dAabs_up, double* dAabs_dn, int32_t nthreads) {
     orc_prep P;
     prep_init(&P, s);
     const int N = s->n_up + s->n_dn, nb = P.n_basis;
@@ -479,15 +484,19 @@ void orc_backward(const orc_system* s, const double* A_up, const double* A_dn,
     nthr = omp_get_max_threads();
 #endif
     size_t szu = (size_t)s->n_up * nb, szd = (size_t)s->n_dn * nb;
-    double* part = (double*)calloc((size_t)nthr * (szu + szd) + 1, sizeof(double));
+    const int want_abs = dR_abs || dAabs_up || dAabs_dn;
+    const size_t per = (szu + szd) * (want_abs ? 2 : 1);
+    double* part = (double*)calloc((size_t)nthr * per + 1, sizeof(double));
 #pragma omp parallel
     {
         int tid = 0;
 #ifdef _OPENMP
         tid = omp_get_thread_num();
 #endif
-        double* my_up = part + (size_t)tid * (szu + szd);
+        double* my_up = part + (size_t)tid * per;
         double* my_dn = my_up + szu;
+        double* myabs_up = want_abs ? my_dn + szd : NULL;
+        double* myabs_dn = want_abs ? myabs_up + szu : NULL;
         int* idx = (int*)malloc(sizeof(int) * (nb + 1));
         double* B = (double*)malloc(sizeof(double) * 5 * (nb + 1));
 #pragma omp for schedule(static)
@@ -498,24 +507,33 @@ void orc_backward(const orc_system* s, const double* A_up, const double* A_dn,
                 const double* A = sp ? A_dn : A_up;
                 const double* Di = (sp ? Dinv_dn : Dinv_up) + (size_t)w * n * n;
                 double* dA = sp ? my_dn : my_up;
+                double* dAa = sp ? myabs_dn : myabs_up;
                 double gw = g[2 * w + sp];
                 for (int e = 0; e < n; ++e) {
                     size_t ge = (size_t)w * N + e0 + e;
                     const double* r = R + ge * 3;
                     int nt = 0;
                     int cnt = ao_eval(&P, r, idx, B, nb + 1, &nt);
-                    double dr[3] = {0, 0, 0};
+                    double dr[3] = {0, 0, 0}, dra[3] = {0, 0, 0};
                     for (int k = 0; k < cnt; ++k) {
                         int j = idx[k];
-                        double h = 0.0;
+                        double h = 0.0, ha = 0.0;
                         for (int i = 0; i < n; ++i) {
                             double Gi = gw * Di[(size_t)e * n + i];
                             h += A[(size_t)i * nb + j] * Gi;
                             dA[(size_t)i * nb + j] += Gi * B[k];
+                            if (dAa) {
+                                ha += fabs(A[(size_t)i * nb + j]) * fabs(Gi);
+                                dAa[(size_t)i * nb + j] += fabs(Gi) * fabs(B[k]);
+                            }
                         }
                         for (int c = 0; c < 3; ++c) dr[c] += h * B[(1 + c) * (nb + 1) + k];
+                        if (dAa)
+                            for (int c = 0; c < 3; ++c) dra[c] += ha * fabs(B[(1 + c) * (nb + 1) + k]);
                     }
                     for (int c = 0; c < 3; ++c) dR[ge * 3 + c] = dr[c];
+                    if (dR_abs)
+                        for (int c = 0; c < 3; ++c) dR_abs[ge * 3 + c] = dra[c];
                 }
             }
         }
@@ -523,10 +541,14 @@ void orc_backward(const orc_system* s, const double* A_up, const double* A_dn,
     }
     if (dA_up) memset(dA_up, 0, sizeof(double) * szu);
     if (dA_dn) memset(dA_dn, 0, sizeof(double) * szd);
+    if (dAabs_up) memset(dAabs_up, 0, sizeof(double) * szu);
+    if (dAabs_dn) memset(dAabs_dn, 0, sizeof(double) * szd);
     for (int t = 0; t < nthr; ++t) {
-        const double* pu = part + (size_t)t * (szu + szd);
+        const double* pu = part + (size_t)t * per;
         if (dA_up) for (size_t q = 0; q < szu; ++q) dA_up[q] += pu[q];
         if (dA_dn) for (size_t q = 0; q < szd; ++q) dA_dn[q] += pu[szu + q];
+        if (dAabs_up) for (size_t q = 0; q < szu; ++q) dAabs_up[q] += pu[szu + szd + q];
+        if (dAabs_dn) for (size_t q = 0; q < szd; ++q) dAabs_dn[q] += pu[2 * szu + szd + q];
     }
     free(part);
     prep_free(&P);

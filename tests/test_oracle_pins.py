@@ -371,6 +371,38 @@ def test_adjoint_finite_difference():
         assert dR[w, e, ax] == pytest.approx((L(A_up, A_dn, Rp) - L(A_up, A_dn, Rm)) / (2 * h), rel=1e-5, abs=1e-7)
 
 
+def test_adjoint_absolute_sums():
+    """The absolute-value sums that scale the adjoint's error bounds: they
+    dominate |dA| and |dR| term by term, scale with |g|, and equal dA exactly
+    when every term is non-negative (s shells only, so chi > 0, with A >= 0,
+    D^-1 >= 0 and g >= 0 passed in)."""
+    sysm, A_up, A_dn = random_tiny(n_atoms=3, n_up=4, n_dn=3, seed=73)
+    R = walkers_near(sysm, 4, seed=12)
+    out = oracle.forward(sysm, A_up, A_dn, R)
+    g = np.random.default_rng(5).normal(size=(4, 2))
+    dR, dAu, dAd, (bR, bAu, bAd) = oracle.backward(sysm, A_up, A_dn, R, out["Dinv_up"], out["Dinv_dn"], g,
+                                                    want_abs=True)
+    assert np.all(bAu >= np.abs(dAu)) and np.all(bAd >= np.abs(dAd)) and np.all(bR >= np.abs(dR))
+    assert bAu.max() > 0 and bR.max() > 0
+    _, _, _, (bR2, bAu2, _) = oracle.backward(sysm, A_up, A_dn, R, out["Dinv_up"], out["Dinv_dn"], -2.0 * g,
+                                              want_abs=True)
+    np.testing.assert_allclose(bAu2, 2.0 * bAu, rtol=1e-14)
+    np.testing.assert_allclose(bR2, 2.0 * bR, rtol=1e-14)
+    # every term non-negative: the absolute sums are the sums themselves
+    rng = np.random.default_rng(6)
+    atoms = rng.normal(scale=1.0, size=(2, 3))
+    shells = [(a, 0, np.exp(rng.uniform(np.log(0.3), np.log(3.0), 2)), rng.uniform(0.2, 1.0, 2))
+              for a in range(2) for _ in range(3)]
+    sp = make_tiny(shells, atoms, 3, 2)
+    nb = sp.n_basis
+    Au, Ad = rng.uniform(0.1, 1.0, size=(3, nb)), rng.uniform(0.1, 1.0, size=(2, nb))
+    Rs = walkers_near(sp, 3, seed=13)
+    Du, Dd = rng.uniform(0.1, 1.0, size=(3, 3, 3)), rng.uniform(0.1, 1.0, size=(3, 2, 2))
+    gp = rng.uniform(0.5, 2.0, size=(3, 2))
+    _, eAu, eAd, (_, fAu, fAd) = oracle.backward(sp, Au, Ad, Rs, Du, Dd, gp, want_abs=True)
+    assert np.array_equal(eAu, fAu) and np.array_equal(eAd, fAd)
+
+
 # ----------------------------------------------- synthetic workload shape
 
 def test_synthetic_survivor_statistics_plausible():
