@@ -418,7 +418,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
 #pragma unroll
                 for (int k = 0; k < QSL_PMAX; ++k) {
                     if (k >= np) break;
-                    const double t = __dmul_rn(exs[k], r2);
+                    const double t = mul_exact(exs[k], r2);
                     if (t <= Tscr) gg += cs[k] * exp_t(-(float)t);
                 }
                 prev = ls;
@@ -470,7 +470,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
                 gg = T(0);
                 const int np = lw_np[wli][ls];
                 for (int k = 0; k < np; ++k) {  // no registers to spare for a batch of loads
-                    const double t = __dmul_rn(lw_exp[wli][ls][k], r2);
+                    const double t = mul_exact(lw_exp[wli][ls][k], r2);
                     if (t <= Tscr) gg += lw_c[wli][ls][k] * exp_t(-(T)t);
                 }
                 prev = ls;

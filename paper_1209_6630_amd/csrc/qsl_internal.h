@@ -121,10 +121,20 @@ __host__ __device__ inline int64_t electron_tiles(int n, int64_t W) { return (in
 // ------------------------------------------------------------------ device
 
 // Exact FP64 squared distance, evaluated as (dx*dx + dy*dy) + dz*dz with
-// no fused multiply-add, so that every screening decision is identical in
-// every precision mode.
+// every product and sum rounded on its own, so that every screening decision
+// is identical in every precision mode (and to a plain IEEE evaluation on the
+// host).  HIP compiles with FP contraction on, and __dmul_rn / __dadd_rn are
+// plain operators in this toolchain, so they would be fused into FMAs once
+// inlined; contraction is switched off for this scope instead.
 __device__ __forceinline__ double dist2_exact(double dx, double dy, double dz) {
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+#pragma clang fp contract(off)
+    return (dx * dx + dy * dy) + dz * dz;
+}
+// gamma * r^2 of the screening test, rounded on its own (never fused with a
+// later subtraction).
+__device__ __forceinline__ double mul_exact(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
 }
 
 __device__ __forceinline__ double exp_t(double x) { return exp(x); }
@@ -188,7 +198,7 @@ __device__ __forceinline__ void rec_values(const WinRec& r, double T_thr, int js
             for (int k = 0; k < QSL_PMAX; ++k) {
                 if (k >= np) break;
                 const double gk = exs[k];
-                const double t = __dmul_rn(gk, r2);
+                const double t = mul_exact(gk, r2);
                 tie |= fabs(t - T_thr) <= tieb;
                 if (t <= T_thr) {
                     const T c = cs[k];
@@ -364,7 +374,9 @@ __host__ __device__ inline int64_t gsplit_elems(int n) {
 }
 
 struct WsLayout {
-    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2], total;
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2];
+    size_t fwd_total;  // end of the forward's regions (tile lists, blocked-inversion copy)
+    size_t total;      // end of the adjoint's regions
 };
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode);
 // The Job of spin s of a forward / adjoint call on workspace ws.

@@ -113,7 +113,7 @@ __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __res
                     double px, py, pz;
                     if (k < MAXE) { px = ex[k]; py = ey[k]; pz = ez[k]; }
                     else { const double* r = gpos(k); px = r[0]; py = r[1]; pz = r[2]; }
-                    const double tt = __dmul_rn(gm, dist2_exact(px - qx, py - qy, pz - qz));
+                    const double tt = mul_exact(gm, dist2_exact(px - qx, py - qy, pz - qz));
                     active |= tt <= s.T;
                     // the smallest exponent of a dropped window decides its
                     // nearest primitive to the threshold: flag that walker
