@@ -7,8 +7,9 @@ the oracle's absolute sum for C_n[e][i]; nnz = survivors per electron):
   FP64    |dC| <= 1e-12 S  (FP64 sums of <= ~10^3 terms and 1-ulp exp)
   FP32    |dC| <= (64 + 2 nnz) u32 S   (AO values with a few roundings and a
           1-ulp expf, a sum of nnz products)
-  BF16X3  |dC| <= (2^-16 + (64 + 2 nnz) u32) S   (the dropped lo*lo term and
-          the bf16 rounding of the lo parts are each <= 2^-18 |a||b|)
+  BF16X3  |dC| <= (3 * 2^-16 + (64 + 2 nnz) u32) S   (bf16 keeps 8 significant
+          bits, so |x - hi| <= 2^-8 |x|: the dropped lo*lo term and the bf16
+          rounding of each lo part are each <= 2^-16 |a||b|)
   log|det|: first order, |d logdet| <= 2 sum_ei |Dinv[e][i]| tol S_1[e][i]
   Dinv:     |dDinv| <= 2 |Dinv| (tol S_1)^T |Dinv| + 1e-12 |Dinv|-scale
 """
@@ -25,7 +26,7 @@ def tol_C(mode, nnz_max):
     if mode == "fp64":
         return 1e-12
     base = (64 + 2 * nnz_max) * U32
-    return base if mode == "fp32" else base + 2.0 ** -16
+    return base if mode == "fp32" else base + 3 * 2.0 ** -16
 
 
 def max_survivors(sysm, R):

@@ -65,7 +65,7 @@ def test_backward_configs(name, W, use_drift, mode):
         # G rounded to FP32, AO values in FP32 (64 u32), FP32 sums of 32
         # electrons (dA) or of MOs (dR) and of nnz AOs
         nnz = max_survivors(sysm, R[:1])
-        tol = (64 + 64 + 2 * nnz) * U32 + (2.0 ** -16 if mode == "bf16x3" else 0.0)
+        tol = (64 + 64 + 2 * nnz) * U32 + (3 * 2.0 ** -16 if mode == "bf16x3" else 0.0)
     rdR, rdAu, rdAd = oracle.backward(sysm, A_up, A_dn, R, ref["Dinv_up"], ref["Dinv_dn"], g)
     bA, bR = _abs_bounds(sysm, A_up, A_dn, R, ref, g)
     assert np.all(np.abs(dAu - rdAu) <= tol * bA[0] + 1e-300), float((np.abs(dAu - rdAu) / (bA[0] + 1e-300)).max())
@@ -92,7 +92,7 @@ def test_backward_few_windows(n_atoms, n_up, n_dn, W, mode):
         g, dR, dAu, dAd, out = _run(sysm, A_up, A_dn, R, mode, use_drift=use_drift)
         ref = {"Dinv_up": out["Dinv_up"], "Dinv_dn": out["Dinv_dn"]}
         nnz = max_survivors(sysm, R[:1])
-        tol = (64 + 64 + 2 * nnz) * U32 + (2.0 ** -16 if mode == "bf16x3" else 0.0)
+        tol = (64 + 64 + 2 * nnz) * U32 + (3 * 2.0 ** -16 if mode == "bf16x3" else 0.0)
         rdR, rdAu, rdAd = oracle.backward(sysm, A_up, A_dn, R, ref["Dinv_up"], ref["Dinv_dn"], g)
         bA, bR = _abs_bounds(sysm, A_up, A_dn, R, ref, g)
         assert np.all(np.abs(dAu - rdAu) <= tol * bA[0] + 1e-300)
@@ -172,3 +172,32 @@ def test_singular_walker_zero_weight_gives_zero_dR(use_drift):
     for w in (0, 2):
         gg = np.concatenate([np.full(sysm.n_up, g[w, 0]), np.full(sysm.n_dn, g[w, 1])])
         np.testing.assert_allclose(dR[w], gg[:, None] * drift[w], rtol=1e-9, atol=1e-12)
+
+
+def test_autograd_singular_walker_gets_no_gradient():
+    """slater_logdet(...).sum().backward() with a singular walker (log|det|
+    = -inf): that walker contributes no gradient, every gradient stays
+    finite, and the rest equals the oracle adjoint with its weight zeroed."""
+    print("[case] autograd singular walker", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import System, slater_logdet
+    sysm, A_up, A_dn = random_tiny(n_atoms=3, n_up=4, n_dn=3, seed=5)
+    R = walkers_near(sysm, 3, seed=2)
+    R[1, 2] = [400.0, -300.0, 250.0]   # beyond every atomic radius: spin up singular
+    S = System.from_synth(sysm)
+    Rt = torch.from_numpy(R).cuda().requires_grad_(True)
+    Au = torch.from_numpy(A_up).cuda().requires_grad_(True)
+    Ad = torch.from_numpy(A_dn).cuda().requires_grad_(True)
+    ld, _ = slater_logdet(Rt, Au, Ad, S, "fp64")
+    assert torch.isneginf(ld[1, 0])
+    ld.sum().backward()
+    for t in (Rt.grad, Au.grad, Ad.grad):
+        assert torch.isfinite(t).all()
+    ref = oracle.forward(sysm, A_up, A_dn, R)
+    g = np.ones((3, 2))
+    g[1] = 0.0
+    Du, Dd = np.nan_to_num(ref["Dinv_up"]), np.nan_to_num(ref["Dinv_dn"])
+    rdR, rdAu, rdAd = oracle.backward(sysm, A_up, A_dn, R, Du, Dd, g)
+    np.testing.assert_allclose(Au.grad.cpu().numpy(), rdAu, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Ad.grad.cpu().numpy(), rdAd, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(Rt.grad.cpu().numpy(), rdR, rtol=1e-9, atol=1e-12)
