@@ -154,12 +154,20 @@ typedef struct {
     size_t ws_bytes;
 } qsl_fwd_args;
 
+/* Workspace selectors of qsl_workspace_size. */
+#define QSL_WS_FORWARD 1   /* what qsl_forward needs                       */
+#define QSL_WS_BACKWARD 2  /* what qsl_backward needs (covers the forward) */
+#define QSL_WS_BOTH 3
+
 /*
- * Device workspace bytes needed by qsl_forward / qsl_backward for W walkers
- * in `mode`.  The same workspace may serve both calls (not concurrently).
- * Errors: INVALID_ARG.
+ * Device workspace bytes needed by qsl_forward (what = QSL_WS_FORWARD) or
+ * qsl_backward (QSL_WS_BACKWARD or QSL_WS_BOTH) for W walkers in `mode`.
+ * The forward's regions come first, so a backward-sized workspace serves
+ * both calls (not concurrently); a forward-only caller needs less (no
+ * walker-group lists, dA accumulator or split G).
+ * Errors: INVALID_ARG (NULL, W < 0, bad mode or selector).
  */
-qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, size_t* bytes);
+qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, int32_t what, size_t* bytes);
 
 /*
  * Forward: screening and compaction of the surviving AO windows per tile of
@@ -283,8 +291,11 @@ qsl_status qsl_plan_destroy(qsl_plan* plan);
  * 1e-4 (other modes) of its largest entry), and set it on the plan.  With
  * cache_path, a JSON file keyed by device, mode and the shapes of the
  * batch: a hit sets the cached tuning without running anything; a miss
- * tunes and writes the entry.  Overwrites the bound outputs; synchronises
- * `stream`.  `chosen` (may be NULL) receives the tuning.
+ * tunes and writes the entry.  Overwrites the bound outputs, dA included:
+ * while tuning, every run writes dA as if accumulate_dA were 0 (the
+ * caller's flags apply again to later launches), so an accumulated dA must
+ * be saved by the caller first.  Synchronises `stream`.  `chosen` (may be
+ * NULL) receives the tuning; on failure the previous tuning stays set.
  * Errors: INVALID_ARG, HIP, OOM; UNSUPPORTED if no candidate passes.
  */
 qsl_status qsl_autotune(qsl_plan* plan, const char* cache_path, void* stream, qsl_tuning* chosen);

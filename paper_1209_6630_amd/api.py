@@ -93,9 +93,12 @@ class System:
             a = np.ascontiguousarray(np.asarray(A, np.float64))
             check(lib().qsl_set_mo(self._h, spin, ct.c_void_p(a.ctypes.data), a.shape[1], 0, _stream()))
 
-    def workspace(self, W, mode):
+    def workspace(self, W, mode, backward=True):
+        """A device workspace for W walkers (grown on demand and kept): the
+        forward's regions only, or (backward) everything."""
         n = ct.c_size_t()
-        check(lib().qsl_workspace_size(self._h, int(W), mode_id(mode), ct.byref(n)))
+        what = _lib.WS_BOTH if backward else _lib.WS_FORWARD
+        check(lib().qsl_workspace_size(self._h, int(W), mode_id(mode), what, ct.byref(n)))
         key = torch.cuda.current_device()
         ws = self._ws.get(key)
         if ws is None or ws.numel() < n.value:
@@ -128,7 +131,7 @@ class System:
         assert R.shape[1:] == (self.n_elec, 3), "R must be [W, n_up+n_dn, 3]"
         if out is None:
             out = self.alloc_outputs(W, mode, drift)
-        ws = self.workspace(W, mode)
+        ws = self.workspace(W, mode, backward=False)
         a = _fwd_args(self, R, mode, out)
         a.ws = ws.data_ptr()
         a.ws_bytes = ws.numel()
@@ -263,14 +266,18 @@ class SlaterLogDet(torch.autograd.Function):
         system.set_mo(1, A_dn.detach())
         out = system.forward(R.detach().contiguous(), mode)
         ctx.system, ctx.mode = system, mode
-        ctx.save_for_backward(R.detach(), out["Dinv_up"], out["Dinv_dn"], out["drift"])
+        ctx.save_for_backward(R.detach(), out["Dinv_up"], out["Dinv_dn"], out["drift"], out["status"])
         ctx.mark_non_differentiable(out["sign"])
         return out["logdet"], out["sign"]
 
     @staticmethod
     def backward(ctx, g_logdet, _g_sign):
-        R, Di_up, Di_dn, drift = ctx.saved_tensors
-        dR, dA_up, dA_dn = ctx.system.backward(R, Di_up, Di_dn, g_logdet, ctx.mode, drift=drift)
+        R, Di_up, Di_dn, drift, status = ctx.saved_tensors
+        # a walker with a singular spin has log|det| = -inf and an undefined
+        # inverse: it gets no gradient (the kernels require g = 0 there)
+        singular = (status & 1).bool()
+        g = torch.where(singular[:, None], torch.zeros_like(g_logdet), g_logdet)
+        dR, dA_up, dA_dn = ctx.system.backward(R, Di_up, Di_dn, g, ctx.mode, drift=drift)
         return dR, dA_up, dA_dn, None, None
 
 

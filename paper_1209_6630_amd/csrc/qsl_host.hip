@@ -113,8 +113,11 @@ ProfScope::~ProfScope() {
 // Walkers per dA group: they share one window list (screened together).
 int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
 
-// Workspace layout: per spin, tile_nwin[T_s] and tile_win[T_s][n_win],
-// the same per walker group of gw walkers, and the FP32 dA accumulator.
+// Workspace layout.  The forward's regions come first: per spin,
+// tile_nwin[T_s] and tile_win[T_s][n_win], and the FP64 copy of the blocked
+// inversion; then the adjoint's: the same lists per walker group of gw
+// walkers, the FP32 dA accumulator and the split-BF16 G.  A forward-only
+// workspace ends at fwd_total.
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
     WsLayout L{};
     size_t off = 0;
@@ -127,6 +130,12 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
         off = round_up(off + tiles * (size_t)d.n_win * sizeof(int), 256);
     }
     for (int s = 0; s < 2; ++s) {
+        const size_t n = (size_t)n_spin(d, s);
+        L.gj_off[s] = off;
+        if (gj_blocked((int)n)) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
+    }
+    L.fwd_total = std::max<size_t>(off, 256);
+    for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
         size_t groups = n ? (size_t)tiles_per_walker(n) * ((W + gw - 1) / std::max(gw, 1)) : 0;
         L.gnwin_off[s] = off;
@@ -137,11 +146,6 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
     for (int s = 0; s < 2; ++s) {
         L.dA32_off[s] = off;
         off = round_up(off + (size_t)n_spin(d, s) * d.n_basis * sizeof(float), 256);
-    }
-    for (int s = 0; s < 2; ++s) {
-        const size_t n = (size_t)n_spin(d, s);
-        L.gj_off[s] = off;
-        if (gj_blocked((int)n)) off = round_up(off + (size_t)W * gj_ws_doubles((int)n) * sizeof(double), 256);
     }
     for (int s = 0; s < 2; ++s) {
         const int n = n_spin(d, s);
@@ -541,11 +545,13 @@ qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld
     return QSL_OK;
 }
 
-qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, size_t* bytes) {
+qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, int32_t what, size_t* bytes) {
     if (!sys || !bytes) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
     if (W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
     if (mode < QSL_FP64 || mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
-    *bytes = ws_layout(sys->d, W, bw_group(W), mode).total;
+    if (what < QSL_WS_FORWARD || what > QSL_WS_BOTH) return bad(QSL_ERR_INVALID_ARG, "bad workspace selector");
+    const WsLayout L = ws_layout(sys->d, W, bw_group(W), mode);
+    *bytes = (what & QSL_WS_BACKWARD) ? L.total : L.fwd_total;
     return QSL_OK;
 }
 
@@ -564,7 +570,7 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
     }
     WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);
-    if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
+    if (!a->ws || a->ws_bytes < L.fwd_total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     hipStream_t st = (hipStream_t)stream;
     char* ws = (char*)a->ws;
     hipError_t e;

@@ -634,6 +634,9 @@ static qsl_status time_plan(qsl_plan* p, hipStream_t st, int reps, double* ms) {
     return r;
 }
 
+static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& key, const char* cache_path,
+                               const qsl_tuning saved, qsl_tuning* chosen);
+
 }  // namespace qsl
 
 extern "C" {
@@ -745,8 +748,31 @@ qsl_status qsl_autotune(qsl_plan* p, const char* cache_path, void* stream, qsl_t
         if (r == QSL_OK && chosen) *chosen = t;
         return r;
     }
-    hipError_t e;
     const qsl_tuning saved = p->tune;
+    // Every tuning run overwrites dA (the reference and each candidate must
+    // produce the same dA, not add to it); the caller's accumulate flags come
+    // back on every return path, and the graph is captured anew.
+    std::vector<int32_t> acc(p->n_sys, 0);
+    for (int i = 0; i < p->n_sys; ++i) {
+        acc[i] = p->bwd[i].accumulate_dA;
+        p->bwd[i].accumulate_dA = 0;
+    }
+    auto restore = [&](qsl_status r) {
+        for (int i = 0; i < p->n_sys; ++i) p->bwd[i].accumulate_dA = acc[i];
+        if (r != QSL_OK) p->tune = saved;
+        p->dirty = true;
+        return r;
+    };
+    return restore(autotune_run(p, st, key, cache_path, saved, chosen));
+}
+
+}  // extern "C"
+
+namespace qsl {
+
+static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& key, const char* cache_path,
+                               const qsl_tuning saved, qsl_tuning* chosen) {
+    hipError_t e;
     // the default tuning is the reference of the self-check
     const qsl_tuning base{1, 0, 0};
     p->tune = base;
@@ -808,4 +834,4 @@ qsl_status qsl_autotune(qsl_plan* p, const char* cache_path, void* stream, qsl_t
     return QSL_OK;
 }
 
-}  // extern "C"
+}  // namespace qsl

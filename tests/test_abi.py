@@ -74,6 +74,26 @@ def test_create_validation_errors(kw, code):
     assert len(lib().qsl_last_error()) > 0
 
 
+def test_nonfinite_atom_coordinate_rejected():
+    """A NaN or infinite atom coordinate is an INVALID_ARG before any device
+    work."""
+    import math
+    from paper_1209_6630_amd._lib import lib
+    for bad in (math.nan, math.inf):
+        d, keep = _desc()
+        keep[0][0, 1] = bad
+        h = ct.c_void_p()
+        assert lib().qsl_system_create(ct.byref(d), ct.byref(h)) == 1
+        assert h.value is None
+        assert b"non-finite" in lib().qsl_last_error()
+
+
+def test_workspace_size_argument_checks():
+    from paper_1209_6630_amd._lib import lib
+    n = ct.c_size_t()
+    assert lib().qsl_workspace_size(None, 4, 0, 3, ct.byref(n)) == 1
+
+
 def test_null_arguments():
     from paper_1209_6630_amd._lib import lib
     h = ct.c_void_p()

@@ -150,3 +150,43 @@ def test_status_near_tie_is_flagged():
     S = make_gpu_system(sysm, np.array([[1.0, 0.5]]), np.array([[0.3, 1.0]]))
     gpu = run_gpu_forward(S, R, "fp64")
     assert gpu["status"][0] & 2
+
+
+def test_workspace_too_small_is_an_error():
+    """A missing or short workspace is QSL_ERR_WORKSPACE; the forward needs
+    only its own regions, the adjoint everything."""
+    print("[case] workspace errors", flush=True)
+    import ctypes as ct
+    import torch
+    from paper_1209_6630_amd import _lib
+    from paper_1209_6630_amd.api import _fwd_args
+    sysm, A_up, A_dn = random_tiny(n_atoms=3, n_up=4, n_dn=3, seed=8)
+    R = walkers_near(sysm, 4, seed=3)
+    S = make_gpu_system(sysm, A_up, A_dn)
+    L = _lib.lib()
+    nf, nb = ct.c_size_t(), ct.c_size_t()
+    _lib.check(L.qsl_workspace_size(S._h, 4, 1, _lib.WS_FORWARD, ct.byref(nf)))
+    _lib.check(L.qsl_workspace_size(S._h, 4, 1, _lib.WS_BOTH, ct.byref(nb)))
+    assert 0 < nf.value < nb.value
+    assert L.qsl_workspace_size(S._h, 4, 1, 7, ct.byref(nf)) == 1
+    Rt = torch.from_numpy(R).cuda()
+    out = S.alloc_outputs(4, "fp32")
+    a = _fwd_args(S, Rt, "fp32", out)
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    a.ws, a.ws_bytes = None, 0
+    assert L.qsl_forward(S._h, ct.byref(a), None) == 4
+    a.ws, a.ws_bytes = ws.data_ptr(), nf.value - 1
+    assert L.qsl_forward(S._h, ct.byref(a), None) == 4
+    a.ws_bytes = nf.value
+    _lib.check(L.qsl_forward(S._h, ct.byref(a), None))
+    b = _lib.BwdArgs()
+    b.W, b.R, b.mode = 4, Rt.data_ptr(), 1
+    b.Dinv[0], b.Dinv[1] = out["Dinv_up"].data_ptr(), out["Dinv_dn"].data_ptr()
+    g = torch.ones((4, 2), dtype=torch.float64, device="cuda")
+    dA = torch.zeros((4, sysm.n_basis), dtype=torch.float64, device="cuda")
+    b.g_logdet, b.dA[0] = g.data_ptr(), dA.data_ptr()
+    b.ws, b.ws_bytes = ws.data_ptr(), nf.value
+    assert L.qsl_backward(S._h, ct.byref(b), None) == 4
+    b.ws_bytes = nb.value
+    _lib.check(L.qsl_backward(S._h, ct.byref(b), None))
+    torch.cuda.synchronize()

@@ -265,3 +265,36 @@ def test_uneven_batch_512_each_fp32_against_oracle():
         _dA_close(ps["dA_up"], g_["dA_up"], mode)
         _dA_close(ps["dA_dn"], g_["dA_dn"], mode)
     P.close()
+
+
+def test_autotune_with_accumulated_dA():
+    """Autotuning a plan bound with accumulate_dA: the tuning runs overwrite
+    dA (all candidates pass the self-check), the caller's flag applies again
+    afterwards, and a launch then adds the new dA to what the buffer holds."""
+    print("[case] autotune with accumulate", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import Plan
+    mode = "fp32"
+    items = _batch([("44e", 32), ("158e", 8)])
+    P = Plan([it["S"] for it in items], [it["R"].shape[0] for it in items], mode, graph=True)
+    bufs = []
+    for i, it in enumerate(items):
+        S, W = it["S"], it["R"].shape[0]
+        out = S.alloc_outputs(W, mode)
+        dR = torch.empty((W, S.n_elec, 3), dtype=torch.float64, device="cuda")
+        dA = (torch.zeros((S.n_up, S.n_basis), dtype=torch.float64, device="cuda"),
+              torch.zeros((S.n_dn, S.n_basis), dtype=torch.float64, device="cuda"))
+        P.bind(i, it["Rt"], out, g=it["gt"], dR=dR, dA=dA, accumulate=True)
+        bufs.append((out, dR, dA))
+    t = P.autotune(None)
+    assert P.tuning == t
+    for _, _, dA in bufs:
+        for a in dA:
+            a.fill_(3.0)
+    P.launch()
+    got = _read(bufs)
+    for it, g_ in zip(items, got):
+        ps = _per_system(it, mode)
+        _dA_close(ps["dA_up"] + 3.0, g_["dA_up"], mode)
+        _dA_close(ps["dA_dn"] + 3.0, g_["dA_dn"], mode)
+    P.close()
