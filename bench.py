@@ -2,18 +2,22 @@
 """Benchmark: walker Slater-builds per second, forward + adjoint, on one GPU.
 
 A step is one pass of the whole hot path over one batch of walkers:
-screening, fused AO evaluation + AO->MO products (split BF16 on MFMA with
-FP32 accumulation), FP64 Gauss-Jordan log|det| / sign / inverse, drift and
-Laplacian, then the adjoint (AO recomputation, dR and dA).  The headline
-workload is the synthetic 434-electron peptide-shaped system (134 atoms,
-1270 AOs, 217 x 1270 MO coefficients per spin) with 4096 walkers; the step
-is one replay of the plan's HIP graph, inputs resident in HBM.
+screening, fused AO evaluation + AO->MO products (FP32 on MFMA: the
+products in single precision, as the paper computes them), FP64
+Gauss-Jordan log|det| / sign / inverse, drift and Laplacian, then the
+adjoint (AO recomputation, dR and dA).  The headline workload is the
+synthetic 434-electron peptide-shaped system (134 atoms, 1270 AOs, 217 x
+1270 MO coefficients per spin) with 4096 walkers; the step is one replay of
+the plan's HIP graph, inputs resident in HBM.
 
-Beside it (in "also"): the same system in plain FP64, and the 1731-electron
-system (531 atoms, 5055 AOs, 866/865 MOs, 512 walkers) in FP32 and FP64,
-each with the mixed-precision error against the FP64 run on the same walkers.
-Per-kernel times come from a second, eager pass of the same steps with HIP
-events around every launch on the launch stream.
+Beside it (in "also"), each with its own roofline and, for the reduced
+precisions, the error of every output against the FP64 run on the same
+walkers: the same system with split-BF16 products and in plain FP64; the
+1731-electron system (531 atoms, 5055 AOs, 866/865 MOs, 512 walkers) in FP32
+and FP64; and the uneven batch of 512 walkers each of the 44-, 158- and
+434-electron systems in one autotuned FP32 plan.  Per-kernel times come from
+a second, eager pass of the same steps with HIP events around every launch
+on the launch stream.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -86,33 +90,58 @@ def work_per_step(sysm, nnz, W, mode):
 
 
 class Workload:
-    """One system, W walkers, one mode: a graph plan and an eager plan bound
-    to the same device buffers (forward + adjoint)."""
+    """Systems (config name, W) in one mode: a graph plan and an eager plan
+    bound to the same device buffers (forward + adjoint of every system)."""
 
-    def __init__(self, config, W, mode):
+    def __init__(self, config, W, mode, more=(), autotune=False):
         import torch
         import qsl_synth as q
         from paper_1209_6630_amd.api import Plan, System
         self.config, self.W, self.mode = config, W, mode
-        self.sysm, A_up, A_dn, self.R_np = q.make_config(config, W=W)
-        self.A = (A_up, A_dn)
-        S = System.from_synth(self.sysm)
-        S.set_mo(0, A_up)
-        S.set_mo(1, A_dn)
-        self.S = S
+        self.items = []
         dev = "cuda"
-        self.R = torch.from_numpy(self.R_np).to(dev)
-        self.out = S.alloc_outputs(W, mode)
-        self.g = torch.ones((W, 2), dtype=torch.float64, device=dev)
-        self.dR = torch.empty((W, S.n_elec, 3), dtype=torch.float64, device=dev)
-        self.dA = (torch.empty((S.n_up, S.n_basis), dtype=torch.float64, device=dev),
-                   torch.empty((S.n_dn, S.n_basis), dtype=torch.float64, device=dev))
+        for name, Wx in [(config, W), *more]:
+            sysm, A_up, A_dn, R_np = q.make_config(name, W=Wx)
+            S = System.from_synth(sysm)
+            S.set_mo(0, A_up)
+            S.set_mo(1, A_dn)
+            it = dict(name=name, W=Wx, sysm=sysm, R_np=R_np, S=S, R=torch.from_numpy(R_np).to(dev),
+                      out=S.alloc_outputs(Wx, mode),
+                      g=torch.ones((Wx, 2), dtype=torch.float64, device=dev),
+                      dR=torch.empty((Wx, S.n_elec, 3), dtype=torch.float64, device=dev),
+                      dA=(torch.empty((S.n_up, S.n_basis), dtype=torch.float64, device=dev),
+                          torch.empty((S.n_dn, S.n_basis), dtype=torch.float64, device=dev)))
+            self.items.append(it)
+        first = self.items[0]
+        self.sysm, self.R_np, self.S = first["sysm"], first["R_np"], first["S"]
+        self.out, self.dR, self.dA = first["out"], first["dR"], first["dA"]
         self.plans = {}
+        self.tuning = None
         for graph in (True, False):
-            P = Plan([S], [W], mode, graph=graph)
-            P.bind(0, self.R, self.out, g=self.g, dR=self.dR, dA=self.dA)
+            P = Plan([it["S"] for it in self.items], [it["W"] for it in self.items], mode, graph=graph)
+            for i, it in enumerate(self.items):
+                P.bind(i, it["R"], it["out"], g=it["g"], dR=it["dR"], dA=it["dA"])
+            if autotune:
+                if self.tuning is None:
+                    self.tuning = P.autotune(None)
+                else:
+                    P.tuning = self.tuning
             self.plans[graph] = P
         torch.cuda.synchronize()
+
+    def work(self):
+        """Algorithmic work per step of every kernel kind, summed over the
+        systems of the plan."""
+        total = {}
+        for it in self.items:
+            nnz = survivors_per_electron(it["sysm"], it["R_np"])
+            it["nnz"] = nnz
+            for k, (amt, bound, peak, unit) in work_per_step(it["sysm"], nnz, it["W"], self.mode).items():
+                if k in total:
+                    total[k] = (total[k][0] + amt,) + total[k][1:]
+                else:
+                    total[k] = (amt, bound, peak, unit)
+        return total
 
     def time(self, steps, warmup):
         """K graph replays bracketed by synchronisations -> ms per step;
@@ -144,6 +173,10 @@ class Workload:
         for P in self.plans.values():
             P.close()
         self.plans = {}
+        for it in self.items:
+            it["S"].close()
+        self.items = []
+        self.out = self.dR = self.dA = self.S = None
 
 
 def kernel_table(prof, steps, kinds):
@@ -159,55 +192,83 @@ def kernel_table(prof, steps, kinds):
 
 
 def err_vs_fp64(mixed, ref):
-    """Mixed precision against the FP64 run on the same walkers: |d logdet|
-    and the normwise relative D^-1 difference per (walker, spin) as median /
-    p99 / max, and sign disagreements.  Ill-conditioned walkers amplify the
-    product error by the condition number of D, hence the long tail."""
+    """Mixed precision against the FP64 run on the same walkers (g = 1 for
+    every walker), each as median / p99 / max over walkers (and spins):
+      logdet   |d logdet|;
+      C_n      normwise relative difference of each of the five products
+               (values, three gradient components, Laplacian) per walker and
+               spin, ||dC_n||_F / ||C_n||_F over the [e][i] block;
+      Dinv     normwise relative difference per walker and spin;
+      drift, lap, dR   per walker, max over electrons of |d x| / max(1, |x|);
+      dA       normwise relative difference per spin (one value each).
+    Ill-conditioned walkers amplify the product error by the condition
+    number of D, hence the long tails of log|det|, D^-1 and what follows from
+    D^-1.  mixed / ref: dicts of the forward outputs plus dR, dA_up, dA_dn."""
     import torch
-    ok = torch.isfinite(ref["logdet"]) & torch.isfinite(mixed["logdet"])
-    ld = (mixed["logdet"] - ref["logdet"]).abs()[ok].double()
-    rels = []
-    for k in ("Dinv_up", "Dinv_dn"):
-        if ref[k].numel() == 0:
-            continue
-        for c0 in range(0, ref[k].shape[0], 256):
-            a, b = mixed[k][c0:c0 + 256], ref[k][c0:c0 + 256]
-            r = torch.linalg.matrix_norm(a - b) / torch.linalg.matrix_norm(b)
-            rels.append(r[torch.isfinite(r)])
-    rel = torch.cat(rels) if rels else torch.zeros(1, dtype=torch.float64, device=ld.device)
 
     def q3(x):
+        x = x[torch.isfinite(x)].double()
         if x.numel() == 0:
             return [0.0, 0.0, 0.0]
         return [float(torch.quantile(x, 0.5)), float(torch.quantile(x, 0.99)), float(x.max())]
 
-    return {"logdet_abs_median_p99_max": q3(ld), "Dinv_normwise_rel_median_p99_max": q3(rel),
-            "sign_mismatch": int((mixed["sign"] != ref["sign"]).sum())}
+    def blockwise(a, b, dims):
+        r = []
+        for c0 in range(0, b.shape[0], 128):
+            x, y = a[c0:c0 + 128].double(), b[c0:c0 + 128].double()
+            r.append(torch.linalg.vector_norm(x - y, dim=dims) / torch.linalg.vector_norm(y, dim=dims))
+        return torch.cat(r)
+
+    ok = torch.isfinite(ref["logdet"]) & torch.isfinite(mixed["logdet"])
+    res = {"logdet_abs": q3((mixed["logdet"] - ref["logdet"]).abs()[ok])}
+    for n, name in enumerate(("C_value", "C_dx", "C_dy", "C_dz", "C_lap")):
+        vals = [blockwise(mixed[k][:, n], ref[k][:, n], (1, 2)) for k in ("C_up", "C_dn") if ref[k].numel()]
+        res[name + "_normwise_rel"] = q3(torch.cat(vals))
+    vals = [blockwise(mixed[k], ref[k], (1, 2)) for k in ("Dinv_up", "Dinv_dn") if ref[k].numel()]
+    res["Dinv_normwise_rel"] = q3(torch.cat(vals))
+    for k, dims in (("drift", (1, 2)), ("lap", (1,)), ("dR", (1, 2))):
+        if k not in mixed or k not in ref:
+            continue
+        d = (mixed[k] - ref[k]).abs() / torch.clamp(ref[k].abs(), min=1.0)
+        res[k + "_rel"] = q3(torch.amax(d, dim=dims))
+    if "dA_up" in mixed:
+        res["dA_normwise_rel"] = [float(torch.linalg.vector_norm(mixed[k] - ref[k]) / torch.linalg.vector_norm(ref[k]))
+                                  for k in ("dA_up", "dA_dn") if ref[k].numel()]
+    res["sign_mismatch"] = int((mixed["sign"] != ref["sign"]).sum())
+    return res
 
 
-def cpu_baseline(sysm, A_up, A_dn, R, target_s=12.0):
-    """The FP64 oracle, forward + adjoint, on a bounded sample of walkers."""
+def cpu_baseline(sysm, A_up, A_dn, R, workload, target_s=12.0, target_1core_s=6.0):
+    """The FP64 oracle, forward + adjoint, on a bounded sample of walkers:
+    on every host thread (OpenMP over walkers), and on one thread (the
+    per-core figure the paper's tables give)."""
     import oracle
     oracle.load()
     nthr = oracle.max_threads()
     W = R.shape[0]
 
-    def run(ws):
+    def run(ws, threads):
         t0 = time.perf_counter()
-        out = oracle.forward(sysm, A_up, A_dn, R[:ws])
+        out = oracle.forward(sysm, A_up, A_dn, R[:ws], nthreads=threads)
         g = np.ones((ws, 2))
-        oracle.backward(sysm, A_up, A_dn, R[:ws], out["Dinv_up"], out["Dinv_dn"], g)
+        oracle.backward(sysm, A_up, A_dn, R[:ws], out["Dinv_up"], out["Dinv_dn"], g, nthreads=threads)
         return time.perf_counter() - t0
 
     cal = max(1, min(W, nthr))
-    t = run(cal)
+    t = run(cal, nthr)
     n = int(min(W, max(cal, round(cal * target_s / max(t, 1e-3)))))
     n = max(cal, (n // cal) * cal)
     log(f"cpu baseline: calibration {cal} walkers {t:.2f}s -> sample {n} walkers")
-    t = run(n)
+    t = run(n, nthr)
+    # one thread: as many walkers as take about target_1core_s at the rate
+    # just measured divided by the thread count
+    n1 = int(max(1, min(W, round(target_1core_s * n / t / nthr))))
+    t1 = run(n1, 1)
     return {"value": n / t, "unit": "walker Slater-builds/s", "cores": nthr, "kind": "oracle",
-            "sample": f"{n} of the {W} walkers of the 434e workload, FP64 forward + adjoint, "
-                      f"OpenMP over walkers on {nthr} threads, {t:.1f} s"}
+            "sample": f"{n} of the {W} walkers of the {workload} workload, FP64 forward + adjoint, "
+                      f"OpenMP over walkers on {nthr} threads, {t:.1f} s",
+            "one_core": {"value": n1 / t1, "unit": "walker Slater-builds/s", "cores": 1,
+                         "sample": f"{n1} walkers of the same workload on one thread, {t1:.1f} s"}}
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -245,16 +306,32 @@ def measured_traffic(workload, kernel):
     return None
 
 
+def roofline_of(kernels, kinds, workload):
+    """The dominant kernel's roofline entry (algorithmic work over its
+    average launch time, against its peak)."""
+    dom = max((k for k in kernels if k in kinds), key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
+    return {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
+            "frac": d["frac"], "traffic": measured_traffic(workload, dom)}
+
+
+def outputs_of(wl):
+    """Forward outputs, dR and dA of the first system of a workload."""
+    r = dict(wl.out)
+    r.update(dR=wl.dR, dA_up=wl.dA[0], dA_dn=wl.dA[1])
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--mode", default="fp32", choices=["bf16x3", "fp32", "fp64"])
     ap.add_argument("--config", default="434e")
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-also", action="store_true", help="skip the FP64 and 1731e companion runs")
+    ap.add_argument("--no-also", action="store_true", help="skip the companion runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after timing, run one plain copy kernel over MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -271,6 +348,7 @@ def main():
     cfg = q.CONFIGS[args.config]
     W = args.walkers or cfg["W"]
     mode = args.mode
+    wname = f"{args.config}-W{W}-{mode}-fwd+adjoint"
     log(f"workload {args.config} W={W} mode={mode}: generating inputs")
     main_wl = Workload(args.config, W, mode)
     log(f"timing {args.steps} graph replays after {args.warmup} warm-up")
@@ -278,14 +356,10 @@ def main():
     value = W / (ms * 1e-3)
     log(f"{ms:.3f} ms/step (eager {ms_eager:.3f}), {value:.1f} walkers/s; kernels {prof}")
     sysm = main_wl.sysm
-    nnz = survivors_per_electron(sysm, main_wl.R_np)
-    kinds = work_per_step(sysm, nnz, W, mode)
+    kinds = main_wl.work()
+    nnz = main_wl.items[0]["nnz"]
     kernels = kernel_table(prof, args.steps, kinds)
-    dom = max((k for k in kernels if k in kinds), key=lambda k: kernels[k]["ms_per_step"])
-    d = kernels[dom]
-    roofline = {"kernel": dom, "bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"],
-                "unit": d["unit"], "frac": d["frac"],
-                "traffic": measured_traffic(f"{args.config}-W{W}-{mode}-fwd+adjoint", dom)}
+    roofline = roofline_of(kernels, kinds, wname)
     if args.copy_calibration > 0:
         # a plain copy of known size: reads and writes MIB MiB once (its HBM
         # counter readings scale the other kernels' readings)
@@ -299,7 +373,7 @@ def main():
         "metric": METRIC, "value": value, "unit": "walker Slater-builds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[mode], "data": "synthetic",
-        "config": {"workload": f"{args.config}-W{W}-{mode}-fwd+adjoint", "electrons": sysm.n_elec,
+        "config": {"workload": wname, "electrons": sysm.n_elec,
                    "n_basis": sysm.n_basis, "walkers": W, "mode": mode, "survivors_per_electron": round(nnz, 1),
                    "singular_walkers": int(((st & 1) != 0).sum()), "timed": "HIP graph replays of the plan",
                    "eager_ms_per_step": ms_eager},
@@ -308,44 +382,63 @@ def main():
     }
 
     also = []
+
+    def companion(name, Wx, m, steps2, more=(), autotune=False, label=None):
+        log(f"companion {label or name} W={Wx} mode={m}")
+        wl = Workload(name, Wx, m, more=more, autotune=autotune)
+        msx, _, prx = wl.time(steps2, 2)
+        lab = label or f"{name}-W{Wx}-{m}-fwd+adjoint"
+        wk = wl.work()
+        ktab = kernel_table(prx, steps2, wk)
+        Wtot = sum(it["W"] for it in wl.items)
+        entry = {"workload": lab, "value": Wtot / (msx * 1e-3), "unit": "walker Slater-builds/s",
+                 "ms_per_step": msx, "steps": steps2, "dtype": DTYPE[m],
+                 "roofline": roofline_of(ktab, wk, lab),
+                 "kernels_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in ktab.items()},
+                 "kernel_frac": {k: round(v["frac"], 4) for k, v in ktab.items() if "frac" in v}}
+        if wl.tuning is not None:
+            entry["tuning"] = wl.tuning
+        also.append(entry)
+        return wl, entry
+
     if not args.no_also:
         steps2 = max(3, args.steps // 2)
-        pairs = [(args.config, W, mode, "fp64"), ("1731e", q.CONFIGS["1731e"]["W"], "fp32", "fp64")]
-        mixed_keep = main_wl
-        for name, Wx, mmode, fmode in pairs:
-            runs = {}
-            for m in (mmode, fmode):
-                if name == args.config and m == mode and mixed_keep is not None:
-                    wl, msx, prx = mixed_keep, ms, prof
-                else:
-                    log(f"companion {name} W={Wx} mode={m}")
-                    wl = Workload(name, Wx, m)
-                    msx, _, prx = wl.time(steps2, 2)
-                    nnz_x = survivors_per_electron(wl.sysm, wl.R_np)
-                    ktab = kernel_table(prx, steps2, work_per_step(wl.sysm, nnz_x, Wx, m))
-                    also.append({"workload": f"{name}-W{Wx}-{m}-fwd+adjoint", "value": Wx / (msx * 1e-3),
-                                 "unit": "walker Slater-builds/s", "ms_per_step": msx, "steps": steps2,
-                                 "dtype": DTYPE[m],
-                                 "kernels_ms_per_step": {k: round(v["ms_per_step"], 3) for k, v in ktab.items()},
-                                 "kernel_frac": {k: round(v["frac"], 4) for k, v in ktab.items() if "frac" in v}})
-                runs[m] = wl
-            e = err_vs_fp64(runs[mmode].out, runs[fmode].out)
-            for a in also:
-                if a["workload"] == f"{name}-W{Wx}-{mmode}-fwd+adjoint":
-                    a["err_vs_fp64"] = e
-            if name == args.config:
-                res["config"]["err_vs_fp64"] = e
-            for m, wl in runs.items():
-                if wl is not main_wl:
-                    wl.close()
-            runs.clear()
+        # the same workload in the other two modes; errors against FP64
+        others = [m for m in ("bf16x3", "fp32") if m != mode]
+        ref_wl, _ = (main_wl, None) if mode == "fp64" else companion(args.config, W, "fp64", steps2)
+        if mode != "fp64":
+            res["config"]["err_vs_fp64"] = err_vs_fp64(outputs_of(main_wl), outputs_of(ref_wl))
+        for m in others:
+            wl, entry = companion(args.config, W, m, steps2)
+            entry["err_vs_fp64"] = err_vs_fp64(outputs_of(wl), outputs_of(ref_wl))
+            wl.close()
+            del wl
             torch.cuda.empty_cache()
+        if ref_wl is not main_wl:
+            ref_wl.close()
+        del ref_wl
+        torch.cuda.empty_cache()
+        # 1731 electrons, FP32 and FP64
+        W5 = q.CONFIGS["1731e"]["W"]
+        wl32, e32 = companion("1731e", W5, "fp32", steps2)
+        wl64, _ = companion("1731e", W5, "fp64", steps2)
+        e32["err_vs_fp64"] = err_vs_fp64(outputs_of(wl32), outputs_of(wl64))
+        wl32.close()
+        wl64.close()
+        del wl32, wl64
+        torch.cuda.empty_cache()
+        # the uneven batch: 512 walkers each of 44e, 158e, 434e, one autotuned FP32 plan
+        wlb, _ = companion("44e", 512, "fp32", steps2, more=(("158e", 512), ("434e", 512)), autotune=True,
+                           label="batch-44e+158e+434e-W512x3-fp32-fwd+adjoint")
+        wlb.close()
+        del wlb
+        torch.cuda.empty_cache()
     res["also"] = also
     main_wl.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         sysm_b, A_up, A_dn, R_b = q.make_config(args.config, W=W)
-        res["cpu_baseline"] = cpu_baseline(sysm_b, A_up, A_dn, R_b)
+        res["cpu_baseline"] = cpu_baseline(sysm_b, A_up, A_dn, R_b, args.config)
     print(json.dumps(res), flush=True)
 
 
