@@ -180,6 +180,25 @@ qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, in
  */
 qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* args, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code being captured into a
+ * HIP graph, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of qsl_forward with its workspace taken from a static device array
+ * of QSL_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs
+ * on until the process ends; args->ws and args->ws_bytes are ignored.  Calls
+ * no hipMalloc, hipFree or other allocating routine, and is not timed by
+ * qsl_profile_enable.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams, other threads) race; nothing
+ * in the array needs to start at zero (each call writes what it reads).
+ * Outputs equal those of qsl_forward bit for bit.
+ * Errors: those of qsl_forward; WORKSPACE when the forward of args->W walkers
+ * needs more than QSL_NOALLOC_SCRATCH_BYTES (qsl_workspace_size with
+ * QSL_WS_FORWARD gives the need: about 43 MB for 4096 walkers of 434
+ * electrons); HIP if the array's device address cannot be found.
+ */
+#define QSL_NOALLOC_SCRATCH_BYTES (64u << 20)
+qsl_status qsl_forward_noalloc(qsl_system* sys, const qsl_fwd_args* args, void* stream);
+
 /* Backward arguments (adjoint of L = sum_w sum_s g[w][s] logdet[w][s]). */
 typedef struct {
     int64_t W;

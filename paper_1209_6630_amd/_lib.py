@@ -48,6 +48,7 @@ class Tuning(ct.Structure):
 
 PLAN_GRAPH = 1
 WS_FORWARD, WS_BACKWARD, WS_BOTH = 1, 2, 3
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class KernelTime(ct.Structure):
@@ -63,6 +64,7 @@ SIGNATURES = {
     "qsl_set_mo": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p]),
     "qsl_workspace_size": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.POINTER(ct.c_size_t)]),
     "qsl_forward": (ct.c_int, [ct.c_void_p, ct.POINTER(FwdArgs), ct.c_void_p]),
+    "qsl_forward_noalloc": (ct.c_int, [ct.c_void_p, ct.POINTER(FwdArgs), ct.c_void_p]),
     "qsl_backward": (ct.c_int, [ct.c_void_p, ct.POINTER(BwdArgs), ct.c_void_p]),
     "qsl_plan_create": (ct.c_int, [ct.c_int32, ct.POINTER(ct.c_void_p), ct.POINTER(ct.c_int64), ct.c_int32,
                                    ct.c_uint32, ct.POINTER(ct.c_void_p)]),

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -95,8 +96,12 @@ struct ProfAgg {
 };
 static std::vector<ProfAgg> g_prof_agg;
 
+// Set while an allocation-free call enqueues: its launches are not timed
+// (timing creates events).
+static thread_local bool g_prof_suspend = false;
+
 ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
-    if (!g_prof_on) return;
+    if (!g_prof_on || g_prof_suspend) return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;  // no events in graphs
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
@@ -555,7 +560,12 @@ qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, in
     return QSL_OK;
 }
 
-qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
+}  // extern "C"
+
+namespace qsl {
+
+// Argument checks of a forward call (everything but the workspace).
+static qsl_status forward_check(qsl_system* sys, const qsl_fwd_args* a) {
     if (!sys || !a) return bad(QSL_ERR_INVALID_ARG, "NULL argument");
     if (a->W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
     if (a->mode < QSL_FP64 || a->mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
@@ -569,10 +579,13 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         if (!a->C[s] || !a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "C and Dinv outputs are required");
         if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
     }
-    WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);
-    if (!a->ws || a->ws_bytes < L.fwd_total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
-    hipStream_t st = (hipStream_t)stream;
-    char* ws = (char*)a->ws;
+    return QSL_OK;
+}
+
+// The forward's launches on workspace ws (at least the forward's part of
+// ws_layout); enqueues kernels only.
+static qsl_status forward_enqueue(qsl_system* sys, const qsl_fwd_args* a, char* ws, hipStream_t st) {
+    const WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
     hipError_t e;
     if (a->status && (e = fill_u32(a->status, 0u, a->W, st)) != hipSuccess) return hip_fail(e, "status clear");
     for (int s = 0; s < 2; ++s) {
@@ -597,6 +610,59 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
         }
     }
     return QSL_OK;
+}
+
+// Workspace of qsl_forward_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself
+// to a kernel (on the host it is only a stand-in for the symbol): the device
+// address of each GPU's copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[QSL_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+static std::mutex g_scratch_mu;
+
+static qsl_status scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "noalloc: hipGetDevice");
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return bad(QSL_ERR_UNSUPPORTED, "noalloc: device index too large");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "noalloc: hipGetSymbolAddress");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QSL_OK;
+}
+
+}  // namespace qsl
+
+extern "C" {
+
+qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
+    qsl_status r = forward_check(sys, a);
+    if (r != QSL_OK || a->W == 0) return r;
+    WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
+    if (!a->ws || a->ws_bytes < L.fwd_total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
+    return forward_enqueue(sys, a, (char*)a->ws, (hipStream_t)stream);
+}
+
+qsl_status qsl_forward_noalloc(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
+    qsl_status r = forward_check(sys, a);
+    if (r != QSL_OK || a->W == 0) return r;
+    const WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
+    if (L.fwd_total > (size_t)QSL_NOALLOC_SCRATCH_BYTES)
+        return bad(QSL_ERR_WORKSPACE, "noalloc: the forward of this many walkers needs " + std::to_string(L.fwd_total) +
+                                          " bytes of workspace, more than the " +
+                                          std::to_string((size_t)QSL_NOALLOC_SCRATCH_BYTES) + " of the static scratch");
+    void* ws = nullptr;
+    if ((r = scratch_address(&ws)) != QSL_OK) return r;
+    g_prof_suspend = true;
+    r = forward_enqueue(sys, a, (char*)ws, (hipStream_t)stream);
+    g_prof_suspend = false;
+    return r;
 }
 
 qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
