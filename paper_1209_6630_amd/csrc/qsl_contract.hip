@@ -15,7 +15,8 @@
 //
 // Precision modes:
 //   FP64   AO eval FP64, v_mfma_f64_16x16x4f64, 64 MOs per workgroup.
-//   FP32   AO eval FP32, v_mfma_f32_32x32x2f32, 256 MOs per workgroup.
+//   FP32   AO eval FP32, v_mfma_f32_32x32x2f32, 256 MOs per workgroup, over
+//          the tile's surviving slots rather than whole windows (below).
 //   BF16X3 AO eval FP32, each operand split x = hi + lo (bf16, round to
 //          nearest even), C += Bhi Ahi + Bhi Alo + Blo Ahi on
 //          v_mfma_f32_32x32x16_bf16 with FP32 accumulation.
@@ -25,6 +26,7 @@ namespace qsl {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
 constexpr int CT_WAVES = 4;
@@ -47,8 +49,269 @@ struct CT {
     static constexpr int LD = MODE == QSL_BF16X3 ? KC + 8 : (MODE == QSL_FP32 ? KC + 4 : KC + 2);
 };
 
+// ---------------------------------------------------------------- FP32
+// The FP32 products take the tile's surviving slots as their K dimension,
+// not whole windows: a window of 8 slots holds two or three shells of one
+// atom, and a shell whose smallest exponent fails the FP64 test for every
+// electron of the tile contributes exact zeros.  The tile's window list is
+// filtered 32 windows at a time (one distance per electron and window, one
+// compare per slot, a wavefront OR over the 32 electrons) into an ascending
+// ring of slot indices; chunks of 64 slots are evaluated into LDS (one
+// thread per slot and eight electrons) and contracted with
+// v_mfma_f32_32x32x2f32, k-step t taking chunk slots t and 32 + t.
+constexpr int F32_MSUB = 2;     // 32-MO sub-blocks per wave (a workgroup covers 256 MOs)
+constexpr int F32_NB = F32_MSUB * CT_WAVES * 32;
+constexpr int F32_MINB = 2;     // workgroups per CU (registers: 160 accumulators + the evaluation)
+constexpr int F32_BATCH = 32;   // windows filtered at a time
+constexpr int F32_KC = 64;      // slots per chunk
+constexpr int F32_RING = 512;   // ring of slot indices (>= 8 * F32_BATCH + F32_KC)
+constexpr int F32_LD = F32_KC + 4;
+
+// Value, gradient and Laplacian of slot record r at electron p (FP32 AO
+// arithmetic, FP64 screening), with the near-tie flag.  The primitives are
+// read from the record one at a time (few registers; they stay in L1).
+__device__ __forceinline__ void slot_values(const SlotRec& r, double T_thr, const double p[3], float v[5],
+                                            bool& tie) {
+    const double dx = p[0] - r.pos[0], dy = p[1] - r.pos[1], dz = p[2] - r.pos[2];
+    const double r2 = dist2_exact(dx, dy, dz);
+    const float X = (float)dx, Y = (float)dy, Z = (float)dz;
+    const double tieb = 1e-12 * T_thr;
+    float g = 0.f, g1 = 0.f, g2 = 0.f;
+    const int np = r.np;
+#pragma unroll 1
+    for (int k = 0; k < np; ++k) {
+        const double gk = r.ex[k];
+        const double t = mul_exact(gk, r2);
+        tie |= fabs(t - T_thr) <= tieb;
+        if (t <= T_thr) {
+            const float ek = r.c32[k] * exp_t(-(float)t);
+            const float gT = (float)gk;
+            g += ek;
+            g1 += -2.f * gT * ek;
+            g2 += ek * (4.f * gT * gT * (float)r2 - 6.f * gT);
+        }
+    }
+    const int pw = r.pw;
+    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
+    float px, ddx, d2x, py, ddy, d2y, pz, ddz, d2z;
+    axis_pow(a, X, px, ddx, d2x);
+    axis_pow(b, Y, py, ddy, d2y);
+    axis_pow(c, Z, pz, ddz, d2z);
+    const float f = r.f32;
+    const float fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
+    const float P = fyz * px;
+    const float pg1 = P * g1;
+    v[0] = P * g;
+    v[1] = fyz * ddx * g + pg1 * X;
+    v[2] = fxz * ddy * g + pg1 * Y;
+    v[3] = fxy * ddz * g + pg1 * Z;
+    v[4] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + (float)(2 * l) * pg1 + P * g2;
+}
+
+__device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) {
+    const DevSys& s = j.s;
+    const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
+    const int64_t W = j.W;
+    const double* __restrict__ R = j.R;
+    const float* __restrict__ AT32 = j.mo.AT32;
+    const SlotRec* __restrict__ srec = s.slot_rec;
+    uint32_t* __restrict__ status = j.status;
+    constexpr int MSUB = F32_MSUB, NSB = CT_WAVES * 32, LD = F32_LD, KC = F32_KC;
+
+    __shared__ double epos[TE][3];
+    __shared__ __attribute__((aligned(16))) float B[5 * TE * LD];
+    __shared__ __attribute__((aligned(16))) int ring[F32_RING];
+    __shared__ __attribute__((aligned(16))) int ringo[F32_RING];  // slot * ldn: the slot's coefficient row
+    __shared__ uint32_t wmask[F32_BATCH];
+    __shared__ int s_tail;
+
+    const int tile = bx;
+    const int n0 = by * MSUB * NSB;
+    const int wbk = walker_blocks(W);
+    const int eidx = tile / wbk;
+    const int w0 = (tile % wbk) * TE;
+    const int ne = (int)min<int64_t>(TE, W - w0);
+    const int N = s.n_up + s.n_dn;
+    const int eoff = spin ? s.n_up : 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double Tscr = s.T;
+
+    if (tid < TE * 3) {
+        const int e = tid / 3, k = tid % 3;
+        epos[e][k] = e < ne ? R[((size_t)(w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
+    }
+    if (tid == 0) s_tail = 0;
+    const int nwin = j.nwin[tile];
+    const int* __restrict__ wins = j.win + (size_t)tile * s.n_win;
+    const int nsub = min(MSUB, (n - n0 + NSB - 1) / NSB);
+    f32x16 acc[MSUB][5];
+#pragma unroll
+    for (int sb = 0; sb < MSUB; ++sb)
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[sb][d][r] = 0.f;
+    uint32_t tiebits = 0;  // near ties seen by this thread, one bit per electron it evaluates
+    bool ftie = false;     // a near tie in the slot filter for electron lane % 32
+    __syncthreads();
+
+    int head = 0, tail = 0, b0 = 0;
+    while (b0 < nwin || head < tail) {
+        if (tail - head < KC && b0 < nwin) {
+            // ---- filter: windows b0 .. b0 + 31 of the tile's list
+            const int e = lane & (TE - 1);
+#pragma unroll
+            for (int it = 0; it < F32_BATCH / 8; ++it) {
+                const int wl = it * 8 + wave * 2 + (lane >> 5);
+                const int q = b0 + wl < nwin ? wins[b0 + wl] : -1;
+                uint32_t m = 0;
+                if (q >= 0 && e < ne) {
+                    const SlotRec* rq = srec + (size_t)q * WIN;
+                    const double r2 = dist2_exact(epos[e][0] - rq->pos[0], epos[e][1] - rq->pos[1],
+                                                  epos[e][2] - rq->pos[2]);
+#pragma unroll
+                    for (int jj = 0; jj < WIN; ++jj) {
+                        const double t = mul_exact(rq[jj].gmin, r2);
+                        if (t <= Tscr) m |= 1u << jj;
+                        else ftie |= t - Tscr <= 1e-12 * Tscr;
+                    }
+                }
+                uint32_t wm = 0;
+#pragma unroll
+                for (int jj = 0; jj < WIN; ++jj) {
+                    const uint64_t bal = __ballot((m >> jj) & 1u);
+                    const uint32_t half = (uint32_t)(lane < 32 ? bal : (bal >> 32));
+                    wm |= (half != 0u ? 1u : 0u) << jj;
+                }
+                if ((lane & 31) == 0) wmask[wl] = wm;
+            }
+            __syncthreads();
+            if (wave == 0 && lane < F32_BATCH) {
+                const uint32_t m = b0 + lane < nwin ? wmask[lane] : 0u;
+                const int q = b0 + lane < nwin ? wins[b0 + lane] : 0;
+                const int c = __popc(m);
+                int x = c;  // inclusive prefix over the 32 windows
+#pragma unroll
+                for (int o = 1; o < 32; o <<= 1) {
+                    const int y = __shfl_up(x, o, 32);
+                    if (lane >= o) x += y;
+                }
+                int pos = tail + x - c;
+                for (uint32_t mm = m; mm; mm &= mm - 1) {
+                    const int sl = q * WIN + __builtin_ctz(mm);
+                    ring[pos & (F32_RING - 1)] = sl;
+                    ringo[pos & (F32_RING - 1)] = sl * ldn;
+                    ++pos;
+                }
+                if (lane == F32_BATCH - 1) s_tail = tail + x;
+            }
+            __syncthreads();
+            tail = s_tail;
+            b0 += F32_BATCH;
+            continue;
+        }
+        // ---- chunk [head, head + 64): AO values into LDS
+        const int cnt = min(KC, tail - head);
+        {
+            const int kk = tid & (KC - 1), eg = tid >> 6;
+            const bool live = kk < cnt;
+            const int slot = live ? ring[(head + kk) & (F32_RING - 1)] : 0;
+            const SlotRec& r = srec[slot];
+#pragma unroll 1
+            for (int i = 0; i < 8; ++i) {
+                const int e = eg + 4 * i;
+                bool tie = false;
+                float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+                if (live && e < ne) {
+                    const double p[3] = {epos[e][0], epos[e][1], epos[e][2]};
+                    slot_values(r, Tscr, p, v, tie);
+                }
+                tiebits |= (tie ? 1u : 0u) << i;
+#pragma unroll
+                for (int d = 0; d < 5; ++d) B[(d * TE + e) * LD + kk] = v[d];
+            }
+        }
+        __syncthreads();
+        // ---- products: k-step t of group u takes chunk slots 4u + t (lanes
+        // 0..31) and 32 + 4u + t (lanes 32..63); the coefficients of the
+        // next group are loaded during this group's MFMAs
+        {
+            const int h = lane >> 5;
+            float bq[MSUB][4], bn[MSUB][4];
+            const float* __restrict__ Acol[MSUB];
+#pragma unroll
+            for (int sb = 0; sb < MSUB; ++sb) Acol[sb] = AT32 + min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
+            auto load_b = [&](int u) __attribute__((always_inline)) {
+                const int pos = head + h * 32 + 4 * u;
+                const int4 so = *(const int4*)&ringo[pos & (F32_RING - 1)];
+                // entries past the list point at row 0 (their B values are zero)
+                const int ov[4] = {pos + 0 < tail ? so.x : 0, pos + 1 < tail ? so.y : 0, pos + 2 < tail ? so.z : 0,
+                                   pos + 3 < tail ? so.w : 0};
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) bn[sb][t] = gmem(Acol[sb])[ov[t]];
+            };
+            load_b(0);
+#pragma unroll
+            for (int u = 0; u < KC / 8; ++u) {
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) bq[sb][t] = bn[sb][t];
+                if (u + 1 < KC / 8) load_b(u + 1);
+                f32x4 a[5];
+#pragma unroll
+                for (int d = 0; d < 5; ++d)
+                    a[d] = *(const f32x4*)&B[(d * TE + (lane & 31)) * LD + h * 32 + 4 * u];
+#pragma unroll
+                for (int sb = 0; sb < MSUB; ++sb) {
+                    if (sb >= nsub) break;
+                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int d = 0; d < 5; ++d)
+                            acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[d][t], bq[sb][t], acc[sb][d], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        head += KC;
+    }
+
+    // near ties flag the walkers of the electrons concerned
+    if (status) {
+        const int eg = tid >> 6;
+        for (uint32_t tb = tiebits; tb; tb &= tb - 1) {
+            const int e = eg + 4 * __builtin_ctz(tb);
+            if (e < ne) atomicOr(status + w0 + e, QSL_STATUS_NEAR_TIE);
+        }
+        if (ftie && (lane & 31) < ne) atomicOr(status + w0 + (lane & 31), QSL_STATUS_NEAR_TIE);
+    }
+    // ---- store C[w][d][e][mo]
+    float* C = (float*)j.C;
+#pragma unroll
+    for (int sb = 0; sb < MSUB; ++sb) {
+        const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
+        if (mo < n) {
+#pragma unroll
+            for (int d = 0; d < 5; ++d)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                    if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc[sb][d][r];
+                }
+        }
+    }
+}
+
 template <int MODE>
 __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
+    if constexpr (MODE == QSL_FP32) {
+        contract_f32_body(j, bx, by);
+    } else {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
     const int64_t W = j.W;
@@ -56,7 +319,6 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const int* __restrict__ tile_nwin = j.nwin;
     const int* __restrict__ tile_win = j.win;
     const double* __restrict__ AT64 = j.mo.AT64;
-    const float* __restrict__ AT32 = j.mo.AT32;
     const uint16_t* __restrict__ Ahi = j.mo.Ahi;
     const uint16_t* __restrict__ Alo = j.mo.Alo;
     void* __restrict__ Cout = j.C;
@@ -235,26 +497,6 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
                         acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[d], bah, acc32[sb][d], 0, 0, 0);
                 }
             }
-        } else if constexpr (MODE == QSL_FP32) {
-            const float* bt = (const float*)bbuf;
-            const int kk = lane >> 5;
-            for (int ks = 0; ks < KC / 2; ++ks) {
-                const int c = ks * 2 + kk;
-                const int slot = wq[c / WIN] * WIN + (c % WIN);
-                float a[5];
-#pragma unroll
-                for (int d = 0; d < 5; ++d) a[d] = bt[(d * TE + (lane & 31)) * LD + c];
-#pragma unroll
-                for (int sb = 0; sb < MSUB; ++sb) {
-                    if (sb >= nsub) break;
-                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
-                    const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
-                    const float b = AT32[(size_t)slot * ldn + mo];
-#pragma unroll
-                    for (int d = 0; d < 5; ++d)
-                        acc32[sb][d] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[d], b, acc32[sb][d], 0, 0, 0);
-                }
-            }
         } else {
             const double* bt = (const double*)bbuf;
             const int kk = lane >> 4;
@@ -307,33 +549,59 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
             }
         }
     }
+    }  // FP64 / BF16X3
 }
 
+// (the per-system launch keeps two workgroups per CU in every mode: with
+// the Job passed by value the FP32 body needs more registers than three allow)
 template <int MODE>
 __global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_kernel(Job j) {
     contract_body<MODE>(j, blockIdx.x, blockIdx.y);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+__global__ __launch_bounds__(CT_WAVES * 64, MODE == QSL_FP32 ? F32_MINB : 2) void contract_batched(const Job* jobs,
+                                                                                                const int* prefix,
+                                                                                                int njobs) {
     batch_block(jobs, prefix, njobs,
                 [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE>(j, bx, by); });
 }
 
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
-    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : CT<QSL_FP32>::NB;
+    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : (j.mode == QSL_FP32 ? F32_NB : CT<QSL_BF16X3>::NB);
     j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.n + nb - 1) / nb;
     j.gz = 1;
+}
+
+// The Job of a per-system launch into device memory (with the block prefix
+// {0, grid}), so the contraction reads it as a batched launch does (passed
+// by value, its fields would crowd the registers).
+__global__ void store_job_kernel(Job j, Job* dst, int* prefix) {
+    if (threadIdx.x == 0) {
+        *dst = j;
+        prefix[0] = 0;
+        prefix[1] = j.gx * j.gy * j.gz;
+    }
 }
 
 hipError_t launch_contract(const Job& j0, hipStream_t st) {
     Job j = j0;
     contract_grid(j);
     if (!j.n || !j.W) return hipSuccess;
-    const dim3 g((unsigned)j.gx, j.gy);
     constexpr int T = CT_WAVES * 64;
+    if (j.jobslot) {
+        Job* dj = (Job*)j.jobslot;
+        int* pre = (int*)((char*)j.jobslot + sizeof(Job));
+        store_job_kernel<<<1, 64, 0, st>>>(j, dj, pre);
+        const int grid = j.gx * j.gy;
+        if (j.mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(dj, pre, 1);
+        else if (j.mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(dj, pre, 1);
+        else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(dj, pre, 1);
+        return hipGetLastError();
+    }
+    const dim3 g((unsigned)j.gx, j.gy);
     if (j.mode == QSL_FP64) contract_kernel<QSL_FP64><<<g, T, 0, st>>>(j);
     else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32><<<g, T, 0, st>>>(j);
     else contract_kernel<QSL_BF16X3><<<g, T, 0, st>>>(j);

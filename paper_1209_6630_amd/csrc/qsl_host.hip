@@ -126,6 +126,8 @@ int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
     WsLayout L{};
     size_t off = 0;
+    L.job_off = off;
+    off += JOBSLOT_BYTES;
     for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
         size_t tiles = n ? (size_t)electron_tiles(n, W) : 0;
@@ -174,6 +176,7 @@ Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws,
     j.R = a->R;
     j.nwin = (int*)(ws + L.nwin_off[s]);
     j.win = (int*)(ws + L.win_off[s]);
+    j.jobslot = ws + L.job_off;
     j.C = a->C[s];
     if (gj_blocked(j.n)) j.gjws = (double*)(ws + L.gj_off[s]);
     j.logdet = a->logdet;
@@ -421,6 +424,26 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             }
         }
 
+        std::vector<SlotRec> slot_rec(std::max(n_slots, 1));
+        for (int q = 0; q < n_slots; ++q) {
+            SlotRec& r = slot_rec[q];
+            memset(&r, 0, sizeof r);
+            const int sh = slot_shell[q];
+            r.pw = -1;
+            r.gmin = std::numeric_limits<double>::infinity();
+            const int at = win_atom[q / WIN];
+            for (int k = 0; k < 3; ++k) r.pos[k] = d->atom_xyz[3 * at + k];
+            if (sh < 0) continue;
+            r.pw = slot_pow[q] & 0xffff;
+            r.f32 = (float)slot_f[q];
+            r.np = sh_np[sh];
+            for (int k = 0; k < sh_np[sh]; ++k) {
+                r.ex[k] = ex[p0[sh] + k];
+                r.c32[k] = c32[p0[sh] + k];
+                r.gmin = std::min(r.gmin, r.ex[k]);
+            }
+        }
+
         // device tables in one allocation
         Arena ar;
         size_t o_xyz = ar.add(d->atom_xyz, sizeof(double) * 3 * d->n_atoms);
@@ -439,6 +462,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         size_t o_wat = ar.add(win_atom.data(), sizeof(int) * win_atom.size());
         size_t o_wgm = ar.add(win_gmin.data(), sizeof(double) * win_gmin.size());
         size_t o_wrec = ar.add(win_rec.data(), sizeof(WinRec) * win_rec.size());
+        size_t o_srec = ar.add(slot_rec.data(), sizeof(SlotRec) * slot_rec.size());
         // MO copies per spin
         size_t o_mo[2][8];
         int ldn[2];
@@ -475,6 +499,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         D.slot_f = (const double*)(b + o_sf); D.slot_ao = (const int*)(b + o_sao);
         D.win_atom = (const int*)(b + o_wat); D.win_gmin = (const double*)(b + o_wgm);
         D.win_rec = (const WinRec*)(b + o_wrec);
+        D.slot_rec = (const SlotRec*)(b + o_srec);
         for (int sp = 0; sp < 2; ++sp) {
             DevMO& m = S->mo[sp];
             m.n = sp ? d->n_dn : d->n_up;

@@ -55,6 +55,22 @@ constexpr int WINREC_Q32 = (int)(offsetof(WinRec, f64) / 16);
 constexpr int WINREC_Q64 = (int)(sizeof(WinRec) / 16);
 static_assert(offsetof(WinRec, f64) % 16 == 0 && sizeof(WinRec) % 16 == 0, "records are copied in 16-byte pieces");
 
+// Everything the AO evaluation of one slot needs (the FP32 contraction
+// evaluates slot by slot): atom position, the smallest exponent of the
+// slot's shell (its survival test), the shell's primitives, the Cartesian
+// factor and powers pw = a | b<<4 | c<<8 | l<<12 (-1 for padding).
+struct SlotRec {
+    double pos[3];
+    double gmin;
+    double ex[QSL_PMAX];
+    float c32[QSL_PMAX];
+    float f32;
+    int pw;
+    int np;
+    int pad;
+};
+static_assert(sizeof(SlotRec) % 16 == 0, "slot records are loaded in 16-byte pieces");
+
 // Device view of a system, passed to kernels by value.
 struct DevSys {
     int n_atoms, n_shells, n_slots, n_win, n_basis;
@@ -76,6 +92,7 @@ struct DevSys {
     const WinRec* win_rec;    // [n_win]
     const int* win_atom;      // [n_win]
     const double* win_gmin;   // [n_win] min exponent over shells meeting the window
+    const SlotRec* slot_rec;  // [n_slots]
 };
 
 // MO coefficient copies of one spin, padded: n rows -> ldn (multiple of 128).
@@ -274,8 +291,11 @@ struct Job {
     float* dA32;
     double* gjws;            // blocked inversion (gj_blocked(n)): W x gj_ws_doubles(n)
     uint16_t* gsplit;        // BF16X3 adjoint: W x gsplit_elems(n) hi, then as many lo
+    void* jobslot;           // per-system launches: device copy of the Job and its block prefix
     int gx, gy, gz;          // the Job's grid in the current phase
 };
+// Bytes of the device Job copy of a per-system launch (Job, then two ints).
+constexpr size_t JOBSLOT_BYTES = (sizeof(Job) + 2 * sizeof(int) + 255) / 256 * 256;
 
 // Block b of a batched launch -> (Job, block coordinates within the Job).
 __device__ __forceinline__ int find_job(const int* __restrict__ prefix, int njobs, int b) {
@@ -374,6 +394,7 @@ __host__ __device__ inline int64_t gsplit_elems(int n) {
 }
 
 struct WsLayout {
+    size_t job_off;  // the device Job copy of per-system launches
     size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2];
     size_t fwd_total;  // end of the forward's regions (tile lists, blocked-inversion copy)
     size_t total;      // end of the adjoint's regions

@@ -20,11 +20,12 @@ __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restri
         const uint16_t h = bf16_rne(f);
         const uint16_t l = bf16_rne(f - bf16_to_f(h));
         const int win = slot / WIN, j = slot % WIN;
+        // bf16 copies packed per window: the MFMA fragments of one window
+        // (8 slots of consecutive MOs, or 8 MOs of its 8 slots) are
+        // contiguous
+        const int64_t pk = ((int64_t)win * ldn + mo) * WIN + j;                        // [win][mo][j]
         AT64[q] = v;
         AT32[q] = f;
-        // bf16 copies packed per window: the MFMA fragments of one window
-        // (8 slots of consecutive MOs, or 8 MOs of its 8 slots) are contiguous
-        const int64_t pk = ((int64_t)win * ldn + mo) * WIN + j;                        // [win][mo][j]
         const int64_t pt = (((int64_t)win * (ldn / 8) + mo / 8) * WIN + j) * 8 + mo % 8;  // [win][mo/8][j][mo%8]
         Ahi[pk] = h;
         Alo[pk] = l;
