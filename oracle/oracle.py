@@ -58,6 +58,13 @@ def load():
         lib.orc_backward.argtypes = [S, _dp, _dp, ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp,
                                      _dp, _dp, _dp, _dp, ct.c_int32]
         lib.orc_max_threads.restype = ct.c_int
+        lib.orc_jastrow_potential.argtypes = [S, _dp, ct.c_double, ct.c_double, ct.c_double, ct.c_double,
+                                              ct.c_int32, _dp, _dp, _dp, _dp, _dp, ct.c_int32]
+        lib.orc_local_energy.argtypes = [ct.c_int32, ct.c_int32, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_drift_diffuse.argtypes = [ct.c_int64, _dp, _dp, _dp, ct.c_double, _dp]
+        lib.orc_branch_weights.argtypes = [ct.c_int64, _dp, _dp, ct.POINTER(ct.c_int8), ct.POINTER(ct.c_int8),
+                                           ct.c_double, ct.c_double, _dp]
+        lib.orc_reconfigure.argtypes = [ct.c_int64, _dp, _dp, ct.POINTER(ct.c_int64), _dp]
         _lib = lib
     return _lib
 
@@ -178,3 +185,62 @@ def backward(sys, A_up, A_dn, R, Dinv_up, Dinv_dn, g, nthreads=0, want_abs=False
 
 def max_threads() -> int:
     return int(load().orc_max_threads())
+
+
+# ------------------------------------------------------------- QMC step
+
+def jastrow_potential(sys, Z, R, c_ee=1.0, b_ee=1.0, c_en=1.0, b_en=1.0, nthreads=0):
+    """Jastrow exponent J[W], its gradient gJ[W,N,3] and Laplacian lJ[W,N]
+    per electron, and the Coulomb potential V[W]."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, np.float64)
+    W, N = R.shape[0], R.shape[1]
+    Z = np.ascontiguousarray(Z, np.float64)
+    J, gJ, lJ, V = np.zeros(W), np.zeros((W, N, 3)), np.zeros((W, N)), np.zeros(W)
+    load().orc_jastrow_potential(o.ref, _p(Z), float(c_ee), float(b_ee), float(c_en), float(b_en), W, _p(R), _p(J),
+                                 _p(gJ), _p(lJ), _p(V), int(nthreads))
+    return J, gJ, lJ, V
+
+
+def local_energy(drift_det, lap_det, gJ, lJ, V):
+    """E_L[W] and the full drift b[W,N,3] of Psi = e^J Det_up Det_dn."""
+    bd = np.ascontiguousarray(drift_det, np.float64)
+    ld = np.ascontiguousarray(lap_det, np.float64)
+    gJ = np.ascontiguousarray(gJ, np.float64)
+    lJ = np.ascontiguousarray(lJ, np.float64)
+    V = np.ascontiguousarray(V, np.float64)
+    W, N = ld.shape
+    EL, b = np.zeros(W), np.zeros((W, N, 3))
+    load().orc_local_energy(W, N, _p(bd), _p(ld), _p(gJ), _p(lJ), _p(V), _p(EL), _p(b))
+    return EL, b
+
+
+def drift_diffuse(R, b, eta, tau):
+    R = np.ascontiguousarray(R, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    eta = np.ascontiguousarray(eta, np.float64)
+    out = np.zeros_like(R)
+    load().orc_drift_diffuse(R.size, _p(R), _p(b), _p(eta), float(tau), _p(out))
+    return out
+
+
+def branch_weights(EL_new, EL_old, sign_new, sign_old, E_T, tau):
+    EL_new = np.ascontiguousarray(EL_new, np.float64)
+    EL_old = np.ascontiguousarray(EL_old, np.float64)
+    sn = np.ascontiguousarray(sign_new, np.int8)
+    so = np.ascontiguousarray(sign_old, np.int8)
+    w = np.zeros(EL_new.shape[0])
+    i8 = ct.POINTER(ct.c_int8)
+    load().orc_branch_weights(w.size, _p(EL_new), _p(EL_old), _p(sn, i8), _p(so, i8), float(E_T), float(tau),
+                              _p(w))
+    return w
+
+
+def reconfigure(w, u):
+    """Parent index of each new walker and the total weight."""
+    w = np.ascontiguousarray(w, np.float64)
+    u = np.ascontiguousarray(u, np.float64)
+    idx = np.zeros(w.size, np.int64)
+    s = np.zeros(1)
+    load().orc_reconfigure(w.size, _p(w), _p(u), _p(idx, ct.POINTER(ct.c_int64)), _p(s))
+    return idx, float(s[0])

@@ -561,3 +561,174 @@ int orc_max_threads(void) {
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* One Monte Carlo step around the Slater part (section "The quantum    */
+/* Monte Carlo method": drift-diffusion move, drift, branching weight,  */
+/* local energy, reconfiguration with a constant number of walkers;    */
+/* the trial wavefunction with a Jastrow factor of its "Critical CPU   */
+/* part" subsection).                                                   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Pair function of the Jastrow factor, u(r) = a r / (1 + b r), with its
+ * first and second derivatives in r.  The electron-electron term takes
+ * a = c_ee / 2 (opposite spins) or c_ee / 4 (same spin), the
+ * electron-nucleus term a = -c_en Z; b >= 0 sets the range.  u'(0) = a:
+ * with c = 1 these are the cusp conditions.  (The paper leaves the U
+ * functions open; this is the reading taken.)
+ */
+static void pair_u(double a, double b, double r, double* u, double* du, double* d2u) {
+    double q = 1.0 + b * r;
+    *u = a * r / q;
+    *du = a / (q * q);
+    *d2u = -2.0 * a * b / (q * q * q);
+}
+
+/*
+ * For every walker: the Jastrow exponent
+ *   J = sum_{i<j} u_ee(r_ij) + sum_{i,alpha} u_en(r_i alpha),
+ * its gradient gJ[w][i][3] and Laplacian lJ[w][i] with respect to each
+ * electron, and the Coulomb potential
+ *   V = sum_{i<j} 1/r_ij - sum_{i,alpha} Z_alpha / r_i alpha
+ *       + sum_{alpha<beta} Z_alpha Z_beta / |Q_alpha - Q_beta|.
+ * The first n_up electrons are spin up.  Any output may be NULL.
+ */
+void orc_jastrow_potential(const orc_system* s, const double* Z, double c_ee, double b_ee, double c_en,
+                           double b_en, int32_t W, const double* R, double* J, double* gJ, double* lJ, double* V,
+                           int32_t nthreads) {
+    const int N = s->n_up + s->n_dn, na = s->n_atoms;
+    double vnn = 0.0;
+    for (int a = 0; a < na; ++a)
+        for (int b = a + 1; b < na; ++b) {
+            double d[3];
+            for (int k = 0; k < 3; ++k) d[k] = s->atom_xyz[3 * a + k] - s->atom_xyz[3 * b + k];
+            vnn += Z[a] * Z[b] / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        }
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(static)
+    for (int w = 0; w < W; ++w) {
+        const double* Rw = R + (size_t)w * N * 3;
+        double jw = 0.0, vw = vnn;
+        for (int i = 0; i < N; ++i) {
+            double g[3] = {0, 0, 0}, l = 0.0;
+            const int si = i < s->n_up;
+            for (int j = 0; j < N; ++j) {
+                if (j == i) continue;
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = Rw[3 * i + k] - Rw[3 * j + k];
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                double a = c_ee * ((si == (j < s->n_up)) ? 0.25 : 0.5);
+                double u, du, d2u;
+                pair_u(a, b_ee, r, &u, &du, &d2u);
+                for (int k = 0; k < 3; ++k) g[k] += du * d[k] / r;
+                l += d2u + 2.0 * du / r;
+                if (j > i) {
+                    jw += u;
+                    vw += 1.0 / r;
+                }
+            }
+            for (int al = 0; al < na; ++al) {
+                double d[3];
+                for (int k = 0; k < 3; ++k) d[k] = Rw[3 * i + k] - s->atom_xyz[3 * al + k];
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                double u, du, d2u;
+                pair_u(-c_en * Z[al], b_en, r, &u, &du, &d2u);
+                for (int k = 0; k < 3; ++k) g[k] += du * d[k] / r;
+                l += d2u + 2.0 * du / r;
+                jw += u;
+                vw -= Z[al] / r;
+            }
+            if (gJ) for (int k = 0; k < 3; ++k) gJ[((size_t)w * N + i) * 3 + k] = g[k];
+            if (lJ) lJ[(size_t)w * N + i] = l;
+        }
+        if (J) J[w] = jw;
+        if (V) V[w] = vw;
+    }
+}
+
+/*
+ * Local energy E_L = H Psi / Psi of Psi = e^J Det_up Det_dn, and the drift
+ * b = grad Psi / Psi, from the determinant's drift bd and Laplacian ratio ld
+ * (per electron, the forward's drift and lap) and the Jastrow derivatives:
+ *   grad_i Psi / Psi = gJ_i + bd_i,
+ *   lap_i Psi / Psi  = lJ_i + |gJ_i|^2 + 2 gJ_i . bd_i + ld_i,
+ *   E_L = -1/2 sum_i lap_i Psi / Psi + V.
+ */
+void orc_local_energy(int32_t W, int32_t N, const double* bd, const double* ld, const double* gJ,
+                      const double* lJ, const double* V, double* EL, double* drift) {
+    for (int w = 0; w < W; ++w) {
+        double t = 0.0;
+        for (int i = 0; i < N; ++i) {
+            size_t q = (size_t)w * N + i;
+            double gg = 0.0, gb = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                gg += gJ[3 * q + k] * gJ[3 * q + k];
+                gb += gJ[3 * q + k] * bd[3 * q + k];
+                if (drift) drift[3 * q + k] = gJ[3 * q + k] + bd[3 * q + k];
+            }
+            t += lJ[q] + gg + 2.0 * gb + ld[q];
+        }
+        EL[w] = -0.5 * t + V[w];
+    }
+}
+
+/* Drift-diffusion move R' = R + tau b(R) + sqrt(tau) eta, per coordinate. */
+void orc_drift_diffuse(int64_t count, const double* R, const double* b, const double* eta, double tau,
+                       double* Rout) {
+    const double st = sqrt(tau);
+    for (int64_t q = 0; q < count; ++q) {
+        double m = tau * b[q];
+        double d = st * eta[q];
+        Rout[q] = (R[q] + m) + d;
+    }
+}
+
+/*
+ * Branching weight w = exp(-tau/2 [(E_L(R') - E_T) + (E_L(R) - E_T)]) of
+ * each walker.  A move that changes the sign of Psi crossed a node of the
+ * trial wavefunction, which the fixed-node walkers cannot: weight 0; so is
+ * a walker whose Psi vanishes.
+ */
+void orc_branch_weights(int64_t W, const double* EL_new, const double* EL_old, const int8_t* sign_new,
+                        const int8_t* sign_old, double E_T, double tau, double* w) {
+    for (int64_t k = 0; k < W; ++k) {
+        if (sign_new[k] == 0 || sign_new[k] != sign_old[k]) {
+            w[k] = 0.0;
+            continue;
+        }
+        double e = (EL_new[k] - E_T) + (EL_old[k] - E_T);
+        w[k] = exp(-0.5 * tau * e);
+    }
+}
+
+/*
+ * Reconfiguration: M = W new walkers drawn among the W walkers with
+ * probabilities p_k = w_k / sum_i w_i.  Draw m takes the uniform u[m] in
+ * [0, 1) and selects the first k whose cumulative weight (summed in walker
+ * order) exceeds u[m] times the total.  idx[m] = k; *wsum = the total
+ * (the population weight of this step is wsum / W).  With a zero total the
+ * population is kept (idx[m] = m).
+ */
+void orc_reconfigure(int64_t W, const double* w, const double* u, int64_t* idx, double* wsum) {
+    double* cum = (double*)malloc(sizeof(double) * (W > 0 ? W : 1));
+    double c = 0.0;
+    for (int64_t k = 0; k < W; ++k) {
+        c += w[k];
+        cum[k] = c;
+    }
+    *wsum = c;
+    for (int64_t m = 0; m < W; ++m) {
+        if (!(c > 0.0)) {
+            idx[m] = m;
+            continue;
+        }
+        double x = u[m] * c;
+        int64_t k = 0;
+        while (k < W - 1 && !(x < cum[k])) ++k;
+        idx[m] = k;
+    }
+    free(cum);
+}

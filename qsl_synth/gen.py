@@ -168,3 +168,16 @@ def make_config(name: str, W: int | None = None):
     a_up, a_dn = make_mos(sys, c["seed"], c["a_fp32"])
     R = make_walkers(sys, c["W"] if W is None else W, c["seed"])
     return sys, a_up, a_dn, R
+
+
+def nuclear_charges(sys: System) -> np.ndarray:
+    """Charges of the synthetic nuclei: a heavy atom carries the 6 electrons
+    the walkers place around it, a hydrogen 1 (a neutral molecule)."""
+    return np.where(sys.atom_heavy, 6.0, 1.0)
+
+
+def dmc_randoms(W: int, N: int, seed: int, step: int):
+    """Standard normal deviates eta [W, N, 3] and uniforms u [W] in [0, 1) of
+    Monte Carlo step `step` (their own PCG64 stream per step)."""
+    rng = np.random.Generator(np.random.PCG64([seed, 7919, step]))
+    return rng.standard_normal((W, N, 3)), rng.random(W)
