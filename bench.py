@@ -306,6 +306,55 @@ def measured_traffic(workload, kernel):
     return None
 
 
+def dmc_line(config, W, mode, steps, warmup=2, tau=0.005):
+    """Time per fixed-node DMC step of the whole population (the analogue of
+    the paper's time per QMC step): drift-diffusion move, the Slater build
+    by a forward-only plan replayed from its HIP graph, Jastrow factor, local
+    energy and drift, branching weights, reconfiguration and gather.  The
+    random deviates of every step are drawn beforehand and resident on the
+    GPU."""
+    import torch
+    import qsl_synth as q
+    from paper_1209_6630_amd import _lib
+    from paper_1209_6630_amd.api import DMC, System
+    sysm, A_up, A_dn, R = q.make_config(config, W=W)
+    S = System.from_synth(sysm)
+    S.set_mo(0, A_up)
+    S.set_mo(1, A_dn)
+    S.set_jastrow(q.nuclear_charges(sysm))
+    N = sysm.n_elec
+    dmc = DMC(S, torch.from_numpy(R).cuda(), mode=mode, tau=tau, E_T=0.0, graph=True)
+    dmc.E_T = float(dmc.EL.mean())
+    rnd = [q.dmc_randoms(W, N, seed=5, step=k) for k in range(warmup + steps)]
+    eta = [torch.from_numpy(e).cuda() for e, _ in rnd]
+    u = [torch.from_numpy(x).cuda() for _, x in rnd]
+    for k in range(warmup):
+        dmc.step(eta[k], u[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        dmc.step(eta[k], u[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    _lib.profile_enable(True)
+    _lib.profile_read(reset=True)
+    for k in range(warmup, warmup + steps):
+        dmc.step(eta[k], u[k])
+    torch.cuda.synchronize()
+    prof = _lib.profile_read(reset=True)
+    _lib.profile_enable(False)
+    EL = dmc.EL.cpu().numpy()
+    dmc.close()
+    S.close()
+    return {"workload": f"dmc-step-{config}-W{W}-{mode}", "value": W / (ms * 1e-3), "unit": "walker DMC steps/s",
+            "ms_per_step": ms, "steps": steps, "dtype": DTYPE[mode],
+            "tau": tau, "mean_local_energy": float(EL.mean()),
+            "timed": "DMC steps (plan graph replay inside), deviates resident on the GPU",
+            "kernels_ms_per_step": {k: round(v[1] / steps, 3) for k, v in prof.items()},
+            "context": "paper Table 3: 0.0119 s per walker step on one Sandy Bridge core for its 434-electron "
+                       "beta-strand (other basis and molecule)"}
+
+
 def roofline_of(kernels, kinds, workload):
     """The dominant kernel's roofline entry (algorithmic work over its
     average launch time, against its peak)."""
@@ -432,6 +481,10 @@ def main():
                            label="batch-44e+158e+434e-W512x3-fp32-fwd+adjoint")
         wlb.close()
         del wlb
+        torch.cuda.empty_cache()
+        # one fixed-node DMC step around the builder, the whole population
+        log(f"dmc step {args.config} W={W} mode={mode}")
+        also.append(dmc_line(args.config, W, mode, steps2))
         torch.cuda.empty_cache()
     res["also"] = also
     main_wl.close()

@@ -319,6 +319,124 @@ qsl_status qsl_plan_destroy(qsl_plan* plan);
  */
 qsl_status qsl_autotune(qsl_plan* plan, const char* cache_path, void* stream, qsl_tuning* chosen);
 
+/* ------------------------------------------------------------- QMC step
+ *
+ * One fixed-node diffusion Monte Carlo step around the Slater part (section
+ * "The quantum Monte Carlo method"), for Psi = e^J Det_up Det_dn with the
+ * Jastrow exponent
+ *   J = sum_{i<j} u_ee(r_ij) + sum_{i,alpha} u_en(r_i alpha),
+ *   u(r) = a r / (1 + b r),
+ *   a = c_ee / 2 (opposite spins), c_ee / 4 (same spin), -c_en Z_alpha (nuclei)
+ * (c = 1: the electron-electron and electron-nucleus cusp conditions; the
+ * paper leaves the U functions open), the Coulomb Hamiltonian of the
+ * electrons and the nuclei of charges Z, and the population reconfigured at
+ * a constant number of walkers.  Everything here is FP64.
+ */
+
+/*
+ * Nuclear charges Z[n_atoms] (host, >= 0) and the Jastrow parameters of a
+ * system (b >= 0; c = 0 switches a term off).  Copies Z to the device.
+ * Errors: INVALID_ARG, OOM, HIP.
+ */
+qsl_status qsl_set_jastrow(qsl_system* sys, const double* Z, double c_ee, double b_ee, double c_en, double b_en);
+
+/* Local energy arguments (device pointers). */
+typedef struct {
+    int64_t W;
+    const double* R;          /* [W][N][3] positions                                */
+    const double* drift_det;  /* [W][N][3] the forward's drift at R (grad Det / Det) */
+    const double* lap_det;    /* [W][N]    the forward's Laplacian ratio at R        */
+    const double* logdet;     /* [W][2], and sign [W][2]: the forward's at R         */
+    const int8_t* sign;
+    double* EL;               /* [W] out: local energy H Psi / Psi                   */
+    double* drift;            /* [W][N][3] out: grad Psi / Psi = grad J + drift_det  */
+    double* logpsi;           /* [W] out or NULL: J + log|Det_up| + log|Det_dn|      */
+    int8_t* psisign;          /* [W] out or NULL: sign of Psi                        */
+    double* J;                /* [W] out or NULL: the Jastrow exponent               */
+    double* V;                /* [W] out or NULL: the Coulomb potential              */
+} qsl_local_args;
+
+/*
+ * Local energy (equation (localenergy)) and drift (equation (drift)) of
+ * Psi = e^J Det_up Det_dn from the forward's determinant drift and Laplacian
+ * ratio: lap_i Psi / Psi = lap_i J + |grad_i J|^2 + 2 grad_i J . drift_det_i
+ * + lap_det_i; E_L = -1/2 sum_i lap_i Psi / Psi + V.  One workgroup per
+ * walker.  Errors: INVALID_ARG (NULL, jastrow never set), UNSUPPORTED (more
+ * than 2048 electrons), HIP.
+ */
+qsl_status qsl_local_energy(qsl_system* sys, const qsl_local_args* args, void* stream);
+
+/*
+ * Drift-diffusion move (equation (proba)): R_out = (R + tau drift) +
+ * sqrt(tau) eta over `count` coordinates, each product and sum rounded on
+ * its own; eta are the caller's standard normal deviates.  R_out may not
+ * overlap R unless equal to it.  Errors: INVALID_ARG (NULL, tau < 0), HIP.
+ */
+qsl_status qsl_drift_diffuse(int64_t count, const double* R, const double* drift, const double* eta, double tau,
+                             double* R_out, void* stream);
+
+/*
+ * Branching weights (equation (w)):
+ * w = exp(-tau/2 [(EL_new - E_T) + (EL_old - E_T)]), and w = 0 where the move
+ * changed the sign of Psi (a node was crossed, which fixed-node walkers
+ * cannot) or Psi vanishes.  Errors: INVALID_ARG, HIP.
+ */
+qsl_status qsl_branch_weights(int64_t W, const double* EL_new, const double* EL_old, const int8_t* sign_new,
+                              const int8_t* sign_old, double E_T, double tau, double* w, void* stream);
+
+/*
+ * Reconfiguration at a constant number of walkers (subsection
+ * "Parallelizing FN-DMC"): new walker m is idx[m], the first walker whose
+ * cumulative weight (summed in walker order into cum[W], a device scratch
+ * array) exceeds u[m] (the caller's uniform deviate in [0, 1)) times the
+ * total; *wsum (device) receives the total, whose ratio to W is this step's
+ * population weight.  A non-positive total keeps the population (idx[m] = m).
+ * Weights must be finite and >= 0.  Errors: INVALID_ARG, HIP.
+ */
+qsl_status qsl_reconfigure(int64_t W, const double* w, const double* u, int64_t* idx, double* wsum, double* cum,
+                           void* stream);
+
+/* dst[m] = src[idx[m]] for W records of `width` bytes (device; distinct
+ * buffers).  Errors: INVALID_ARG, HIP. */
+qsl_status qsl_gather_walkers(int64_t W, int64_t width, const int64_t* idx, const void* src, void* dst, void* stream);
+
+/* State and inputs of a DMC step of system sys_index of a plan. */
+typedef struct {
+    int32_t sys_index;
+    int64_t W;                /* the plan's walkers of that system                  */
+    double tau, E_T;          /* time step, reference energy                         */
+    double* R;                /* [W][N][3] population (in/out); not the plan's R     */
+    double* EL;               /* [W] local energy at R (in/out)                      */
+    double* drift;            /* [W][N][3] grad Psi / Psi at R (in/out)              */
+    int8_t* psisign;          /* [W] sign of Psi at R (in/out)                       */
+    double* logpsi;           /* [W] log|Psi| at R (in/out) or NULL                  */
+    const double* eta;        /* [W][N][3] standard normal deviates of the step      */
+    const double* u;          /* [W] uniform deviates in [0, 1) of the step          */
+    int64_t* idx;             /* [W] out: parent of each new walker                  */
+    double* wsum;             /* [1] out: total branching weight of the step         */
+    void* ws;                 /* device workspace, qsl_dmc_workspace_size bytes      */
+    size_t ws_bytes;
+} qsl_dmc_args;
+
+qsl_status qsl_dmc_workspace_size(int64_t W, int32_t n_elec, size_t* bytes);
+
+/*
+ * State of the population R: copies R to the plan's bound positions, runs
+ * the plan (its forward must be bound with drift, lap, logdet and sign; bind
+ * it without an adjoint for DMC) and the local energy, writing EL, drift,
+ * psisign (and logpsi).  Errors: INVALID_ARG, SHAPE, UNSUPPORTED, HIP.
+ */
+qsl_status qsl_dmc_init(qsl_plan* plan, const qsl_dmc_args* args, void* stream);
+
+/*
+ * One step: the drift-diffusion move of R into the plan's positions, the
+ * plan's Slater build there, the local energy, the branching weights
+ * against the state at R, the reconfiguration with u, and the gather of the
+ * selected walkers' positions and state back into R, EL, drift, psisign
+ * (and logpsi).  Only enqueues work.  Errors: as qsl_dmc_init, WORKSPACE.
+ */
+qsl_status qsl_dmc_step(qsl_plan* plan, const qsl_dmc_args* args, void* stream);
+
 /*
  * Kernel timing (for benchmarks and profilers).  While enabled, every
  * kernel the library enqueues is bracketed by two HIP events recorded on the

@@ -46,6 +46,19 @@ class Tuning(ct.Structure):
     _fields_ = [("batched", ct.c_int32), ("adj_group", ct.c_int32), ("gj_bias", ct.c_int32)]
 
 
+class LocalArgs(ct.Structure):
+    _fields_ = [("W", ct.c_int64), ("R", ct.c_void_p), ("drift_det", ct.c_void_p), ("lap_det", ct.c_void_p),
+                ("logdet", ct.c_void_p), ("sign", ct.c_void_p), ("EL", ct.c_void_p), ("drift", ct.c_void_p),
+                ("logpsi", ct.c_void_p), ("psisign", ct.c_void_p), ("J", ct.c_void_p), ("V", ct.c_void_p)]
+
+
+class DmcArgs(ct.Structure):
+    _fields_ = [("sys_index", ct.c_int32), ("W", ct.c_int64), ("tau", ct.c_double), ("E_T", ct.c_double),
+                ("R", ct.c_void_p), ("EL", ct.c_void_p), ("drift", ct.c_void_p), ("psisign", ct.c_void_p),
+                ("logpsi", ct.c_void_p), ("eta", ct.c_void_p), ("u", ct.c_void_p), ("idx", ct.c_void_p),
+                ("wsum", ct.c_void_p), ("ws", ct.c_void_p), ("ws_bytes", ct.c_size_t)]
+
+
 PLAN_GRAPH = 1
 WS_FORWARD, WS_BACKWARD, WS_BOTH = 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -76,6 +89,19 @@ SIGNATURES = {
     "qsl_autotune": (ct.c_int, [ct.c_void_p, ct.c_char_p, ct.c_void_p, ct.POINTER(Tuning)]),
     "qsl_profile_enable": (ct.c_int, [ct.c_int32]),
     "qsl_profile_read": (ct.c_int, [ct.POINTER(KernelTime), ct.c_int32, ct.POINTER(ct.c_int32), ct.c_int32]),
+    "qsl_set_jastrow": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.c_double, ct.c_double, ct.c_double,
+                                   ct.c_double]),
+    "qsl_local_energy": (ct.c_int, [ct.c_void_p, ct.POINTER(LocalArgs), ct.c_void_p]),
+    "qsl_drift_diffuse": (ct.c_int, [ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_double, ct.c_void_p,
+                                     ct.c_void_p]),
+    "qsl_branch_weights": (ct.c_int, [ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_double,
+                                      ct.c_double, ct.c_void_p, ct.c_void_p]),
+    "qsl_reconfigure": (ct.c_int, [ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                   ct.c_void_p]),
+    "qsl_gather_walkers": (ct.c_int, [ct.c_int64, ct.c_int64, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "qsl_dmc_workspace_size": (ct.c_int, [ct.c_int64, ct.c_int32, ct.POINTER(ct.c_size_t)]),
+    "qsl_dmc_init": (ct.c_int, [ct.c_void_p, ct.POINTER(DmcArgs), ct.c_void_p]),
+    "qsl_dmc_step": (ct.c_int, [ct.c_void_p, ct.POINTER(DmcArgs), ct.c_void_p]),
     "qsl_status_string": (ct.c_char_p, [ct.c_int]),
     "qsl_last_error": (ct.c_char_p, []),
 }

@@ -11,7 +11,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BwdArgs, FwdArgs, MODES, PLAN_GRAPH, SystemDesc, Tuning, check, lib
+from ._lib import BwdArgs, DmcArgs, FwdArgs, LocalArgs, MODES, PLAN_GRAPH, SystemDesc, Tuning, check, lib
 
 
 def _ptr(t):
@@ -92,6 +92,31 @@ class System:
         else:
             a = np.ascontiguousarray(np.asarray(A, np.float64))
             check(lib().qsl_set_mo(self._h, spin, ct.c_void_p(a.ctypes.data), a.shape[1], 0, _stream()))
+
+    def set_jastrow(self, Z, c_ee=1.0, b_ee=1.0, c_en=1.0, b_en=1.0):
+        """Nuclear charges Z[n_atoms] and the Jastrow parameters (see
+        qsl_set_jastrow)."""
+        z = np.ascontiguousarray(Z, np.float64)
+        self._Z = z
+        check(lib().qsl_set_jastrow(self._h, z.ctypes.data_as(ct.POINTER(ct.c_double)), float(c_ee), float(b_ee),
+                                    float(c_en), float(b_en)))
+
+    def local_energy(self, R, out):
+        """E_L, the full drift, log|Psi| and sign of Psi at R from the forward
+        outputs `out` at R.  Returns a dict of CUDA tensors."""
+        W, N = R.shape[0], self.n_elec
+        dev = R.device
+        res = dict(EL=torch.empty(W, dtype=torch.float64, device=dev),
+                   drift=torch.empty((W, N, 3), dtype=torch.float64, device=dev),
+                   logpsi=torch.empty(W, dtype=torch.float64, device=dev),
+                   psisign=torch.empty(W, dtype=torch.int8, device=dev),
+                   J=torch.empty(W, dtype=torch.float64, device=dev),
+                   V=torch.empty(W, dtype=torch.float64, device=dev))
+        a = LocalArgs(W, R.data_ptr(), out["drift"].data_ptr(), out["lap"].data_ptr(), out["logdet"].data_ptr(),
+                      out["sign"].data_ptr(), res["EL"].data_ptr(), res["drift"].data_ptr(),
+                      res["logpsi"].data_ptr(), res["psisign"].data_ptr(), res["J"].data_ptr(), res["V"].data_ptr())
+        check(lib().qsl_local_energy(self._h, ct.byref(a), _stream()))
+        return res
 
     def workspace(self, W, mode, backward=True):
         """A device workspace for W walkers (grown on demand and kept): the
@@ -283,3 +308,80 @@ class SlaterLogDet(torch.autograd.Function):
 
 def slater_logdet(R, A_up, A_dn, system, mode="fp64"):
     return SlaterLogDet.apply(R, A_up, A_dn, system, mode)
+
+
+# ------------------------------------------------------------- QMC step
+
+def drift_diffuse(R, drift, eta, tau):
+    out = torch.empty_like(R)
+    check(lib().qsl_drift_diffuse(R.numel(), _ptr(R), _ptr(drift), _ptr(eta), float(tau), _ptr(out), _stream()))
+    return out
+
+
+def branch_weights(EL_new, EL_old, sign_new, sign_old, E_T, tau):
+    w = torch.empty_like(EL_new)
+    check(lib().qsl_branch_weights(EL_new.numel(), _ptr(EL_new), _ptr(EL_old), _ptr(sign_new), _ptr(sign_old),
+                                   float(E_T), float(tau), _ptr(w), _stream()))
+    return w
+
+
+def reconfigure(w, u):
+    """Parent indices (int64) and the total weight (a 1-element tensor)."""
+    W = w.numel()
+    idx = torch.empty(W, dtype=torch.int64, device=w.device)
+    wsum = torch.empty(1, dtype=torch.float64, device=w.device)
+    cum = torch.empty(max(W, 1), dtype=torch.float64, device=w.device)
+    check(lib().qsl_reconfigure(W, _ptr(w), _ptr(u), _ptr(idx), _ptr(wsum), _ptr(cum), _stream()))
+    return idx, wsum
+
+
+def gather_walkers(idx, src):
+    dst = torch.empty_like(src)
+    W = idx.numel()
+    width = src.numel() // max(W, 1) * src.element_size()
+    check(lib().qsl_gather_walkers(W, width, _ptr(idx), _ptr(src), _ptr(dst), _stream()))
+    return dst
+
+
+class DMC:
+    """Fixed-node DMC with reconfiguration for one system: the population R
+    (kept on the GPU) and its state; each step() moves, rebuilds the Slater
+    part through a forward-only plan (graph-replayed), evaluates the local
+    energy, weights and reconfigures.  eta and u are the caller's random
+    deviates of the step (CUDA float64 tensors)."""
+
+    def __init__(self, system, R, mode="fp32", tau=0.01, E_T=0.0, graph=True):
+        W, N = R.shape[0], system.n_elec
+        self.S, self.W, self.N, self.mode = system, W, N, mode
+        self.tau, self.E_T = float(tau), float(E_T)
+        dev = R.device
+        self.R = R.clone().contiguous()
+        self.Rp = torch.empty_like(self.R)
+        self.out = system.alloc_outputs(W, mode)
+        self.plan = Plan([system], [W], mode, graph=graph)
+        self.plan.bind(0, self.Rp, self.out)
+        self.EL = torch.empty(W, dtype=torch.float64, device=dev)
+        self.drift = torch.empty((W, N, 3), dtype=torch.float64, device=dev)
+        self.psisign = torch.empty(W, dtype=torch.int8, device=dev)
+        self.logpsi = torch.empty(W, dtype=torch.float64, device=dev)
+        self.idx = torch.empty(W, dtype=torch.int64, device=dev)
+        self.wsum = torch.empty(1, dtype=torch.float64, device=dev)
+        n = ct.c_size_t()
+        check(lib().qsl_dmc_workspace_size(W, N, ct.byref(n)))
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        self._eta = self._u = None
+        check(lib().qsl_dmc_init(self.plan._h, ct.byref(self._args()), _stream()))
+
+    def _args(self):
+        return DmcArgs(0, self.W, self.tau, self.E_T, self.R.data_ptr(), self.EL.data_ptr(), self.drift.data_ptr(),
+                       self.psisign.data_ptr(), self.logpsi.data_ptr(),
+                       self._eta.data_ptr() if self._eta is not None else None,
+                       self._u.data_ptr() if self._u is not None else None,
+                       self.idx.data_ptr(), self.wsum.data_ptr(), self.ws.data_ptr(), self.ws.numel())
+
+    def step(self, eta, u):
+        self._eta, self._u = eta, u
+        check(lib().qsl_dmc_step(self.plan._h, ct.byref(self._args()), _stream()))
+
+    def close(self):
+        self.plan.close()

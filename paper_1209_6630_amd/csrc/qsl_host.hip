@@ -526,6 +526,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
 qsl_status qsl_system_destroy(qsl_system* sys) {
     if (!sys) return QSL_OK;
     if (sys->dev_block) hipFree(sys->dev_block);
+    if (sys->atom_Z) hipFree(sys->atom_Z);
     delete sys;
     return QSL_OK;
 }

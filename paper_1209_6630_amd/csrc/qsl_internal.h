@@ -121,6 +121,11 @@ struct qsl_system {
     std::vector<int> ao_atom, ao_shell;
     std::vector<int8_t> ao_nxyz;
     std::vector<int> slot_ao;
+    // Jastrow factor and nuclear charges (qsl_set_jastrow)
+    bool jastrow_set = false;
+    double* atom_Z = nullptr;  // device [n_atoms]
+    double c_ee = 0, b_ee = 1, c_en = 0, b_en = 1;
+    double v_nn = 0;           // nuclear repulsion
 };
 
 namespace qsl {
@@ -472,5 +477,16 @@ hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, i
 hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
 hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A_dev, int64_t ld,
                            hipStream_t st);
+
+}  // namespace qsl
+
+struct qsl_plan;
+
+namespace qsl {
+// The plan's system i and its bound forward arguments (NULL when out of
+// range or never bound).
+qsl_system* plan_system(qsl_plan* p, int i);
+const qsl_fwd_args* plan_fwd(const qsl_plan* p, int i);
+int64_t plan_walkers(const qsl_plan* p, int i);
 
 }  // namespace qsl

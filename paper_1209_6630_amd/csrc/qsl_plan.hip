@@ -637,6 +637,12 @@ static qsl_status time_plan(qsl_plan* p, hipStream_t st, int reps, double* ms) {
 static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& key, const char* cache_path,
                                const qsl_tuning saved, qsl_tuning* chosen);
 
+qsl_system* plan_system(qsl_plan* p, int i) { return p && i >= 0 && i < p->n_sys ? p->sys[i] : nullptr; }
+const qsl_fwd_args* plan_fwd(const qsl_plan* p, int i) {
+    return p && i >= 0 && i < p->n_sys && p->bound[i] ? &p->fwd[i] : nullptr;
+}
+int64_t plan_walkers(const qsl_plan* p, int i) { return p && i >= 0 && i < p->n_sys ? p->W[i] : -1; }
+
 }  // namespace qsl
 
 extern "C" {

@@ -1,0 +1,210 @@
+"""The Monte Carlo step on the GPU against the FP64 oracle: the local energy
+kernel (Jastrow factor, Coulomb potential, drift) on the oracle's
+determinant quantities and end to end, the drift-diffusion move bit for bit,
+the branching weights, the reconfiguration's selection bit for bit on the
+same seeded weights and deviates, and whole DMC steps through a plan.
+
+Tolerances: the local energy sums O(N^2) FP64 terms in another order than
+the oracle (relative error of a few 1e-16 per term against the sum of the
+absolute values, bounded here by 1e-10 relative to max(|E_L|, |V|)); the
+weights differ only by the exponential's last bit (2 ulp)."""
+import numpy as np
+import pytest
+
+import oracle
+import qsl_synth as q
+from tests.gpu_common import make_gpu_system
+from tests.systems import random_tiny, walkers_near
+
+pytestmark = pytest.mark.gpu
+
+JP = dict(c_ee=1.0, b_ee=1.0, c_en=1.0, b_en=1.0)
+
+
+def _cuda(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return (t if dtype is None else t.to(dtype)).cuda()
+
+
+def _system(name, W):
+    if name == "tiny":
+        sysm, A_up, A_dn = random_tiny(n_atoms=3, n_up=5, n_dn=4, seed=29)
+        R = walkers_near(sysm, W, seed=6)
+        Z = np.array([3.0, 4.0, 2.0])
+    else:
+        sysm, A_up, A_dn, R = q.make_config(name, W=W)
+        Z = q.nuclear_charges(sysm)
+    S = make_gpu_system(sysm, A_up, A_dn)
+    S.set_jastrow(Z, **JP)
+    return sysm, A_up, A_dn, R, Z, S
+
+
+@pytest.mark.parametrize("name,W", [("tiny", 5), ("44e", 16), ("434e", 6)])
+def test_local_energy_kernel_on_oracle_inputs(name, W):
+    """The GPU local energy from the oracle's determinant drift, Laplacian
+    ratio, log|det| and sign equals the oracle's local energy."""
+    print(f"[case] local energy {name} W={W}", flush=True)
+    import torch
+    sysm, A_up, A_dn, R, Z, S = _system(name, W)
+    ref = oracle.forward(sysm, A_up, A_dn, R)
+    J, gJ, lJ, V = oracle.jastrow_potential(sysm, Z, R, **JP)
+    EL, b = oracle.local_energy(ref["drift"], ref["lap"], gJ, lJ, V)
+    out = {"drift": _cuda(ref["drift"]), "lap": _cuda(ref["lap"]), "logdet": _cuda(ref["logdet"]),
+           "sign": _cuda(ref["sign"])}
+    got = S.local_energy(_cuda(R), out)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in got.items()}
+    scale = np.maximum(np.abs(EL), np.abs(V))
+    assert np.all(np.abs(g["EL"] - EL) <= 1e-10 * scale), float((np.abs(g["EL"] - EL) / scale).max())
+    assert np.all(np.abs(g["V"] - V) <= 1e-10 * np.abs(V))
+    assert np.all(np.abs(g["J"] - J) <= 1e-10 * np.maximum(1.0, np.abs(J)))
+    np.testing.assert_allclose(g["drift"], b, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(g["logpsi"], J + ref["logdet"].sum(1), rtol=1e-12)
+    np.testing.assert_array_equal(g["psisign"], ref["sign"].prod(1).astype(np.int8))
+
+
+@pytest.mark.parametrize("name,W", [("44e", 16), ("158e", 8)])
+def test_local_energy_end_to_end_fp64(name, W):
+    """GPU forward (FP64) then GPU local energy, against the oracle's whole
+    chain (the forward bound carried through: 1e-9 relative)."""
+    print(f"[case] local energy end to end {name} W={W}", flush=True)
+    import torch
+    sysm, A_up, A_dn, R, Z, S = _system(name, W)
+    Rt = _cuda(R)
+    out = S.forward(Rt, "fp64")
+    got = S.local_energy(Rt, out)
+    torch.cuda.synchronize()
+    ref = oracle.forward(sysm, A_up, A_dn, R)
+    J, gJ, lJ, V = oracle.jastrow_potential(sysm, Z, R, **JP)
+    EL, b = oracle.local_energy(ref["drift"], ref["lap"], gJ, lJ, V)
+    np.testing.assert_allclose(got["EL"].cpu().numpy(), EL, rtol=1e-9)
+    np.testing.assert_allclose(got["drift"].cpu().numpy(), b, rtol=1e-8, atol=1e-10)
+
+
+def test_drift_diffusion_bit_for_bit():
+    print("[case] drift-diffusion", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import drift_diffuse
+    rng = np.random.default_rng(5)
+    R, b, eta = rng.normal(size=(64, 44, 3)), rng.normal(size=(64, 44, 3)) * 3, rng.normal(size=(64, 44, 3))
+    for tau in (0.01, 0.003, 0.0):
+        got = drift_diffuse(_cuda(R), _cuda(b), _cuda(eta), tau)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), oracle.drift_diffuse(R, b, eta, tau))
+
+
+def test_branch_weights_against_oracle():
+    print("[case] branch weights", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import branch_weights
+    rng = np.random.default_rng(8)
+    W = 4096
+    ELn, ELo = rng.normal(-75.0, 3.0, W), rng.normal(-75.0, 3.0, W)
+    sn = rng.choice([-1, 1], W).astype(np.int8)
+    so = sn.copy()
+    so[::17] *= -1
+    sn[::101] = 0
+    w = branch_weights(_cuda(ELn), _cuda(ELo), _cuda(sn), _cuda(so), -74.0, 0.01)
+    torch.cuda.synchronize()
+    want = oracle.branch_weights(ELn, ELo, sn, so, -74.0, 0.01)
+    got = w.cpu().numpy()
+    np.testing.assert_array_equal(got == 0, want == 0)
+    np.testing.assert_allclose(got, want, rtol=5e-16, atol=0)
+
+
+@pytest.mark.parametrize("W", [1, 7, 4096, 20000])
+def test_reconfiguration_bit_for_bit(W):
+    """Same seeded weights (some zero) and uniforms (some just below 1): the
+    same parents and the same total, bit for bit."""
+    print(f"[case] reconfiguration W={W}", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import reconfigure
+    rng = np.random.default_rng(W)
+    w = rng.exponential(size=W)
+    w[::5] = 0.0
+    if W > 1:
+        w[0] = 0.0
+    u = rng.random(W)
+    u[::13] = 1.0 - 2.0 ** -53
+    idx, s = reconfigure(_cuda(w), _cuda(u))
+    torch.cuda.synchronize()
+    ridx, rs = oracle.reconfigure(w, u)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+    assert float(s.cpu().numpy()[0]) == rs
+    idx0, s0 = reconfigure(_cuda(np.zeros(W)), _cuda(u))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(idx0.cpu().numpy(), np.arange(W))
+
+
+def _oracle_dmc_step(sysm, A_up, A_dn, Z, R, state, eta, u, tau, E_T):
+    Rp = oracle.drift_diffuse(R, state["drift"], eta, tau)
+    ref = oracle.forward(sysm, A_up, A_dn, Rp)
+    J, gJ, lJ, V = oracle.jastrow_potential(sysm, Z, Rp, **JP)
+    EL, b = oracle.local_energy(ref["drift"], ref["lap"], gJ, lJ, V)
+    sg = ref["sign"].prod(1).astype(np.int8)
+    w = oracle.branch_weights(EL, state["EL"], sg, state["psisign"], E_T, tau)
+    idx, s = oracle.reconfigure(w, u)
+    return Rp[idx], {"EL": EL[idx], "drift": b[idx], "psisign": sg[idx]}, idx, s, w
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_dmc_steps_fp64_against_oracle(graph):
+    """Three DMC steps of the 44-electron system (64 walkers, FP64 products)
+    through a plan against the oracle's steps on the same deviates: the
+    parents equal the oracle's wherever the oracle's draw is not within
+    1e-9 of a boundary of the cumulative weights; each side continues from
+    its own population, compared while they agree."""
+    print(f"[case] dmc fp64 graph={graph}", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import DMC
+    sysm, A_up, A_dn, R, Z, S = _system("44e", 64)
+    tau, E_T = 0.01, -60.0
+    dmc = DMC(S, _cuda(R), mode="fp64", tau=tau, E_T=E_T, graph=graph)
+    torch.cuda.synchronize()
+    ref = oracle.forward(sysm, A_up, A_dn, R)
+    J, gJ, lJ, V = oracle.jastrow_potential(sysm, Z, R, **JP)
+    EL, b = oracle.local_energy(ref["drift"], ref["lap"], gJ, lJ, V)
+    state = {"EL": EL, "drift": b, "psisign": ref["sign"].prod(1).astype(np.int8)}
+    np.testing.assert_allclose(dmc.EL.cpu().numpy(), EL, rtol=1e-9)
+    Rc = R
+    for step in range(3):
+        eta, u = q.dmc_randoms(64, sysm.n_up + sysm.n_dn, seed=77, step=step)
+        dmc.step(_cuda(eta), _cuda(u))
+        torch.cuda.synchronize()
+        Rn, nstate, ridx, rs, w = _oracle_dmc_step(sysm, A_up, A_dn, Z, Rc, state, eta, u, tau, E_T)
+        gidx = dmc.idx.cpu().numpy()
+        assert float(dmc.wsum.cpu().numpy()[0]) == pytest.approx(rs, rel=1e-9)
+        cum = np.cumsum(w)
+        near = np.min(np.abs(u[:, None] * rs - cum[None, :]), axis=1) <= 1e-9 * rs
+        assert np.all((gidx == ridx) | near), (step, np.nonzero((gidx != ridx) & ~near))
+        assert np.all(w[gidx] > 0)
+        ok = gidx == ridx
+        np.testing.assert_allclose(dmc.R.cpu().numpy()[ok], Rn[ok], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dmc.EL.cpu().numpy()[ok], nstate["EL"][ok], rtol=1e-9)
+        np.testing.assert_allclose(dmc.drift.cpu().numpy()[ok], nstate["drift"][ok], rtol=1e-8, atol=1e-10)
+        np.testing.assert_array_equal(dmc.psisign.cpu().numpy()[ok], nstate["psisign"][ok])
+        if not ok.all():
+            break  # a draw on a boundary: the two populations part here
+        Rc, state = Rn, nstate
+    dmc.close()
+
+
+def test_dmc_steps_434e_fp32_valid():
+    """The benchmark's configuration in miniature: 434 electrons, FP32
+    products, 256 walkers, two steps: finite energies and drifts, parents
+    with non-zero weight, a positive total weight."""
+    print("[case] dmc 434e fp32", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import DMC
+    sysm, A_up, A_dn, R, Z, S = _system("434e", 256)
+    dmc = DMC(S, _cuda(R), mode="fp32", tau=0.005, E_T=-1300.0, graph=True)
+    for step in range(2):
+        eta, u = q.dmc_randoms(256, sysm.n_up + sysm.n_dn, seed=3, step=step)
+        dmc.step(_cuda(eta), _cuda(u))
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(dmc.EL.cpu().numpy())) and np.all(np.isfinite(dmc.drift.cpu().numpy()))
+    assert float(dmc.wsum.cpu().numpy()[0]) > 0
+    idx = dmc.idx.cpu().numpy()
+    assert idx.min() >= 0 and idx.max() < 256
+    dmc.close()
