@@ -65,6 +65,8 @@ def load():
         lib.orc_branch_weights.argtypes = [ct.c_int64, _dp, _dp, ct.POINTER(ct.c_int8), ct.POINTER(ct.c_int8),
                                            ct.c_double, ct.c_double, _dp]
         lib.orc_reconfigure.argtypes = [ct.c_int64, _dp, _dp, ct.POINTER(ct.c_int64), _dp]
+        lib.orc_multidet.argtypes = [S, _dp, _dp, ct.c_int32, _ip, _dp, ct.c_int32, _dp, _dp,
+                                     ct.POINTER(ct.c_int8), _dp, _dp, _dp, ct.POINTER(ct.c_int8), ct.c_int32]
         _lib = lib
     return _lib
 
@@ -244,3 +246,23 @@ def reconfigure(w, u):
     s = np.zeros(1)
     load().orc_reconfigure(w.size, _p(w), _p(u), _p(idx, ct.POINTER(ct.c_int64)), _p(s))
     return idx, float(s[0])
+
+
+def multidet(sys, A_up_orb, A_dn_orb, occ, coef, R, nthreads=0):
+    """Psi_det = sum_K coef[K] Det_K_up Det_K_dn: log|Psi|[W], sign[W],
+    drift[W,N,3], lap[W,N], and per determinant logdet, sign [n_det,W,2]."""
+    o = _osys(sys)
+    R = np.ascontiguousarray(R, np.float64)
+    W, N = R.shape[0], R.shape[1]
+    Au = np.ascontiguousarray(A_up_orb, np.float64)
+    Ad = np.ascontiguousarray(A_dn_orb, np.float64)
+    occ = np.ascontiguousarray(occ, np.int32)
+    coef = np.ascontiguousarray(coef, np.float64)
+    nd = occ.shape[0]
+    out = dict(logpsi=np.zeros(W), sign=np.zeros(W, np.int8), drift=np.zeros((W, N, 3)), lap=np.zeros((W, N)),
+               det_logdet=np.zeros((nd, W, 2)), det_sign=np.zeros((nd, W, 2), np.int8))
+    i8 = ct.POINTER(ct.c_int8)
+    load().orc_multidet(o.ref, _p(Au), _p(Ad), nd, _p(occ, _ip), _p(coef), W, _p(R), _p(out["logpsi"]),
+                        _p(out["sign"], i8), _p(out["drift"]), _p(out["lap"]), _p(out["det_logdet"]),
+                        _p(out["det_sign"], i8), int(nthreads))
+    return out

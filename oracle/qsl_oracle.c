@@ -732,3 +732,87 @@ void orc_reconfigure(int64_t W, const double* w, const double* u, int64_t* idx, 
     }
     free(cum);
 }
+
+/* ------------------------------------------------------------------ */
+/* Several determinants (the trial wavefunction equation of section    */
+/* "The quantum Monte Carlo method")                                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Psi_det = sum_K c_K Det_K_up Det_K_dn.  Determinant K takes the rows
+ * occ[K][0..n_up) of the spin-up orbital set A_up_orb (n_orb_up x N_b) and
+ * the rows occ[K][n_up..N) of the spin-down one; each is evaluated by the
+ * single-determinant forward above.  Then per walker, with L_K = log|Det_K_up|
+ * + log|Det_K_dn| + log|c_K| and s_K the sign of c_K Det_K_up Det_K_dn:
+ *   m = max_K L_K over the non-zero terms, S = sum_K s_K e^(L_K - m),
+ *   log|Psi_det| = m + log|S|, sign = sign(S),
+ *   drift_e = sum_K w_K drift_K(e), lap_e = sum_K w_K lap_K(e),
+ *   w_K = s_K e^(L_K - m) / S
+ * (grad_e and lap_e of a product of an up and a down determinant act on
+ * the one of electron e's spin).  Outputs det_logdet [n_det][W][2] and
+ * det_sign [n_det][W][2] may be NULL.
+ */
+void orc_multidet(const orc_system* s, const double* A_up_orb, const double* A_dn_orb, int32_t n_det,
+                  const int32_t* occ, const double* coef, int32_t W, const double* R, double* logpsi,
+                  int8_t* sign, double* drift, double* lap, double* det_logdet, int8_t* det_sign,
+                  int32_t nthreads) {
+    const int N = s->n_up + s->n_dn, nb = orc_n_basis(s);
+    const int nu = s->n_up, nd = s->n_dn;
+    double* Au = (double*)malloc(sizeof(double) * ((size_t)nu * nb + 1));
+    double* Ad = (double*)malloc(sizeof(double) * ((size_t)nd * nb + 1));
+    double* L = (double*)malloc(sizeof(double) * (size_t)n_det * W * 2);
+    int8_t* sg = (int8_t*)malloc((size_t)n_det * W * 2);
+    double* dr = (double*)malloc(sizeof(double) * (size_t)n_det * W * N * 3);
+    double* lp = (double*)malloc(sizeof(double) * (size_t)n_det * W * N);
+    double* Cu = (double*)malloc(sizeof(double) * ((size_t)W * 5 * nu * nu + 1));
+    double* Cd = (double*)malloc(sizeof(double) * ((size_t)W * 5 * nd * nd + 1));
+    double* Iu = (double*)malloc(sizeof(double) * ((size_t)W * nu * nu + 1));
+    double* Id = (double*)malloc(sizeof(double) * ((size_t)W * nd * nd + 1));
+    uint32_t* st = (uint32_t*)malloc(sizeof(uint32_t) * (W > 0 ? W : 1));
+    for (int K = 0; K < n_det; ++K) {
+        for (int i = 0; i < nu; ++i)
+            memcpy(Au + (size_t)i * nb, A_up_orb + (size_t)occ[(size_t)K * N + i] * nb, sizeof(double) * nb);
+        for (int i = 0; i < nd; ++i)
+            memcpy(Ad + (size_t)i * nb, A_dn_orb + (size_t)occ[(size_t)K * N + nu + i] * nb, sizeof(double) * nb);
+        orc_forward(s, Au, Ad, W, R, Cu, Cd, NULL, NULL, L + (size_t)K * W * 2, sg + (size_t)K * W * 2, Iu, Id,
+                    dr + (size_t)K * W * N * 3, lp + (size_t)K * W * N, st, nthreads);
+    }
+    for (int w = 0; w < W; ++w) {
+        double m = -INFINITY;
+        for (int K = 0; K < n_det; ++K) {
+            int sK = sg[((size_t)K * W + w) * 2] * sg[((size_t)K * W + w) * 2 + 1];
+            if (sK == 0 || coef[K] == 0.0) continue;
+            double LK = L[((size_t)K * W + w) * 2] + L[((size_t)K * W + w) * 2 + 1] + log(fabs(coef[K]));
+            if (LK > m) m = LK;
+        }
+        double S = 0.0;
+        for (int K = 0; K < n_det; ++K) {
+            int sK = sg[((size_t)K * W + w) * 2] * sg[((size_t)K * W + w) * 2 + 1];
+            if (sK == 0 || coef[K] == 0.0) continue;
+            if (coef[K] < 0) sK = -sK;
+            double LK = L[((size_t)K * W + w) * 2] + L[((size_t)K * W + w) * 2 + 1] + log(fabs(coef[K]));
+            S += sK * exp(LK - m);
+        }
+        logpsi[w] = S != 0.0 ? m + log(fabs(S)) : -INFINITY;
+        sign[w] = S > 0 ? 1 : (S < 0 ? -1 : 0);
+        for (int e = 0; e < N; ++e) {
+            double g[3] = {0, 0, 0}, l = 0.0;
+            for (int K = 0; K < n_det && S != 0.0; ++K) {
+                int sK = sg[((size_t)K * W + w) * 2] * sg[((size_t)K * W + w) * 2 + 1];
+                if (sK == 0 || coef[K] == 0.0) continue;
+                if (coef[K] < 0) sK = -sK;
+                double LK = L[((size_t)K * W + w) * 2] + L[((size_t)K * W + w) * 2 + 1] + log(fabs(coef[K]));
+                double wK = sK * exp(LK - m) / S;
+                size_t r = ((size_t)K * W + w) * N + e;
+                for (int k = 0; k < 3; ++k) g[k] += wK * dr[3 * r + k];
+                l += wK * lp[r];
+            }
+            if (S == 0.0) g[0] = g[1] = g[2] = l = NAN;
+            if (drift) for (int k = 0; k < 3; ++k) drift[((size_t)w * N + e) * 3 + k] = g[k];
+            if (lap) lap[(size_t)w * N + e] = l;
+        }
+    }
+    if (det_logdet) memcpy(det_logdet, L, sizeof(double) * (size_t)n_det * W * 2);
+    if (det_sign) memcpy(det_sign, sg, (size_t)n_det * W * 2);
+    free(Au); free(Ad); free(L); free(sg); free(dr); free(lp); free(Cu); free(Cd); free(Iu); free(Id); free(st);
+}
