@@ -319,6 +319,61 @@ qsl_status qsl_plan_destroy(qsl_plan* plan);
  */
 qsl_status qsl_autotune(qsl_plan* plan, const char* cache_path, void* stream, qsl_tuning* chosen);
 
+/* ------------------------------------------------------- determinants
+ *
+ * Psi_det = sum_K c_K Det_K_up Det_K_dn (the trial wavefunction equation of
+ * section "The quantum Monte Carlo method"): every determinant takes n_s of
+ * the n_orb >= n_s orbitals of an orbital set per spin.
+ */
+
+/*
+ * Orbital set of spin s: A is n_orb x N_b (n_orb >= the spin's electrons),
+ * row-major with leading dimension ld, host (on_device = 0) or device memory.
+ * It replaces the MO coefficients of that spin; qsl_forward, qsl_backward
+ * and plans need n_orb equal to the spin's electrons again (qsl_set_mo) and
+ * report SHAPE otherwise.  May reallocate the library's MO copies (it then
+ * synchronises `stream`; plans of the system rebuild their work lists at
+ * their next launch).  Errors: INVALID_ARG, OOM, HIP.
+ */
+qsl_status qsl_set_orbitals(qsl_system* sys, int32_t spin, const double* A, int32_t n_orb, int64_t ld,
+                            int32_t on_device, void* stream);
+
+typedef struct {
+    int64_t W;
+    const double* R;          /* [W][N][3] device                                      */
+    int32_t mode;             /* qsl_mode of the products                               */
+    int32_t n_det;            /* >= 1                                                   */
+    const int32_t* occ;       /* host [n_det][n_up + n_dn]: orbital indices of each
+                                 determinant, its n_up spin-up orbitals then its n_dn
+                                 spin-down ones (rows of the spin's orbital set)      */
+    const double* coef;       /* host [n_det]: c_K                                      */
+    double* logpsi;           /* [W] log|Psi_det| (-inf where it vanishes)              */
+    int8_t* sign;             /* [W] sign of Psi_det                                    */
+    double* drift;            /* [W][N][3] grad Psi_det / Psi_det (may be NULL)         */
+    double* lap;              /* [W][N]    lap_e Psi_det / Psi_det (may be NULL)        */
+    uint32_t* status;         /* [W] QSL_STATUS_* bits (may be NULL)                    */
+    double* det_logdet;       /* [n_det][W][2] per determinant and spin (may be NULL)  */
+    int8_t* det_sign;         /* [n_det][W][2] (may be NULL)                            */
+    void* ws;                 /* device workspace of qsl_multidet_workspace_size        */
+    size_t ws_bytes;
+} qsl_multidet_args;
+
+qsl_status qsl_multidet_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, int32_t n_det, size_t* bytes);
+
+/*
+ * The products of the whole orbital set once per spin (equation (abc)),
+ * then for each determinant: its columns of C gathered, the FP64
+ * Gauss-Jordan log|det|, sign and inverse, its drift and Laplacian ratio;
+ * then per walker the max-shifted combination
+ *   log|Psi_det| = m + log|S|, S = sum_K sign_K e^(log|c_K Det_K| - m),
+ *   drift_e = sum_K w_K drift_K(e), lap_e = sum_K w_K lap_K(e),
+ *   w_K = c_K Det_K_up Det_K_dn / Psi_det.
+ * Uploads occ and coef with asynchronous copies from host memory (not for
+ * graph capture).  Errors: INVALID_ARG (NULL, orbital index out of range,
+ * non-finite c_K, orbitals never set), UNSUPPORTED, WORKSPACE, HIP.
+ */
+qsl_status qsl_multidet_forward(qsl_system* sys, const qsl_multidet_args* args, void* stream);
+
 /* ------------------------------------------------------------- QMC step
  *
  * One fixed-node diffusion Monte Carlo step around the Slater part (section

@@ -59,6 +59,13 @@ class DmcArgs(ct.Structure):
                 ("wsum", ct.c_void_p), ("ws", ct.c_void_p), ("ws_bytes", ct.c_size_t)]
 
 
+class MultidetArgs(ct.Structure):
+    _fields_ = [("W", ct.c_int64), ("R", ct.c_void_p), ("mode", ct.c_int32), ("n_det", ct.c_int32),
+                ("occ", ct.POINTER(ct.c_int32)), ("coef", ct.POINTER(ct.c_double)), ("logpsi", ct.c_void_p),
+                ("sign", ct.c_void_p), ("drift", ct.c_void_p), ("lap", ct.c_void_p), ("status", ct.c_void_p),
+                ("det_logdet", ct.c_void_p), ("det_sign", ct.c_void_p), ("ws", ct.c_void_p), ("ws_bytes", ct.c_size_t)]
+
+
 PLAN_GRAPH = 1
 WS_FORWARD, WS_BACKWARD, WS_BOTH = 1, 2, 3
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -89,6 +96,11 @@ SIGNATURES = {
     "qsl_autotune": (ct.c_int, [ct.c_void_p, ct.c_char_p, ct.c_void_p, ct.POINTER(Tuning)]),
     "qsl_profile_enable": (ct.c_int, [ct.c_int32]),
     "qsl_profile_read": (ct.c_int, [ct.POINTER(KernelTime), ct.c_int32, ct.POINTER(ct.c_int32), ct.c_int32]),
+    "qsl_set_orbitals": (ct.c_int, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_int32,
+                                    ct.c_void_p]),
+    "qsl_multidet_workspace_size": (ct.c_int, [ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32,
+                                               ct.POINTER(ct.c_size_t)]),
+    "qsl_multidet_forward": (ct.c_int, [ct.c_void_p, ct.POINTER(MultidetArgs), ct.c_void_p]),
     "qsl_set_jastrow": (ct.c_int, [ct.c_void_p, ct.POINTER(ct.c_double), ct.c_double, ct.c_double, ct.c_double,
                                    ct.c_double]),
     "qsl_local_energy": (ct.c_int, [ct.c_void_p, ct.POINTER(LocalArgs), ct.c_void_p]),

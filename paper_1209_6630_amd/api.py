@@ -11,7 +11,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import BwdArgs, DmcArgs, FwdArgs, LocalArgs, MODES, PLAN_GRAPH, SystemDesc, Tuning, check, lib
+from ._lib import (BwdArgs, DmcArgs, FwdArgs, LocalArgs, MODES, MultidetArgs, PLAN_GRAPH, SystemDesc, Tuning, check,
+                   lib)
 
 
 def _ptr(t):
@@ -92,6 +93,40 @@ class System:
         else:
             a = np.ascontiguousarray(np.asarray(A, np.float64))
             check(lib().qsl_set_mo(self._h, spin, ct.c_void_p(a.ctypes.data), a.shape[1], 0, _stream()))
+
+    def set_orbitals(self, spin, A):
+        """Orbital set of a spin for several determinants: A [n_orb, N_basis]
+        float64 host array, n_orb >= the spin's electrons."""
+        a = np.ascontiguousarray(np.asarray(A, np.float64))
+        check(lib().qsl_set_orbitals(self._h, spin, ct.c_void_p(a.ctypes.data), a.shape[0], a.shape[1], 0,
+                                     _stream()))
+
+    def multidet_forward(self, R, occ, coef, mode="fp64"):
+        """Psi_det = sum_K coef[K] Det_K_up Det_K_dn with occ [n_det, n_up +
+        n_dn] orbital indices (up then down).  Returns a dict of CUDA
+        tensors: logpsi, sign, drift, lap, status, det_logdet, det_sign."""
+        occ = np.ascontiguousarray(occ, np.int32)
+        coef = np.ascontiguousarray(coef, np.float64)
+        W, N, nd = R.shape[0], self.n_elec, occ.shape[0]
+        dev = R.device
+        out = dict(logpsi=torch.empty(W, dtype=torch.float64, device=dev),
+                   sign=torch.empty(W, dtype=torch.int8, device=dev),
+                   drift=torch.empty((W, N, 3), dtype=torch.float64, device=dev),
+                   lap=torch.empty((W, N), dtype=torch.float64, device=dev),
+                   status=torch.empty(W, dtype=torch.int32, device=dev),
+                   det_logdet=torch.empty((nd, W, 2), dtype=torch.float64, device=dev),
+                   det_sign=torch.empty((nd, W, 2), dtype=torch.int8, device=dev))
+        n = ct.c_size_t()
+        check(lib().qsl_multidet_workspace_size(self._h, W, mode_id(mode), nd, ct.byref(n)))
+        ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+        a = MultidetArgs(W, R.data_ptr(), mode_id(mode), nd, occ.ctypes.data_as(ct.POINTER(ct.c_int32)),
+                         coef.ctypes.data_as(ct.POINTER(ct.c_double)), out["logpsi"].data_ptr(),
+                         out["sign"].data_ptr(), out["drift"].data_ptr(), out["lap"].data_ptr(),
+                         out["status"].data_ptr(), out["det_logdet"].data_ptr(), out["det_sign"].data_ptr(),
+                         ws.data_ptr(), ws.numel())
+        check(lib().qsl_multidet_forward(self._h, ct.byref(a), _stream()))
+        out["_ws"] = ws
+        return out
 
     def set_jastrow(self, Z, c_ee=1.0, b_ee=1.0, c_en=1.0, b_en=1.0):
         """Nuclear charges Z[n_atoms] and the Jastrow parameters (see

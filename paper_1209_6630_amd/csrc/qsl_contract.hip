@@ -110,7 +110,9 @@ __device__ __forceinline__ void slot_values(const SlotRec& r, double T_thr, cons
 
 __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) {
     const DevSys& s = j.s;
-    const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
+    // n electrons of the spin (rows of a tile's C), nmo MOs (columns; n for
+    // a Slater matrix, more for the orbital set of several determinants)
+    const int spin = j.spin, n = j.n, nmo = j.mo.n, ldn = j.mo.ldn;
     const int64_t W = j.W;
     const double* __restrict__ R = j.R;
     const float* __restrict__ AT32 = j.mo.AT32;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
     if (tid == 0) s_tail = 0;
     const int nwin = j.nwin[tile];
     const int* __restrict__ wins = j.win + (size_t)tile * s.n_win;
-    const int nsub = min(MSUB, (n - n0 + NSB - 1) / NSB);
+    const int nsub = min(MSUB, (nmo - n0 + NSB - 1) / NSB);
     f32x16 acc[MSUB][5];
 #pragma unroll
     for (int sb = 0; sb < MSUB; ++sb)
@@ -268,7 +270,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
-                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
+                    if (n0 + sb * NSB + wave * 32 >= nmo) continue;  // this wave's 32 MOs are all padding
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -295,13 +297,13 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
 #pragma unroll
     for (int sb = 0; sb < MSUB; ++sb) {
         const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
-        if (mo < n) {
+        if (mo < nmo) {
 #pragma unroll
             for (int d = 0; d < 5; ++d)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc[sb][d][r];
+                    if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo] = acc[sb][d][r];
                 }
         }
     }
@@ -313,7 +315,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         contract_f32_body(j, bx, by);
     } else {
     const DevSys& s = j.s;
-    const int spin = j.spin, n = j.n, ldn = j.mo.ldn;
+    const int spin = j.spin, n = j.n, nmo = j.mo.n, ldn = j.mo.ldn;
     const int64_t W = j.W;
     const double* __restrict__ R = j.R;
     const int* __restrict__ tile_nwin = j.nwin;
@@ -355,7 +357,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const int* wins = tile_win + (size_t)tile * s.n_win;
 
     constexpr int MSUB = P::MSUB, NSB = P::NSB;
-    const int nsub = min(MSUB, (n - n0 + NSB - 1) / NSB);  // sub-blocks below n (uniform)
+    const int nsub = min(MSUB, (nmo - n0 + NSB - 1) / NSB);  // sub-blocks below nmo (uniform)
     f32x16 acc32[MSUB][5];
     f64x4 acc64[MSUB][5][2];
 #pragma unroll
@@ -482,7 +484,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
-                    if (n0 + sb * NSB + wave * 32 >= n) continue;  // this wave's 32 MOs are all padding
+                    if (n0 + sb * NSB + wave * 32 >= nmo) continue;  // this wave's 32 MOs are all padding
                     const bf16x8 bah = cah[sb], bal = cal[sb];
                     // the three products of one accumulator are dependent:
                     // issue them five accumulators apart
@@ -528,23 +530,23 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
         if constexpr (MODE == QSL_FP64) {
             double* C = (double*)Cout;
             const int mo = n0 + sb * NSB + wave * 16 + (lane & 15);
-            if (mo < n) {
+            if (mo < nmo) {
                 for (int d = 0; d < 5; ++d)
                     for (int h = 0; h < 2; ++h)
                         for (int r = 0; r < 4; ++r) {
                             // v_mfma_f64_16x16x4f64 result: row (lane / 16) + 4 r, column lane % 16
                             const int el = h * 16 + (lane >> 4) + 4 * r;
-                            if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc64[sb][d][h][r];
+                            if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo] = acc64[sb][d][h][r];
                         }
             }
         } else {
             float* C = (float*)Cout;
             const int mo = n0 + sb * NSB + wave * 32 + (lane & 31);
-            if (mo < n) {
+            if (mo < nmo) {
                 for (int d = 0; d < 5; ++d)
                     for (int r = 0; r < 16; ++r) {
                         const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                        if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * n + mo] = acc32[sb][d][r];
+                        if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo] = acc32[sb][d][r];
                     }
             }
         }
@@ -571,7 +573,7 @@ __global__ __launch_bounds__(CT_WAVES * 64, MODE == QSL_FP32 ? F32_MINB : 2) voi
 void contract_grid(Job& j) {
     const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : (j.mode == QSL_FP32 ? F32_NB : CT<QSL_BF16X3>::NB);
     j.gx = (int)electron_tiles(j.n, j.W);
-    j.gy = (j.n + nb - 1) / nb;
+    j.gy = (j.mo.n + nb - 1) / nb;  // MO blocks (n for a Slater matrix)
     j.gz = 1;
 }
 

@@ -513,6 +513,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             m.A64 = (double*)(b + o_mo[sp][6]);
             m.A32 = (float*)(b + o_mo[sp][7]);
             m.set = (m.n == 0);
+            S->mo_cap[sp] = ldn[sp];
         }
         *out = S;
         return QSL_OK;
@@ -527,6 +528,8 @@ qsl_status qsl_system_destroy(qsl_system* sys) {
     if (!sys) return QSL_OK;
     if (sys->dev_block) hipFree(sys->dev_block);
     if (sys->atom_Z) hipFree(sys->atom_Z);
+    for (int sp = 0; sp < 2; ++sp)
+        if (sys->mo_block[sp]) hipFree(sys->mo_block[sp]);
     delete sys;
     return QSL_OK;
 }
@@ -545,14 +548,49 @@ qsl_status qsl_ao_info(const qsl_system* sys, int32_t* ao_atom, int32_t* ao_shel
     return QSL_OK;
 }
 
-qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld, int32_t on_device,
-                      void* stream) {
-    if (!sys) return bad(QSL_ERR_INVALID_ARG, "NULL system");
-    if (spin != 0 && spin != 1) return bad(QSL_ERR_INVALID_ARG, "spin must be 0 or 1");
+}  // extern "C"
+
+namespace qsl {
+
+// Copies of n_rows MO coefficient rows of one spin: in the system's own
+// tables when they hold round_up(n_rows, 128) rows, else in a separate
+// allocation (an orbital set larger than the spin's electrons).
+static qsl_status set_mo_rows(qsl_system* sys, int32_t spin, const double* A, int n_rows, int64_t ld,
+                              int32_t on_device, void* stream) {
     DevMO& m = sys->mo[spin];
-    if (m.n == 0) return QSL_OK;
-    if (!A) return bad(QSL_ERR_INVALID_ARG, "NULL A");
-    if (ld < sys->d.n_basis) return bad(QSL_ERR_INVALID_ARG, "ld < N_basis");
+    const int need = (int)round_up((size_t)n_rows, 128);
+    if (need > sys->mo_cap[spin]) {
+        const size_t cells = (size_t)sys->d.n_slots * need;
+        // FP64, FP32, four bf16 and the [ldn][slot] FP64 / FP32 copies
+        const size_t o32 = round_up(cells * 8, 256), o16 = o32 + round_up(cells * 4, 256),
+                     oa64 = o16 + 4 * round_up(cells * 2, 256), oa32 = oa64 + round_up(cells * 8, 256),
+                     total = oa32 + round_up(cells * 4, 256);
+        void* blk = nullptr;
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);  // earlier calls may still read the old copies
+        if (e != hipSuccess) return hip_fail(e, "orbitals: synchronize");
+        if ((e = hipMalloc(&blk, total)) != hipSuccess) return bad(QSL_ERR_OOM, "orbitals: allocation of MO copies");
+        if (sys->mo_block[spin]) hipFree(sys->mo_block[spin]);
+        sys->mo_block[spin] = blk;
+        char* b = (char*)blk;
+        m.AT64 = (double*)b;
+        m.AT32 = (float*)(b + o32);
+        m.Ahi = (uint16_t*)(b + o16);
+        m.Alo = (uint16_t*)(b + o16 + round_up(cells * 2, 256));
+        m.AThi = (uint16_t*)(b + o16 + 2 * round_up(cells * 2, 256));
+        m.ATlo = (uint16_t*)(b + o16 + 3 * round_up(cells * 2, 256));
+        m.A64 = (double*)(b + oa64);
+        m.A32 = (float*)(b + oa32);
+        sys->mo_cap[spin] = need;
+        ++sys->mo_generation;
+    }
+    if (m.n != n_rows || m.ldn != need) ++sys->mo_generation;
+    m.n = n_rows;
+    m.ldn = need;
+    m.set = false;
+    if (n_rows == 0) {
+        m.set = true;
+        return QSL_OK;
+    }
     hipStream_t st = (hipStream_t)stream;
     const double* src = A;
     double* tmp = nullptr;
@@ -574,6 +612,31 @@ qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld
     }
     m.set = true;
     return QSL_OK;
+}
+
+}  // namespace qsl
+
+extern "C" {
+
+qsl_status qsl_set_mo(qsl_system* sys, int32_t spin, const double* A, int64_t ld, int32_t on_device,
+                      void* stream) {
+    if (!sys) return bad(QSL_ERR_INVALID_ARG, "NULL system");
+    if (spin != 0 && spin != 1) return bad(QSL_ERR_INVALID_ARG, "spin must be 0 or 1");
+    const int n = n_spin(sys->d, spin);
+    if (n == 0) return set_mo_rows(sys, spin, A, 0, ld, on_device, stream);
+    if (!A) return bad(QSL_ERR_INVALID_ARG, "NULL A");
+    if (ld < sys->d.n_basis) return bad(QSL_ERR_INVALID_ARG, "ld < N_basis");
+    return set_mo_rows(sys, spin, A, n, ld, on_device, stream);
+}
+
+qsl_status qsl_set_orbitals(qsl_system* sys, int32_t spin, const double* A, int32_t n_orb, int64_t ld,
+                            int32_t on_device, void* stream) {
+    if (!sys) return bad(QSL_ERR_INVALID_ARG, "NULL system");
+    if (spin != 0 && spin != 1) return bad(QSL_ERR_INVALID_ARG, "spin must be 0 or 1");
+    if (n_orb < n_spin(sys->d, spin)) return bad(QSL_ERR_INVALID_ARG, "n_orb below the spin's electron count");
+    if (n_orb > 0 && !A) return bad(QSL_ERR_INVALID_ARG, "NULL A");
+    if (ld < sys->d.n_basis) return bad(QSL_ERR_INVALID_ARG, "ld < N_basis");
+    return set_mo_rows(sys, spin, A, n_orb, ld, on_device, stream);
 }
 
 qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, int32_t what, size_t* bytes) {
@@ -602,6 +665,9 @@ static qsl_status forward_check(qsl_system* sys, const qsl_fwd_args* a) {
         int n = n_spin(d, s);
         if (!n) continue;
         if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
+        if (sys->mo[s].n != n)
+            return bad(QSL_ERR_SHAPE, "the MO set of a spin has more rows than electrons (qsl_set_orbitals): "
+                                      "use qsl_multidet_forward");
         if (!a->C[s] || !a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "C and Dinv outputs are required");
         if (n > GJ_NMAX) return bad(QSL_ERR_UNSUPPORTED, "more electrons of one spin than the inversion supports");
     }
@@ -711,6 +777,8 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
     for (int s = 0; s < 2; ++s) {
         if (!n_spin(d, s)) continue;
         if (!sys->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "MO coefficients of a spin were never set");
+        if (sys->mo[s].n != n_spin(d, s))
+            return bad(QSL_ERR_SHAPE, "the MO set of a spin has more rows than electrons (qsl_set_orbitals)");
         if (!a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "NULL Dinv");
     }
     WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);

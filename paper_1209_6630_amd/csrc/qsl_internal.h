@@ -121,6 +121,11 @@ struct qsl_system {
     std::vector<int> ao_atom, ao_shell;
     std::vector<int8_t> ao_nxyz;
     std::vector<int> slot_ao;
+    // MO copies per spin: capacity (padded rows) and a separate allocation
+    // when an orbital set larger than the spin's electrons was set
+    int mo_cap[2] = {0, 0};
+    void* mo_block[2] = {nullptr, nullptr};
+    int64_t mo_generation = 0;  // raised when the MO copies move or change shape (plans rebuild their Jobs)
     // Jastrow factor and nuclear charges (qsl_set_jastrow)
     bool jastrow_set = false;
     double* atom_Z = nullptr;  // device [n_atoms]

@@ -69,6 +69,7 @@ struct qsl_plan {
     void* lists = nullptr;
     size_t lists_cap = 0;
     bool dirty = true;
+    std::vector<int64_t> mo_gen;  // the systems' MO generations the Jobs were built from
     // graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -102,8 +103,14 @@ static void set_prefix(PhaseList& L) {
 
 // Workspace, Jobs and device work lists for the current bindings and tuning.
 static qsl_status prepare(qsl_plan* p, hipStream_t st) {
-    for (int i = 0; i < p->n_sys; ++i)
+    for (int i = 0; i < p->n_sys; ++i) {
         if (!p->bound[i]) return bad(QSL_ERR_INVALID_ARG, "plan: system " + std::to_string(i) + " was never bound");
+        for (int s = 0; s < 2; ++s)
+            if (p->sys[i]->mo[s].n != n_spin(p->sys[i]->d, s))
+                return bad(QSL_ERR_SHAPE, "plan: the MO set of a spin has more rows than electrons");
+    }
+    p->mo_gen.resize(p->n_sys);
+    for (int i = 0; i < p->n_sys; ++i) p->mo_gen[i] = p->sys[i]->mo_generation;
     hipError_t e;
     // nothing of an earlier launch may still read the buffers replaced here
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "plan: stream synchronize");
@@ -422,6 +429,8 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
 
 static qsl_status launch_plan(qsl_plan* p, hipStream_t st) {
     hipError_t e;
+    for (int i = 0; i < p->n_sys && !p->dirty; ++i)
+        if (i >= (int)p->mo_gen.size() || p->mo_gen[i] != p->sys[i]->mo_generation) p->dirty = true;
     if (p->dirty) {
         qsl_status r = prepare(p, st);
         if (r != QSL_OK) return r;
@@ -685,6 +694,8 @@ qsl_status qsl_plan_bind(qsl_plan* p, int32_t i, const qsl_fwd_args* f, const qs
     for (int s = 0; s < 2; ++s) {
         if (!n_spin(d, s) || !f->W) continue;
         if (!p->sys[i]->mo[s].set) return bad(QSL_ERR_INVALID_ARG, "plan bind: MO coefficients of a spin never set");
+        if (p->sys[i]->mo[s].n != n_spin(d, s))
+            return bad(QSL_ERR_SHAPE, "plan bind: the MO set of a spin has more rows than electrons");
         if (!f->C[s] || !f->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "plan bind: C and Dinv outputs are required");
     }
     if (b) {
