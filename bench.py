@@ -355,6 +355,49 @@ def dmc_line(config, W, mode, steps, warmup=2, tau=0.005):
                        "beta-strand (other basis and molecule)"}
 
 
+def sparse_a_line(config, W, radii, steps=3):
+    """The paper's dense-versus-sparse A question on MFMA: FP32 contraction
+    time of the same walkers with dense MO coefficients and with localised
+    ones (zero beyond a radius of each MO's centre, block-sparse along the
+    chain) whose all-zero 32-MO blocks the products skip; forward-only plan,
+    eager launches with kernel timing."""
+    import torch
+    import qsl_synth as q
+    from paper_1209_6630_amd import _lib
+    from paper_1209_6630_amd.api import Plan, System
+    sysm, A_up, A_dn, R_np = q.make_config(config, W=W)
+    S = System.from_synth(sysm)
+    R = torch.from_numpy(R_np).cuda()
+    out = S.alloc_outputs(W, "fp32")
+    rows = []
+    for rad in [None] + list(radii):
+        au, ad = (A_up, A_dn) if rad is None else q.localize_mos(sysm, A_up, A_dn, rad)
+        S.set_mo(0, au)
+        S.set_mo(1, ad)
+        P = Plan([S], [W], "fp32", graph=False)
+        P.bind(0, R, out)
+        P.launch()
+        torch.cuda.synchronize()
+        _lib.profile_enable(True)
+        _lib.profile_read(reset=True)
+        for _ in range(steps):
+            P.launch()
+        torch.cuda.synchronize()
+        prof = _lib.profile_read(reset=True)
+        _lib.profile_enable(False)
+        P.close()
+        n = sysm.n_up
+        blk = np.mean([(au[b:b + 32] != 0).any(0) for b in range(0, n, 32)])
+        rows.append({"radius_bohr": rad, "element_density": float((au != 0).mean()),
+                     "block_density_32mo": float(blk),
+                     "contract_fp32_ms": prof["contract_fp32"][1] / steps,
+                     "gauss_jordan_ms": prof["gauss_jordan"][1] / steps})
+    S.close()
+    return {"workload": f"sparse-A-{config}-W{W}-fp32-forward", "rows": rows,
+            "note": "radius None: dense A; the products skip MFMA groups whose 32-MO block has no non-zero "
+                    "coefficient on the group's eight slots"}
+
+
 def roofline_of(kernels, kinds, workload):
     """The dominant kernel's roofline entry (algorithmic work over its
     average launch time, against its peak)."""
@@ -481,6 +524,11 @@ def main():
                            label="batch-44e+158e+434e-W512x3-fp32-fwd+adjoint")
         wlb.close()
         del wlb
+        torch.cuda.empty_cache()
+        # dense versus localised (block-sparse) MO coefficients
+        log("sparse A sweep")
+        also.append(sparse_a_line("1731e", q.CONFIGS["1731e"]["W"], (25.0, 15.0, 10.0)))
+        also.append(sparse_a_line(args.config, W, (15.0, 10.0)))
         torch.cuda.empty_cache()
         # one fixed-node DMC step around the builder, the whole population
         log(f"dmc step {args.config} W={W} mode={mode}")

@@ -124,6 +124,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
     __shared__ __attribute__((aligned(16))) float B[5 * TE * LD];
     __shared__ __attribute__((aligned(16))) int ring[F32_RING];
     __shared__ __attribute__((aligned(16))) int ringo[F32_RING];  // slot * ldn: the slot's coefficient row
+    __shared__ __attribute__((aligned(16))) uint64_t ringm[F32_RING];  // the slot's MO-block mask
     __shared__ uint32_t wmask[F32_BATCH];
     __shared__ int s_tail;
 
@@ -204,6 +205,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
                     const int sl = q * WIN + __builtin_ctz(mm);
                     ring[pos & (F32_RING - 1)] = sl;
                     ringo[pos & (F32_RING - 1)] = sl * ldn;
+                    ringm[pos & (F32_RING - 1)] = j.mo.blkmask[sl];
                     ++pos;
                 }
                 if (lane == F32_BATCH - 1) s_tail = tail + x;
@@ -267,10 +269,22 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
 #pragma unroll
                 for (int d = 0; d < 5; ++d)
                     a[d] = *(const f32x4*)&B[(d * TE + (lane & 31)) * LD + h * 32 + 4 * u];
+                // the group's eight slots (four per half-wave): the MO blocks
+                // with a non-zero coefficient on any of them (a block with
+                // none adds exact zeros, so its MFMAs are skipped: localised
+                // MOs give block-sparse A)
+                uint64_t gm = 0;
+                {
+                    const int pos = head + h * 32 + 4 * u;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) gm |= pos + t < tail ? ringm[(pos + t) & (F32_RING - 1)] : 0ull;
+                }
 #pragma unroll
                 for (int sb = 0; sb < MSUB; ++sb) {
                     if (sb >= nsub) break;
-                    if (n0 + sb * NSB + wave * 32 >= nmo) continue;  // this wave's 32 MOs are all padding
+                    const int mb0 = n0 + sb * NSB + wave * 32;
+                    if (mb0 >= nmo) continue;  // this wave's 32 MOs are all padding
+                    if (__ballot((gm >> ((mb0 >> 5) & 63)) & 1ull) == 0ull) continue;
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
 #pragma unroll

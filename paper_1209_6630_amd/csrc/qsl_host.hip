@@ -464,7 +464,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         size_t o_wrec = ar.add(win_rec.data(), sizeof(WinRec) * win_rec.size());
         size_t o_srec = ar.add(slot_rec.data(), sizeof(SlotRec) * slot_rec.size());
         // MO copies per spin
-        size_t o_mo[2][8];
+        size_t o_mo[2][9];
         int ldn[2];
         for (int sp = 0; sp < 2; ++sp) {
             int n = sp ? d->n_dn : d->n_up;
@@ -475,6 +475,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             for (int k = 2; k < 6; ++k) o_mo[sp][k] = ar.reserve(cells * 2);
             o_mo[sp][6] = ar.reserve(cells * 8);
             o_mo[sp][7] = ar.reserve(cells * 4);
+            o_mo[sp][8] = ar.reserve((size_t)n_slots * 8);
         }
         void* blk = nullptr;
         hipError_t e = hipMalloc(&blk, ar.buf.size());
@@ -512,6 +513,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             m.ATlo = (uint16_t*)(b + o_mo[sp][5]);
             m.A64 = (double*)(b + o_mo[sp][6]);
             m.A32 = (float*)(b + o_mo[sp][7]);
+            m.blkmask = (uint64_t*)(b + o_mo[sp][8]);
             m.set = (m.n == 0);
             S->mo_cap[sp] = ldn[sp];
         }
@@ -564,7 +566,8 @@ static qsl_status set_mo_rows(qsl_system* sys, int32_t spin, const double* A, in
         // FP64, FP32, four bf16 and the [ldn][slot] FP64 / FP32 copies
         const size_t o32 = round_up(cells * 8, 256), o16 = o32 + round_up(cells * 4, 256),
                      oa64 = o16 + 4 * round_up(cells * 2, 256), oa32 = oa64 + round_up(cells * 8, 256),
-                     total = oa32 + round_up(cells * 4, 256);
+                     omask = oa32 + round_up(cells * 4, 256),
+                     total = omask + round_up((size_t)sys->d.n_slots * 8, 256);
         void* blk = nullptr;
         hipError_t e = hipStreamSynchronize((hipStream_t)stream);  // earlier calls may still read the old copies
         if (e != hipSuccess) return hip_fail(e, "orbitals: synchronize");
@@ -580,6 +583,7 @@ static qsl_status set_mo_rows(qsl_system* sys, int32_t spin, const double* A, in
         m.ATlo = (uint16_t*)(b + o16 + 3 * round_up(cells * 2, 256));
         m.A64 = (double*)(b + oa64);
         m.A32 = (float*)(b + oa32);
+        m.blkmask = (uint64_t*)(b + omask);
         sys->mo_cap[spin] = need;
         ++sys->mo_generation;
     }

@@ -107,6 +107,9 @@ struct DevMO {
     uint16_t* ATlo = nullptr;
     double* A64 = nullptr;      // [ldn][n_slots]
     float* A32 = nullptr;       // [ldn][n_slots]
+    // [n_slots]: bit b set when some MO of block [32 b, 32 b + 32) has a
+    // non-zero coefficient on the slot (all bits set past 64 blocks)
+    uint64_t* blkmask = nullptr;
 };
 
 }  // namespace qsl

@@ -36,12 +36,31 @@ __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restri
     }
 }
 
+// Block occupancy of the FP32 copy: one wavefront per slot, lane l tests
+// the MOs l, l + 64, ...; bit b of the slot's mask is set when a non-zero
+// coefficient lies in MO block b (32 MOs).  With more than 64 blocks every
+// bit is set (no block is skipped).
+__global__ void mo_mask_kernel(int n_slots, int n, int ldn, const float* __restrict__ AT32,
+                               uint64_t* __restrict__ mask) {
+    const int slot = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (slot >= n_slots) return;
+    const int nblk = (n + 31) / 32;
+    uint64_t m = 0;
+    for (int mo = lane; mo < n; mo += 64)
+        if (AT32[(size_t)slot * ldn + mo] != 0.f) m |= 1ull << (mo >> 5);
+    for (int o = 32; o >= 1; o >>= 1) m |= __shfl_xor(m, o);
+    if (lane == 0) mask[slot] = nblk > 64 ? ~0ull : m;
+}
+
 hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A, int64_t ld, hipStream_t st) {
     const int64_t total = (int64_t)s.n_slots * mo.ldn;
     if (!total) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
     build_mo_kernel<<<blocks, 256, 0, st>>>(s, mo.n, mo.ldn, A, ld, mo.AT64, mo.AT32, mo.Ahi, mo.Alo, mo.AThi,
                                             mo.ATlo, mo.A64, mo.A32);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    mo_mask_kernel<<<(s.n_slots + 3) / 4, 256, 0, st>>>(s.n_slots, mo.n, mo.ldn, mo.AT32, mo.blkmask);
     return hipGetLastError();
 }
 

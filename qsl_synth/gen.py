@@ -181,3 +181,18 @@ def dmc_randoms(W: int, N: int, seed: int, step: int):
     Monte Carlo step `step` (their own PCG64 stream per step)."""
     rng = np.random.Generator(np.random.PCG64([seed, 7919, step]))
     return rng.standard_normal((W, N, 3)), rng.random(W)
+
+
+def localize_mos(sys: System, a_up: np.ndarray, a_dn: np.ndarray, radius: float):
+    """Localised stand-ins for the MO coefficients: MO i of a spin keeps its
+    coefficients on the AOs of atoms within `radius` bohr of the home atom of
+    electron i of that spin and is zero elsewhere (MOs stay ordered along the
+    chain, so the non-zeros form blocks).  Returns copies."""
+    home = electron_atoms(sys)
+    ao_atom = np.repeat(sys.shell_atom, (sys.shell_l + 1) * (sys.shell_l + 2) // 2)
+    d = np.linalg.norm(sys.atom_xyz[:, None, :] - sys.atom_xyz[None, :, :], axis=2)
+    out = []
+    for a, centers in ((a_up, home[:sys.n_up]), (a_dn, home[sys.n_up:])):
+        keep = d[centers][:, ao_atom] <= radius
+        out.append(np.where(keep, a, 0.0))
+    return out[0], out[1]
