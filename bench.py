@@ -169,6 +169,27 @@ class Workload:
         _lib.profile_enable(False)
         return ms, ms_eager, prof
 
+    def time_tunings(self, variants, steps):
+        """Graph replays of the plan under each variant of its tuning (a dict
+        of changed fields) -> ms per step; the tuning is restored after."""
+        import torch
+        P = self.plans[True]
+        base = P.tuning
+        out = {}
+        for name, delta in variants.items():
+            P.tuning = {**base, **delta}
+            P.launch()  # re-plans and captures (untimed)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                P.launch()
+            torch.cuda.synchronize()
+            out[name] = round((time.perf_counter() - t0) * 1e3 / steps, 4)
+        P.tuning = base
+        P.launch()
+        torch.cuda.synchronize()
+        return out
+
     def close(self):
         for P in self.plans.values():
             P.close()
@@ -447,6 +468,12 @@ def main():
     ms, ms_eager, prof = main_wl.time(args.steps, args.warmup)
     value = W / (ms * 1e-3)
     log(f"{ms:.3f} ms/step (eager {ms_eager:.3f}), {value:.1f} walkers/s; kernels {prof}")
+    forms = {f"tile{t}-{'persistent' if p_ else 'per-item'}": dict(contract_tile=t, persistent=p_)
+             for t in (0, 1) for p_ in (0, 1)}
+    forms["det_dA"] = dict(det_dA=1)
+    log("launch forms")
+    by_form = main_wl.time_tunings(forms, max(3, args.steps // 2))
+    log(f"launch forms: {by_form}")
     sysm = main_wl.sysm
     kinds = main_wl.work()
     nnz = main_wl.items[0]["nnz"]
@@ -468,7 +495,7 @@ def main():
         "config": {"workload": wname, "electrons": sysm.n_elec,
                    "n_basis": sysm.n_basis, "walkers": W, "mode": mode, "survivors_per_electron": round(nnz, 1),
                    "singular_walkers": int(((st & 1) != 0).sum()), "timed": "HIP graph replays of the plan",
-                   "eager_ms_per_step": ms_eager},
+                   "eager_ms_per_step": ms_eager, "ms_per_step_by_launch_form": by_form},
         "roofline": roofline,
         "kernels": kernels,
     }
@@ -520,8 +547,14 @@ def main():
         del wl32, wl64
         torch.cuda.empty_cache()
         # the uneven batch: 512 walkers each of 44e, 158e, 434e, one autotuned FP32 plan
-        wlb, _ = companion("44e", 512, "fp32", steps2, more=(("158e", 512), ("434e", 512)), autotune=True,
-                           label="batch-44e+158e+434e-W512x3-fp32-fwd+adjoint")
+        wlb, eb = companion("44e", 512, "fp32", steps2, more=(("158e", 512), ("434e", 512)), autotune=True,
+                            label="batch-44e+158e+434e-W512x3-fp32-fwd+adjoint")
+        # the launch forms around the tuned choice: one workgroup per item or
+        # persistent, both contraction tiles, atomic or deterministic dA
+        forms = {f"tile{t}-{'persistent' if p_ else 'per-item'}": dict(contract_tile=t, persistent=p_)
+                 for t in (0, 1) for p_ in (0, 1)}
+        forms["det_dA"] = dict(det_dA=1)
+        eb["ms_per_step_by_launch_form"] = wlb.time_tunings(forms, steps2)
         wlb.close()
         del wlb
         torch.cuda.empty_cache()

@@ -246,7 +246,8 @@ typedef struct qsl_plan qsl_plan;
                               the first qsl_plan_launch after a bind or a
                               tuning change, and replay it afterwards       */
 
-/* Runtime tuning parameters of a plan (what qsl_autotune searches). */
+/* Runtime tuning parameters of a plan (what qsl_autotune searches, except
+ * det_dA, which the caller chooses). */
 typedef struct {
     int32_t batched;    /* 1: one launch per phase over the work list of all
                            systems; 0: one launch per system and spin       */
@@ -254,6 +255,20 @@ typedef struct {
                            0: min(W, 128) per system                          */
     int32_t gj_bias;    /* 0: the smallest Gauss-Jordan block shape holding
                            n; 1: the next larger one (when there is one)      */
+    int32_t contract_tile; /* FP32 products: 0 = 256 MOs per workgroup, two
+                              workgroups per CU; 1 = 128 MOs, three per CU   */
+    int32_t persistent; /* 1 (with batched): the products run as resident
+                           workgroups taking work items from a device counter
+                           (largest systems first) instead of one workgroup
+                           per item                                          */
+    int32_t det_dA;     /* 1: dA summed without atomics: one adjoint dA
+                           launch per 32-electron range, each walker group
+                           adding into partial sums of its own (ranges in
+                           ascending order), then the partials summed in
+                           FP64 in ascending group order: the same dA on
+                           every launch, for ceil(W / group) x n x N_b more
+                           words of plan workspace per spin; 0: atomic
+                           accumulation                                     */
 } qsl_tuning;
 
 /*
@@ -290,7 +305,8 @@ qsl_status qsl_plan_get_tuning(const qsl_plan* plan, qsl_tuning* t);
  * Enqueue the forward of every system, then the adjoint of every system
  * bound with `bwd`, on `stream`.  Results equal those of qsl_forward /
  * qsl_backward per system with the same tuning (bit for bit, except dA,
- * whose atomic sums over walker groups may round in any order).  The first
+ * whose atomic sums over walker groups may round in any order; with
+ * det_dA = 1, dA too is the same on every launch).  The first
  * launch after a bind or a tuning change synchronises `stream`, uploads the
  * work lists and (QSL_PLAN_GRAPH) captures the graph; later launches only
  * enqueue.  Launches of one plan must not overlap.
@@ -303,7 +319,9 @@ qsl_status qsl_plan_destroy(qsl_plan* plan);
 
 /*
  * Autotune: time every candidate tuning (batched 0/1 x adj_group in
- * {16, 32, 64, 128, 256} x gj_bias 0/1) on the bound buffers, keep the
+ * {16, 32, 64, 128, 256} x gj_bias 0/1, then, from the fastest of those,
+ * the FP32 contraction tile and the persistent launch; det_dA stays as
+ * set) on the bound buffers, keep the
  * fastest whose outputs pass a parity self-check against the default
  * tuning (logdet, sign, D^-1, drift, Laplacian and dR of the first and last
  * walkers of every system within 1e-9 relative, dA within 1e-10 (FP64) or

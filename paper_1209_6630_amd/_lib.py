@@ -43,7 +43,11 @@ class BwdArgs(ct.Structure):
 
 
 class Tuning(ct.Structure):
-    _fields_ = [("batched", ct.c_int32), ("adj_group", ct.c_int32), ("gj_bias", ct.c_int32)]
+    _fields_ = [("batched", ct.c_int32), ("adj_group", ct.c_int32), ("gj_bias", ct.c_int32),
+                ("contract_tile", ct.c_int32), ("persistent", ct.c_int32), ("det_dA", ct.c_int32)]
+
+
+TUNING_FIELDS = ("batched", "adj_group", "gj_bias", "contract_tile", "persistent", "det_dA")
 
 
 class LocalArgs(ct.Structure):

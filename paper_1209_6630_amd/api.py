@@ -292,17 +292,17 @@ class Plan:
     def tuning(self):
         t = Tuning()
         check(lib().qsl_plan_get_tuning(self._h, ct.byref(t)))
-        return {"batched": t.batched, "adj_group": t.adj_group, "gj_bias": t.gj_bias}
+        return {k: getattr(t, k) for k in _lib.TUNING_FIELDS}
 
     @tuning.setter
     def tuning(self, d):
-        t = Tuning(int(d.get("batched", 1)), int(d.get("adj_group", 0)), int(d.get("gj_bias", 0)))
+        t = Tuning(*[int(d.get(k, 1 if k == "batched" else 0)) for k in _lib.TUNING_FIELDS])
         check(lib().qsl_plan_set_tuning(self._h, ct.byref(t)))
 
     def autotune(self, cache_path=None):
         t = Tuning()
         check(lib().qsl_autotune(self._h, cache_path.encode() if cache_path else None, _stream(), ct.byref(t)))
-        return {"batched": t.batched, "adj_group": t.adj_group, "gj_bias": t.gj_bias}
+        return {k: getattr(t, k) for k in _lib.TUNING_FIELDS}
 
     def close(self):
         if getattr(self, "_h", None):

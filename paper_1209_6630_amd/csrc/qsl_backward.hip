@@ -306,7 +306,7 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     __shared__ __attribute__((aligned(16))) unsigned char xbuf[BF ? 2 * 2 * NS * LDX : sizeof(T) * TE * LDX];
 
     const int ngw = (int)((W + gw - 1) / gw);
-    const int grp = bx;
+    const int grp = j.t_fix >= 0 ? j.t_fix * ngw + bx : bx;
     const int t = grp / ngw, wb = grp % ngw;
     const int w0 = wb * gw;
     const int nw = (int)min<int64_t>(gw, W - w0);
@@ -728,7 +728,11 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
             if (i >= n || qw < 0 || v == T(0)) continue;
             const int ao = s.slot_ao[qw * WIN + (c % WIN)];
             if (ao < 0) continue;
-            if constexpr (MODE == QSL_FP64) {
+            if (j.dApart) {
+                // this (walker group, MO, AO) has one writer per launch
+                T* pt = (T*)j.dApart + ((size_t)wb * n + i) * s.n_basis + ao;
+                *pt += v;
+            } else if constexpr (MODE == QSL_FP64) {
                 if (dA64) atomicAdd(dA64 + (size_t)i * s.n_basis + ao, v);
             } else {
                 if (dA32) atomicAdd(dA32 + (size_t)i * s.n_basis + ao, v);
@@ -829,7 +833,7 @@ void adj_h_grid(Job& j) {
 
 void adj_da_grid(Job& j) {
     const int nwb = j.mode == QSL_FP64 ? AdCfg<QSL_FP64>::NWB : AdCfg<QSL_FP32>::NWB;
-    j.gx = tiles_per_walker(j.n) * (int)((j.W + j.gw - 1) / j.gw);
+    j.gx = (j.t_fix >= 0 ? 1 : tiles_per_walker(j.n)) * (int)((j.W + j.gw - 1) / j.gw);
     j.gy = (j.s.n_win + nwb - 1) / nwb;
     j.gz = (j.n + ADJ_MB - 1) / ADJ_MB;
 }
@@ -849,7 +853,7 @@ hipError_t launch_adj_da(const Job& j0, hipStream_t st) {
     Job j = j0;
     if (j.gw < 1) return hipErrorInvalidValue;
     adj_da_grid(j);
-    if (!j.n || !j.W || (!j.dA64 && !j.dA32)) return hipSuccess;
+    if (!j.n || !j.W || (!j.dA64 && !j.dA32 && !j.dApart)) return hipSuccess;
     const dim3 grid((unsigned)j.gx, j.gy, j.gz);
     if (j.mode == QSL_FP64) adj_da_kernel<QSL_FP64><<<grid, AD_THREADS, 0, st>>>(j);
     else if (j.mode == QSL_FP32) adj_da_kernel<QSL_FP32><<<grid, AD_THREADS, 0, st>>>(j);

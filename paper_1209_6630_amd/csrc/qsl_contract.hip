@@ -59,9 +59,15 @@ struct CT {
 // ring of slot indices; chunks of 64 slots are evaluated into LDS (one
 // thread per slot and eight electrons) and contracted with
 // v_mfma_f32_32x32x2f32, k-step t taking chunk slots t and 32 + t.
-constexpr int F32_MSUB = 2;     // 32-MO sub-blocks per wave (a workgroup covers 256 MOs)
-constexpr int F32_NB = F32_MSUB * CT_WAVES * 32;
-constexpr int F32_MINB = 2;     // workgroups per CU (registers: 160 accumulators + the evaluation)
+// Two workgroup shapes (tuning): tile 0 holds two 32-MO sub-blocks per wave
+// (256 MOs, 160 accumulators, two workgroups per CU), tile 1 one (128 MOs,
+// 80 accumulators, three per CU; the AOs are evaluated once per 128 MOs).
+template <int TILE>
+struct F32T {
+    static constexpr int MSUB = TILE == 0 ? 2 : 1;
+    static constexpr int NB = MSUB * CT_WAVES * 32;
+    static constexpr int MINB = TILE == 0 ? 2 : 3;
+};
 constexpr int F32_BATCH = 32;   // windows filtered at a time
 constexpr int F32_KC = 64;      // slots per chunk
 constexpr int F32_RING = 512;   // ring of slot indices (>= 8 * F32_BATCH + F32_KC)
@@ -108,7 +114,8 @@ __device__ __forceinline__ void slot_values(const SlotRec& r, double T_thr, cons
     v[4] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + (float)(2 * l) * pg1 + P * g2;
 }
 
-__device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) {
+template <int TILE>
+__device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, int tid_in) {
     const DevSys& s = j.s;
     // n electrons of the spin (rows of a tile's C), nmo MOs (columns; n for
     // a Slater matrix, more for the orbital set of several determinants)
@@ -118,7 +125,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
     const float* __restrict__ AT32 = j.mo.AT32;
     const SlotRec* __restrict__ srec = s.slot_rec;
     uint32_t* __restrict__ status = j.status;
-    constexpr int MSUB = F32_MSUB, NSB = CT_WAVES * 32, LD = F32_LD, KC = F32_KC;
+    constexpr int MSUB = F32T<TILE>::MSUB, NSB = CT_WAVES * 32, LD = F32_LD, KC = F32_KC;
 
     __shared__ double epos[TE][3];
     __shared__ __attribute__((aligned(16))) float B[5 * TE * LD];
@@ -136,7 +143,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
     const int ne = (int)min<int64_t>(TE, W - w0);
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = tid_in, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const double Tscr = s.T;
 
@@ -324,9 +331,9 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by) 
 }
 
 template <int MODE>
-__device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
+__device__ __forceinline__ void contract_body(const Job& j, int bx, int by, int tid_in) {
     if constexpr (MODE == QSL_FP32) {
-        contract_f32_body(j, bx, by);
+        contract_f32_body<0>(j, bx, by, tid_in);
     } else {
     const DevSys& s = j.s;
     const int spin = j.spin, n = j.n, nmo = j.mo.n, ldn = j.mo.ldn;
@@ -360,7 +367,7 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     const int ne = (int)min<int64_t>(TE, W - w0);
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = tid_in, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
 
     if (tid < TE * 3) {
@@ -568,24 +575,64 @@ __device__ __forceinline__ void contract_body(const Job& j, int bx, int by) {
     }  // FP64 / BF16X3
 }
 
-// (the per-system launch keeps two workgroups per CU in every mode: with
-// the Job passed by value the FP32 body needs more registers than three allow)
 template <int MODE>
-__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_kernel(Job j) {
-    contract_body<MODE>(j, blockIdx.x, blockIdx.y);
+__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs,
+                [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) {
+                    contract_body<MODE>(j, bx, by, threadIdx.x);
+                });
+}
+
+__global__ __launch_bounds__(CT_WAVES * 64, F32T<1>::MINB) void contract_batched_f32t1(const Job* jobs,
+                                                                                       const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) {
+        contract_f32_body<1>(j, bx, by, threadIdx.x);
+    });
+}
+
+// Persistent form: `gridDim.x` resident workgroups take the items of the
+// work list in order from a device counter (zeroed before the launch) until
+// it passes the last; every workgroup leaves once the counter does.
+template <int MODE, int TILE>
+__device__ __forceinline__ void contract_persist_body(const Job* __restrict__ jobs, const int* __restrict__ prefix,
+                                                      int njobs, unsigned* __restrict__ queue) {
+    __shared__ int s_item;
+    const int total = prefix[njobs];
+    for (;;) {
+        __syncthreads();  // the previous item's LDS is no longer read
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int b = __builtin_amdgcn_readfirstlane(s_item);  // uniform: scalar registers
+        if (b >= total) break;
+        // the thread index, opaque per item: values derived from it are not
+        // hoisted out of the loop (held across the body, they would spill)
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int ji = __builtin_amdgcn_readfirstlane(find_job(prefix, njobs, b));
+        const Job& j = jobs[ji];
+        const int lb = b - prefix[ji];
+        if constexpr (MODE == QSL_FP32) contract_f32_body<TILE>(j, lb % j.gx, (lb / j.gx) % j.gy, tid);
+        else contract_body<MODE>(j, lb % j.gx, (lb / j.gx) % j.gy, tid);
+    }
 }
 
 template <int MODE>
-__global__ __launch_bounds__(CT_WAVES * 64, MODE == QSL_FP32 ? F32_MINB : 2) void contract_batched(const Job* jobs,
-                                                                                                const int* prefix,
-                                                                                                int njobs) {
-    batch_block(jobs, prefix, njobs,
-                [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) { contract_body<MODE>(j, bx, by); });
+__global__ __launch_bounds__(CT_WAVES * 64, 2) void contract_persist(const Job* jobs, const int* prefix, int njobs,
+                                                                     unsigned* queue) {
+    contract_persist_body<MODE, 0>(jobs, prefix, njobs, queue);
+}
+
+__global__ __launch_bounds__(CT_WAVES * 64, F32T<1>::MINB) void contract_persist_f32t1(const Job* jobs,
+                                                                                       const int* prefix, int njobs,
+                                                                                       unsigned* queue) {
+    contract_persist_body<QSL_FP32, 1>(jobs, prefix, njobs, queue);
 }
 
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
-    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB : (j.mode == QSL_FP32 ? F32_NB : CT<QSL_BF16X3>::NB);
+    const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB
+                                      : (j.mode == QSL_FP32 ? (j.f32_tile ? F32T<1>::NB : F32T<0>::NB)
+                                                            : CT<QSL_BF16X3>::NB);
     j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.mo.n + nb - 1) / nb;  // MO blocks (n for a Slater matrix)
     j.gz = 1;
@@ -606,30 +653,31 @@ hipError_t launch_contract(const Job& j0, hipStream_t st) {
     Job j = j0;
     contract_grid(j);
     if (!j.n || !j.W) return hipSuccess;
-    constexpr int T = CT_WAVES * 64;
-    if (j.jobslot) {
-        Job* dj = (Job*)j.jobslot;
-        int* pre = (int*)((char*)j.jobslot + sizeof(Job));
-        store_job_kernel<<<1, 64, 0, st>>>(j, dj, pre);
-        const int grid = j.gx * j.gy;
-        if (j.mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(dj, pre, 1);
-        else if (j.mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(dj, pre, 1);
-        else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(dj, pre, 1);
-        return hipGetLastError();
-    }
-    const dim3 g((unsigned)j.gx, j.gy);
-    if (j.mode == QSL_FP64) contract_kernel<QSL_FP64><<<g, T, 0, st>>>(j);
-    else if (j.mode == QSL_FP32) contract_kernel<QSL_FP32><<<g, T, 0, st>>>(j);
-    else contract_kernel<QSL_BF16X3><<<g, T, 0, st>>>(j);
-    return hipGetLastError();
+    if (!j.jobslot) return hipErrorInvalidValue;  // every caller's workspace holds one
+    Job* dj = (Job*)j.jobslot;
+    int* pre = (int*)((char*)j.jobslot + sizeof(Job));
+    store_job_kernel<<<1, 64, 0, st>>>(j, dj, pre);
+    return launch_contract_batched(j.mode, j.f32_tile, nullptr, dj, pre, 1, j.gx * j.gy, st);
 }
 
-hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
-                                   hipStream_t st) {
+int contract_per_cu(int mode, int tile) { return mode == QSL_FP32 && tile ? F32T<1>::MINB : 2; }
+
+hipError_t launch_contract_batched(int mode, int tile, unsigned* queue, const Job* jobs, const int* prefix, int njobs,
+                                   int grid, hipStream_t st) {
     constexpr int T = CT_WAVES * 64;
-    if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs);
-    else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs);
-    else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+    if (grid <= 0) return hipSuccess;
+    const bool t1 = mode == QSL_FP32 && tile;
+    if (queue) {
+        if (mode == QSL_FP64) contract_persist<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
+        else if (t1) contract_persist_f32t1<<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
+        else if (mode == QSL_FP32) contract_persist<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
+        else contract_persist<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
+    } else {
+        if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+        else if (t1) contract_batched_f32t1<<<grid, T, 0, st>>>(jobs, prefix, njobs);
+        else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+        else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs);
+    }
     return hipGetLastError();
 }
 

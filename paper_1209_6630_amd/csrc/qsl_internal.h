@@ -305,6 +305,13 @@ struct Job {
     double* gjws;            // blocked inversion (gj_blocked(n)): W x gj_ws_doubles(n)
     uint16_t* gsplit;        // BF16X3 adjoint: W x gsplit_elems(n) hi, then as many lo
     void* jobslot;           // per-system launches: device copy of the Job and its block prefix
+    int f32_tile;            // FP32 products: 0 = 256 MOs per workgroup, 1 = 128
+    // Deterministic dA: one launch per electron range t_fix (-1: one launch
+    // for all ranges, atomic flush), each walker group adding its block into
+    // its own partial sum dApart[wb][n][N_b] (float, or double in FP64) with
+    // plain loads and stores; the partials are reduced in a fixed order.
+    void* dApart;
+    int t_fix = -1;
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 // Bytes of the device Job copy of a per-system launch (Job, then two ints).
@@ -439,8 +446,13 @@ hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, 
 // Fused AO evaluation + the five AO->MO products C_n = A B_n.
 void contract_grid(Job& j);
 hipError_t launch_contract(const Job& j, hipStream_t st);
-hipError_t launch_contract_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
-                                   hipStream_t st);
+// tile: the FP32 workgroup shape (Job.f32_tile); queue: NULL for one
+// workgroup per item, else a zeroed device counter that `grid` resident
+// workgroups draw items from (persistent launch).
+hipError_t launch_contract_batched(int mode, int tile, unsigned* queue, const Job* jobs, const int* prefix, int njobs,
+                                   int grid, hipStream_t st);
+// Workgroups of one contraction launch that fit on a CU at once.
+int contract_per_cu(int mode, int tile);
 // Gauss-Jordan inversion, log|det| and sign (one block per matrix; the
 // block shape depends on n, so a batched launch serves one variant).
 int gj_variant(int n);
@@ -483,6 +495,9 @@ hipError_t launch_adj_h_batched(int mode, const Job* jobs, const int* prefix, in
 hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                     hipStream_t st);
 hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
+// dA = [dA +] sum_p part[p] (p ascending; float or double partials).
+hipError_t launch_reduce_dA(const void* part, bool fp64, int npart, int64_t count, double* dA, int accumulate,
+                            hipStream_t st);
 hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A_dev, int64_t ld,
                            hipStream_t st);
 

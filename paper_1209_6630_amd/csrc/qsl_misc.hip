@@ -78,6 +78,27 @@ hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int 
     return hipGetLastError();
 }
 
+// dA (caller, FP64) = [dA +] sum over p = 0, 1, ... of the partial sums
+// part[p] (the deterministic dA: the same order on every call).
+template <typename T>
+__global__ void reduce_dA_kernel(const T* __restrict__ part, int npart, int64_t count, double* __restrict__ dA,
+                                 int accumulate) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < count; q += (int64_t)gridDim.x * blockDim.x) {
+        double acc = accumulate ? dA[q] : 0.0;
+        for (int p = 0; p < npart; ++p) acc += (double)part[(size_t)p * count + q];
+        dA[q] = acc;
+    }
+}
+
+hipError_t launch_reduce_dA(const void* part, bool fp64, int npart, int64_t count, double* dA, int accumulate,
+                            hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>((count + 255) / 256, 8192);
+    if (fp64) reduce_dA_kernel<double><<<blocks, 256, 0, st>>>((const double*)part, npart, count, dA, accumulate);
+    else reduce_dA_kernel<float><<<blocks, 256, 0, st>>>((const float*)part, npart, count, dA, accumulate);
+    return hipGetLastError();
+}
+
 // drift[e] = sum_i Dinv[e][i] C_{2..4}[e][i], lap[e] = sum_i Dinv[e][i] C_5[e][i]
 // (the determinant's "vector products"), one wavefront per electron.
 template <typename Tc>

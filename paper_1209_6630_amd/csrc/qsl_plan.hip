@@ -56,8 +56,10 @@ struct qsl_plan {
     std::vector<qsl_fwd_args> fwd;
     std::vector<qsl_bwd_args> bwd;
     std::vector<char> bound, has_bwd;
-    qsl_tuning tune{1, 0, 0};
-    // workspace: per system window lists and dA accumulators
+    qsl_tuning tune{1, 0, 0, 0, 0, 0};
+    int n_cu = 256;  // compute units (the persistent launch's grid)
+    // workspace: the persistent launch's item counter, then per system window
+    // lists and dA accumulators, then the deterministic dA's partial sums
     void* ws = nullptr;
     size_t ws_cap = 0;
     std::vector<size_t> ws_off;
@@ -66,6 +68,7 @@ struct qsl_plan {
     // per-job (system, spin) Jobs and the device work lists of the phases
     std::vector<Job> fjobs, bjobs;
     PhaseList ph[PH_COUNT];
+    std::vector<PhaseList> da_t;  // deterministic dA: the adjoint dA launch of each electron range
     void* lists = nullptr;
     size_t lists_cap = 0;
     bool dirty = true;
@@ -118,12 +121,25 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     p->lay.resize(p->n_sys);
     p->ws_off.resize(p->n_sys);
     p->gw.resize(p->n_sys);
-    size_t total = 0;
+    size_t total = 256;  // the item counter
     for (int i = 0; i < p->n_sys; ++i) {
         p->gw[i] = plan_gw(p, i);
         p->lay[i] = ws_layout(p->sys[i]->d, p->W[i], p->gw[i], p->mode);
         p->ws_off[i] = total;
         total = round_up(total + p->lay[i].total, 256);
+    }
+    // deterministic dA: one partial sum [n][N_b] per walker group and spin
+    const bool det = p->tune.det_dA != 0;
+    std::vector<size_t> part_off(2 * p->n_sys, 0);
+    const size_t elem = p->mode == QSL_FP64 ? sizeof(double) : sizeof(float);
+    for (int i = 0; i < p->n_sys && det; ++i) {
+        if (!p->has_bwd[i]) continue;
+        const int64_t ngw = (p->W[i] + p->gw[i] - 1) / p->gw[i];
+        for (int s = 0; s < 2; ++s) {
+            if (!p->bwd[i].dA[s]) continue;
+            part_off[2 * i + s] = total;
+            total = round_up(total + (size_t)ngw * n_spin(p->sys[i]->d, s) * p->sys[i]->d.n_basis * elem, 256);
+        }
     }
     if (total > p->ws_cap) {
         if (p->ws) hipFree(p->ws);
@@ -139,13 +155,16 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
         for (int s = 0; s < 2; ++s) {
             Job f = fwd_job(p->sys[i], &p->fwd[i], p->lay[i], ws + p->ws_off[i], s);
             f.gj_bias = p->tune.gj_bias;
+            f.f32_tile = p->tune.contract_tile;
             p->fjobs.push_back(f);
             if (p->has_bwd[i]) {
                 Job b = bwd_job(p->sys[i], &p->bwd[i], p->lay[i], ws + p->ws_off[i], s, p->gw[i]);
+                if (det && part_off[2 * i + s] && (b.dA64 || b.dA32)) b.dApart = ws + part_off[2 * i + s];
                 p->bjobs.push_back(b);
             }
         }
     for (auto& L : p->ph) { L.jobs.clear(); L.prefix.clear(); }
+    p->da_t.clear();
     for (const Job& f : p->fjobs) {
         if (!f.n || !f.W) continue;
         Job j = f;
@@ -202,20 +221,34 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
                 j.gx = gsplit_blocks(j); j.gy = 1; j.gz = 1;
                 p->ph[PH_GSPLIT].jobs.push_back(j);
             }
-            j = b;
-            adj_da_grid(j);
-            p->ph[PH_ADJ_DA].jobs.push_back(j);
+            if (b.dApart) {
+                // electron range t of every Job in launch t (ascending)
+                const int T = tiles_per_walker(b.n);
+                if ((int)p->da_t.size() < T) p->da_t.resize(T);
+                for (int t = 0; t < T; ++t) {
+                    j = b;
+                    j.t_fix = t;
+                    adj_da_grid(j);
+                    p->da_t[t].jobs.push_back(j);
+                }
+            } else {
+                j = b;
+                adj_da_grid(j);
+                p->ph[PH_ADJ_DA].jobs.push_back(j);
+            }
         }
     }
     size_t bytes = 0;
-    for (auto& L : p->ph) {
+    auto place = [&](PhaseList& L) {
         sort_jobs(L.jobs);
         set_prefix(L);
         L.jobs_off = bytes;
         bytes = round_up(bytes + L.jobs.size() * sizeof(Job), 256);
         L.prefix_off = bytes;
         bytes = round_up(bytes + L.prefix.size() * sizeof(int), 256);
-    }
+    };
+    for (auto& L : p->ph) place(L);
+    for (auto& L : p->da_t) place(L);
     if (bytes > p->lists_cap) {
         if (p->lists) hipFree(p->lists);
         p->lists = nullptr;
@@ -224,22 +257,26 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
         p->lists_cap = bytes;
     }
     std::vector<char> host(bytes, 0);
-    for (auto& L : p->ph) {
+    auto put = [&](const PhaseList& L) {
         if (!L.jobs.empty()) memcpy(host.data() + L.jobs_off, L.jobs.data(), L.jobs.size() * sizeof(Job));
         memcpy(host.data() + L.prefix_off, L.prefix.data(), L.prefix.size() * sizeof(int));
-    }
+    };
+    for (auto& L : p->ph) put(L);
+    for (auto& L : p->da_t) put(L);
     if (bytes && (e = hipMemcpy(p->lists, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "plan: work list upload");
     p->dirty = false;
     return QSL_OK;
 }
 
-static const Job* dev_jobs(const qsl_plan* p, int ph) {
-    return (const Job*)((const char*)p->lists + p->ph[ph].jobs_off);
+static const Job* dev_jobs(const qsl_plan* p, const PhaseList& L) {
+    return (const Job*)((const char*)p->lists + L.jobs_off);
 }
-static const int* dev_prefix(const qsl_plan* p, int ph) {
-    return (const int*)((const char*)p->lists + p->ph[ph].prefix_off);
+static const int* dev_prefix(const qsl_plan* p, const PhaseList& L) {
+    return (const int*)((const char*)p->lists + L.prefix_off);
 }
+static const Job* dev_jobs(const qsl_plan* p, int ph) { return dev_jobs(p, p->ph[ph]); }
+static const int* dev_prefix(const qsl_plan* p, int ph) { return dev_prefix(p, p->ph[ph]); }
 
 static const char* contract_name(int mode) {
     return mode == QSL_FP64 ? "contract_fp64" : mode == QSL_FP32 ? "contract_fp32" : "contract_bf16x3";
@@ -267,6 +304,11 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         for (int s = 0; s < 2; ++s, ++k) {
             const Job& j = p->bjobs[k];
             const int64_t cnt = (int64_t)j.n * j.s.n_basis;
+            if (j.dApart) {
+                const int64_t words = cnt * ((j.W + j.gw - 1) / j.gw) * (mode == QSL_FP64 ? 2 : 1);
+                if ((e = fill_u32((uint32_t*)j.dApart, 0u, words, st)) != hipSuccess) return hip_fail(e, "dA clear");
+                continue;
+            }
             if (j.dA32 && (e = fill_u32((uint32_t*)j.dA32, 0u, cnt, st)) != hipSuccess) return hip_fail(e, "dA clear");
             if (j.dA64 && !p->bwd[i].accumulate_dA && (e = fill_f64(j.dA64, 0.0, cnt, st)) != hipSuccess)
                 return hip_fail(e, "dA clear");
@@ -284,8 +326,16 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         auto& C = p->ph[PH_CONTRACT];
         if (C.blocks()) {
             ProfScope ps(contract_name(mode), st);
-            if ((e = launch_contract_batched(mode, dev_jobs(p, PH_CONTRACT), dev_prefix(p, PH_CONTRACT),
-                                             (int)C.jobs.size(), C.blocks(), st)) != hipSuccess)
+            const int tile = p->tune.contract_tile;
+            unsigned* queue = nullptr;
+            int grid = C.blocks();
+            if (p->tune.persistent) {
+                queue = (unsigned*)p->ws;
+                grid = std::min(grid, p->n_cu * contract_per_cu(mode, tile));
+                if ((e = fill_u32(queue, 0u, 1, st)) != hipSuccess) return hip_fail(e, "item counter clear");
+            }
+            if ((e = launch_contract_batched(mode, tile, queue, dev_jobs(p, PH_CONTRACT), dev_prefix(p, PH_CONTRACT),
+                                             (int)C.jobs.size(), grid, st)) != hipSuccess)
                 return hip_fail(e, "contraction kernel");
         }
         for (int v = 0; v <= 4; ++v) {
@@ -394,6 +444,13 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                            (int)DA.jobs.size(), DA.blocks(), st)) != hipSuccess)
                 return hip_fail(e, "adjoint dA kernel");
         }
+        for (const PhaseList& L : p->da_t) {
+            if (!L.blocks()) continue;
+            ProfScope ps("adjoint_dA", st);
+            if ((e = launch_adj_da_batched(mode, dev_jobs(p, L), dev_prefix(p, L), (int)L.jobs.size(), L.blocks(),
+                                           st)) != hipSuccess)
+                return hip_fail(e, "adjoint dA kernel");
+        }
     } else {
         for (const Job& j : H.jobs) {
             ProfScope ps("adjoint_h", st);
@@ -412,12 +469,24 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             ProfScope ps("adjoint_dA", st);
             if ((e = launch_adj_da(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");
         }
+        for (const PhaseList& L : p->da_t)
+            for (const Job& j : L.jobs) {
+                ProfScope ps("adjoint_dA", st);
+                if ((e = launch_adj_da(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");
+            }
     }
     // FP32 dA accumulators -> the caller's FP64 dA
     for (int i = 0, k = 0; i < p->n_sys; ++i) {
         if (!p->has_bwd[i]) continue;
         for (int s = 0; s < 2; ++s, ++k) {
             const Job& j = p->bjobs[k];
+            if (j.dApart && j.n) {
+                if ((e = launch_reduce_dA(j.dApart, mode == QSL_FP64, (int)((j.W + j.gw - 1) / j.gw),
+                                          (int64_t)j.n * j.s.n_basis, p->bwd[i].dA[s], p->bwd[i].accumulate_dA, st)) !=
+                    hipSuccess)
+                    return hip_fail(e, "dA reduction");
+                continue;
+            }
             if (!j.dA32 || !j.n) continue;
             if ((e = launch_finalize_dA(j.dA32, p->bwd[i].dA[s], (int64_t)j.n * j.s.n_basis, p->bwd[i].accumulate_dA,
                                         st)) != hipSuccess)
@@ -484,7 +553,8 @@ static bool parse_int(const std::string& line, const char* name, int* out) {
 }
 
 // The cache file holds one entry per line:
-// {"key": "...", "batched": 1, "adj_group": 64, "gj_bias": 0, "ms": 1.25},
+// {"key": "...", "batched": 1, "adj_group": 64, "gj_bias": 0, "contract_tile": 0,
+//  "persistent": 0, "det_dA": 0, "ms": 1.25},  (on one line)
 static bool cache_lookup(const char* path, const std::string& key, qsl_tuning* t) {
     std::ifstream f(path);
     if (!f) return false;
@@ -495,6 +565,10 @@ static bool cache_lookup(const char* path, const std::string& key, qsl_tuning* t
         qsl_tuning r{};
         if (parse_int(line, "batched", &r.batched) && parse_int(line, "adj_group", &r.adj_group) &&
             parse_int(line, "gj_bias", &r.gj_bias)) {
+            // fields added later read as 0 when an entry lacks them
+            parse_int(line, "contract_tile", &r.contract_tile);
+            parse_int(line, "persistent", &r.persistent);
+            parse_int(line, "det_dA", &r.det_dA);
             *t = r;
             return true;
         }
@@ -515,8 +589,10 @@ static bool cache_store(const char* path, const std::string& key, const qsl_tuni
             }
     }
     char buf[512];
-    snprintf(buf, sizeof buf, "{\"key\": \"%s\", \"batched\": %d, \"adj_group\": %d, \"gj_bias\": %d, \"ms\": %.6f}",
-             key.c_str(), t.batched, t.adj_group, t.gj_bias, ms);
+    snprintf(buf, sizeof buf,
+             "{\"key\": \"%s\", \"batched\": %d, \"adj_group\": %d, \"gj_bias\": %d, \"contract_tile\": %d, "
+             "\"persistent\": %d, \"det_dA\": %d, \"ms\": %.6f}",
+             key.c_str(), t.batched, t.adj_group, t.gj_bias, t.contract_tile, t.persistent, t.det_dA, ms);
     keep.push_back(buf);
     const std::string tmp = std::string(path) + ".tmp";
     {
@@ -675,6 +751,9 @@ qsl_status qsl_plan_create(int32_t n_sys, qsl_system* const* sys, const int64_t*
     p->mode = mode;
     p->flags = flags;
     hipGetDevice(&p->device);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
+        p->n_cu = ncu;
     p->sys.assign(sys, sys + n_sys);
     p->W.assign(W, W + n_sys);
     p->fwd.assign(n_sys, qsl_fwd_args{});
@@ -723,8 +802,9 @@ qsl_status qsl_plan_bind(qsl_plan* p, int32_t i, const qsl_fwd_args* f, const qs
 
 qsl_status qsl_plan_set_tuning(qsl_plan* p, const qsl_tuning* t) {
     if (!p || !t) return bad(QSL_ERR_INVALID_ARG, "plan tuning: NULL argument");
-    if ((t->batched != 0 && t->batched != 1) || t->adj_group < 0 || t->adj_group > 4096 || t->gj_bias < 0 ||
-        t->gj_bias > 1)
+    auto flag = [](int32_t v) { return v == 0 || v == 1; };
+    if (!flag(t->batched) || t->adj_group < 0 || t->adj_group > 4096 || !flag(t->gj_bias) || !flag(t->contract_tile) ||
+        !flag(t->persistent) || !flag(t->det_dA))
         return bad(QSL_ERR_INVALID_ARG, "plan tuning: value out of range");
     p->tune = *t;
     p->dirty = true;
@@ -790,8 +870,9 @@ namespace qsl {
 static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& key, const char* cache_path,
                                const qsl_tuning saved, qsl_tuning* chosen) {
     hipError_t e;
-    // the default tuning is the reference of the self-check
-    const qsl_tuning base{1, 0, 0};
+    // the default tuning is the reference of the self-check; every
+    // candidate keeps the caller's choice of the deterministic dA
+    const qsl_tuning base{1, 0, 0, 0, 0, saved.det_dA};
     p->tune = base;
     p->dirty = true;
     Snapshot ref, got;
@@ -815,28 +896,41 @@ static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& k
             for (int g : groups) {
                 if (!any_bwd && g) continue;
                 if (g > 16 && g >= 2 * wmax) continue;  // the same as a smaller group for every system
-                cands.push_back(qsl_tuning{bt, g, gb});
+                cands.push_back(qsl_tuning{bt, g, gb, 0, 0, saved.det_dA});
             }
         }
     double best_ms = 1e300;
     qsl_tuning best = base;
     bool found = false;
-    for (const qsl_tuning& c : cands) {
+    auto trial = [&](const qsl_tuning& c) -> qsl_status {
         p->tune = c;
         p->dirty = true;
         double ms = 0.0;
-        if ((r = time_plan(p, st, 3, &ms)) != QSL_OK) {
-            p->tune = saved;
-            p->dirty = true;
-            return r;
-        }
+        qsl_status q = time_plan(p, st, 3, &ms);
+        if (q != QSL_OK) return q;
         if ((e = snapshot(p, got)) != hipSuccess) return hip_fail(e, "autotune: copy");
-        if (!same_results(p, ref, got)) continue;
+        if (!same_results(p, ref, got)) return QSL_OK;
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
             found = true;
         }
+        return QSL_OK;
+    };
+    // coordinate descent: the launch and group shapes first, then the
+    // contraction's tile and persistent launch around the best of those
+    for (const qsl_tuning& c : cands)
+        if ((r = trial(c)) != QSL_OK) return r;
+    if (found) {
+        const qsl_tuning b0 = best;
+        for (int tile = 0; tile <= 1; ++tile)
+            for (int pers = 0; pers <= (b0.batched ? 1 : 0); ++pers) {
+                if (!tile && !pers) continue;  // b0 itself
+                qsl_tuning c = b0;
+                c.contract_tile = tile;
+                c.persistent = pers;
+                if ((r = trial(c)) != QSL_OK) return r;
+            }
     }
     if (!found) {
         p->tune = saved;

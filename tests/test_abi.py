@@ -114,7 +114,7 @@ def test_plan_argument_checks():
     assert L.qsl_plan_create(1, None, W, 0, 0, ct.byref(h)) == 1
     assert L.qsl_plan_launch(None, None) == 1
     assert L.qsl_plan_bind(None, 0, None, None) == 1
-    t = Tuning(1, 0, 0)
+    t = Tuning(1, 0, 0, 0, 0, 0)
     assert L.qsl_plan_set_tuning(None, ct.byref(t)) == 1
     assert L.qsl_plan_get_tuning(None, ct.byref(t)) == 1
     assert L.qsl_autotune(None, None, None, None) == 1

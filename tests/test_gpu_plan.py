@@ -1,7 +1,9 @@
 """Uneven batches (plans): batched launches equal per-system launches bit for
-bit, graph replays equal eager launches, the autotuner's choice and cache,
-and the 512 x (44e, 158e, 434e) FP32 batch against the FP64 oracle on
-sampled walkers."""
+bit, graph replays equal eager launches, every tuning (launch form, group
+size, Gauss-Jordan block, FP32 contraction tile, persistent launch,
+deterministic dA) agrees with the default, the deterministic dA repeats
+bit for bit, the autotuner's choice and cache, and the 512 x (44e, 158e,
+434e) FP32 batch against the FP64 oracle on sampled walkers."""
 import json
 import os
 
@@ -177,23 +179,102 @@ def test_graph_replays_follow_new_coordinates():
     Pe.close()
 
 
-@pytest.mark.parametrize("tuning", [dict(batched=0, adj_group=16, gj_bias=0),
-                                    dict(batched=1, adj_group=32, gj_bias=1),
-                                    dict(batched=1, adj_group=256, gj_bias=1)])
-def test_tunings_agree(tuning):
-    print(f"[case] tuning {tuning}", flush=True)
-    mode = "fp32"
+TUNINGS = [dict(batched=0, adj_group=16, gj_bias=0),
+           dict(batched=1, adj_group=32, gj_bias=1),
+           dict(batched=1, adj_group=256, gj_bias=1),
+           dict(batched=1, adj_group=0, gj_bias=0, contract_tile=1),
+           dict(batched=1, adj_group=0, gj_bias=0, persistent=1),
+           dict(batched=1, adj_group=64, gj_bias=0, contract_tile=1, persistent=1),
+           dict(batched=1, adj_group=16, gj_bias=0, det_dA=1),
+           dict(batched=0, adj_group=0, gj_bias=0, contract_tile=1, det_dA=1)]
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp64", "bf16x3"])
+@pytest.mark.parametrize("tuning", TUNINGS)
+def test_tunings_agree(tuning, mode):
+    if mode != "fp32" and (tuning.get("contract_tile") or tuning["gj_bias"]):
+        pytest.skip("the contraction tile is an FP32 choice; block shapes are covered in FP32")
+    print(f"[case] tuning {tuning} mode={mode}", flush=True)
     items = _batch([("44e", 40), ("158e", 6), (("tiny", 70, 60), 3)])
     P0, b0 = _plan(items, mode, graph=False)
     P0.launch()
     ref = _read(b0)
     P1, b1 = _plan(items, mode, graph=True, tuning=tuning)
-    assert P1.tuning == tuning
+    assert {k: P1.tuning[k] for k in tuning} == tuning
     P1.launch()
     got = _read(b1)
     for r, g_ in zip(ref, got):
-        # another Gauss-Jordan block shape may break pivot ties differently
+        # another Gauss-Jordan block shape may break pivot ties differently;
+        # the contraction tile and the persistent launch change no sum
         _same(r, g_, mode, exact=tuning["gj_bias"] == 0)
+    P0.close()
+    P1.close()
+
+
+@pytest.mark.parametrize("mode", ["fp32", "fp64", "bf16x3"])
+def test_deterministic_dA_repeats_bit_for_bit(mode):
+    """With det_dA the adjoint's dA is the same on every launch, in a plan
+    and in a second plan of the same tuning, and accumulates onto what the
+    buffer holds; the atomic dA agrees with it to rounding."""
+    print(f"[case] deterministic dA mode={mode}", flush=True)
+    import torch
+    from paper_1209_6630_amd.api import Plan
+    items = _batch([("44e", 96), ("158e", 20), (("tiny", 40, 33), 7)])
+    det = dict(batched=1, adj_group=16, gj_bias=0, det_dA=1)
+    P1, b1 = _plan(items, mode, graph=True, tuning=det)
+    P2, b2 = _plan(items, mode, graph=False, tuning=det)
+    P1.launch()
+    first = _read(b1)
+    P1.launch()
+    P2.launch()
+    second, other = _read(b1), _read(b2)
+    for a, b, c in zip(first, second, other):
+        for k in ("dA_up", "dA_dn"):
+            np.testing.assert_array_equal(a[k], b[k])
+            np.testing.assert_array_equal(a[k], c[k])
+    P0, b0 = _plan(items, mode, graph=False, tuning=dict(det, det_dA=0))
+    P0.launch()
+    for r, g_ in zip(_read(b0), first):
+        _same(r, g_, mode)
+    # accumulate: the partial sums are added to the buffer's contents
+    P3 = Plan([it["S"] for it in items], [it["R"].shape[0] for it in items], mode, graph=True)
+    P3.tuning = det
+    acc = []
+    for i, it in enumerate(items):
+        S, W = it["S"], it["R"].shape[0]
+        out = S.alloc_outputs(W, mode)
+        dR = torch.empty((W, S.n_elec, 3), dtype=torch.float64, device="cuda")
+        dA = (torch.full((S.n_up, S.n_basis), 3.0, dtype=torch.float64, device="cuda"),
+              torch.full((S.n_dn, S.n_basis), 3.0, dtype=torch.float64, device="cuda"))
+        P3.bind(i, it["Rt"], out, g=it["gt"], dR=dR, dA=dA, accumulate=True)
+        acc.append((out, dR, dA))
+    P3.launch()
+    for r, g_ in zip(first, _read(acc)):
+        for k in ("dA_up", "dA_dn"):
+            # (3 + p_0) + p_1 + ... against 3 + (p_0 + p_1 + ...): rounding only
+            np.testing.assert_allclose(g_[k], r[k] + 3.0, rtol=0, atol=1e-12 * max(3.0, np.abs(r[k]).max()))
+    for p_ in (P0, P1, P2, P3):
+        p_.close()
+
+
+@pytest.mark.parametrize("tile,persistent", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_contract_tiles_against_oracle(tile, persistent):
+    """Each FP32 contraction tile, in one launch per item or persistent,
+    on the 434- and 44-electron systems against the FP64 oracle on sampled
+    walkers (the forward bounds of the per-system tests)."""
+    print(f"[case] contraction tile={tile} persistent={persistent}", flush=True)
+    mode = "fp32"
+    items = _batch([("434e", 64), ("44e", 100)])
+    P, bufs = _plan(items, mode, graph=False,
+                    tuning=dict(batched=1, adj_group=0, gj_bias=0, contract_tile=tile, persistent=persistent))
+    P.launch()
+    got = _read(bufs)
+    for it, g_ in zip(items, got):
+        sysm, A_up, A_dn, R = it["sysm"], it["A_up"], it["A_dn"], it["R"]
+        sample = [0, 13, R.shape[0] - 1]
+        gs = {k: v[sample] for k, v in g_.items() if k in FWD_KEYS}
+        compare_forward(sysm, A_up, A_dn, R[sample], gs, mode)
+    P.close()
 
 
 def test_autotune_and_cache(tmp_path):
@@ -209,7 +290,7 @@ def test_autotune_and_cache(tmp_path):
     doc = json.load(open(cache))
     entries = doc["qslater_autotune"]
     assert len(entries) == 1 and entries[0]["batched"] == t["batched"]
-    assert entries[0]["adj_group"] == t["adj_group"] and entries[0]["gj_bias"] == t["gj_bias"]
+    assert all(entries[0][k] == t[k] for k in t)
     P.launch()
     tuned = _read(bufs)
     P0, b0 = _plan(items, mode, graph=False)
@@ -230,7 +311,10 @@ def test_autotune_and_cache(tmp_path):
     P3, _ = _plan(items3, mode, graph=False)
     P3.autotune(cache)
     assert len(json.load(open(cache))["qslater_autotune"]) == 2
-    for p_ in (P, P0, P2, P3):
+    # the caller's choice of the deterministic dA is kept
+    P4, _ = _plan(items3, mode, graph=False, tuning=dict(batched=1, adj_group=0, gj_bias=0, det_dA=1))
+    assert P4.autotune(None)["det_dA"] == 1
+    for p_ in (P, P0, P2, P3, P4):
         p_.close()
 
 
