@@ -217,7 +217,12 @@ typedef struct {
 
 /*
  * Backward: recomputes the AO values (never stored by the forward) and
- * accumulates dA = sum_w G chi over walkers, G = g D^-1.  dR: with drift
+ * accumulates dA = sum_w G chi over walkers, G = g D^-1: in FP32 by
+ * electron index (per electron and group of up to 1024 walkers, the slots
+ * that survive for some walker of the group, the walkers as the products'
+ * contraction dimension), in the other modes by ranges of 32 electrons over
+ * groups of up to 128 walkers; sums across groups are FP32 (FP64 in FP64
+ * mode) atomic adds, then added to dA in FP64.  dR: with drift
  * given, dR[w][e] = g[w][s(e)] drift[w][e] (0 where g = 0), since
  * d log|det D^s| / dr_e = sum_i D^-1[e][i] grad phi_i(r_e) is the drift
  * ("vector products" equations); without it, G A at the recomputed AO
@@ -252,7 +257,8 @@ typedef struct {
     int32_t batched;    /* 1: one launch per phase over the work list of all
                            systems; 0: one launch per system and spin       */
     int32_t adj_group;  /* walkers per dA group of the adjoint, 1..4096;
-                           0: min(W, 128) per system                          */
+                           0: min(W, 1024) for the FP32 dA by electron,
+                           min(W, 128) for the dA by 32-electron range     */
     int32_t gj_bias;    /* 0: the smallest Gauss-Jordan block shape holding
                            n; 1: the next larger one (when there is one)      */
     int32_t contract_tile; /* FP32 products: 0 = 256 MOs per workgroup, two
@@ -319,7 +325,7 @@ qsl_status qsl_plan_destroy(qsl_plan* plan);
 
 /*
  * Autotune: time every candidate tuning (batched 0/1 x adj_group in
- * {16, 32, 64, 128, 256} x gj_bias 0/1, then, from the fastest of those,
+ * {0, 16, 32, ..., 1024} x gj_bias 0/1, then, from the fastest of those,
  * the FP32 contraction tile and the persistent launch; det_dA stays as
  * set) on the bound buffers, keep the
  * fastest whose outputs pass a parity self-check against the default

@@ -741,6 +741,198 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
     }
 }
 
+// ------------------------------------------------- dA by electron (FP32)
+// dA[i][slot] += sum over the walkers w of a group of
+//   G_w[e][i] chi_slot(r_we),   G_w = g_w D_w^-1 (0 where g_w = 0),
+// for one electron index e at a time: its walkers share one exact slot list
+// (group_slots), so the products run over those slots only.  One 256-thread
+// workgroup per (electron, walker group, chunk stride, 224 MOs); it takes
+// the chunks cs, cs + DE_NCH, ... of 128 slots of the list.  Per chunk the
+// 224 x 128 block of dA stays in the accumulators (wave v: slot block v,
+// seven MO blocks) while the group's walkers stream through 32 at a time as
+// the contraction dimension (v_mfma_f32_32x32x2f32, k-step s taking walkers
+// 2s and 2s + 1); one atomic flush per chunk into the FP32 accumulator.
+// Per batch of 32 walkers: the G rows (FP32, written by the epilogue or the
+// g32 pre-pass) are copied from global memory straight into LDS while the
+// AO values of the batch are evaluated from the chunk's slot records (in
+// LDS), then the 16 k-steps run.
+constexpr int DE_NS = 128;  // slots per chunk (four waves x 32)
+constexpr int DE_MB = ADJ_MB;  // MOs per workgroup (seven blocks of 32)
+constexpr int DE_KW = 32;   // walkers per batch
+constexpr int DE_NCH = 4;   // chunk stride: workgroups per (electron, group, MO block)
+constexpr int DE_THREADS = 256;
+constexpr int DE_RQ = (int)(sizeof(SlotRec) / 16);  // 16-byte pieces of a slot record
+constexpr int DE_GP = DE_KW * DE_MB / 4;            // 16-byte pieces of a batch's G rows
+static_assert(DE_NS == (DE_THREADS / 64) * 32, "one 32-slot block per wave");
+static_assert(DE_GP % DE_THREADS == 0, "whole passes of the G copy");
+
+// Value of slot record r at electron p (FP32 AO arithmetic, FP64 screening
+// as in the forward).
+__device__ __forceinline__ float slot_value(const SlotRec& r, double T_thr, double px, double py, double pz) {
+    const double dx = px - r.pos[0], dy = py - r.pos[1], dz = pz - r.pos[2];
+    const double r2 = dist2_exact(dx, dy, dz);
+    float g = 0.f;
+    const int np = r.np;
+#pragma unroll 1
+    for (int k = 0; k < np; ++k) {
+        const double t = mul_exact(r.ex[k], r2);
+        if (t <= T_thr) g += r.c32[k] * exp_t(-(float)t);
+    }
+    const int pw = r.pw;
+    float p1, p2, p3, d, d2;
+    axis_pow(pw & 15, (float)dx, p1, d, d2);
+    axis_pow((pw >> 4) & 15, (float)dy, p2, d, d2);
+    axis_pow((pw >> 8) & 15, (float)dz, p3, d, d2);
+    return (r.f32 * p2 * p3) * p1 * g;
+}
+
+__device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
+    const DevSys& s = j.s;
+    const int n = j.n, gw = j.gw, spin = j.spin;
+    const int64_t W = j.W;
+    const int ngw = (int)((W + gw - 1) / gw);
+    const int cs = bx % DE_NCH, grp = bx / DE_NCH;
+    const int e = grp / ngw, g = grp % ngw;
+    const int nsl = j.gnwin[grp];
+    if (cs * DE_NS >= nsl) return;
+    const int* __restrict__ sl = j.gwin + (size_t)grp * WIN * s.n_win;
+    const int64_t w0 = (int64_t)g * gw;
+    const int nw = (int)min<int64_t>(gw, W - w0);
+    const int i0 = by * DE_MB;
+    const int ldg = g32_ld(n);
+    const int N = s.n_up + s.n_dn, eoff = spin ? s.n_up : 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double Tscr = readlane_f64(s.T, 0);
+    const float* __restrict__ G32 = j.g32;
+    const SlotRec* __restrict__ srec = s.slot_rec;
+    float* __restrict__ dA32 = j.dA32;
+
+    __shared__ double ep[DE_KW][3];
+    __shared__ __attribute__((aligned(16))) float X[DE_KW * DE_NS];
+    __shared__ __attribute__((aligned(16))) float G[DE_KW * DE_MB];
+    __shared__ __attribute__((aligned(16))) uint4 recq[DE_NS * DE_RQ];
+    __shared__ int qao[DE_NS];
+    auto pos_of = [&](int wb) -> double {  // coordinate tid of batch wb (tid < 96)
+        const int k = tid / 3;
+        return wb + k < nw ? j.R[((size_t)(w0 + wb + k) * N + eoff + e) * 3 + tid % 3] : 0.0;
+    };
+
+    for (int c0 = cs * DE_NS; c0 < nsl; c0 += DE_NCH * DE_NS) {
+        const int cnt = min(DE_NS, nsl - c0);
+        __syncthreads();  // the previous chunk's evaluation and flush are done with recq and qao
+        for (int p = tid; p < DE_NS * DE_RQ; p += DE_THREADS) {
+            const int ql = p / DE_RQ;
+            const int q = sl[c0 + min(ql, cnt - 1)];  // slots past the chunk repeat its last (their values are dropped)
+            recq[p] = ((const uint4*)(srec + q))[p % DE_RQ];
+        }
+        if (tid < DE_NS) qao[tid] = tid < cnt ? s.slot_ao[sl[c0 + tid]] : -1;
+        f32x16 acc[DE_MB / 32];
+#pragma unroll
+        for (int mb = 0; mb < DE_MB / 32; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+        double pnext = tid < DE_KW * 3 ? pos_of(0) : 0.0;
+        for (int wb = 0; wb < nw; wb += DE_KW) {
+            const int kw = min(DE_KW, nw - wb);
+            __syncthreads();  // the previous batch's products are done with X and G; recq and qao are visible
+            // G rows of the batch straight into LDS: piece p = 56 row + c of
+            // 16 bytes; rows past the group repeat its last walker (their
+            // AO values are zero)
+#pragma unroll
+            for (int ps = 0; ps < DE_GP / DE_THREADS; ++ps) {
+                const int p = ps * DE_THREADS + tid;
+                const int row = min(p / (DE_MB / 4), kw - 1), c = p % (DE_MB / 4);
+                const float* src = G32 + ((size_t)(w0 + wb + row) * n + e) * ldg + i0 + 4 * c;
+                __builtin_amdgcn_global_load_lds((const void*)src,
+                                                 (__attribute__((address_space(3))) void*)&G[(ps * DE_THREADS + wave * 64) * 4],
+                                                 16, 0, 0);
+            }
+            if (tid < DE_KW * 3) ep[tid / 3][tid % 3] = pnext;
+            __syncthreads();  // positions visible
+            if (tid < DE_KW * 3 && wb + DE_KW < nw) pnext = pos_of(wb + DE_KW);
+            // AO values: thread (slot tid % 128, walkers of parity tid / 128)
+            {
+                const int ql = tid & (DE_NS - 1);
+                const SlotRec& r = *(const SlotRec*)&recq[ql * DE_RQ];
+                const bool live = ql < cnt;
+#pragma unroll 1
+                for (int k = tid >> 7; k < DE_KW; k += 2) {
+                    float v = 0.f;
+                    if (live && k < kw) v = slot_value(r, Tscr, ep[k][0], ep[k][1], ep[k][2]);
+                    X[k * DE_NS + ql] = v;
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's copies into LDS have landed
+            __syncthreads();
+            if (wave * 32 < cnt) {
+                const int h = lane >> 5, c = lane & 31;
+#pragma unroll 4
+                for (int s2 = 0; s2 < DE_KW / 2; ++s2) {
+                    const int k = 2 * s2 + h;
+                    const float b = X[k * DE_NS + wave * 32 + c];
+#pragma unroll
+                    for (int mb = 0; mb < DE_MB / 32; ++mb) {
+                        if (i0 + mb * 32 < n) {  // uniform: MO blocks past n are skipped
+                            const float a = G[k * DE_MB + mb * 32 + c];
+                            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[mb], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        // flush: lanes of one register cover 32 consecutive slots of one MO
+        // row; row di of the lane's base row adds di N_b to its address (the
+        // base and row limit are made opaque here, so that the 112 row
+        // offsets are not computed ahead of the loop and held in registers)
+        if (wave * 32 < cnt) {
+            const int col = wave * 32 + (lane & 31);
+            const int ao = col < cnt ? qao[col] : -1;
+            int nbas = __builtin_amdgcn_readfirstlane(s.n_basis);
+            int lim = n - i0 - 4 * (lane >> 5);  // rows di < lim exist
+            asm volatile("" : "+s"(nbas));
+            asm volatile("" : "+v"(lim));
+            float* rowp = dA32 + (size_t)(i0 + 4 * (lane >> 5)) * nbas + max(ao, 0);
+#pragma unroll
+            for (int mb = 0; mb < DE_MB / 32; ++mb) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int di = mb * 32 + 8 * (r >> 2) + (r & 3);
+                    const float v = acc[mb][r];
+                    if (di < lim && ao >= 0 && v != 0.f) atomicAdd(rowp + (size_t)di * nbas, v);
+                }
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_kernel(Job j) { adj_dae_body(j, blockIdx.x, blockIdx.y); }
+
+__global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { adj_dae_body(j, bx, by); });
+}
+
+void adj_dae_grid(Job& j) {
+    j.gx = j.n * (int)((j.W + j.gw - 1) / j.gw) * DE_NCH;
+    j.gy = (j.n + DE_MB - 1) / DE_MB;
+    j.gz = 1;
+}
+
+hipError_t launch_adj_dae(const Job& j0, hipStream_t st) {
+    Job j = j0;
+    if (j.gw < 1 || j.mode != QSL_FP32 || !j.by_e || (j.n && j.W && j.dA32 && !j.g32)) return hipErrorInvalidValue;
+    adj_dae_grid(j);
+    if (!j.n || !j.W || !j.dA32) return hipSuccess;
+    adj_dae_kernel<<<dim3((unsigned)j.gx, j.gy), DE_THREADS, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_dae_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    adj_dae_batched<<<grid, DE_THREADS, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- G split
 // G = g D^-1 (0 where g = 0) rounded to FP32 and split hi = bf16(G),
 // lo = bf16(G - hi) (the arithmetic the dA kernel applied per window block

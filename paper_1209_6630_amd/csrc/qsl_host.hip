@@ -116,14 +116,18 @@ ProfScope::~ProfScope() {
 
 
 // Walkers per dA group: they share one window list (screened together).
-int bw_group(int64_t W) { return (int)std::min<int64_t>(W, 128); }
+// Default walkers per dA group: by electron, the groups are long (the
+// flush is one atomic per dA entry and group); by 32-electron range, the
+// group's window union stays small.
+int bw_group(int64_t W, bool by_e) { return (int)std::min<int64_t>(W, by_e ? 1024 : 128); }
 
 // Workspace layout.  The forward's regions come first: per spin,
 // tile_nwin[T_s] and tile_win[T_s][n_win], and the FP64 copy of the blocked
-// inversion; then the adjoint's: the same lists per walker group of gw
-// walkers, the FP32 dA accumulator and the split-BF16 G.  A forward-only
-// workspace ends at fwd_total.
-WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
+// inversion; then the adjoint's: the lists per walker group of gw walkers
+// (windows per 32-electron range, or slots per electron with by_e), the
+// FP32 dA accumulator and the split-BF16 G.  A forward-only workspace ends
+// at fwd_total.
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e) {
     WsLayout L{};
     size_t off = 0;
     L.job_off = off;
@@ -144,11 +148,13 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
     L.fwd_total = std::max<size_t>(off, 256);
     for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
-        size_t groups = n ? (size_t)tiles_per_walker(n) * ((W + gw - 1) / std::max(gw, 1)) : 0;
+        const size_t ngw = (size_t)((W + gw - 1) / std::max(gw, 1));
+        size_t groups = n ? (by_e ? (size_t)n : (size_t)tiles_per_walker(n)) * ngw : 0;
+        const size_t cap = by_e ? (size_t)WIN * d.n_win : (size_t)d.n_win;
         L.gnwin_off[s] = off;
         off = round_up(off + groups * sizeof(int), 256);
         L.gwin_off[s] = off;
-        off = round_up(off + groups * (size_t)d.n_win * sizeof(int), 256);
+        off = round_up(off + groups * cap * sizeof(int), 256);
     }
     for (int s = 0; s < 2; ++s) {
         L.dA32_off[s] = off;
@@ -158,6 +164,11 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode) {
         const int n = n_spin(d, s);
         L.gs_off[s] = off;
         if (mode == QSL_BF16X3 && n) off = round_up(off + (size_t)W * gsplit_elems(n) * 2 * sizeof(uint16_t), 256);
+    }
+    for (int s = 0; s < 2; ++s) {
+        const int n = n_spin(d, s);
+        L.g32_off[s] = off;
+        if (by_e && n) off = round_up(off + (size_t)W * n * g32_ld(n) * sizeof(float), 256);
     }
     L.total = std::max<size_t>(off, 256);
     return L;
@@ -189,7 +200,7 @@ Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws,
 }
 
 // The Job of one spin of an adjoint call.
-Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw) {
+Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw, bool by_e) {
     Job j{};
     j.s = sys->d;
     j.mo = sys->mo[s];
@@ -197,6 +208,7 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
     j.n = n_spin(sys->d, s);
     j.mode = a->mode;
     j.gw = gw;
+    j.by_e = by_e ? 1 : 0;
     j.W = a->W;
     j.R = a->R;
     j.nwin = (int*)(ws + L.nwin_off[s]);
@@ -211,6 +223,7 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
         if (a->mode == QSL_FP64) j.dA64 = a->dA[s];
         else j.dA32 = (float*)(ws + L.dA32_off[s]);
         if (a->mode == QSL_BF16X3) j.gsplit = (uint16_t*)(ws + L.gs_off[s]);
+        if (by_e) j.g32 = (float*)(ws + L.g32_off[s]);
     }
     return j;
 }
@@ -648,7 +661,8 @@ qsl_status qsl_workspace_size(const qsl_system* sys, int64_t W, int32_t mode, in
     if (W < 0) return bad(QSL_ERR_INVALID_ARG, "W < 0");
     if (mode < QSL_FP64 || mode > QSL_BF16X3) return bad(QSL_ERR_INVALID_ARG, "bad mode");
     if (what < QSL_WS_FORWARD || what > QSL_WS_BOTH) return bad(QSL_ERR_INVALID_ARG, "bad workspace selector");
-    const WsLayout L = ws_layout(sys->d, W, bw_group(W), mode);
+    const bool by_e = dA_by_electron(mode, false) && sys->d.n_win <= UNION_MAXWIN;
+    const WsLayout L = ws_layout(sys->d, W, bw_group(W, by_e), mode, by_e);
     *bytes = (what & QSL_WS_BACKWARD) ? L.total : L.fwd_total;
     return QSL_OK;
 }
@@ -681,7 +695,7 @@ static qsl_status forward_check(qsl_system* sys, const qsl_fwd_args* a) {
 // The forward's launches on workspace ws (at least the forward's part of
 // ws_layout); enqueues kernels only.
 static qsl_status forward_enqueue(qsl_system* sys, const qsl_fwd_args* a, char* ws, hipStream_t st) {
-    const WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
+    const WsLayout L = ws_layout(sys->d, a->W, 1, a->mode, false);  // the forward's part only
     hipError_t e;
     if (a->status && (e = fill_u32(a->status, 0u, a->W, st)) != hipSuccess) return hip_fail(e, "status clear");
     for (int s = 0; s < 2; ++s) {
@@ -740,7 +754,7 @@ extern "C" {
 qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
     qsl_status r = forward_check(sys, a);
     if (r != QSL_OK || a->W == 0) return r;
-    WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
+    WsLayout L = ws_layout(sys->d, a->W, 1, a->mode, false);
     if (!a->ws || a->ws_bytes < L.fwd_total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     return forward_enqueue(sys, a, (char*)a->ws, (hipStream_t)stream);
 }
@@ -748,7 +762,7 @@ qsl_status qsl_forward(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
 qsl_status qsl_forward_noalloc(qsl_system* sys, const qsl_fwd_args* a, void* stream) {
     qsl_status r = forward_check(sys, a);
     if (r != QSL_OK || a->W == 0) return r;
-    const WsLayout L = ws_layout(sys->d, a->W, bw_group(a->W), a->mode);
+    const WsLayout L = ws_layout(sys->d, a->W, 1, a->mode, false);
     if (L.fwd_total > (size_t)QSL_NOALLOC_SCRATCH_BYTES)
         return bad(QSL_ERR_WORKSPACE, "noalloc: the forward of this many walkers needs " + std::to_string(L.fwd_total) +
                                           " bytes of workspace, more than the " +
@@ -785,14 +799,16 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
             return bad(QSL_ERR_SHAPE, "the MO set of a spin has more rows than electrons (qsl_set_orbitals)");
         if (!a->Dinv[s]) return bad(QSL_ERR_INVALID_ARG, "NULL Dinv");
     }
-    WsLayout L = ws_layout(d, a->W, bw_group(a->W), a->mode);
+    const bool by_e = dA_by_electron(a->mode, false) && d.n_win <= UNION_MAXWIN;
+    const int gw = bw_group(a->W, by_e);
+    WsLayout L = ws_layout(d, a->W, gw, a->mode, by_e);
     if (!a->ws || a->ws_bytes < L.total) return bad(QSL_ERR_WORKSPACE, "workspace missing or too small");
     char* ws = (char*)a->ws;
     // with the drift, dR is written whole (every electron of both spins)
     if (a->dR && !a->drift && (e = fill_f64(a->dR, 0.0, a->W * N * 3, st)) != hipSuccess)
         return hip_fail(e, "dR clear");
     for (int s = 0; s < 2; ++s) {
-        Job j = bwd_job(sys, a, L, ws, s, bw_group(a->W));
+        Job j = bwd_job(sys, a, L, ws, s, gw, by_e);
         if (!j.n) continue;
         const bool f32acc = j.dA32 != nullptr;
         if (f32acc && (e = fill_u32((uint32_t*)j.dA32, 0u, (int64_t)j.n * d.n_basis, st)) != hipSuccess)
@@ -808,7 +824,24 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
             ProfScope ps("adjoint_h", st);
             if ((e = launch_adj_h(j, st)) != hipSuccess) return hip_fail(e, "adjoint H kernel");
         }
-        if (a->dA[s]) {
+        if (a->dA[s] && by_e) {
+            // the tile lists (as the forward screens them), then the slot
+            // lists of the (electron, walker group) pairs
+            if (!(a->dR && !a->drift)) {
+                ProfScope ps("screen", st);
+                if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
+            }
+            {
+                ProfScope ps("screen_group", st);
+                if ((e = launch_group_slots(j, st)) != hipSuccess) return hip_fail(e, "group slot kernel");
+            }
+            {
+                ProfScope ps("g32", st);
+                if ((e = launch_g32(j, st)) != hipSuccess) return hip_fail(e, "G kernel");
+            }
+            ProfScope ps("adjoint_dA", st);
+            if ((e = launch_adj_dae(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");
+        } else if (a->dA[s]) {
             {
                 ProfScope ps("screen_group", st);
                 if ((e = launch_screen(j, 1, st)) != hipSuccess) return hip_fail(e, "group screen kernel");

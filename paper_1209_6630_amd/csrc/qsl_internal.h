@@ -312,6 +312,12 @@ struct Job {
     // plain loads and stores; the partials are reduced in a fixed order.
     void* dApart;
     int t_fix = -1;
+    // dA by electron index: gnwin / gwin hold, per (electron, walker group
+    // of gw walkers), the count and ascending list of the group's slots;
+    // g32 = G = g D^-1 in FP32, [W][n][g32_ld(n)] (0 where g = 0 and past
+    // n), written by the epilogue or a pre-pass
+    int by_e;
+    float* g32;
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 // Bytes of the device Job copy of a per-system launch (Job, then two ints).
@@ -399,7 +405,12 @@ size_t round_up(size_t x, size_t a);
 hipError_t fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t st);
 // Default walkers per dA group: they share one window list.
-int bw_group(int64_t W);
+int bw_group(int64_t W, bool by_e);
+// The adjoint's dA runs by electron index (walker groups of one electron,
+// an exact slot list per group, walkers as the contraction dimension) in
+// FP32 unless the deterministic reduction is asked for; by 32-electron
+// ranges otherwise.
+inline bool dA_by_electron(int mode, bool det) { return mode == QSL_FP32 && !det; }
 
 // Workspace of one system: byte offsets of the per-spin tile and group
 // window lists and of the FP32 dA accumulator.
@@ -415,14 +426,14 @@ __host__ __device__ inline int64_t gsplit_elems(int n) {
 
 struct WsLayout {
     size_t job_off;  // the device Job copy of per-system launches
-    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2];
+    size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2], g32_off[2];
     size_t fwd_total;  // end of the forward's regions (tile lists, blocked-inversion copy)
     size_t total;      // end of the adjoint's regions
 };
-WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode);
+WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e);
 // The Job of spin s of a forward / adjoint call on workspace ws.
 Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s);
-Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw);
+Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw, bool by_e);
 
 // ------------------------------------------------------------- launchers
 
@@ -440,6 +451,11 @@ int screen_blocks(const Job& j, int group);
 constexpr int UNION_MAXWIN = 8192;
 hipError_t launch_group_union(const Job& j, hipStream_t st);
 hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
+// Slot lists of the dA by electron (Job.by_e): one block per (electron,
+// walker group), from the tile lists; systems of at most UNION_MAXWIN windows.
+int group_slots_blocks(const Job& j);
+hipError_t launch_group_slots(const Job& j, hipStream_t st);
+hipError_t launch_group_slots_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_screen(const Job& j, int group, hipStream_t st);
 hipError_t launch_screen_batched(const Job* jobs, const int* prefix, int njobs, int grid, int group,
                                     hipStream_t st);
@@ -466,7 +482,14 @@ hipError_t launch_gjb_batched(int mode, const Job* jobs, const int* prefix, int 
 hipError_t launch_gj(const Job& j, hipStream_t st);
 hipError_t launch_gj_batched(int mode, int v, const Job* jobs, const int* prefix, int njobs, int grid,
                              hipStream_t st);
-// Drift and Laplacian (four electrons per block).
+// Row length of the FP32 G of the dA by electron: whole blocks of 224 MOs.
+__host__ __device__ inline int g32_ld(int n) { return (n + ADJ_MB - 1) / ADJ_MB * ADJ_MB; }
+// G = g D^-1 in FP32 (Job.g32) for walkers bound without the epilogue.
+int g32_blocks(const Job& j);
+hipError_t launch_g32(const Job& j, hipStream_t st);
+hipError_t launch_g32_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
+// Drift and Laplacian (four electrons per block); with Job.g32 set the same
+// pass writes G = g D^-1 in FP32 for the dA by electron.
 int epilogue_blocks(const Job& j);
 // dR of one spin from the forward's drift: dR[w][e] = g[w][s] drift[w][e].
 int dr_drift_blocks(const Job& j);
@@ -494,6 +517,11 @@ hipError_t launch_adj_h_batched(int mode, const Job* jobs, const int* prefix, in
                                    hipStream_t st);
 hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, int njobs, int grid,
                                     hipStream_t st);
+// dA by electron (FP32, Job.by_e): grid (electron x walker group x chunk
+// stride, MO blocks of 224) over the group slot lists.
+void adj_dae_grid(Job& j);
+hipError_t launch_adj_dae(const Job& j, hipStream_t st);
+hipError_t launch_adj_dae_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
 // dA = [dA +] sum_p part[p] (p ascending; float or double partials).
 hipError_t launch_reduce_dA(const void* part, bool fp64, int npart, int64_t count, double* dA, int accumulate,

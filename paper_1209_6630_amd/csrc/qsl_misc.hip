@@ -119,6 +119,9 @@ __device__ __forceinline__ void epilogue_body(const Job& j, int bx) {
     const double* d = Dinv + (w * n + e) * n;
     const size_t nn = (size_t)n * n;
     const Tc* Cw = C + (size_t)w * 5 * nn + (size_t)e * n;
+    // G row of the dA by electron (FP32 mode with that adjoint)
+    float* __restrict__ grow = j.g32 ? j.g32 + (size_t)(w * n + e) * g32_ld(n) : nullptr;
+    const double gv = grow ? j.g[2 * w + spin] : 0.0;
     double acc[4] = {0, 0, 0, 0};
     // four strides of 64 per pass, their loads issued together (clamped
     // addresses; past n nothing is added)
@@ -137,8 +140,11 @@ __device__ __forceinline__ void epilogue_body(const Job& j, int bx) {
             if (i0 + 64 * u + lane < n) {
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[c] = fma(di[u], (double)cv[u][c], acc[c]);
+                if (grow) gmem(grow)[i0 + 64 * u + lane] = gv != 0.0 ? (float)(gv * di[u]) : 0.f;
             }
     }
+    if (grow)
+        for (int i = n + lane; i < g32_ld(n); i += 64) gmem(grow)[i] = 0.f;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1)
 #pragma unroll
@@ -165,6 +171,40 @@ __global__ __launch_bounds__(256) void epilogue_batched(const Job* jobs, const i
 }
 
 int epilogue_blocks(const Job& j) { return (int)((j.W * j.n + 3) / 4); }
+
+// G = g D^-1 rounded to FP32 (0 where g = 0, and past n), [W][n][g32_ld(n)]:
+// the dA by electron's operand, for walkers bound without the epilogue.
+__device__ __forceinline__ void g32_body(const Job& j, int bx) {
+    const int n = j.n, ld = g32_ld(n);
+    const int64_t q = (int64_t)bx * 256 + threadIdx.x;
+    if (q >= j.W * n * ld) return;
+    const int i = (int)(q % ld);
+    const int64_t we = q / ld;  // w * n + e
+    const double gv = j.g[2 * (we / n) + j.spin];
+    float v = 0.f;
+    if (i < n && gv != 0.0) v = (float)(gv * gmem(j.Dinv)[we * n + i]);
+    gmem(j.g32)[q] = v;
+}
+
+__global__ __launch_bounds__(256) void g32_kernel(Job j) { g32_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(256) void g32_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { g32_body(j, bx); });
+}
+
+int g32_blocks(const Job& j) { return (int)((j.W * j.n * g32_ld(j.n) + 255) / 256); }
+
+hipError_t launch_g32(const Job& j, hipStream_t st) {
+    if (!j.g32 || !j.n || !j.W) return hipSuccess;
+    g32_kernel<<<(unsigned)g32_blocks(j), 256, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_g32_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    g32_batched<<<grid, 256, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
 
 hipError_t launch_epilogue(const Job& j0, hipStream_t st) {
     Job j = j0;

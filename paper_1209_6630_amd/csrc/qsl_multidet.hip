@@ -111,7 +111,7 @@ struct MDLayout {
 
 static MDLayout md_layout(const DevSys& d, const DevMO mo[2], int64_t W, int mode, int n_det) {
     MDLayout L{};
-    L.base = ws_layout(d, W, bw_group(W), mode);
+    L.base = ws_layout(d, W, 1, mode, false);  // the forward's part
     size_t off = L.base.fwd_total;
     const size_t cb = mode == QSL_FP64 ? 8 : 4;
     const int N = d.n_up + d.n_dn;

@@ -32,7 +32,10 @@ enum Phase {
     PH_ADJ_H,        // H = G A, dR (no drift bound)
     PH_SCREEN_G,     // per walker-group window lists
     PH_GSPLIT,       // split-BF16 G^T for dA (BF16X3)
-    PH_ADJ_DA,       // dA
+    PH_ADJ_DA,       // dA by 32-electron range
+    PH_SLOTS_G,      // dA by electron: the (electron, walker group) slot lists
+    PH_G32,          // dA by electron: G = g D^-1 in FP32 where no epilogue writes it
+    PH_ADJ_DAE,      // dA by electron
     PH_COUNT
 };
 
@@ -88,9 +91,15 @@ static void drop_graph(qsl_plan* p) {
     p->graph = nullptr;
 }
 
+// The plan's dA runs by electron (FP32 without det_dA, systems whose
+// windows fit the slot screen's bitmap) or by 32-electron range.
+static bool plan_by_e(const qsl_plan* p, int i) {
+    return dA_by_electron(p->mode, p->tune.det_dA != 0) && p->sys[i]->d.n_win <= UNION_MAXWIN;
+}
+
 static int plan_gw(const qsl_plan* p, int i) {
     const int64_t W = std::max<int64_t>(p->W[i], 1);
-    return p->tune.adj_group > 0 ? (int)std::min<int64_t>(p->tune.adj_group, W) : bw_group(W);
+    return p->tune.adj_group > 0 ? (int)std::min<int64_t>(p->tune.adj_group, W) : bw_group(W, plan_by_e(p, i));
 }
 
 // Jobs in falling order of n (the larger systems' blocks start first);
@@ -124,7 +133,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     size_t total = 256;  // the item counter
     for (int i = 0; i < p->n_sys; ++i) {
         p->gw[i] = plan_gw(p, i);
-        p->lay[i] = ws_layout(p->sys[i]->d, p->W[i], p->gw[i], p->mode);
+        p->lay[i] = ws_layout(p->sys[i]->d, p->W[i], p->gw[i], p->mode, plan_by_e(p, i));
         p->ws_off[i] = total;
         total = round_up(total + p->lay[i].total, 256);
     }
@@ -158,7 +167,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
             f.f32_tile = p->tune.contract_tile;
             p->fjobs.push_back(f);
             if (p->has_bwd[i]) {
-                Job b = bwd_job(p->sys[i], &p->bwd[i], p->lay[i], ws + p->ws_off[i], s, p->gw[i]);
+                Job b = bwd_job(p->sys[i], &p->bwd[i], p->lay[i], ws + p->ws_off[i], s, p->gw[i], plan_by_e(p, i));
                 if (det && part_off[2 * i + s] && (b.dA64 || b.dA32)) b.dApart = ws + part_off[2 * i + s];
                 p->bjobs.push_back(b);
             }
@@ -192,6 +201,13 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
                 j.gx = epilogue_g_blocks(j); j.gy = 1; j.gz = 1;
                 p->ph[PH_EPI_G].jobs.push_back(j);
             } else {
+                // FP32 with the dA by electron: the epilogue also writes G
+                for (const Job& b : p->bjobs)
+                    if (b.g32 && b.by_e && (b.dA64 || b.dA32) && b.Dinv == f.Dinv && b.spin == f.spin &&
+                        b.W == f.W && b.n == f.n) {
+                        j.g = b.g;
+                        j.g32 = b.g32;
+                    }
                 j.gx = epilogue_blocks(j); j.gy = 1; j.gz = 1;
                 p->ph[PH_EPILOGUE].jobs.push_back(j);
             }
@@ -212,7 +228,21 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
             adj_h_grid(j);
             p->ph[PH_ADJ_H].jobs.push_back(j);
         }
-        if (b.dA64 || b.dA32) {
+        if ((b.dA64 || b.dA32) && b.by_e) {
+            j = b;
+            j.gx = group_slots_blocks(j); j.gy = 1; j.gz = 1;
+            p->ph[PH_SLOTS_G].jobs.push_back(j);
+            bool g_written = false;
+            for (const Job& ej : p->ph[PH_EPILOGUE].jobs) g_written |= ej.g32 == b.g32;
+            if (!g_written) {
+                j = b;
+                j.gx = g32_blocks(j); j.gy = 1; j.gz = 1;
+                p->ph[PH_G32].jobs.push_back(j);
+            }
+            j = b;
+            adj_dae_grid(j);
+            p->ph[PH_ADJ_DAE].jobs.push_back(j);
+        } else if (b.dA64 || b.dA32) {
             j = b;
             j.gx = screen_blocks(j, 1); j.gy = 1; j.gz = 1;
             p->ph[PH_SCREEN_G].jobs.push_back(j);
@@ -431,6 +461,27 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
                                               SG.blocks(), 1, st);
             if (e != hipSuccess) return hip_fail(e, "group screen kernel");
         }
+        auto& SL = p->ph[PH_SLOTS_G];
+        if (SL.blocks()) {
+            ProfScope ps("screen_group", st);
+            if ((e = launch_group_slots_batched(dev_jobs(p, PH_SLOTS_G), dev_prefix(p, PH_SLOTS_G), (int)SL.jobs.size(),
+                                                SL.blocks(), st)) != hipSuccess)
+                return hip_fail(e, "group slot kernel");
+        }
+        auto& G3 = p->ph[PH_G32];
+        if (G3.blocks()) {
+            ProfScope ps("g32", st);
+            if ((e = launch_g32_batched(dev_jobs(p, PH_G32), dev_prefix(p, PH_G32), (int)G3.jobs.size(), G3.blocks(),
+                                        st)) != hipSuccess)
+                return hip_fail(e, "G kernel");
+        }
+        auto& DE = p->ph[PH_ADJ_DAE];
+        if (DE.blocks()) {
+            ProfScope ps("adjoint_dA", st);
+            if ((e = launch_adj_dae_batched(dev_jobs(p, PH_ADJ_DAE), dev_prefix(p, PH_ADJ_DAE), (int)DE.jobs.size(),
+                                            DE.blocks(), st)) != hipSuccess)
+                return hip_fail(e, "adjoint dA kernel");
+        }
         auto& GS = p->ph[PH_GSPLIT];
         if (GS.blocks()) {
             ProfScope ps("g_split", st);
@@ -460,6 +511,18 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             ProfScope ps("screen_group", st);
             e = j.s.n_win <= UNION_MAXWIN ? launch_group_union(j, st) : launch_screen(j, 1, st);
             if (e != hipSuccess) return hip_fail(e, "group screen kernel");
+        }
+        for (const Job& j : p->ph[PH_SLOTS_G].jobs) {
+            ProfScope ps("screen_group", st);
+            if ((e = launch_group_slots(j, st)) != hipSuccess) return hip_fail(e, "group slot kernel");
+        }
+        for (const Job& j : p->ph[PH_G32].jobs) {
+            ProfScope ps("g32", st);
+            if ((e = launch_g32(j, st)) != hipSuccess) return hip_fail(e, "G kernel");
+        }
+        for (const Job& j : p->ph[PH_ADJ_DAE].jobs) {
+            ProfScope ps("adjoint_dA", st);
+            if ((e = launch_adj_dae(j, st)) != hipSuccess) return hip_fail(e, "adjoint dA kernel");
         }
         for (const Job& j : p->ph[PH_GSPLIT].jobs) {
             ProfScope ps("g_split", st);
@@ -892,7 +955,7 @@ static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& k
     for (int bt = 1; bt >= 0; --bt)
         for (int gb = 0; gb <= 1; ++gb) {
             if (gb && gj_variant(nmax) >= 3) continue;  // no larger block shape
-            const int groups[] = {0, 16, 32, 64, 128, 256};
+            const int groups[] = {0, 16, 32, 64, 128, 256, 512, 1024};
             for (int g : groups) {
                 if (!any_bwd && g) continue;
                 if (g > 16 && g >= 2 * wmax) continue;  // the same as a smaller group for every system

@@ -257,4 +257,155 @@ hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int nj
     return hipGetLastError();
 }
 
+// Slot lists of the adjoint's dA by electron: for walker group g (gw
+// walkers) of electron index e, the ascending slots whose smallest exponent
+// passes the screening test, gmin r^2 <= T in the exact FP64 arithmetic of
+// the forward, for at least one walker of the group: every slot with a
+// surviving primitive for some walker, and only those (a slot none of whose
+// primitives survives for any walker adds nothing).  Candidates are the
+// windows of the forward's tile lists of electron e over the group's walker
+// blocks; each wave decides whole windows, stopping early once every slot
+// of a window is in.  Output: gnwin[group] and gwin[group][WIN * n_win].
+constexpr int GS_POS = 512;  // walker positions staged in LDS at a time
+
+__device__ __forceinline__ void group_slots_body(const Job& j, int bx) {
+    __shared__ uint32_t bits[UNION_MAXWIN / 32];
+    __shared__ int uw[UNION_MAXWIN];
+    __shared__ uint8_t sm[UNION_MAXWIN];
+    __shared__ double ep[GS_POS][3];
+    __shared__ int wtot[SCREEN_THREADS / 64];
+    const DevSys& s = j.s;
+    const int nwin_all = s.n_win;
+    const int64_t W = j.W;
+    const int gw = j.gw;
+    const int ngw = (int)((W + gw - 1) / gw);
+    const int e = bx / ngw, g = bx % ngw;
+    const int64_t w0 = (int64_t)g * gw, wend = min<int64_t>(W, w0 + gw);
+    const int N = s.n_up + s.n_dn, eoff = j.spin ? s.n_up : 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int NWAVE = SCREEN_THREADS / 64;
+    const double T = s.T;
+    const int nwords = (nwin_all + 31) / 32;
+    if (tid < nwords) bits[tid] = 0u;
+    __syncthreads();
+    // candidate windows: the union of the tile lists of electron e
+    const int wbk = walker_blocks(W);
+    const int b0 = (int)(w0 / TE), nb = (int)((wend - 1) / TE) - b0 + 1;
+    for (int tt = wave; tt < nb; tt += NWAVE) {
+        const int tile = e * wbk + b0 + tt;
+        const int cnt = j.nwin[tile];
+        const int* lst = j.win + (size_t)tile * nwin_all;
+        for (int q = lane; q < cnt; q += 64) {
+            const int wd = lst[q];
+            atomicOr(&bits[wd >> 5], 1u << (wd & 31));
+        }
+    }
+    __syncthreads();
+    int U;
+    {
+        const uint32_t word = tid < nwords ? bits[tid] : 0u;
+        const int c = __popc(word);
+        int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wtot[wave] = x;
+        __syncthreads();
+        int off = 0;
+        U = 0;
+        for (int v = 0; v < NWAVE; ++v) {
+            if (v < wave) off += wtot[v];
+            U += wtot[v];
+        }
+        int pos = off + x - c;
+        for (uint32_t wd = word; wd; wd &= wd - 1) uw[pos++] = tid * 32 + __builtin_ctz(wd);
+    }
+    for (int k = tid; k < U; k += SCREEN_THREADS) sm[k] = 0;
+    // slot masks, positions staged GS_POS walkers at a time
+    const SlotRec* __restrict__ srec = s.slot_rec;
+    for (int64_t p0 = w0; p0 < wend; p0 += GS_POS) {
+        const int np = (int)min<int64_t>(GS_POS, wend - p0);
+        __syncthreads();  // uw / sm written; the previous positions are no longer read
+        for (int q = tid; q < np * 3; q += SCREEN_THREADS)
+            ep[q / 3][q % 3] = j.R[((size_t)(p0 + q / 3) * N + eoff + e) * 3 + q % 3];
+        __syncthreads();
+        for (int k = wave; k < U; k += NWAVE) {
+            const SlotRec* rq = srec + (size_t)uw[k] * WIN;
+            uint32_t full = 0;
+            double gm[WIN];
+#pragma unroll
+            for (int jj = 0; jj < WIN; ++jj) {
+                gm[jj] = rq[jj].gmin;
+                full |= (gm[jj] < INFINITY ? 1u : 0u) << jj;
+            }
+            uint32_t m = sm[k];
+            const double qx = rq->pos[0], qy = rq->pos[1], qz = rq->pos[2];
+            for (int wl = 0; wl < np && m != full; wl += 64) {
+                uint32_t mine = 0;
+                if (wl + lane < np) {
+                    const double r2 = dist2_exact(ep[wl + lane][0] - qx, ep[wl + lane][1] - qy, ep[wl + lane][2] - qz);
+#pragma unroll
+                    for (int jj = 0; jj < WIN; ++jj)
+                        if (!((m >> jj) & 1u) && mul_exact(gm[jj], r2) <= T) mine |= 1u << jj;
+                }
+#pragma unroll
+                for (int jj = 0; jj < WIN; ++jj) m |= (__ballot((mine >> jj) & 1u) != 0ull ? 1u : 0u) << jj;
+            }
+            if (lane == 0) sm[k] = (uint8_t)m;
+        }
+    }
+    __syncthreads();
+    // compaction: thread tid takes windows [k0, k1) in order
+    const int per = (U + SCREEN_THREADS - 1) / SCREEN_THREADS;
+    const int k0 = min(U, tid * per), k1 = min(U, k0 + per);
+    int c = 0;
+    for (int k = k0; k < k1; ++k) c += __popc((uint32_t)sm[k]);
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();  // wtot of the window compaction is no longer read
+    if (lane == 63) wtot[wave] = x;
+    __syncthreads();
+    int off = 0;
+    for (int v = 0; v < wave; ++v) off += wtot[v];
+    int pos = off + x - c;
+    int* out = j.gwin + (size_t)bx * WIN * nwin_all;
+    for (int k = k0; k < k1; ++k)
+        for (uint32_t mm = sm[k]; mm; mm &= mm - 1) out[pos++] = uw[k] * WIN + __builtin_ctz(mm);
+    if (tid == SCREEN_THREADS - 1) j.gnwin[bx] = off + x;
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void group_slots_kernel(Job j) { group_slots_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(SCREEN_THREADS) void group_slots_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { group_slots_body(j, bx); });
+}
+
+int group_slots_blocks(const Job& j) {
+    if (!j.n || !j.W || j.gw < 1) return 0;
+    return j.n * (int)((j.W + j.gw - 1) / j.gw);
+}
+
+hipError_t launch_group_slots(const Job& j, hipStream_t st) {
+    if (j.gw < 1 || j.s.n_win > UNION_MAXWIN) return hipErrorInvalidValue;
+    const int blocks = group_slots_blocks(j);
+    if (!blocks) return hipSuccess;
+    Job jj = j;
+    jj.gx = blocks; jj.gy = 1; jj.gz = 1;
+    group_slots_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(jj);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_slots_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    group_slots_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
 }  // namespace qsl

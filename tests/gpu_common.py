@@ -29,6 +29,33 @@ def tol_C(mode, nnz_max):
     return base if mode == "fp32" else base + 3 * 2.0 ** -16
 
 
+def default_dA_group(mode, W, det=False):
+    """Walkers per dA walker group when the tuning leaves adj_group at 0:
+    1024 for the FP32 dA by electron index, 128 for the dA by 32-electron
+    range (FP64, split BF16, and FP32 with the deterministic reduction)."""
+    return min(W, 1024 if mode == "fp32" and not det else 128)
+
+
+def dA_tol(mode, W, n, gw=None, det=False):
+    """Worst-case bound on |dA_gpu - dA| / bA (bA: the oracle's sum of
+    absolute values of the terms), FP32 and split-BF16 modes: 64 u32 for
+    the FP32 AO value, 1 u32 for the FP32 rounding of G = g D^-1, and the
+    longest chain m of FP32 additions into one dA element:
+      by electron (FP32): the gw walkers of a group in one MFMA
+        accumulator, then one atomic add per (electron, walker group):
+        m = gw + ceil(W / gw) n;
+      by 32-electron range: gw walkers of 32 electrons with up to three
+        split products per term, then one atomic add per (walker group,
+        electron range): m = 3 gw 32 + ceil(W / gw) ceil(n / 32);
+    plus 3 2^-16 for the split-BF16 products."""
+    gw = gw or default_dA_group(mode, W, det)
+    if mode == "fp32" and not det:
+        m = gw + -(-W // gw) * n
+    else:
+        m = 3 * gw * 32 + -(-W // gw) * -(-n // 32)
+    return (64 + 1 + m) * U32 + (3 * 2.0 ** -16 if mode == "bf16x3" else 0.0)
+
+
 def max_survivors(sysm, R):
     return max(oracle.ao_eval(sysm, r)[0].size for r in R.reshape(-1, 3))
 

@@ -1,6 +1,8 @@
 """The HIP path against the FP64 oracle at the batch sizes the benchmark runs:
-the adjoint of the 434-electron plan over 1024 walkers (eight walker groups,
-FP32 atomic accumulation across groups), the 1731-electron plan over its 512
+the adjoint of the 434-electron plan over 1024 walkers (FP32 dA by electron
+in one group of 1024 walkers or eight of 128, by 32-electron range with the
+deterministic reduction, split BF16; FP32 atomics across groups), the
+1731-electron plan over its 512
 walkers (forward on sampled walkers, dA over 64 of them), the FP64 adjoint
 through the oracle's own inverse (the whole chain), and the screening's
 survivor sets compared bit for bit.
@@ -8,13 +10,16 @@ survivor sets compared bit for bit.
 Bounds (u32 = 2^-24; bA, bR are the oracle's sums of absolute values of
 every term of dA and dR, oracle.backward(..., want_abs=True)):
   dA   FP32 / BF16X3: (64 + 1 + m) u32 bA  [+ 3 * 2^-16 bA in BF16X3]
-       with m = 3 gw 32 + ceil(W / gw) ceil(n / 32) the longest chain of FP32
-       additions into one dA element: gw walkers of a group, 32 electrons
-       each, at most three split products per term, accumulated in one MFMA
-       accumulator, then one atomic add per (walker group, electron range);
-       64 u32 covers the FP32 AO value, 1 u32 the FP32 rounding of G = g D^-1,
-       3 * 2^-16 the split-BF16 products (hi*hi + hi*lo + lo*hi: the dropped
-       lo*lo and the bf16 rounding of both lo parts).
+       (tests/gpu_common.py dA_tol) with m the longest chain of FP32
+       additions into one dA element: by electron (FP32), m = gw +
+       ceil(W / gw) n (the group's walkers in one MFMA accumulator, then one
+       atomic add per (electron, walker group)); by 32-electron range,
+       m = 3 gw 32 + ceil(W / gw) ceil(n / 32) (gw walkers of 32 electrons,
+       at most three split products per term, then one atomic add per
+       (walker group, electron range)); 64 u32 covers the FP32 AO value,
+       1 u32 the FP32 rounding of G = g D^-1, 3 * 2^-16 the split-BF16
+       products (hi*hi + hi*lo + lo*hi: the dropped lo*lo and the bf16
+       rounding of both lo parts).
   dR   (the plan takes dR = g * drift, the drift from the forward's C):
        tol_C bR + 1e-12 bR, the forward's product bound carried through the
        drift sum, plus its FP64 rounding.
@@ -30,16 +35,16 @@ import pytest
 
 import oracle
 import qsl_synth as q
-from tests.gpu_common import U32, compare_forward, max_survivors, tol_C
+from tests.gpu_common import U32, compare_forward, dA_tol, default_dA_group, max_survivors, tol_C
 
 pytestmark = pytest.mark.gpu
 
 TE = 32
 
 
-def _plan_run(sysm, A_up, A_dn, R, mode, g, keep_walkers=None):
+def _plan_run(sysm, A_up, A_dn, R, mode, g, keep_walkers=None, tuning=None):
     """Forward + adjoint of one system through an eager plan with the default
-    tuning (as the benchmark's plan).  Returns numpy copies of log|det|,
+    tuning (as the benchmark's plan) or `tuning`.  Returns numpy copies of log|det|,
     sign, status, drift, dR and dA, and of D^-1 and C for keep_walkers
     (all walkers when None)."""
     import torch
@@ -56,6 +61,8 @@ def _plan_run(sysm, A_up, A_dn, R, mode, g, keep_walkers=None):
           torch.empty((S.n_dn, S.n_basis), dtype=torch.float64, device="cuda"))
     P = Plan([S], [W], mode, graph=False)
     P.bind(0, Rt, out, g=gt, dR=dR, dA=dA)
+    if tuning is not None:
+        P.tuning = tuning
     P.launch()
     torch.cuda.synchronize()
     idx = torch.arange(W, device="cuda") if keep_walkers is None else torch.as_tensor(keep_walkers, device="cuda")
@@ -64,18 +71,14 @@ def _plan_run(sysm, A_up, A_dn, R, mode, g, keep_walkers=None):
         res[k] = out[k].index_select(0, idx).cpu().numpy()
     res["dR"] = dR.cpu().numpy()
     res["dA_up"], res["dA_dn"] = dA[0].cpu().numpy(), dA[1].cpu().numpy()
-    res["gw"] = P.tuning["adj_group"] or min(W, 128)
+    t = P.tuning
+    res["det"] = bool(t["det_dA"])
+    res["gw"] = t["adj_group"] or default_dA_group(mode, W, res["det"])
     P.close()
     S.close()
     del out, Rt, dR, dA
     torch.cuda.empty_cache()
     return res
-
-
-def _dA_tol(mode, W, gw, n):
-    m = 3 * gw * TE + math.ceil(W / gw) * math.ceil(n / TE)
-    t = (64 + 1 + m) * U32
-    return t + (3 * 2.0 ** -16 if mode == "bf16x3" else 0.0)
 
 
 def _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W_plan, group_of=None):
@@ -89,7 +92,7 @@ def _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W_plan, group_of=
     rdR, rdAu, rdAd, (bR, bAu, bAd) = oracle.backward(sysm, A_up, A_dn, R, Du, Dd, g, want_abs=True)
     for s, (got, want, b) in enumerate([(res["dA_up"], rdAu, bAu), (res["dA_dn"], rdAd, bAd)]):
         n = sysm.n_dn if s else sysm.n_up
-        tol = _dA_tol(mode, W, gw, n)
+        tol = dA_tol(mode, W, n, gw, det=res.get("det", False))
         err = np.abs(got - want)
         assert np.all(err <= tol * b + 1e-300), (s, float((err / (b + 1e-300)).max()), tol)
         print(f"  dA spin {s}: max |err| / bA = {float((err / (b + 1e-300)).max()):.3e} (bound {tol:.3e}), "
@@ -110,20 +113,23 @@ def _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W_plan, group_of=
             assert np.linalg.norm(got - want) <= 0.01 * smallest, (np.linalg.norm(got - want), smallest)
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
-def test_adjoint_434e_plan_1024_walkers(mode):
-    """dA over 1024 walkers (eight groups of 128, seven electron ranges per
-    spin, FP32 atomics across them) and dR of every walker against the
-    oracle, through the benchmark's plan."""
+@pytest.mark.parametrize("mode,tuning", [("fp32", None), ("fp32", dict(adj_group=128)),
+                                         ("fp32", dict(det_dA=1)), ("bf16x3", None)])
+def test_adjoint_434e_plan_1024_walkers(mode, tuning):
+    """dA over 1024 walkers and dR of every walker against the oracle,
+    through the benchmark's plan: FP32 by electron (one group of 1024, or
+    eight of 128), FP32 by 32-electron range with the deterministic
+    reduction (eight groups of 128), split BF16 (eight groups of 128, seven
+    electron ranges per spin); FP32 atomics across groups and ranges."""
     W = 1024
-    print(f"[case] adjoint 434e plan W={W} mode={mode}", flush=True)
+    print(f"[case] adjoint 434e plan W={W} mode={mode} tuning={tuning}", flush=True)
     sysm, A_up, A_dn, R = q.make_config("434e", W=W)
     g = np.random.default_rng(11).normal(size=(W, 2))
-    res = _plan_run(sysm, A_up, A_dn, R, mode, g)
+    res = _plan_run(sysm, A_up, A_dn, R, mode, g, tuning=tuning)
     sing = (res["status"] & 1) != 0
     assert not sing.any()
     gw = res["gw"]
-    assert math.ceil(W / gw) >= 8
+    assert math.ceil(W / gw) >= (1 if mode == "fp32" and not tuning else 8)
     nnz = max_survivors(sysm, R[:2])
     _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W, group_of=np.arange(W) // gw)
 

@@ -116,15 +116,16 @@ def test_plan_equals_per_system_calls(mode, graph):
     P.close()
 
 
+@pytest.mark.parametrize("mode", ["bf16x3", "fp32"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_plan_without_drift_splits_g_itself(graph):
-    """A BF16X3 plan bound without drift and Laplacian outputs: dR comes
-    from recomputed AO gradients and the split G from its own pre-pass (no
-    epilogue to write it); equal to the per-system calls."""
+def test_plan_without_drift_splits_g_itself(graph, mode):
+    """A plan bound without drift and Laplacian outputs: dR comes from
+    recomputed AO gradients and the dA adjoint's G (split BF16, or FP32 for
+    the dA by electron) from its own pre-pass (no epilogue to write it);
+    equal to the per-system calls."""
     import torch
     from paper_1209_6630_amd.api import Plan
-    print(f"[case] plan without drift graph={graph}", flush=True)
-    mode = "bf16x3"
+    print(f"[case] plan without drift graph={graph} mode={mode}", flush=True)
     items = _batch([("44e", 6), ("158e", 3)])
     P = Plan([it["S"] for it in items], [it["R"].shape[0] for it in items], mode, graph=graph)
     bufs = []
