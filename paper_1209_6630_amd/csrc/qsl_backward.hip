@@ -754,37 +754,54 @@ __device__ __forceinline__ void adj_da_body(const Job& j, int bx, int by, int bz
 // 2s and 2s + 1); one atomic flush per chunk into the FP32 accumulator.
 // Per batch of 32 walkers: the G rows (FP32, written by the epilogue or the
 // g32 pre-pass) are copied from global memory straight into LDS while the
-// AO values of the batch are evaluated from the chunk's slot records (in
-// LDS), then the 16 k-steps run.
+// AO values of the batch are evaluated (each thread keeps the record of its
+// slot in registers for the whole chunk), then the 16 k-steps run.
 constexpr int DE_NS = 128;  // slots per chunk (four waves x 32)
 constexpr int DE_MB = ADJ_MB;  // MOs per workgroup (seven blocks of 32)
 constexpr int DE_KW = 32;   // walkers per batch
 constexpr int DE_NCH = 4;   // chunk stride: workgroups per (electron, group, MO block)
 constexpr int DE_THREADS = 256;
-constexpr int DE_RQ = (int)(sizeof(SlotRec) / 16);  // 16-byte pieces of a slot record
-constexpr int DE_GP = DE_KW * DE_MB / 4;            // 16-byte pieces of a batch's G rows
+constexpr int DE_GP = DE_KW * DE_MB / 4;  // 16-byte pieces of a batch's G rows
+constexpr int DE_LDX = DE_NS + 32;        // AO value rows: walkers 2s and 2s + 1 in other banks
 static_assert(DE_NS == (DE_THREADS / 64) * 32, "one 32-slot block per wave");
 static_assert(DE_GP % DE_THREADS == 0, "whole passes of the G copy");
 
-// Value of slot record r at electron p (FP32 AO arithmetic, FP64 screening
-// as in the forward).
-__device__ __forceinline__ float slot_value(const SlotRec& r, double T_thr, double px, double py, double pz) {
-    const double dx = px - r.pos[0], dy = py - r.pos[1], dz = pz - r.pos[2];
-    const double r2 = dist2_exact(dx, dy, dz);
-    float g = 0.f;
-    const int np = r.np;
-#pragma unroll 1
-    for (int k = 0; k < np; ++k) {
-        const double t = mul_exact(r.ex[k], r2);
-        if (t <= T_thr) g += r.c32[k] * exp_t(-(float)t);
+// A slot record in registers: what the value of the AO needs.
+struct SlotRegs {
+    double x, y, z;
+    double ex[QSL_PMAX];
+    float c[QSL_PMAX];
+    float f;
+    int pw, np;
+    __device__ __forceinline__ void load(const SlotRec& r) {
+        x = r.pos[0]; y = r.pos[1]; z = r.pos[2];
+#pragma unroll
+        for (int k = 0; k < QSL_PMAX; ++k) {
+            ex[k] = r.ex[k];
+            c[k] = r.c32[k];
+        }
+        f = r.f32; pw = r.pw; np = r.np;
     }
-    const int pw = r.pw;
-    float p1, p2, p3, d, d2;
-    axis_pow(pw & 15, (float)dx, p1, d, d2);
-    axis_pow((pw >> 4) & 15, (float)dy, p2, d, d2);
-    axis_pow((pw >> 8) & 15, (float)dz, p3, d, d2);
-    return (r.f32 * p2 * p3) * p1 * g;
-}
+    // Value at electron p (FP32 AO arithmetic, FP64 screening as in the
+    // forward).
+    __device__ __forceinline__ float value(double T_thr, double px, double py, double pz) const {
+        const double dx = px - x, dy = py - y, dz = pz - z;
+        const double r2 = dist2_exact(dx, dy, dz);
+        float g = 0.f;
+#pragma unroll
+        for (int k = 0; k < QSL_PMAX; ++k) {
+            if (k < np) {
+                const double t = mul_exact(ex[k], r2);
+                if (t <= T_thr) g += c[k] * exp_t(-(float)t);
+            }
+        }
+        float p1, p2, p3, d, d2;
+        axis_pow(pw & 15, (float)dx, p1, d, d2);
+        axis_pow((pw >> 4) & 15, (float)dy, p2, d, d2);
+        axis_pow((pw >> 8) & 15, (float)dz, p3, d, d2);
+        return (f * p2 * p3) * p1 * g;
+    }
+};
 
 __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
     const DevSys& s = j.s;
@@ -809,9 +826,8 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
     float* __restrict__ dA32 = j.dA32;
 
     __shared__ double ep[DE_KW][3];
-    __shared__ __attribute__((aligned(16))) float X[DE_KW * DE_NS];
+    __shared__ __attribute__((aligned(16))) float X[DE_KW * DE_LDX];
     __shared__ __attribute__((aligned(16))) float G[DE_KW * DE_MB];
-    __shared__ __attribute__((aligned(16))) uint4 recq[DE_NS * DE_RQ];
     __shared__ int qao[DE_NS];
     auto pos_of = [&](int wb) -> double {  // coordinate tid of batch wb (tid < 96)
         const int k = tid / 3;
@@ -820,13 +836,14 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
 
     for (int c0 = cs * DE_NS; c0 < nsl; c0 += DE_NCH * DE_NS) {
         const int cnt = min(DE_NS, nsl - c0);
-        __syncthreads();  // the previous chunk's evaluation and flush are done with recq and qao
-        for (int p = tid; p < DE_NS * DE_RQ; p += DE_THREADS) {
-            const int ql = p / DE_RQ;
-            const int q = sl[c0 + min(ql, cnt - 1)];  // slots past the chunk repeat its last (their values are dropped)
-            recq[p] = ((const uint4*)(srec + q))[p % DE_RQ];
-        }
+        __syncthreads();  // the previous chunk's flush is done with qao
         if (tid < DE_NS) qao[tid] = tid < cnt ? s.slot_ao[sl[c0 + tid]] : -1;
+        // this thread's slot (slots past the chunk repeat its last; their
+        // values are not computed)
+        const int ql = tid & (DE_NS - 1);
+        const bool live = ql < cnt;
+        SlotRegs rg;
+        rg.load(srec[sl[c0 + min(ql, cnt - 1)]]);
         f32x16 acc[DE_MB / 32];
 #pragma unroll
         for (int mb = 0; mb < DE_MB / 32; ++mb)
@@ -852,16 +869,11 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
             __syncthreads();  // positions visible
             if (tid < DE_KW * 3 && wb + DE_KW < nw) pnext = pos_of(wb + DE_KW);
             // AO values: thread (slot tid % 128, walkers of parity tid / 128)
-            {
-                const int ql = tid & (DE_NS - 1);
-                const SlotRec& r = *(const SlotRec*)&recq[ql * DE_RQ];
-                const bool live = ql < cnt;
 #pragma unroll 1
-                for (int k = tid >> 7; k < DE_KW; k += 2) {
-                    float v = 0.f;
-                    if (live && k < kw) v = slot_value(r, Tscr, ep[k][0], ep[k][1], ep[k][2]);
-                    X[k * DE_NS + ql] = v;
-                }
+            for (int k = tid >> 7; k < DE_KW; k += 2) {
+                float v = 0.f;
+                if (live && k < kw) v = rg.value(Tscr, ep[k][0], ep[k][1], ep[k][2]);
+                X[k * DE_LDX + ql] = v;
             }
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this thread's copies into LDS have landed
             __syncthreads();
@@ -870,7 +882,7 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
 #pragma unroll 4
                 for (int s2 = 0; s2 < DE_KW / 2; ++s2) {
                     const int k = 2 * s2 + h;
-                    const float b = X[k * DE_NS + wave * 32 + c];
+                    const float b = X[k * DE_LDX + wave * 32 + c];
 #pragma unroll
                     for (int mb = 0; mb < DE_MB / 32; ++mb) {
                         if (i0 + mb * 32 < n) {  // uniform: MO blocks past n are skipped
