@@ -72,6 +72,9 @@ def work_per_step(sysm, nnz, W, mode):
 
     def gsplit_bytes(D_read):
         return sum(((8.0 * n * n if D_read else 0.0) + 4.0 * -(-n // 32) * 32 * -(-n // 224) * 224) * W for n in ns)
+    # FP32 dA by electron: G = g D^-1 in FP32, rows of whole 224-MO blocks,
+    # written by the drift / Laplacian epilogue (D^-1 read once for both)
+    g32 = sum(4.0 * n * -(-n // 224) * 224 * W for n in ns) if mode == "fp32" else 0.0
     return {
         f"contract_{mode}": (contract, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         # n <= 224: register-resident elimination on FP64 vector FMAs; larger
@@ -79,7 +82,8 @@ def work_per_step(sysm, nnz, W, mode):
         "gauss_jordan": (gj, "mfma" if max(ns) > 224 else "alu", PEAK_FP64, "TFLOP/s"),
         "adjoint_h": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
         "adjoint_dA": (adjoint, PEAK[mode][0], PEAK[mode][1], "TFLOP/s"),
-        "drift_lap": (epi, "hbm", HBM_PEAK, "GB/s"),
+        "drift_lap": (epi + g32, "hbm", HBM_PEAK, "GB/s"),
+        "g32": (sum(8.0 * n * n * W for n in ns) + g32, "hbm", HBM_PEAK, "GB/s"),
         # dR = g drift: drift read, dR written, g read per component
         "dR_drift": (sum(56.0 * n * W for n in ns), "hbm", HBM_PEAK, "GB/s"),
         # split-BF16 G^T: D^-1 read, hi + lo written over the padded tiles
@@ -293,11 +297,12 @@ def cpu_baseline(sysm, A_up, A_dn, R, workload, target_s=12.0, target_1core_s=6.
 
 
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                            "traffic_434e_W4096_bf16x3.md")
+                            "traffic_434e_W4096_fp32.md")
 KERNEL_SOURCES = {
     "contract": ["qsl_contract.hip", "qsl_internal.h"],
     "gauss_jordan": ["qsl_gj.hip", "qsl_internal.h"],
     "adjoint_dA": ["qsl_backward.hip", "qsl_internal.h"],
+    "drift_lap": ["qsl_misc.hip", "qsl_internal.h"],
 }
 
 
@@ -327,13 +332,15 @@ def measured_traffic(workload, kernel):
     return None
 
 
-def dmc_line(config, W, mode, steps, warmup=2, tau=0.005):
+def dmc_line(config, W, mode, steps, warmup=2, tau=1e-4):
     """Time per fixed-node DMC step of the whole population (the analogue of
     the paper's time per QMC step): drift-diffusion move, the Slater build
     by a forward-only plan replayed from its HIP graph, Jastrow factor, local
     energy and drift, branching weights, reconfiguration and gather.  The
     random deviates of every step are drawn beforehand and resident on the
-    GPU."""
+    GPU.  tau is small enough that the synthetic trial function's drifts
+    (up to a few thousand bohr^-1 near its nodes) move an electron by less
+    than a bohr, so the population stays spread over its walkers."""
     import torch
     import qsl_synth as q
     from paper_1209_6630_amd import _lib
@@ -345,7 +352,8 @@ def dmc_line(config, W, mode, steps, warmup=2, tau=0.005):
     S.set_jastrow(q.nuclear_charges(sysm))
     N = sysm.n_elec
     dmc = DMC(S, torch.from_numpy(R).cuda(), mode=mode, tau=tau, E_T=0.0, graph=True)
-    dmc.E_T = float(dmc.EL.mean())
+    EL0 = dmc.EL.cpu().numpy()
+    dmc.E_T = float(EL0[np.isfinite(EL0)].mean())
     rnd = [q.dmc_randoms(W, N, seed=5, step=k) for k in range(warmup + steps)]
     eta = [torch.from_numpy(e).cuda() for e, _ in rnd]
     u = [torch.from_numpy(x).cuda() for _, x in rnd]
@@ -365,11 +373,14 @@ def dmc_line(config, W, mode, steps, warmup=2, tau=0.005):
     prof = _lib.profile_read(reset=True)
     _lib.profile_enable(False)
     EL = dmc.EL.cpu().numpy()
+    parents = int(np.unique(dmc.idx.cpu().numpy()).size)
     dmc.close()
     S.close()
+    fin = np.isfinite(EL)
     return {"workload": f"dmc-step-{config}-W{W}-{mode}", "value": W / (ms * 1e-3), "unit": "walker DMC steps/s",
             "ms_per_step": ms, "steps": steps, "dtype": DTYPE[mode],
-            "tau": tau, "mean_local_energy": float(EL.mean()),
+            "tau": tau, "E_T": dmc.E_T, "mean_local_energy": float(EL[fin].mean()) if fin.any() else None,
+            "finite_local_energies": int(fin.sum()), "distinct_parents_last_step": parents,
             "timed": "DMC steps (plan graph replay inside), deviates resident on the GPU",
             "kernels_ms_per_step": {k: round(v[1] / steps, 3) for k, v in prof.items()},
             "context": "paper Table 3: 0.0119 s per walker step on one Sandy Bridge core for its 434-electron "
@@ -445,6 +456,7 @@ def main():
     ap.add_argument("--walkers", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the companion runs")
+    ap.add_argument("--no-forms", action="store_true", help="skip timing the other launch forms of the tuning")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after timing, run one plain copy kernel over MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -471,9 +483,11 @@ def main():
     forms = {f"tile{t}-{'persistent' if p_ else 'per-item'}": dict(contract_tile=t, persistent=p_)
              for t in (0, 1) for p_ in (0, 1)}
     forms["det_dA"] = dict(det_dA=1)
-    log("launch forms")
-    by_form = main_wl.time_tunings(forms, max(3, args.steps // 2))
-    log(f"launch forms: {by_form}")
+    by_form = None
+    if not args.no_forms:
+        log("launch forms")
+        by_form = main_wl.time_tunings(forms, max(3, args.steps // 2))
+        log(f"launch forms: {by_form}")
     sysm = main_wl.sysm
     kinds = main_wl.work()
     nnz = main_wl.items[0]["nnz"]

@@ -700,7 +700,10 @@ void orc_branch_weights(int64_t W, const double* EL_new, const double* EL_old, c
             continue;
         }
         double e = (EL_new[k] - E_T) + (EL_old[k] - E_T);
-        w[k] = exp(-0.5 * tau * e);
+        double v = exp(-0.5 * tau * e);
+        /* a walker whose weight is not a finite number (a non-finite local
+           energy, or an overflow) is dropped */
+        w[k] = isfinite(v) ? v : 0.0;
     }
 }
 

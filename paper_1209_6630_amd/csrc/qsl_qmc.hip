@@ -155,7 +155,8 @@ __global__ void weights_kernel(int64_t W, const double* __restrict__ ELn, const 
         return;
     }
     const double e = (ELn[k] - ET) + (ELo[k] - ET);
-    w[k] = exp((-0.5 * tau) * e);
+    const double v = exp((-0.5 * tau) * e);
+    w[k] = isfinite(v) ? v : 0.0;  // a non-finite local energy (or an overflow) drops the walker
 }
 
 // The cumulative weights in walker order, by one thread (the order of the

@@ -105,6 +105,8 @@ def test_branch_weights_against_oracle():
     so = sn.copy()
     so[::17] *= -1
     sn[::101] = 0
+    ELn[5::211] = np.nan       # non-finite local energies and overflowing weights: dropped
+    ELn[7::307] = -1e6
     w = branch_weights(_cuda(ELn), _cuda(ELo), _cuda(sn), _cuda(so), -74.0, 0.01)
     torch.cuda.synchronize()
     want = oracle.branch_weights(ELn, ELo, sn, so, -74.0, 0.01)

@@ -157,6 +157,10 @@ def test_branch_weight_values():
     # (1 - .5) + (1 - .5) = 1 -> 1/2; (-2.5) + 2.5 = 0 -> 1; node crossed -> 0;
     # (2.5 + 2.5) -> 2^-5; Psi vanishes -> 0
     np.testing.assert_allclose(w, [0.5, 1.0, 0.0, 2.0 ** -5, 0.0], rtol=1e-15)
+    # a non-finite local energy, or a weight past the double range, drops the walker
+    w = oracle.branch_weights(np.array([np.nan, np.inf, -1e6, 1.0]), np.array([1.0, 1.0, -1e6, 1.0]),
+                              np.ones(4, np.int8), np.ones(4, np.int8), E_T=0.0, tau=1.0)
+    np.testing.assert_array_equal(w, [0.0, 0.0, 0.0, math.exp(-1.0)])
 
 
 def test_reconfiguration_properties():
