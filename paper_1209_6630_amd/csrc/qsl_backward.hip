@@ -764,6 +764,7 @@ constexpr int DE_THREADS = 256;
 constexpr int DE_GP = DE_KW * DE_MB / 4;  // 16-byte pieces of a batch's G rows
 constexpr int DE_LDX = DE_NS + 32;        // AO value rows: walkers 2s and 2s + 1 in other banks
 static_assert(DE_NS == (DE_THREADS / 64) * 32, "one 32-slot block per wave");
+static_assert(DE_NCH == 4, "the block mapping puts the four chunk strides of a group on one XCD");
 static_assert(DE_GP % DE_THREADS == 0, "whole passes of the G copy");
 
 // A slot record in registers: what the value of the AO needs.
@@ -808,7 +809,13 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
     const int n = j.n, gw = j.gw, spin = j.spin;
     const int64_t W = j.W;
     const int ngw = (int)((W + gw - 1) / gw);
-    const int cs = bx % DE_NCH, grp = bx / DE_NCH;
+    // blocks 32 t + o: group 8 t + o % 8, chunk stride o / 8.  The hardware
+    // hands consecutive blocks to the eight XCDs in turn, and every Job's
+    // block count is a multiple of 32 (adj_dae_grid), so the four chunk
+    // workgroups of a group run on one XCD and read its G rows through one L2.
+    const int o = bx & 31;
+    const int grp = (bx >> 5) * 8 + (o & 7), cs = o >> 3;
+    if (grp >= j.n * ngw) return;
     const int e = grp / ngw, g = grp % ngw;
     const int nsl = j.gnwin[grp];
     if (cs * DE_NS >= nsl) return;
@@ -925,7 +932,7 @@ __global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_batched(const Job* jobs
 }
 
 void adj_dae_grid(Job& j) {
-    j.gx = j.n * (int)((j.W + j.gw - 1) / j.gw) * DE_NCH;
+    j.gx = (j.n * (int)((j.W + j.gw - 1) / j.gw) + 7) / 8 * 32;  // whole runs of 8 groups x 4 chunk strides
     j.gy = (j.n + DE_MB - 1) / DE_MB;
     j.gz = 1;
 }
