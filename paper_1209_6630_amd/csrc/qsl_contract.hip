@@ -114,6 +114,77 @@ __device__ __forceinline__ void slot_values(const SlotRec& r, double T_thr, cons
     v[4] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + (float)(2 * l) * pg1 + P * g2;
 }
 
+// The part of a slot record the evaluation reads for every electron, held
+// in registers for a chunk: position, the first three primitives, factor,
+// powers, count (a shell with more primitives reads the rest from memory).
+constexpr int SR_NP = 3;
+struct SlotR {
+    double x, y, z;
+    double ex[SR_NP];
+    float c[SR_NP];
+    float f;
+    int pw, np;
+    __device__ __forceinline__ void load(const SlotRec* r) {
+        typedef __attribute__((ext_vector_type(2))) double f64x2;
+        typedef __attribute__((ext_vector_type(4))) float f32x4v;
+        typedef __attribute__((ext_vector_type(4))) int i32x4;
+        const f64x2 p01 = *gmem((const f64x2*)&r->pos[0]);
+        const f64x2 p2g = *gmem((const f64x2*)&r->pos[2]);
+        const f64x2 e01 = *gmem((const f64x2*)&r->ex[0]);
+        const f64x2 e23 = *gmem((const f64x2*)&r->ex[2]);
+        const f32x4v cc = *gmem((const f32x4v*)&r->c32[0]);
+        const i32x4 tl = *gmem((const i32x4*)&r->f32);
+        x = p01.x; y = p01.y; z = p2g.x;
+        ex[0] = e01.x; ex[1] = e01.y; ex[2] = e23.x;
+        c[0] = cc.x; c[1] = cc.y; c[2] = cc.z;
+        f = __int_as_float(tl.x); pw = tl.y; np = tl.z;
+    }
+};
+static_assert(offsetof(SlotRec, pos) == 0 && offsetof(SlotRec, ex) == 32 && offsetof(SlotRec, c32) == 96 &&
+                  offsetof(SlotRec, f32) == 128 && offsetof(SlotRec, pw) == 132 && offsetof(SlotRec, np) == 136,
+              "slot record layout read by SlotR::load");
+
+// slot_values on a record held (in part) in registers.
+__device__ __forceinline__ void slot_values_r(const SlotR& r, const SlotRec* __restrict__ rec, double T_thr,
+                                              const double p[3], float v[5], bool& tie) {
+    const double dx = p[0] - r.x, dy = p[1] - r.y, dz = p[2] - r.z;
+    const double r2 = dist2_exact(dx, dy, dz);
+    const float X = (float)dx, Y = (float)dy, Z = (float)dz;
+    const double tieb = 1e-12 * T_thr;
+    float g = 0.f, g1 = 0.f, g2 = 0.f;
+    auto prim = [&](double gk, float ck) __attribute__((always_inline)) {
+        const double t = mul_exact(gk, r2);
+        tie |= fabs(t - T_thr) <= tieb;
+        if (t <= T_thr) {
+            const float ek = ck * exp_t(-(float)t);
+            const float gT = (float)gk;
+            g += ek;
+            g1 += -2.f * gT * ek;
+            g2 += ek * (4.f * gT * gT * (float)r2 - 6.f * gT);
+        }
+    };
+#pragma unroll
+    for (int k = 0; k < SR_NP; ++k)
+        if (k < r.np) prim(r.ex[k], r.c[k]);
+#pragma unroll 1
+    for (int k = SR_NP; k < r.np; ++k) prim(gmem(rec)->ex[k], gmem(rec)->c32[k]);
+    const int pw = r.pw;
+    const int a = pw & 15, b = (pw >> 4) & 15, c = (pw >> 8) & 15, l = (pw >> 12) & 15;
+    float px, ddx, d2x, py, ddy, d2y, pz, ddz, d2z;
+    axis_pow(a, X, px, ddx, d2x);
+    axis_pow(b, Y, py, ddy, d2y);
+    axis_pow(c, Z, pz, ddz, d2z);
+    const float f = r.f;
+    const float fyz = f * py * pz, fxz = f * px * pz, fxy = f * px * py;
+    const float P = fyz * px;
+    const float pg1 = P * g1;
+    v[0] = P * g;
+    v[1] = fyz * ddx * g + pg1 * X;
+    v[2] = fxz * ddy * g + pg1 * Y;
+    v[3] = fxy * ddz * g + pg1 * Z;
+    v[4] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + (float)(2 * l) * pg1 + P * g2;
+}
+
 template <int TILE>
 __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, int tid_in) {
     const DevSys& s = j.s;
@@ -228,7 +299,8 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
             const int kk = tid & (KC - 1), eg = tid >> 6;
             const bool live = kk < cnt;
             const int slot = live ? ring[(head + kk) & (F32_RING - 1)] : 0;
-            const SlotRec& r = srec[slot];
+            SlotR r;
+            r.load(srec + slot);
 #pragma unroll 1
             for (int i = 0; i < 8; ++i) {
                 const int e = eg + 4 * i;
@@ -236,7 +308,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
                 float v[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
                 if (live && e < ne) {
                     const double p[3] = {epos[e][0], epos[e][1], epos[e][2]};
-                    slot_values(r, Tscr, p, v, tie);
+                    slot_values_r(r, srec + slot, Tscr, p, v, tie);
                 }
                 tiebits |= (tie ? 1u : 0u) << i;
 #pragma unroll
