@@ -886,17 +886,28 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
             __syncthreads();
             if (wave * 32 < cnt) {
                 const int h = lane >> 5, c = lane & 31;
-#pragma unroll 4
-                for (int s2 = 0; s2 < DE_KW / 2; ++s2) {
+                // every MO block runs: G is zero past n, so blocks there add
+                // zeros (per-block branches kept the compiler from batching
+                // the operand reads).  The operands of k-step s + 1 are read
+                // before the MFMAs of k-step s.
+                constexpr int NMB = DE_MB / 32;
+                float a[2][NMB], bv[2];
+                auto fetch = [&](int s2, int q) __attribute__((always_inline)) {
                     const int k = 2 * s2 + h;
-                    const float b = X[k * DE_LDX + wave * 32 + c];
+                    bv[q] = X[k * DE_LDX + wave * 32 + c];
 #pragma unroll
-                    for (int mb = 0; mb < DE_MB / 32; ++mb) {
-                        if (i0 + mb * 32 < n) {  // uniform: MO blocks past n are skipped
-                            const float a = G[k * DE_MB + mb * 32 + c];
-                            acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc[mb], 0, 0, 0);
-                        }
-                    }
+                    for (int mb = 0; mb < NMB; ++mb) a[q][mb] = G[k * DE_MB + mb * 32 + c];
+                };
+                fetch(0, 0);
+#pragma unroll
+                for (int s2 = 0; s2 < DE_KW / 2; ++s2) {
+                    if (s2 + 1 < DE_KW / 2) fetch(s2 + 1, (s2 + 1) & 1);
+#pragma unroll
+                    for (int mb = 0; mb < NMB; ++mb)
+                        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s2 & 1][mb], bv[s2 & 1], acc[mb], 0, 0, 0);
+                    // schedule: the next k-step's LDS reads, then this one's MFMAs
+                    if (s2 + 1 < DE_KW / 2) __builtin_amdgcn_sched_group_barrier(0x100, NMB + 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, NMB, 0);
                 }
             }
         }

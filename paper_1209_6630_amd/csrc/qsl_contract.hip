@@ -396,7 +396,12 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    if (el < ne) gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo] = acc[sb][d][r];
+                    // C streams out (non-temporal): written once here, read by
+                    // later kernels, it should not push the MO coefficients
+                    // out of L2
+                    if (el < ne)
+                        __builtin_nontemporal_store(acc[sb][d][r],
+                                                    &gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo]);
                 }
         }
     }
