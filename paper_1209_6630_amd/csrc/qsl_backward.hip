@@ -125,12 +125,14 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
     __shared__ T dX[3][TE][AH_KC + 1];
     __shared__ T Hb[2][TE][AH_KC + 1];
 
-    // row r of the tile is electron eidx of walker w0 + r (ne valid rows)
+    // row r of the tile is electron eidx of walker wr(r): position w0 + r of
+    // the walker order (ne valid rows)
     const int tile = bx;
     const int wbk = walker_blocks(W);
     const int eidx = tile / wbk;
     const int w0 = (tile % wbk) * TE;
     const int ne = (int)min<int64_t>(TE, W - w0);
+    auto wr = [&](int r) -> int64_t { return walker_of(j.wperm, W, eidx, w0 + r); };
     const int i0 = by * ADJ_MB;
     const int N = s.n_up + s.n_dn;
     const int eoff = spin ? s.n_up : 0;
@@ -142,14 +144,15 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
-        epos[e][k] = e < ne ? R[((size_t)(w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
+        epos[e][k] = e < ne ? R[((size_t)wr(e) * N + eoff + eidx) * 3 + k] : 0.0;
     }
     for (int q = tid; q < TE * ADJ_MB; q += AH_THREADS) {
         const int e = q / ADJ_MB, ii = q % ADJ_MB;
         double v = 0.0;
         if (e < ne && i0 + ii < n) {
-            const double gw = g[2 * (w0 + e) + spin];
-            if (gw != 0.0) v = gw * Dinv[((size_t)(w0 + e) * n + eidx) * n + i0 + ii];
+            const int64_t w = wr(e);
+            const double gw = g[2 * w + spin];
+            if (gw != 0.0) v = gw * Dinv[((size_t)w * n + eidx) * n + i0 + ii];
         }
         if constexpr (BF) {
             const float f = (float)v;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void adj_h_body(const Job& j, int bx, int by) {
         T acc = 0;
 #pragma unroll
         for (int grp = 0; grp < AH_THREADS / TE; ++grp) acc += red[(comp * (AH_THREADS / TE) + grp) * TE + e];
-        if (e < ne) atomicAdd(dR + ((size_t)(w0 + e) * N + eoff + eidx) * 3 + comp, (double)acc);
+        if (e < ne) atomicAdd(dR + ((size_t)wr(e) * N + eoff + eidx) * 3 + comp, (double)acc);
     }
 }
 
@@ -833,12 +836,18 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
     float* __restrict__ dA32 = j.dA32;
 
     __shared__ double ep[DE_KW][3];
+    __shared__ int wl[DE_KW];  // the batch's walkers (Job.wperm order)
     __shared__ __attribute__((aligned(16))) float X[DE_KW * DE_LDX];
     __shared__ __attribute__((aligned(16))) float G[DE_KW * DE_MB];
     __shared__ int qao[DE_NS];
-    auto pos_of = [&](int wb) -> double {  // coordinate tid of batch wb (tid < 96)
+    // walker of position wb + tid of the group (tid < 32) and coordinate
+    // tid of batch wb (tid < 96; -1 past the group)
+    auto walker_at = [&](int wb) -> int {
+        return wb + tid < nw ? (int)walker_of(j.wperm, W, e, w0 + wb + tid) : -1;
+    };
+    auto pos_of = [&](int wb) -> double {
         const int k = tid / 3;
-        return wb + k < nw ? j.R[((size_t)(w0 + wb + k) * N + eoff + e) * 3 + tid % 3] : 0.0;
+        return wb + k < nw ? j.R[((size_t)walker_of(j.wperm, W, e, w0 + wb + k) * N + eoff + e) * 3 + tid % 3] : 0.0;
     };
 
     for (int c0 = cs * DE_NS; c0 < nsl; c0 += DE_NCH * DE_NS) {
@@ -857,9 +866,13 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
         double pnext = tid < DE_KW * 3 ? pos_of(0) : 0.0;
+        int wnext = tid < DE_KW ? walker_at(0) : 0;
         for (int wb = 0; wb < nw; wb += DE_KW) {
             const int kw = min(DE_KW, nw - wb);
-            __syncthreads();  // the previous batch's products are done with X and G; recq and qao are visible
+            __syncthreads();  // the previous batch's products are done with X, G, ep and wl; qao is visible
+            if (tid < DE_KW * 3) ep[tid / 3][tid % 3] = pnext;
+            if (tid < DE_KW) wl[tid] = wnext;
+            __syncthreads();  // positions and walkers of the batch visible
             // G rows of the batch straight into LDS: piece p = 56 row + c of
             // 16 bytes; rows past the group repeat its last walker (their
             // AO values are zero)
@@ -867,14 +880,15 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
             for (int ps = 0; ps < DE_GP / DE_THREADS; ++ps) {
                 const int p = ps * DE_THREADS + tid;
                 const int row = min(p / (DE_MB / 4), kw - 1), c = p % (DE_MB / 4);
-                const float* src = G32 + ((size_t)(w0 + wb + row) * n + e) * ldg + i0 + 4 * c;
+                const float* src = G32 + ((size_t)wl[row] * n + e) * ldg + i0 + 4 * c;
                 __builtin_amdgcn_global_load_lds((const void*)src,
                                                  (__attribute__((address_space(3))) void*)&G[(ps * DE_THREADS + wave * 64) * 4],
                                                  16, 0, 0);
             }
-            if (tid < DE_KW * 3) ep[tid / 3][tid % 3] = pnext;
-            __syncthreads();  // positions visible
-            if (tid < DE_KW * 3 && wb + DE_KW < nw) pnext = pos_of(wb + DE_KW);
+            if (wb + DE_KW < nw) {
+                if (tid < DE_KW * 3) pnext = pos_of(wb + DE_KW);
+                if (tid < DE_KW) wnext = walker_at(wb + DE_KW);
+            }
             // AO values: thread (slot tid % 128, walkers of parity tid / 128)
 #pragma unroll 1
             for (int k = tid >> 7; k < DE_KW; k += 2) {

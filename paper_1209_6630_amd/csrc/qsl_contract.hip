@@ -205,6 +205,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
     __shared__ __attribute__((aligned(16))) uint64_t ringm[F32_RING];  // the slot's MO-block mask
     __shared__ uint32_t wmask[F32_BATCH];
     __shared__ int s_tail;
+    __shared__ int wt[TE];  // the tile's walkers (Job.wperm order)
 
     const int tile = bx;
     const int n0 = by * MSUB * NSB;
@@ -220,8 +221,9 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
 
     if (tid < TE * 3) {
         const int e = tid / 3, k = tid % 3;
-        epos[e][k] = e < ne ? R[((size_t)(w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
+        epos[e][k] = e < ne ? R[((size_t)walker_of(j.wperm, W, eidx, w0 + e) * N + eoff + eidx) * 3 + k] : 0.0;
     }
+    if (tid < TE) wt[tid] = tid < ne ? (int)walker_of(j.wperm, W, eidx, w0 + tid) : 0;
     if (tid == 0) s_tail = 0;
     const int nwin = j.nwin[tile];
     const int* __restrict__ wins = j.win + (size_t)tile * s.n_win;
@@ -381,9 +383,9 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
         const int eg = tid >> 6;
         for (uint32_t tb = tiebits; tb; tb &= tb - 1) {
             const int e = eg + 4 * __builtin_ctz(tb);
-            if (e < ne) atomicOr(status + w0 + e, QSL_STATUS_NEAR_TIE);
+            if (e < ne) atomicOr(status + wt[e], QSL_STATUS_NEAR_TIE);
         }
-        if (ftie && (lane & 31) < ne) atomicOr(status + w0 + (lane & 31), QSL_STATUS_NEAR_TIE);
+        if (ftie && (lane & 31) < ne) atomicOr(status + wt[lane & 31], QSL_STATUS_NEAR_TIE);
     }
     // ---- store C[w][d][e][mo]
     float* C = (float*)j.C;
@@ -401,7 +403,7 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
                     // out of L2
                     if (el < ne)
                         __builtin_nontemporal_store(acc[sb][d][r],
-                                                    &gmem(C)[(((size_t)(w0 + el) * 5 + d) * n + eidx) * nmo + mo]);
+                                                    &gmem(C)[(((size_t)wt[el] * 5 + d) * n + eidx) * nmo + mo]);
                 }
         }
     }

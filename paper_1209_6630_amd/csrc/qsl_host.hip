@@ -133,6 +133,10 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e) {
     L.job_off = off;
     off += JOBSLOT_BYTES;
     for (int s = 0; s < 2; ++s) {
+        L.perm_off[s] = off;
+        if (mode == QSL_FP32) off = round_up(off + (size_t)n_spin(d, s) * W * sizeof(int), 256);
+    }
+    for (int s = 0; s < 2; ++s) {
         int n = n_spin(d, s);
         size_t tiles = n ? (size_t)electron_tiles(n, W) : 0;
         L.nwin_off[s] = off;
@@ -175,7 +179,7 @@ WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e) {
 }
 
 // The Job of one spin of a forward call: inputs, workspace lists, outputs.
-Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s) {
+Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s, bool sorted) {
     Job j{};
     j.s = sys->d;
     j.mo = sys->mo[s];
@@ -188,6 +192,7 @@ Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws,
     j.nwin = (int*)(ws + L.nwin_off[s]);
     j.win = (int*)(ws + L.win_off[s]);
     j.jobslot = ws + L.job_off;
+    if (sorted && a->mode == QSL_FP32) j.wperm = (const int*)(ws + L.perm_off[s]);
     j.C = a->C[s];
     if (gj_blocked(j.n)) j.gjws = (double*)(ws + L.gj_off[s]);
     j.logdet = a->logdet;
@@ -209,6 +214,9 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
     j.mode = a->mode;
     j.gw = gw;
     j.by_e = by_e ? 1 : 0;
+    // FP32: the walker order of the tiles, as the forward's (the dA by
+    // electron's groups and the tile kernels read it)
+    if (a->mode == QSL_FP32) j.wperm = (const int*)(ws + L.perm_off[s]);
     j.W = a->W;
     j.R = a->R;
     j.nwin = (int*)(ws + L.nwin_off[s]);
@@ -504,6 +512,15 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         DevSys& D = S->d;
         D.n_atoms = d->n_atoms; D.n_shells = d->n_shells; D.n_slots = n_slots; D.n_win = n_win;
         D.n_basis = ao; D.n_up = d->n_up; D.n_dn = d->n_dn; D.T = T;
+        for (int k = 0; k < 3; ++k) {
+            D.box[k] = INFINITY;
+            D.box[3 + k] = -INFINITY;
+        }
+        for (int a = 0; a < d->n_atoms; ++a)
+            for (int k = 0; k < 3; ++k) {
+                D.box[k] = std::min(D.box[k], d->atom_xyz[3 * a + k] - 8.0);
+                D.box[3 + k] = std::max(D.box[3 + k], d->atom_xyz[3 * a + k] + 8.0);
+            }
         D.atom_xyz = (const double*)(b + o_xyz); D.atom_gmin = (const double*)(b + o_agm);
         D.shell_atom = (const int*)(b + o_sat); D.shell_l = (const int*)(b + o_sl);
         D.shell_p0 = (const int*)(b + o_sp0); D.shell_np = (const int*)(b + o_snp);
@@ -699,8 +716,14 @@ static qsl_status forward_enqueue(qsl_system* sys, const qsl_fwd_args* a, char* 
     hipError_t e;
     if (a->status && (e = fill_u32(a->status, 0u, a->W, st)) != hipSuccess) return hip_fail(e, "status clear");
     for (int s = 0; s < 2; ++s) {
-        Job j = fwd_job(sys, a, L, ws, s);
+        // FP32: each electron index's walkers in space-filling-curve order,
+        // so the tiles' survivor unions are tighter
+        Job j = fwd_job(sys, a, L, ws, s, /*sorted=*/true);
         if (j.n) {
+            if (j.wperm) {
+                ProfScope ps("walker_order", st);
+                if ((e = launch_wsort(j, st)) != hipSuccess) return hip_fail(e, "walker order kernel");
+            }
             {
                 ProfScope ps("screen", st);
                 if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
@@ -810,6 +833,10 @@ qsl_status qsl_backward(qsl_system* sys, const qsl_bwd_args* a, void* stream) {
     for (int s = 0; s < 2; ++s) {
         Job j = bwd_job(sys, a, L, ws, s, gw, by_e);
         if (!j.n) continue;
+        if (j.wperm) {  // the walker order of the tiles (as the forward's)
+            ProfScope ps("walker_order", st);
+            if ((e = launch_wsort(j, st)) != hipSuccess) return hip_fail(e, "walker order kernel");
+        }
         const bool f32acc = j.dA32 != nullptr;
         if (f32acc && (e = fill_u32((uint32_t*)j.dA32, 0u, (int64_t)j.n * d.n_basis, st)) != hipSuccess)
             return hip_fail(e, "dA accumulator clear");

@@ -76,6 +76,7 @@ struct DevSys {
     int n_atoms, n_shells, n_slots, n_win, n_basis;
     int n_up, n_dn;
     double T;
+    double box[6];            // lo x, y, z, hi x, y, z: the atoms' box widened by 8 bohr (walker order keys)
     const double* atom_xyz;   // [n_atoms*3]
     const double* atom_gmin;  // [n_atoms] min exponent of the atom
     const int* shell_atom;    // [n_shells]
@@ -318,6 +319,11 @@ struct Job {
     // n), written by the epilogue or a pre-pass
     int by_e;
     float* g32;
+    // FP32 with the dA by electron: the walkers of each electron index in
+    // space-filling-curve order, wperm[e][k] = walker at position k; tile
+    // (e, b) and walker group (e, g) take positions [32 b, 32 b + 32) and
+    // [g gw, (g + 1) gw) (NULL: walker order)
+    const int* wperm;
     int gx, gy, gz;          // the Job's grid in the current phase
 };
 // Bytes of the device Job copy of a per-system launch (Job, then two ints).
@@ -427,12 +433,13 @@ __host__ __device__ inline int64_t gsplit_elems(int n) {
 struct WsLayout {
     size_t job_off;  // the device Job copy of per-system launches
     size_t nwin_off[2], win_off[2], dA32_off[2], gnwin_off[2], gwin_off[2], gj_off[2], gs_off[2], g32_off[2];
+    size_t perm_off[2];  // walker order per electron (FP32), [n][W] int
     size_t fwd_total;  // end of the forward's regions (tile lists, blocked-inversion copy)
     size_t total;      // end of the adjoint's regions
 };
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e);
 // The Job of spin s of a forward / adjoint call on workspace ws.
-Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s);
+Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s, bool sorted = false);
 Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw, bool by_e);
 
 // ------------------------------------------------------------- launchers
@@ -451,6 +458,16 @@ int screen_blocks(const Job& j, int group);
 constexpr int UNION_MAXWIN = 8192;
 hipError_t launch_group_union(const Job& j, hipStream_t st);
 hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
+// Walker k of electron e in the order of Job.wperm.
+__device__ __forceinline__ int64_t walker_of(const int* __restrict__ wperm, int64_t W, int e, int64_t k) {
+    return wperm ? (int64_t)wperm[(size_t)e * W + k] : k;
+}
+// Walker order of each electron index (Job.wperm): one block per (electron,
+// segment of 4096 walkers) sorting them by the Morton code of the
+// electron's position in the system box (ties by walker index).
+int wsort_blocks(const Job& j);
+hipError_t launch_wsort(const Job& j, hipStream_t st);
+hipError_t launch_wsort_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 // Slot lists of the dA by electron (Job.by_e): one block per (electron,
 // walker group), from the tile lists; systems of at most UNION_MAXWIN windows.
 int group_slots_blocks(const Job& j);

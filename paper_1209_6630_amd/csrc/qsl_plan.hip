@@ -36,6 +36,7 @@ enum Phase {
     PH_SLOTS_G,      // dA by electron: the (electron, walker group) slot lists
     PH_G32,          // dA by electron: G = g D^-1 in FP32 where no epilogue writes it
     PH_ADJ_DAE,      // dA by electron
+    PH_SORT,         // walker order per electron index (FP32 with the dA by electron; runs first)
     PH_COUNT
 };
 
@@ -162,7 +163,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     p->bjobs.clear();
     for (int i = 0; i < p->n_sys; ++i)
         for (int s = 0; s < 2; ++s) {
-            Job f = fwd_job(p->sys[i], &p->fwd[i], p->lay[i], ws + p->ws_off[i], s);
+            Job f = fwd_job(p->sys[i], &p->fwd[i], p->lay[i], ws + p->ws_off[i], s, /*sorted=*/true);
             f.gj_bias = p->tune.gj_bias;
             f.f32_tile = p->tune.contract_tile;
             p->fjobs.push_back(f);
@@ -177,6 +178,11 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
     for (const Job& f : p->fjobs) {
         if (!f.n || !f.W) continue;
         Job j = f;
+        if (f.wperm) {
+            j.gx = wsort_blocks(j); j.gy = 1; j.gz = 1;
+            p->ph[PH_SORT].jobs.push_back(j);
+            j = f;
+        }
         j.gx = screen_blocks(j, 0); j.gy = 1; j.gz = 1;
         p->ph[PH_SCREEN].jobs.push_back(j);
         j = f;
@@ -346,6 +352,13 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
     }
     // forward
     if (batched) {
+        auto& WS = p->ph[PH_SORT];
+        if (WS.blocks()) {
+            ProfScope ps("walker_order", st);
+            if ((e = launch_wsort_batched(dev_jobs(p, PH_SORT), dev_prefix(p, PH_SORT), (int)WS.jobs.size(), WS.blocks(),
+                                          st)) != hipSuccess)
+                return hip_fail(e, "walker order kernel");
+        }
         auto& S = p->ph[PH_SCREEN];
         if (S.blocks()) {
             ProfScope ps("screen", st);
@@ -384,6 +397,10 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
             if (e != hipSuccess) return hip_fail(e, "inversion kernel");
         }
     } else {
+        for (const Job& j : p->ph[PH_SORT].jobs) {
+            ProfScope ps("walker_order", st);
+            if ((e = launch_wsort(j, st)) != hipSuccess) return hip_fail(e, "walker order kernel");
+        }
         for (const Job& j : p->ph[PH_SCREEN].jobs) {
             ProfScope ps("screen", st);
             if ((e = launch_screen(j, 0, st)) != hipSuccess) return hip_fail(e, "screen kernel");
@@ -451,8 +468,10 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         // the adjoint's walker-group lists: the union of the forward's tile
         // lists (same positions), or a screening of their own for systems
         // with more windows than the union bitmap holds
+        // (tiles in a walker order of their own (FP32) cannot give the
+        // unions of consecutive walkers: those groups are screened directly)
         bool small = true;
-        for (const Job& j : SG.jobs) small = small && j.s.n_win <= UNION_MAXWIN;
+        for (const Job& j : SG.jobs) small = small && j.s.n_win <= UNION_MAXWIN && !j.wperm;
         if (SG.blocks()) {
             ProfScope ps("screen_group", st);
             e = small ? launch_group_union_batched(dev_jobs(p, PH_SCREEN_G), dev_prefix(p, PH_SCREEN_G),
@@ -509,7 +528,7 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         }
         for (const Job& j : SG.jobs) {
             ProfScope ps("screen_group", st);
-            e = j.s.n_win <= UNION_MAXWIN ? launch_group_union(j, st) : launch_screen(j, 1, st);
+            e = j.s.n_win <= UNION_MAXWIN && !j.wperm ? launch_group_union(j, st) : launch_screen(j, 1, st);
             if (e != hipSuccess) return hip_fail(e, "group screen kernel");
         }
         for (const Job& j : p->ph[PH_SLOTS_G].jobs) {

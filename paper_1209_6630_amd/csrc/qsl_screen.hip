@@ -62,7 +62,9 @@ __device__ __forceinline__ void screen_body(const Job& j, bool group, int* __res
         nall = (int)min<int64_t>(TE, W - w0);
         kstride = 1;
     }
-    auto kw = [&](int k) { return w0 + k / kstride; };
+    // tiles read their walkers in the order of wperm (positions w0 + k)
+    const int* __restrict__ wp = group ? nullptr : j.wperm;
+    auto kw = [&](int k) -> int64_t { return wp ? walker_of(wp, W, e0, w0 + k) : w0 + k / kstride; };
     auto ke = [&](int k) { return e0 + k % kstride; };
     auto valid = [&](int k) { return k % kstride < ne; };
     auto gpos = [&](int k) -> const double* { return R + ((size_t)kw(k) * N + eoff + ke(k)) * 3; };
@@ -257,6 +259,92 @@ hipError_t launch_group_union_batched(const Job* jobs, const int* prefix, int nj
     return hipGetLastError();
 }
 
+// Walker order of each electron index: the walkers of a segment of 4096 by
+// the Morton code of electron e's position (10 bits per axis over the
+// system box, positions outside it clamped), ties by walker index, with a
+// bitonic sort of (code, index) keys in LDS.  wperm[e][k] = walker at
+// position k.  Walkers whose electron e is close in space then share tiles
+// and walker groups, whose survivor unions are tighter.
+constexpr int WS_SEG = 4096;
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {  // bit i -> bit 3 i
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ void wsort_body(const Job& j, int bx) {
+    __shared__ uint64_t key[WS_SEG];
+    const DevSys& s = j.s;
+    const int64_t W = j.W;
+    const int nseg = (int)((W + WS_SEG - 1) / WS_SEG);
+    const int e = bx / nseg, seg = bx % nseg;
+    const int64_t s0 = (int64_t)seg * WS_SEG;
+    const int m = (int)min<int64_t>(WS_SEG, W - s0);
+    int P = 64;
+    while (P < m) P <<= 1;
+    const int N = s.n_up + s.n_dn, eoff = j.spin ? s.n_up : 0;
+    const int tid = threadIdx.x;
+    for (int k = tid; k < P; k += SCREEN_THREADS) {
+        uint64_t v = ~0ull;  // padding sorts last
+        if (k < m) {
+            const double* r = j.R + ((size_t)(s0 + k) * N + eoff + e) * 3;
+            uint32_t code = 0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double u = (r[a] - s.box[a]) / (s.box[3 + a] - s.box[a]) * 1023.0;
+                const uint32_t q = u > 0.0 ? (u < 1023.0 ? (uint32_t)u : 1023u) : 0u;  // NaN -> 0
+                code |= spread10(q) << a;
+            }
+            v = ((uint64_t)code << 32) | (uint32_t)k;
+        }
+        key[k] = v;
+    }
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < P / 2; t += SCREEN_THREADS) {
+                const int i = 2 * t - (t & (stride - 1));
+                const bool up = (i & size) == 0;
+                const uint64_t a = key[i], b = key[i + stride];
+                if ((a > b) == up) {
+                    key[i] = b;
+                    key[i + stride] = a;
+                }
+            }
+            __syncthreads();
+        }
+    int* out = const_cast<int*>(j.wperm) + (size_t)e * W + s0;
+    for (int k = tid; k < m; k += SCREEN_THREADS) out[k] = (int)(s0 + (int64_t)(uint32_t)key[k]);
+}
+
+__global__ __launch_bounds__(SCREEN_THREADS) void wsort_kernel(Job j) { wsort_body(j, blockIdx.x); }
+
+__global__ __launch_bounds__(SCREEN_THREADS) void wsort_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { wsort_body(j, bx); });
+}
+
+int wsort_blocks(const Job& j) {
+    if (!j.n || !j.W || !j.wperm) return 0;
+    return j.n * (int)((j.W + WS_SEG - 1) / WS_SEG);
+}
+
+hipError_t launch_wsort(const Job& j, hipStream_t st) {
+    const int blocks = wsort_blocks(j);
+    if (!blocks) return hipSuccess;
+    wsort_kernel<<<dim3((unsigned)blocks), SCREEN_THREADS, 0, st>>>(j);
+    return hipGetLastError();
+}
+
+hipError_t launch_wsort_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+    if (grid <= 0) return hipSuccess;
+    wsort_batched<<<dim3((unsigned)grid), SCREEN_THREADS, 0, st>>>(jobs, prefix, njobs);
+    return hipGetLastError();
+}
+
 // Slot lists of the adjoint's dA by electron: for walker group g (gw
 // walkers) of electron index e, the ascending slots whose smallest exponent
 // passes the screening test, gmin r^2 <= T in the exact FP64 arithmetic of
@@ -330,7 +418,7 @@ __device__ __forceinline__ void group_slots_body(const Job& j, int bx) {
         const int np = (int)min<int64_t>(GS_POS, wend - p0);
         __syncthreads();  // uw / sm written; the previous positions are no longer read
         for (int q = tid; q < np * 3; q += SCREEN_THREADS)
-            ep[q / 3][q % 3] = j.R[((size_t)(p0 + q / 3) * N + eoff + e) * 3 + q % 3];
+            ep[q / 3][q % 3] = j.R[((size_t)walker_of(j.wperm, W, e, p0 + q / 3) * N + eoff + e) * 3 + q % 3];
         __syncthreads();
         for (int k = wave; k < U; k += NWAVE) {
             const SlotRec* rq = srec + (size_t)uw[k] * WIN;
