@@ -398,12 +398,9 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int el = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                    // C streams out (non-temporal): written once here, read by
-                    // later kernels, it should not push the MO coefficients
-                    // out of L2
-                    if (el < ne)
-                        __builtin_nontemporal_store(acc[sb][d][r],
-                                                    &gmem(C)[(((size_t)wt[el] * 5 + d) * n + eidx) * nmo + mo]);
+                    // ordinary stores: the L2 merges the partial lines at the
+                    // ends of a wave's 128-byte segments of a C row
+                    if (el < ne) gmem(C)[(((size_t)wt[el] * 5 + d) * n + eidx) * nmo + mo] = acc[sb][d][r];
                 }
         }
     }

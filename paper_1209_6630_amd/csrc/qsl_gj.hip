@@ -4,7 +4,8 @@
 // One workgroup inverts one n x n matrix held entirely in registers, by
 // Gauss-Jordan elimination with partial pivoting on the rows of D: at step k
 // the pivot is the largest |D[i][k]| over rows not yet used (smallest i on
-// exact ties).  Pivot rows are not moved; the pivot sequence p_k is recorded
+// exact ties; for 128 < n <= 224, among values within 2^-12 relative of the
+// largest, which leaves the elimination as stable).  Pivot rows are not moved; the pivot sequence p_k is recorded
 // and the result is un-permuted on the way out: D^-1[k][p_j] = M[p_k][j].
 // The pivots are the diagonal of U in P D = L U, so log|det| = sum log|pivot|
 // and sign = sign(permutation) prod sign(pivot).  2 n^3 flops per matrix.
@@ -290,46 +291,38 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
 template <int RPL, typename Before>
 __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int li, int half, uint32_t used,
                                            double* colout, int* piv_idx, double* piv_val, Before&& before) {
-    // |a| over the candidate rows (unused, i < n), -1 elsewhere; NaN never
-    // wins; the lane's maximum by a tree
-    double a[RPL];
+    // One 32-bit key per candidate row (unused, i < n, not NaN): the high
+    // word of |a| (sign 0, exponent, 20 significand bits) with its low 8 bits
+    // replaced by 255 - i; 0 elsewhere.  As unsigned integers the keys order
+    // like |a| to 2^-12 relative, and among values that close the smallest
+    // row wins; the row comes back from the key.
+    uint32_t best = 0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         const int i = li + 32 * r;
-        a[r] = (i < n && !((used >> r) & 1u)) ? fabs(col[r]) : -1.0;
+        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(col[r]) >> 32) & 0x7fffffffu;
+        // rows past n are marked used from the start
+        const uint32_t keep = ((used >> r) & 1u) - 1u;  // all ones for a candidate row
+        const uint32_t kr = ((hi & ~0xFFu) | (uint32_t)(255 - i)) & keep;
+        best = max(best, col[r] == col[r] ? kr : 0u);
     }
-    double m[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) m[r] = a[r];
-#pragma unroll
-    for (int w = 1; w < RPL; w *= 2)
-#pragma unroll
-        for (int r = 0; r + w < RPL; r += 2 * w) m[r] = fmax(m[r], m[r + w]);
-    double best = fmax(m[0], -1.0);
-    // largest value: inside rows of 16 lanes by DPP (quad swaps, half-row
-    // and row mirrors), then the owning half's two rows
-    best = fmax(best, dpp_f64<0xB1>(best));
-    best = fmax(best, dpp_f64<0x4E>(best));
-    best = fmax(best, dpp_f64<0x141>(best));
-    best = fmax(best, dpp_f64<0x140>(best));
+    // inside rows of 16 lanes by DPP (quad swaps, half-row and row mirrors),
+    // then the owning half's two rows
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0xB1, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x4E, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x141, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x140, 0xf, 0xf, false));
     const int l0 = 32 * half;
-    const double gmax = fmax(readlane_f64(best, l0), readlane_f64(best, l0 + 16));
-    // smallest row attaining it: the first register row r with a hit in the
-    // owning half, its lowest lane; the sign comes from the same ballot row
-    int si = 0x7fffffff;
-    bool neg = false;
+    const uint32_t gk = max((uint32_t)__builtin_amdgcn_readlane((int)best, l0),
+                            (uint32_t)__builtin_amdgcn_readlane((int)best, l0 + 16));
+    const bool any = gk != 0;
+    const int si = any ? 255 - (int)(gk & 0xFF) : 0x7fffffff;  // wave-uniform
+    // the pivot value itself: register row si / 32 of lane si % 32 of the half
+    const int rs = any ? si >> 5 : 0, ls = any ? si & 31 : 0;
+    double cv = col[0];
 #pragma unroll
-    for (int r = RPL - 1; r >= 0; --r) {
-        const uint32_t hit = (uint32_t)(__ballot(a[r] == gmax) >> l0);
-        const uint32_t ng = (uint32_t)(__ballot(col[r] < 0.0) >> l0);
-        if (hit) {
-            const int lw = __builtin_ctz(hit);
-            si = 32 * r + lw;
-            neg = (ng >> lw) & 1u;
-        }
-    }
-    if (!(gmax >= 0.0)) si = 0x7fffffff;  // no candidate row
-    const double pv = neg ? -gmax : gmax;
+    for (int r = 1; r < RPL; ++r) cv = rs == r ? col[r] : cv;
+    const double pv = any ? readlane_f64(cv, l0 + ls) : 0.0;
     // 1/pv: hardware reciprocal and two Newton steps (the error squares each
     // step), shorter than the general division on this step's critical path
     double inv = __builtin_amdgcn_rcp(pv);
@@ -339,7 +332,7 @@ __device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int 
     if ((threadIdx.x & 63) >> 5 == half) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const int i = li + 32 * r;
+            const int i = li + 32 * r;  // < 32 RPL, the buffer's length
             if (i < n) colout[i] = i == si ? 0.0 : -col[r] * inv;
         }
     }
@@ -430,7 +423,10 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
             if (it >= 4) __builtin_amdgcn_s_sleep(1);
         }
     };
-    uint32_t used = 0;  // bit r: row li + 32 r already a pivot row
+    uint32_t used = 0;  // bit r: row li + 32 r already a pivot row, or past n
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+        if (li + 32 * r >= n) used |= 1u << r;
     int rot = 0;        // rotations of this wave's register columns (mod CPW)
     if (wave == 0) {
         double col[RPL];
@@ -450,17 +446,24 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
         double pv;
         double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
         bool live = true;
+        int seen = k;
         for (int it = 0;; ++it) {
             const int fv = flag_load(&pub);
             p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
             pv = readlane_f64(piv_val[b], 0);
 #pragma unroll
             for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
-            if (__builtin_amdgcn_readfirstlane(fv) >= k) break;
+            seen = __builtin_amdgcn_readfirstlane(fv);
+            if (seen >= k) break;
             if (stop(it)) { live = give_up(); break; }
             if (it >= 4) __builtin_amdgcn_s_sleep(1);
         }
         if (!live) break;
+        // a wave behind the published steps takes issue priority over its
+        // SIMD mates until it has caught up
+        if (seen >= k + 2) __builtin_amdgcn_s_setprio(2);
+        else if (seen == k + 1) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
         if (lane == 0) flag_store(&prog[wave], k);  // after the reads above
         if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
             singular = true;
