@@ -481,7 +481,7 @@ def main():
     value = W / (ms * 1e-3)
     log(f"{ms:.3f} ms/step (eager {ms_eager:.3f}), {value:.1f} walkers/s; kernels {prof}")
     forms = {f"tile{t}-{'persistent' if p_ else 'per-item'}": dict(contract_tile=t, persistent=p_)
-             for t in (0, 1) for p_ in (0, 1)}
+             for t in (0, 1, 2) for p_ in (0, 1)}
     forms["det_dA"] = dict(det_dA=1)
     by_form = None
     if not args.no_forms:
@@ -566,7 +566,7 @@ def main():
         # the launch forms around the tuned choice: one workgroup per item or
         # persistent, both contraction tiles, atomic or deterministic dA
         forms = {f"tile{t}-{'persistent' if p_ else 'per-item'}": dict(contract_tile=t, persistent=p_)
-                 for t in (0, 1) for p_ in (0, 1)}
+                 for t in (0, 1, 2) for p_ in (0, 1)}
         forms["det_dA"] = dict(det_dA=1)
         eb["ms_per_step_by_launch_form"] = wlb.time_tunings(forms, steps2)
         wlb.close()

@@ -262,7 +262,11 @@ typedef struct {
     int32_t gj_bias;    /* 0: the smallest Gauss-Jordan block shape holding
                            n; 1: the next larger one (when there is one)      */
     int32_t contract_tile; /* FP32 products: 0 = 256 MOs per workgroup, two
-                              workgroups per CU; 1 = 128 MOs, three per CU   */
+                              workgroups per CU; 1 = 128 MOs, three per CU;
+                              2 = as 0, each FP32 operand split exactly into
+                              three bf16 and the six leading products taken
+                              on bf16 MFMA with FP32 accumulation (per
+                              product 2^-23 relative against FP32's 2^-24) */
     int32_t persistent; /* 1 (with batched): the products run as resident
                            workgroups taking work items from a device counter
                            (largest systems first) instead of one workgroup

@@ -48,6 +48,8 @@ class Tuning(ct.Structure):
 
 
 TUNING_FIELDS = ("batched", "adj_group", "gj_bias", "contract_tile", "persistent", "det_dA")
+# what a field left out of a tuning dict takes (the library's defaults)
+TUNING_DEFAULTS = {"batched": 1, "adj_group": 0, "gj_bias": 0, "contract_tile": 2, "persistent": 0, "det_dA": 0}
 
 
 class LocalArgs(ct.Structure):

@@ -296,7 +296,7 @@ class Plan:
 
     @tuning.setter
     def tuning(self, d):
-        t = Tuning(*[int(d.get(k, 1 if k == "batched" else 0)) for k in _lib.TUNING_FIELDS])
+        t = Tuning(*[int(d.get(k, _lib.TUNING_DEFAULTS[k])) for k in _lib.TUNING_FIELDS])
         check(lib().qsl_plan_set_tuning(self._h, ct.byref(t)))
 
     def autotune(self, cache_path=None):

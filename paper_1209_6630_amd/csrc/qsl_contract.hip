@@ -59,19 +59,27 @@ struct CT {
 // ring of slot indices; chunks of 64 slots are evaluated into LDS (one
 // thread per slot and eight electrons) and contracted with
 // v_mfma_f32_32x32x2f32, k-step t taking chunk slots t and 32 + t.
-// Two workgroup shapes (tuning): tile 0 holds two 32-MO sub-blocks per wave
-// (256 MOs, 160 accumulators, two workgroups per CU), tile 1 one (128 MOs,
-// 80 accumulators, three per CU; the AOs are evaluated once per 128 MOs).
+// Three workgroup shapes (tuning): tile 0 holds two 32-MO sub-blocks per
+// wave (256 MOs, 160 accumulators, two workgroups per CU), tile 1 one (128
+// MOs, 80 accumulators, three per CU; the AOs are evaluated once per 128
+// MOs).  Tile 2 is tile 0 with the products on v_mfma_f32_32x32x16_bf16: both
+// FP32 operands split exactly into three bf16 (x = hi + mid + lo), C += the
+// six products hi.hi, hi.mid, mid.hi, hi.lo, mid.mid, lo.hi with FP32
+// accumulation.  The three dropped products are below 2^-23 relative of
+// each term, next to the 2^-24 of an FP32 product; the bf16 products take
+// 2.7 times fewer matrix-core cycles than the FP32 ones and, unlike them,
+// run beside the VALU work of the AO evaluation.
 template <int TILE>
 struct F32T {
-    static constexpr int MSUB = TILE == 0 ? 2 : 1;
+    static constexpr int MSUB = TILE == 1 ? 1 : 2;
     static constexpr int NB = MSUB * CT_WAVES * 32;
-    static constexpr int MINB = TILE == 0 ? 2 : 3;
+    static constexpr int MINB = TILE == 1 ? 3 : 2;
 };
 constexpr int F32_BATCH = 32;   // windows filtered at a time
 constexpr int F32_KC = 64;      // slots per chunk
 constexpr int F32_RING = 512;   // ring of slot indices (>= 8 * F32_BATCH + F32_KC)
 constexpr int F32_LD = F32_KC + 4;
+constexpr int F32_LD3 = F32_KC + 8;  // bf16 row stride of tile 2's B planes
 
 // Value, gradient and Laplacian of slot record r at electron p (FP32 AO
 // arithmetic, FP64 screening), with the near-tie flag.  The primitives are
@@ -185,6 +193,91 @@ __device__ __forceinline__ void slot_values_r(const SlotR& r, const SlotRec* __r
     v[4] = (d2x * fyz + d2y * fxz + d2z * fxy) * g + (float)(2 * l) * pg1 + P * g2;
 }
 
+// Tile 2's products over one chunk: k-block q (16 ring slots) gives the
+// lanes of half h the slots 16 q + 8 h .. + 7.  One (k-block, sub-block) at
+// a time: its coefficient triples (8 bytes per slot and MO, loaded one unit
+// ahead) are repacked into the three bf16 operand planes with byte permutes;
+// B is read one plane at a time for the five quantities, so consecutive
+// products go to five different accumulators.
+template <int MSUB>
+__device__ __forceinline__ void contract_s3_products(const Job& j, const uint16_t* B3, const int* ringo,
+                                                     const uint64_t* ringm, int head, int tail, int n0, int nsub,
+                                                     int nmo, int ldn, int wave, int lane, f32x16 (&acc)[MSUB][5]) {
+    constexpr int NSB = CT_WAVES * 32, PL = 5 * TE * F32_LD3;  // plane size in elements
+    constexpr int NQ = F32_KC / 16;
+    const int h = lane >> 5;
+    const char* __restrict__ a3b = (const char*)j.mo.A3;
+    uint64_t cr[8];
+    // uniform base + 32-bit byte offset: one address register per load;
+    // entries past the list point at row 0 (their B values are zero)
+    auto load_c = [&](int q, int sb) __attribute__((always_inline)) {
+        const int pos = head + 16 * q + 8 * h;  // a multiple of 8: the ring reads are aligned
+        const int4 s0 = *(const int4*)&ringo[pos & (F32_RING - 1)];
+        const int4 s1 = *(const int4*)&ringo[(pos + 4) & (F32_RING - 1)];
+        const int ov[8] = {pos + 0 < tail ? s0.x : 0, pos + 1 < tail ? s0.y : 0, pos + 2 < tail ? s0.z : 0,
+                           pos + 3 < tail ? s0.w : 0, pos + 4 < tail ? s1.x : 0, pos + 5 < tail ? s1.y : 0,
+                           pos + 6 < tail ? s1.z : 0, pos + 7 < tail ? s1.w : 0};
+        const int mcol = min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) cr[t] = *gmem((const uint64_t*)(a3b + (size_t)(uint32_t)((ov[t] + mcol) * 8)));
+    };
+    load_c(0, 0);
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
+        uint64_t gm = 0;  // MO blocks with a non-zero coefficient on this half's 8 slots
+        {
+            const int pos = head + 16 * q + 8 * h;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) gm |= pos + t < tail ? ringm[(pos + t) & (F32_RING - 1)] : 0ull;
+        }
+#pragma unroll
+        for (int sb = 0; sb < MSUB; ++sb) {
+            uint32_t x[4], y[4], z[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t a0 = (uint32_t)cr[2 * i], a1 = (uint32_t)cr[2 * i + 1];
+                const uint32_t b0 = (uint32_t)(cr[2 * i] >> 32), b1 = (uint32_t)(cr[2 * i + 1] >> 32);
+                x[i] = __builtin_amdgcn_perm(a1, a0, 0x05040100u);  // hi
+                y[i] = __builtin_amdgcn_perm(a1, a0, 0x07060302u);  // mid
+                z[i] = __builtin_amdgcn_perm(b1, b0, 0x05040100u);  // lo
+            }
+            const bf16x8 ch = __builtin_bit_cast(bf16x8, uint4{x[0], x[1], x[2], x[3]});
+            const bf16x8 cm = __builtin_bit_cast(bf16x8, uint4{y[0], y[1], y[2], y[3]});
+            const bf16x8 cl = __builtin_bit_cast(bf16x8, uint4{z[0], z[1], z[2], z[3]});
+            __builtin_amdgcn_sched_barrier(0);  // the planes are made before cr is reloaded
+            if (sb + 1 < MSUB) load_c(q, sb + 1);
+            else if (q + 1 < NQ) load_c(q + 1, 0);
+            // work: inside n, and (block-sparse A) some non-zero coefficient
+            // of the wave's 32 MOs on the k-block's 16 slots
+            const int mb0 = n0 + sb * NSB + wave * 32;
+            if (sb >= nsub || mb0 >= nmo || __ballot((gm >> ((mb0 >> 5) & 63)) & 1ull) == 0ull) continue;
+            const int off = (lane & 31) * F32_LD3 + 16 * q + 8 * h;
+            bf16x8 b[5];
+#pragma unroll
+            for (int d = 0; d < 5; ++d) b[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(B3 + 2 * PL + d * TE * F32_LD3 + off));
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], ch, acc[sb][d], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) b[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(B3 + PL + d * TE * F32_LD3 + off));
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], cm, acc[sb][d], 0, 0, 0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], ch, acc[sb][d], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) b[d] = __builtin_bit_cast(bf16x8, *(const uint4*)(B3 + d * TE * F32_LD3 + off));
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], cl, acc[sb][d], 0, 0, 0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], cm, acc[sb][d], 0, 0, 0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) acc[sb][d] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[d], ch, acc[sb][d], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 template <int TILE>
 __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, int tid_in) {
     const DevSys& s = j.s;
@@ -199,7 +292,10 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
     constexpr int MSUB = F32T<TILE>::MSUB, NSB = CT_WAVES * 32, LD = F32_LD, KC = F32_KC;
 
     __shared__ double epos[TE][3];
-    __shared__ __attribute__((aligned(16))) float B[5 * TE * LD];
+    // B: FP32 [5][TE][LD], or (tile 2) its three bf16 planes [3][5][TE][LD3]
+    __shared__ __attribute__((aligned(16))) unsigned char Bbuf[TILE == 2 ? 3 * 5 * TE * F32_LD3 * 2 : 5 * TE * LD * 4];
+    float* B = (float*)Bbuf;
+    uint16_t* B3 = (uint16_t*)Bbuf;
     __shared__ __attribute__((aligned(16))) int ring[F32_RING];
     __shared__ __attribute__((aligned(16))) int ringo[F32_RING];  // slot * ldn: the slot's coefficient row
     __shared__ __attribute__((aligned(16))) uint64_t ringm[F32_RING];  // the slot's MO-block mask
@@ -313,11 +409,25 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
                     slot_values_r(r, srec + slot, Tscr, p, v, tie);
                 }
                 tiebits |= (tie ? 1u : 0u) << i;
+                if constexpr (TILE == 2) {
 #pragma unroll
-                for (int d = 0; d < 5; ++d) B[(d * TE + e) * LD + kk] = v[d];
+                    for (int d = 0; d < 5; ++d) {
+                        uint16_t hv, mv, lv;
+                        bf16_split3(v[d], hv, mv, lv);
+                        B3[((0 * 5 + d) * TE + e) * F32_LD3 + kk] = hv;
+                        B3[((1 * 5 + d) * TE + e) * F32_LD3 + kk] = mv;
+                        B3[((2 * 5 + d) * TE + e) * F32_LD3 + kk] = lv;
+                    }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 5; ++d) B[(d * TE + e) * LD + kk] = v[d];
+                }
             }
         }
         __syncthreads();
+        if constexpr (TILE == 2) {
+            contract_s3_products<MSUB>(j, B3, ringo, ringm, head, tail, n0, nsub, nmo, ldn, wave, lane, acc);
+        } else
         // ---- products: k-step t of group u takes chunk slots 4u + t (lanes
         // 0..31) and 32 + 4u + t (lanes 32..63); the coefficients of the
         // next group are loaded during this group's MFMAs
@@ -666,6 +776,13 @@ __global__ __launch_bounds__(CT_WAVES * 64, F32T<1>::MINB) void contract_batched
     });
 }
 
+__global__ __launch_bounds__(CT_WAVES * 64, F32T<2>::MINB) void contract_batched_f32t2(const Job* jobs,
+                                                                                       const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) __attribute__((always_inline)) {
+        contract_f32_body<2>(j, bx, by, threadIdx.x);
+    });
+}
+
 // Persistent form: `gridDim.x` resident workgroups take the items of the
 // work list in order from a device counter (zeroed before the launch) until
 // it passes the last; every workgroup leaves once the counter does.
@@ -704,10 +821,16 @@ __global__ __launch_bounds__(CT_WAVES * 64, F32T<1>::MINB) void contract_persist
     contract_persist_body<QSL_FP32, 1>(jobs, prefix, njobs, queue);
 }
 
+__global__ __launch_bounds__(CT_WAVES * 64, F32T<2>::MINB) void contract_persist_f32t2(const Job* jobs,
+                                                                                       const int* prefix, int njobs,
+                                                                                       unsigned* queue) {
+    contract_persist_body<QSL_FP32, 2>(jobs, prefix, njobs, queue);
+}
+
 // Grid of the contraction phase of a Job: tiles x MO blocks.
 void contract_grid(Job& j) {
     const int nb = j.mode == QSL_FP64 ? CT<QSL_FP64>::NB
-                                      : (j.mode == QSL_FP32 ? (j.f32_tile ? F32T<1>::NB : F32T<0>::NB)
+                                      : (j.mode == QSL_FP32 ? (j.f32_tile == 1 ? F32T<1>::NB : F32T<0>::NB)
                                                             : CT<QSL_BF16X3>::NB);
     j.gx = (int)electron_tiles(j.n, j.W);
     j.gy = (j.mo.n + nb - 1) / nb;  // MO blocks (n for a Slater matrix)
@@ -736,21 +859,23 @@ hipError_t launch_contract(const Job& j0, hipStream_t st) {
     return launch_contract_batched(j.mode, j.f32_tile, nullptr, dj, pre, 1, j.gx * j.gy, st);
 }
 
-int contract_per_cu(int mode, int tile) { return mode == QSL_FP32 && tile ? F32T<1>::MINB : 2; }
+int contract_per_cu(int mode, int tile) { return mode == QSL_FP32 && tile == 1 ? F32T<1>::MINB : 2; }
 
 hipError_t launch_contract_batched(int mode, int tile, unsigned* queue, const Job* jobs, const int* prefix, int njobs,
                                    int grid, hipStream_t st) {
     constexpr int T = CT_WAVES * 64;
     if (grid <= 0) return hipSuccess;
-    const bool t1 = mode == QSL_FP32 && tile;
+    const bool t1 = mode == QSL_FP32 && tile == 1, t2 = mode == QSL_FP32 && tile == 2;
     if (queue) {
         if (mode == QSL_FP64) contract_persist<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
         else if (t1) contract_persist_f32t1<<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
+        else if (t2) contract_persist_f32t2<<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
         else if (mode == QSL_FP32) contract_persist<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
         else contract_persist<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs, queue);
     } else {
         if (mode == QSL_FP64) contract_batched<QSL_FP64><<<grid, T, 0, st>>>(jobs, prefix, njobs);
         else if (t1) contract_batched_f32t1<<<grid, T, 0, st>>>(jobs, prefix, njobs);
+        else if (t2) contract_batched_f32t2<<<grid, T, 0, st>>>(jobs, prefix, njobs);
         else if (mode == QSL_FP32) contract_batched<QSL_FP32><<<grid, T, 0, st>>>(jobs, prefix, njobs);
         else contract_batched<QSL_BF16X3><<<grid, T, 0, st>>>(jobs, prefix, njobs);
     }

@@ -193,6 +193,7 @@ Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws,
     j.win = (int*)(ws + L.win_off[s]);
     j.jobslot = ws + L.job_off;
     if (sorted && a->mode == QSL_FP32) j.wperm = (const int*)(ws + L.perm_off[s]);
+    j.f32_tile = F32_TILE_DEFAULT;
     j.C = a->C[s];
     if (gj_blocked(j.n)) j.gjws = (double*)(ws + L.gj_off[s]);
     j.logdet = a->logdet;
@@ -485,7 +486,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
         size_t o_wrec = ar.add(win_rec.data(), sizeof(WinRec) * win_rec.size());
         size_t o_srec = ar.add(slot_rec.data(), sizeof(SlotRec) * slot_rec.size());
         // MO copies per spin
-        size_t o_mo[2][9];
+        size_t o_mo[2][10];
         int ldn[2];
         for (int sp = 0; sp < 2; ++sp) {
             int n = sp ? d->n_dn : d->n_up;
@@ -497,6 +498,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             o_mo[sp][6] = ar.reserve(cells * 8);
             o_mo[sp][7] = ar.reserve(cells * 4);
             o_mo[sp][8] = ar.reserve((size_t)n_slots * 8);
+            o_mo[sp][9] = ar.reserve(cells * 8);
         }
         void* blk = nullptr;
         hipError_t e = hipMalloc(&blk, ar.buf.size());
@@ -544,6 +546,7 @@ qsl_status qsl_system_create(const qsl_system_desc* d, qsl_system** out) {
             m.A64 = (double*)(b + o_mo[sp][6]);
             m.A32 = (float*)(b + o_mo[sp][7]);
             m.blkmask = (uint64_t*)(b + o_mo[sp][8]);
+            m.A3 = (uint64_t*)(b + o_mo[sp][9]);
             m.set = (m.n == 0);
             S->mo_cap[sp] = ldn[sp];
         }
@@ -593,11 +596,12 @@ static qsl_status set_mo_rows(qsl_system* sys, int32_t spin, const double* A, in
     const int need = (int)round_up((size_t)n_rows, 128);
     if (need > sys->mo_cap[spin]) {
         const size_t cells = (size_t)sys->d.n_slots * need;
-        // FP64, FP32, four bf16 and the [ldn][slot] FP64 / FP32 copies
+        // FP64, FP32, four bf16, the [ldn][slot] FP64 / FP32 copies, the
+        // block masks and the three-way bf16 split
         const size_t o32 = round_up(cells * 8, 256), o16 = o32 + round_up(cells * 4, 256),
                      oa64 = o16 + 4 * round_up(cells * 2, 256), oa32 = oa64 + round_up(cells * 8, 256),
-                     omask = oa32 + round_up(cells * 4, 256),
-                     total = omask + round_up((size_t)sys->d.n_slots * 8, 256);
+                     omask = oa32 + round_up(cells * 4, 256), oa3 = omask + round_up((size_t)sys->d.n_slots * 8, 256),
+                     total = oa3 + round_up(cells * 8, 256);
         void* blk = nullptr;
         hipError_t e = hipStreamSynchronize((hipStream_t)stream);  // earlier calls may still read the old copies
         if (e != hipSuccess) return hip_fail(e, "orbitals: synchronize");
@@ -614,6 +618,7 @@ static qsl_status set_mo_rows(qsl_system* sys, int32_t spin, const double* A, in
         m.A64 = (double*)(b + oa64);
         m.A32 = (float*)(b + oa32);
         m.blkmask = (uint64_t*)(b + omask);
+        m.A3 = (uint64_t*)(b + oa3);
         sys->mo_cap[spin] = need;
         ++sys->mo_generation;
     }

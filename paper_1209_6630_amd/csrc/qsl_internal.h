@@ -108,6 +108,9 @@ struct DevMO {
     uint16_t* ATlo = nullptr;
     double* A64 = nullptr;      // [ldn][n_slots]
     float* A32 = nullptr;       // [ldn][n_slots]
+    // [n_slots][ldn]: the FP32 value x as bf16 bits hi | mid << 16 | lo << 32
+    // with x = hi + mid + lo exactly (each rounded to nearest even)
+    uint64_t* A3 = nullptr;
     // [n_slots]: bit b set when some MO of block [32 b, 32 b + 32) has a
     // non-zero coefficient on the slot (all bits set past 64 blocks)
     uint64_t* blkmask = nullptr;
@@ -277,6 +280,16 @@ __device__ __forceinline__ void bf16_split2(float a, float b, uint32_t& hi, uint
     lo = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)ra, (__bf16)rb});
 }
 
+// Exact three-way split of a float: x = hi + mid + lo, each bf16 rounded to
+// nearest even from the remainder of the previous ones (x has 24 significand
+// bits, each part takes 8, so the last remainder is exact).
+__device__ __forceinline__ void bf16_split3(float x, uint16_t& hi, uint16_t& mid, uint16_t& lo) {
+    hi = bf16_rne(x);
+    const float r1 = x - bf16_to_f(hi);
+    mid = bf16_rne(r1);
+    lo = bf16_rne(r1 - bf16_to_f(mid));
+}
+
 // One (system, spin) unit of work of a kernel phase: everything the kernel
 // bodies read.  A per-system launch passes one Job by value; a batched
 // launch walks the blocks of several Jobs (an uneven batch of systems) with
@@ -306,7 +319,7 @@ struct Job {
     double* gjws;            // blocked inversion (gj_blocked(n)): W x gj_ws_doubles(n)
     uint16_t* gsplit;        // BF16X3 adjoint: W x gsplit_elems(n) hi, then as many lo
     void* jobslot;           // per-system launches: device copy of the Job and its block prefix
-    int f32_tile;            // FP32 products: 0 = 256 MOs per workgroup, 1 = 128
+    int f32_tile;            // FP32 products: 0 = 256 MOs per workgroup, 1 = 128, 2 = 256 on split bf16
     // Deterministic dA: one launch per electron range t_fix (-1: one launch
     // for all ranges, atomic flush), each walker group adding its block into
     // its own partial sum dApart[wb][n][N_b] (float, or double in FP64) with
@@ -439,6 +452,9 @@ struct WsLayout {
 };
 WsLayout ws_layout(const DevSys& d, int64_t W, int gw, int mode, bool by_e);
 // The Job of spin s of a forward / adjoint call on workspace ws.
+// The FP32 products' default tile (per-system calls and a new plan): the
+// split-bf16 products, as accurate as FP32 MFMA and faster.
+constexpr int F32_TILE_DEFAULT = 2;
 Job fwd_job(qsl_system* sys, const qsl_fwd_args* a, const WsLayout& L, char* ws, int s, bool sorted = false);
 Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws, int s, int gw, bool by_e);
 

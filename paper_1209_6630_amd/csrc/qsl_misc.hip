@@ -7,10 +7,11 @@ namespace qsl {
 // A^s (n x N_b, row-major, leading dimension ld, FP64) -> the library's
 // padded copies: AT64/AT32 [slot][ldn], A64/A32 [ldn][slot], and hi/lo bf16
 // splits (hi = bf16(x), lo = bf16(x - hi) of the FP32 value x) packed per
-// window: Ahi/Alo [window][ldn][8], AThi/ATlo [window][ldn/8][8][8].
+// window: Ahi/Alo [window][ldn][8], AThi/ATlo [window][ldn/8][8][8]; and
+// the exact three-way bf16 split of the FP32 value, A3 [slot][ldn].
 __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restrict__ A, int64_t ld,
                                 double* AT64, float* AT32, uint16_t* Ahi, uint16_t* Alo, uint16_t* AThi,
-                                uint16_t* ATlo, double* A64, float* A32) {
+                                uint16_t* ATlo, double* A64, float* A32, uint64_t* A3) {
     const int64_t total = (int64_t)s.n_slots * ldn;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
         const int slot = (int)(q / ldn), mo = (int)(q % ldn);
@@ -33,6 +34,9 @@ __global__ void build_mo_kernel(DevSys s, int n, int ldn, const double* __restri
         ATlo[pt] = l;
         A64[(int64_t)mo * s.n_slots + slot] = v;
         A32[(int64_t)mo * s.n_slots + slot] = f;
+        uint16_t h3, m3, l3;
+        bf16_split3(f, h3, m3, l3);
+        A3[q] = (uint64_t)h3 | ((uint64_t)m3 << 16) | ((uint64_t)l3 << 32);
     }
 }
 
@@ -57,7 +61,7 @@ hipError_t launch_build_mo(const DevSys& s, DevMO& mo, const double* A, int64_t 
     if (!total) return hipSuccess;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 8192);
     build_mo_kernel<<<blocks, 256, 0, st>>>(s, mo.n, mo.ldn, A, ld, mo.AT64, mo.AT32, mo.Ahi, mo.Alo, mo.AThi,
-                                            mo.ATlo, mo.A64, mo.A32);
+                                            mo.ATlo, mo.A64, mo.A32, mo.A3);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     mo_mask_kernel<<<(s.n_slots + 3) / 4, 256, 0, st>>>(s.n_slots, mo.n, mo.ldn, mo.AT32, mo.blkmask);

@@ -216,6 +216,7 @@ qsl_status qsl_multidet_forward(qsl_system* sys, const qsl_multidet_args* a, voi
         j.nwin = (int*)(ws + L.base.nwin_off[s]);
         j.win = (int*)(ws + L.base.win_off[s]);
         j.jobslot = ws + L.base.job_off;
+        j.f32_tile = F32_TILE_DEFAULT;
         j.status = st0;
         if (n) {
             // the products of the whole orbital set, once

@@ -60,7 +60,7 @@ struct qsl_plan {
     std::vector<qsl_fwd_args> fwd;
     std::vector<qsl_bwd_args> bwd;
     std::vector<char> bound, has_bwd;
-    qsl_tuning tune{1, 0, 0, 0, 0, 0};
+    qsl_tuning tune{1, 0, 0, F32_TILE_DEFAULT, 0, 0};
     int n_cu = 256;  // compute units (the persistent launch's grid)
     // workspace: the persistent launch's item counter, then per system window
     // lists and dA accumulators, then the deterministic dA's partial sums
@@ -885,7 +885,8 @@ qsl_status qsl_plan_bind(qsl_plan* p, int32_t i, const qsl_fwd_args* f, const qs
 qsl_status qsl_plan_set_tuning(qsl_plan* p, const qsl_tuning* t) {
     if (!p || !t) return bad(QSL_ERR_INVALID_ARG, "plan tuning: NULL argument");
     auto flag = [](int32_t v) { return v == 0 || v == 1; };
-    if (!flag(t->batched) || t->adj_group < 0 || t->adj_group > 4096 || !flag(t->gj_bias) || !flag(t->contract_tile) ||
+    if (!flag(t->batched) || t->adj_group < 0 || t->adj_group > 4096 || !flag(t->gj_bias) || t->contract_tile < 0 ||
+        t->contract_tile > 2 ||
         !flag(t->persistent) || !flag(t->det_dA))
         return bad(QSL_ERR_INVALID_ARG, "plan tuning: value out of range");
     p->tune = *t;
@@ -952,16 +953,27 @@ namespace qsl {
 static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& key, const char* cache_path,
                                const qsl_tuning saved, qsl_tuning* chosen) {
     hipError_t e;
-    // the default tuning is the reference of the self-check; every
-    // candidate keeps the caller's choice of the deterministic dA
-    const qsl_tuning base{1, 0, 0, 0, 0, saved.det_dA};
-    p->tune = base;
-    p->dirty = true;
-    Snapshot ref, got;
-    qsl_status r = launch_plan(p, st);
+    // the reference of the self-check is the default tuning with the
+    // candidate's FP32 contraction tile (the tiles round differently: FP32
+    // or split-bf16 products), run once per tile; every candidate keeps the
+    // caller's choice of the deterministic dA
+    const qsl_tuning base{1, 0, 0, F32_TILE_DEFAULT, 0, saved.det_dA};
+    Snapshot refs[3], got;
+    bool have_ref[3] = {false, false, false};
+    auto reference = [&](int tile) -> qsl_status {
+        if (have_ref[tile]) return QSL_OK;
+        p->tune = base;
+        p->tune.contract_tile = tile;
+        p->dirty = true;
+        qsl_status q = launch_plan(p, st);
+        if (q != QSL_OK) return q;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "autotune: sync");
+        if ((e = snapshot(p, refs[tile])) != hipSuccess) return hip_fail(e, "autotune: copy");
+        have_ref[tile] = true;
+        return QSL_OK;
+    };
+    qsl_status r = reference(base.contract_tile);
     if (r != QSL_OK) return r;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "autotune: sync");
-    if ((e = snapshot(p, ref)) != hipSuccess) return hip_fail(e, "autotune: copy");
     int64_t wmax = 1;
     int nmax = 0;
     for (int i = 0; i < p->n_sys; ++i) {
@@ -978,20 +990,22 @@ static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& k
             for (int g : groups) {
                 if (!any_bwd && g) continue;
                 if (g > 16 && g >= 2 * wmax) continue;  // the same as a smaller group for every system
-                cands.push_back(qsl_tuning{bt, g, gb, 0, 0, saved.det_dA});
+                cands.push_back(qsl_tuning{bt, g, gb, base.contract_tile, 0, saved.det_dA});
             }
         }
     double best_ms = 1e300;
     qsl_tuning best = base;
     bool found = false;
     auto trial = [&](const qsl_tuning& c) -> qsl_status {
+        qsl_status q0 = reference(c.contract_tile);
+        if (q0 != QSL_OK) return q0;
         p->tune = c;
         p->dirty = true;
         double ms = 0.0;
         qsl_status q = time_plan(p, st, 3, &ms);
         if (q != QSL_OK) return q;
         if ((e = snapshot(p, got)) != hipSuccess) return hip_fail(e, "autotune: copy");
-        if (!same_results(p, ref, got)) return QSL_OK;
+        if (!same_results(p, refs[c.contract_tile], got)) return QSL_OK;
         if (ms < best_ms) {
             best_ms = ms;
             best = c;
@@ -1005,11 +1019,13 @@ static qsl_status autotune_run(qsl_plan* p, hipStream_t st, const std::string& k
         if ((r = trial(c)) != QSL_OK) return r;
     if (found) {
         const qsl_tuning b0 = best;
-        for (int tile = 0; tile <= 1; ++tile)
+        const int tiles = p->mode == QSL_FP32 ? 2 : 0;  // the tile is an FP32 choice
+        for (int tile = 0; tile <= tiles; ++tile)
             for (int pers = 0; pers <= (b0.batched ? 1 : 0); ++pers) {
-                if (!tile && !pers) continue;  // b0 itself
+                if (tiles && tile == b0.contract_tile && pers == b0.persistent) continue;  // b0 itself
+                if (!tiles && !pers) continue;
                 qsl_tuning c = b0;
-                c.contract_tile = tile;
+                c.contract_tile = tiles ? tile : b0.contract_tile;
                 c.persistent = pers;
                 if ((r = trial(c)) != QSL_OK) return r;
             }

@@ -187,7 +187,9 @@ TUNINGS = [dict(batched=0, adj_group=16, gj_bias=0),
            dict(batched=1, adj_group=0, gj_bias=0, persistent=1),
            dict(batched=1, adj_group=64, gj_bias=0, contract_tile=1, persistent=1),
            dict(batched=1, adj_group=16, gj_bias=0, det_dA=1),
-           dict(batched=0, adj_group=0, gj_bias=0, contract_tile=1, det_dA=1)]
+           dict(batched=0, adj_group=0, gj_bias=0, contract_tile=1, det_dA=1),
+           dict(batched=1, adj_group=0, gj_bias=0, contract_tile=2),
+           dict(batched=1, adj_group=32, gj_bias=0, contract_tile=2, persistent=1)]
 
 
 @pytest.mark.parametrize("mode", ["fp32", "fp64", "bf16x3"])
@@ -197,7 +199,11 @@ def test_tunings_agree(tuning, mode):
         pytest.skip("the contraction tile is an FP32 choice; block shapes are covered in FP32")
     print(f"[case] tuning {tuning} mode={mode}", flush=True)
     items = _batch([("44e", 40), ("158e", 6), (("tiny", 70, 60), 3)])
-    P0, b0 = _plan(items, mode, graph=False)
+    # the reference: the default tuning with the same FP32 tile family (tiles
+    # 0 and 1 round alike, the split-bf16 tile 2 otherwise; each against the
+    # oracle in test_contract_tiles_against_oracle)
+    ref_tile = 2 if tuning.get("contract_tile", 2) == 2 else 0
+    P0, b0 = _plan(items, mode, graph=False, tuning=dict(contract_tile=ref_tile))
     P0.launch()
     ref = _read(b0)
     P1, b1 = _plan(items, mode, graph=True, tuning=tuning)
@@ -206,7 +212,7 @@ def test_tunings_agree(tuning, mode):
     got = _read(b1)
     for r, g_ in zip(ref, got):
         # another Gauss-Jordan block shape may break pivot ties differently;
-        # the contraction tile and the persistent launch change no sum
+        # tiles of one family and the persistent launch change no sum
         _same(r, g_, mode, exact=tuning["gj_bias"] == 0)
     P0.close()
     P1.close()
@@ -258,7 +264,7 @@ def test_deterministic_dA_repeats_bit_for_bit(mode):
         p_.close()
 
 
-@pytest.mark.parametrize("tile,persistent", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("tile,persistent", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
 def test_contract_tiles_against_oracle(tile, persistent):
     """Each FP32 contraction tile, in one launch per item or persistent,
     on the 434- and 44-electron systems against the FP64 oracle on sampled
