@@ -950,10 +950,200 @@ __device__ __forceinline__ void adj_dae_body(const Job& j, int bx, int by) {
     }
 }
 
+// The same dA with the products on split-bf16 MFMA (FP32 tile 2): G and
+// the AO values are split exactly into three bf16 each (x = hi + mid + lo)
+// and dA += the six leading products on v_mfma_f32_32x32x16_bf16 (K = 16
+// walkers), FP32 accumulation; per product 2^-23 relative next to the
+// 2^-24 of an FP32 one.  The batch's G rows pass through registers into
+// three transposed bf16 planes [plane][MO][walker] (shared by the four
+// waves); each wave splits the AO values of its own 32 slots when it forms
+// its operand.
+constexpr int DS_GW = DE_KW + 8;        // bf16 row stride (walkers) of the G planes
+constexpr int DS_PL = DE_MB * DS_GW;    // elements per plane
+constexpr int DS_UNITS = (DE_MB / 4) * (DE_KW / 2);  // (MO quad, walker pair) units of the G split
+constexpr int DS_PASS = (DS_UNITS + DE_THREADS - 1) / DE_THREADS;
+
+__device__ __forceinline__ void adj_dae_s3_body(const Job& j, int bx, int by) {
+    typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+    const DevSys& s = j.s;
+    const int n = j.n, gw = j.gw, spin = j.spin;
+    const int64_t W = j.W;
+    const int ngw = (int)((W + gw - 1) / gw);
+    // the XCD-aware block mapping of adj_dae_body
+    const int o = bx & 31;
+    const int grp = (bx >> 5) * 8 + (o & 7), cs = o >> 3;
+    if (grp >= j.n * ngw) return;
+    const int e = grp / ngw, g = grp % ngw;
+    const int nsl = j.gnwin[grp];
+    if (cs * DE_NS >= nsl) return;
+    const int* __restrict__ sl = j.gwin + (size_t)grp * WIN * s.n_win;
+    const int64_t w0 = (int64_t)g * gw;
+    const int nw = (int)min<int64_t>(gw, W - w0);
+    const int i0 = by * DE_MB;
+    const int ldg = g32_ld(n);
+    const int N = s.n_up + s.n_dn, eoff = spin ? s.n_up : 0;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double Tscr = readlane_f64(s.T, 0);
+    const float* __restrict__ G32 = j.g32;
+    const SlotRec* __restrict__ srec = s.slot_rec;
+    float* __restrict__ dA32 = j.dA32;
+
+    __shared__ double ep[DE_KW][3];
+    __shared__ int wl[DE_KW];
+    __shared__ __attribute__((aligned(16))) float X[DE_KW * DE_LDX];
+    __shared__ __attribute__((aligned(16))) uint16_t G3[3 * DS_PL];
+    __shared__ int qao[DE_NS];
+    auto walker_at = [&](int wb) -> int {
+        return wb + tid < nw ? (int)walker_of(j.wperm, W, e, w0 + wb + tid) : -1;
+    };
+    auto pos_of = [&](int wb) -> double {
+        const int k = tid / 3;
+        return wb + k < nw ? j.R[((size_t)walker_of(j.wperm, W, e, w0 + wb + k) * N + eoff + e) * 3 + tid % 3] : 0.0;
+    };
+
+    for (int c0 = cs * DE_NS; c0 < nsl; c0 += DE_NCH * DE_NS) {
+        const int cnt = min(DE_NS, nsl - c0);
+        __syncthreads();  // the previous chunk's flush is done with qao
+        if (tid < DE_NS) qao[tid] = tid < cnt ? s.slot_ao[sl[c0 + tid]] : -1;
+        const int ql = tid & (DE_NS - 1);
+        const bool live = ql < cnt;
+        SlotRegs rg;
+        rg.load(srec[sl[c0 + min(ql, cnt - 1)]]);
+        f32x16 acc[DE_MB / 32];
+#pragma unroll
+        for (int mb = 0; mb < DE_MB / 32; ++mb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+        double pnext = tid < DE_KW * 3 ? pos_of(0) : 0.0;
+        int wnext = tid < DE_KW ? walker_at(0) : 0;
+        for (int wb = 0; wb < nw; wb += DE_KW) {
+            const int kw = min(DE_KW, nw - wb);
+            __syncthreads();  // the previous batch's products are done with X, G3, ep and wl
+            if (tid < DE_KW * 3) ep[tid / 3][tid % 3] = pnext;
+            if (tid < DE_KW) wl[tid] = wnext;
+            __syncthreads();  // positions and walkers of the batch visible
+            // G rows into registers: unit u = (MO quad u / 16, walker pair
+            // u % 16), its 16-byte pieces of both walkers' rows (rows past the
+            // group repeat its last walker: their AO values are zero)
+            float4 ga[DS_PASS], gb[DS_PASS];
+#pragma unroll
+            for (int ps = 0; ps < DS_PASS; ++ps) {
+                const int u = ps * DE_THREADS + tid;
+                const int kp = u % (DE_KW / 2), mq = min(u / (DE_KW / 2), DE_MB / 4 - 1);
+                const int r0 = min(2 * kp, kw - 1), r1 = min(2 * kp + 1, kw - 1);
+                ga[ps] = *(const float4*)(G32 + ((size_t)wl[r0] * n + e) * ldg + i0 + 4 * mq);
+                gb[ps] = *(const float4*)(G32 + ((size_t)wl[r1] * n + e) * ldg + i0 + 4 * mq);
+            }
+            if (wb + DE_KW < nw) {
+                if (tid < DE_KW * 3) pnext = pos_of(wb + DE_KW);
+                if (tid < DE_KW) wnext = walker_at(wb + DE_KW);
+            }
+            // AO values (FP32): thread (slot tid % 128, walkers of parity tid / 128)
+#pragma unroll 1
+            for (int k = tid >> 7; k < DE_KW; k += 2) {
+                float v = 0.f;
+                if (live && k < kw) v = rg.value(Tscr, ep[k][0], ep[k][1], ep[k][2]);
+                X[k * DE_LDX + ql] = v;
+            }
+            // the G planes: per unit and MO, one packed pair (walkers 2 kp,
+            // 2 kp + 1) per plane; sixteen lanes fill one row's 64 bytes
+#pragma unroll
+            for (int ps = 0; ps < DS_PASS; ++ps) {
+                const int u = ps * DE_THREADS + tid;
+                if (u < DS_UNITS) {
+                    const int kp = u % (DE_KW / 2), mq = u / (DE_KW / 2);
+                    const float va[4] = {ga[ps].x, ga[ps].y, ga[ps].z, ga[ps].w};
+                    const float vb[4] = {gb[ps].x, gb[ps].y, gb[ps].z, gb[ps].w};
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        uint32_t h3, m3, l3;
+                        bf16_split3_pair(va[t], vb[t], h3, m3, l3);
+                        const int off = (4 * mq + t) * DS_GW + 2 * kp;
+                        *(uint32_t*)&G3[off] = h3;
+                        *(uint32_t*)&G3[DS_PL + off] = m3;
+                        *(uint32_t*)&G3[2 * DS_PL + off] = l3;
+                    }
+                }
+            }
+            __syncthreads();
+            if (wave * 32 < cnt) {
+                const int h = lane >> 5, c = lane & 31;
+                constexpr int NMB = DE_MB / 32;
+#pragma unroll
+                for (int kb = 0; kb < DE_KW / 16; ++kb) {
+                    // this wave's operand: slot wave * 32 + c, walkers
+                    // 16 kb + 8 h .. + 7, split into three planes
+                    uint32_t xh[4], xm[4], xl[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = 16 * kb + 8 * h + 2 * i;
+                        bf16_split3_pair(X[k * DE_LDX + wave * 32 + c], X[(k + 1) * DE_LDX + wave * 32 + c], xh[i],
+                                         xm[i], xl[i]);
+                    }
+                    const bf16x8 bh = __builtin_bit_cast(bf16x8, uint4{xh[0], xh[1], xh[2], xh[3]});
+                    const bf16x8 bm = __builtin_bit_cast(bf16x8, uint4{xm[0], xm[1], xm[2], xm[3]});
+                    const bf16x8 bl = __builtin_bit_cast(bf16x8, uint4{xl[0], xl[1], xl[2], xl[3]});
+                    // MO blocks two at a time, so that consecutive products go
+                    // to different accumulators
+#pragma unroll
+                    for (int m0 = 0; m0 < NMB; m0 += 2) {
+                        constexpr int P = 2;
+                        bf16x8 gh[P], gm[P], gl[P];
+#pragma unroll
+                        for (int q = 0; q < P; ++q) {
+                            const int mb = min(m0 + q, NMB - 1);
+                            const int off = (mb * 32 + c) * DS_GW + 16 * kb + 8 * h;
+                            gh[q] = __builtin_bit_cast(bf16x8, *(const uint4*)&G3[off]);
+                            gm[q] = __builtin_bit_cast(bf16x8, *(const uint4*)&G3[DS_PL + off]);
+                            gl[q] = __builtin_bit_cast(bf16x8, *(const uint4*)&G3[2 * DS_PL + off]);
+                        }
+#define QSL_DS3(GA, XB)                                                                                    \
+    _Pragma("unroll") for (int q = 0; q < P; ++q) if (m0 + q < NMB) acc[m0 + q] =                          \
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(GA[q], XB, acc[m0 + q], 0, 0, 0);
+                        QSL_DS3(gl, bh)
+                        QSL_DS3(gm, bm)
+                        QSL_DS3(gh, bl)
+                        QSL_DS3(gm, bh)
+                        QSL_DS3(gh, bm)
+                        QSL_DS3(gh, bh)
+#undef QSL_DS3
+                    }
+                }
+            }
+        }
+        // flush, as adj_dae_body
+        if (wave * 32 < cnt) {
+            const int col = wave * 32 + (lane & 31);
+            const int ao = col < cnt ? qao[col] : -1;
+            int nbas = __builtin_amdgcn_readfirstlane(s.n_basis);
+            int lim = n - i0 - 4 * (lane >> 5);  // rows di < lim exist
+            asm volatile("" : "+s"(nbas));
+            asm volatile("" : "+v"(lim));
+            float* rowp = dA32 + (size_t)(i0 + 4 * (lane >> 5)) * nbas + max(ao, 0);
+#pragma unroll
+            for (int mb = 0; mb < DE_MB / 32; ++mb) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int di = mb * 32 + 8 * (r >> 2) + (r & 3);
+                    const float v = acc[mb][r];
+                    if (di < lim && ao >= 0 && v != 0.f) atomicAdd(rowp + (size_t)di * nbas, v);
+                }
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_kernel(Job j) { adj_dae_body(j, blockIdx.x, blockIdx.y); }
 
 __global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_batched(const Job* jobs, const int* prefix, int njobs) {
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { adj_dae_body(j, bx, by); });
+}
+
+__global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_s3_kernel(Job j) { adj_dae_s3_body(j, blockIdx.x, blockIdx.y); }
+
+__global__ __launch_bounds__(DE_THREADS, 2) void adj_dae_s3_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int by, int) { adj_dae_s3_body(j, bx, by); });
 }
 
 void adj_dae_grid(Job& j) {
@@ -967,13 +1157,15 @@ hipError_t launch_adj_dae(const Job& j0, hipStream_t st) {
     if (j.gw < 1 || j.mode != QSL_FP32 || !j.by_e || (j.n && j.W && j.dA32 && !j.g32)) return hipErrorInvalidValue;
     adj_dae_grid(j);
     if (!j.n || !j.W || !j.dA32) return hipSuccess;
-    adj_dae_kernel<<<dim3((unsigned)j.gx, j.gy), DE_THREADS, 0, st>>>(j);
+    if (j.f32_tile == 2) adj_dae_s3_kernel<<<dim3((unsigned)j.gx, j.gy), DE_THREADS, 0, st>>>(j);
+    else adj_dae_kernel<<<dim3((unsigned)j.gx, j.gy), DE_THREADS, 0, st>>>(j);
     return hipGetLastError();
 }
 
-hipError_t launch_adj_dae_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
+hipError_t launch_adj_dae_batched(int tile, const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st) {
     if (grid <= 0) return hipSuccess;
-    adj_dae_batched<<<grid, DE_THREADS, 0, st>>>(jobs, prefix, njobs);
+    if (tile == 2) adj_dae_s3_batched<<<grid, DE_THREADS, 0, st>>>(jobs, prefix, njobs);
+    else adj_dae_batched<<<grid, DE_THREADS, 0, st>>>(jobs, prefix, njobs);
     return hipGetLastError();
 }
 

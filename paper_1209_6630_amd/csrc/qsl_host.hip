@@ -234,6 +234,7 @@ Job bwd_job(qsl_system* sys, const qsl_bwd_args* a, const WsLayout& L, char* ws,
         if (a->mode == QSL_BF16X3) j.gsplit = (uint16_t*)(ws + L.gs_off[s]);
         if (by_e) j.g32 = (float*)(ws + L.g32_off[s]);
     }
+    j.f32_tile = F32_TILE_DEFAULT;
     return j;
 }
 

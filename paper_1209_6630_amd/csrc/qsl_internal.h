@@ -280,6 +280,16 @@ __device__ __forceinline__ void bf16_split2(float a, float b, uint32_t& hi, uint
     lo = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)ra, (__bf16)rb});
 }
 
+// The same split of two floats at once, as packed bf16 pairs (a in the low
+// half): three packed conversions.
+__device__ __forceinline__ void bf16_split3_pair(float a, float b, uint32_t& hi, uint32_t& mid, uint32_t& lo) {
+    hi = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)a, (__bf16)b});
+    const float ra = a - __uint_as_float(hi << 16), rb = b - __uint_as_float(hi & 0xffff0000u);
+    mid = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)ra, (__bf16)rb});
+    const float sa = ra - __uint_as_float(mid << 16), sb = rb - __uint_as_float(mid & 0xffff0000u);
+    lo = __builtin_bit_cast(uint32_t, bf16x2_t{(__bf16)sa, (__bf16)sb});
+}
+
 // Exact three-way split of a float: x = hi + mid + lo, each bf16 rounded to
 // nearest even from the remainder of the previous ones (x has 24 significand
 // bits, each part takes 8, so the last remainder is exact).
@@ -554,7 +564,7 @@ hipError_t launch_adj_da_batched(int mode, const Job* jobs, const int* prefix, i
 // stride, MO blocks of 224) over the group slot lists.
 void adj_dae_grid(Job& j);
 hipError_t launch_adj_dae(const Job& j, hipStream_t st);
-hipError_t launch_adj_dae_batched(const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
+hipError_t launch_adj_dae_batched(int tile, const Job* jobs, const int* prefix, int njobs, int grid, hipStream_t st);
 hipError_t launch_finalize_dA(const float* dA32, double* dA, int64_t count, int accumulate, hipStream_t st);
 // dA = [dA +] sum_p part[p] (p ascending; float or double partials).
 hipError_t launch_reduce_dA(const void* part, bool fp64, int npart, int64_t count, double* dA, int accumulate,

@@ -169,6 +169,7 @@ static qsl_status prepare(qsl_plan* p, hipStream_t st) {
             p->fjobs.push_back(f);
             if (p->has_bwd[i]) {
                 Job b = bwd_job(p->sys[i], &p->bwd[i], p->lay[i], ws + p->ws_off[i], s, p->gw[i], plan_by_e(p, i));
+                b.f32_tile = p->tune.contract_tile;
                 if (det && part_off[2 * i + s] && (b.dA64 || b.dA32)) b.dApart = ws + part_off[2 * i + s];
                 p->bjobs.push_back(b);
             }
@@ -497,7 +498,7 @@ static qsl_status enqueue(qsl_plan* p, hipStream_t st) {
         auto& DE = p->ph[PH_ADJ_DAE];
         if (DE.blocks()) {
             ProfScope ps("adjoint_dA", st);
-            if ((e = launch_adj_dae_batched(dev_jobs(p, PH_ADJ_DAE), dev_prefix(p, PH_ADJ_DAE), (int)DE.jobs.size(),
+            if ((e = launch_adj_dae_batched(p->tune.contract_tile, dev_jobs(p, PH_ADJ_DAE), dev_prefix(p, PH_ADJ_DAE), (int)DE.jobs.size(),
                                             DE.blocks(), st)) != hipSuccess)
                 return hip_fail(e, "adjoint dA kernel");
         }
