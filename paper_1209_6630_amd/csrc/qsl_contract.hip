@@ -209,14 +209,13 @@ __device__ __forceinline__ void contract_s3_products(const Job& j, const uint16_
     const char* __restrict__ a3b = (const char*)j.mo.A3;
     uint64_t cr[8];
     // uniform base + 32-bit byte offset: one address register per load;
-    // entries past the list point at row 0 (their B values are zero)
+    // entries past the list hold row 0 and no MO block (their B values are
+    // zero)
     auto load_c = [&](int q, int sb) __attribute__((always_inline)) {
         const int pos = head + 16 * q + 8 * h;  // a multiple of 8: the ring reads are aligned
         const int4 s0 = *(const int4*)&ringo[pos & (F32_RING - 1)];
         const int4 s1 = *(const int4*)&ringo[(pos + 4) & (F32_RING - 1)];
-        const int ov[8] = {pos + 0 < tail ? s0.x : 0, pos + 1 < tail ? s0.y : 0, pos + 2 < tail ? s0.z : 0,
-                           pos + 3 < tail ? s0.w : 0, pos + 4 < tail ? s1.x : 0, pos + 5 < tail ? s1.y : 0,
-                           pos + 6 < tail ? s1.z : 0, pos + 7 < tail ? s1.w : 0};
+        const int ov[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
         const int mcol = min(n0 + sb * NSB + wave * 32, ldn - 32) + (lane & 31);
 #pragma unroll
         for (int t = 0; t < 8; ++t) cr[t] = *gmem((const uint64_t*)(a3b + (size_t)(uint32_t)((ov[t] + mcol) * 8)));
@@ -228,7 +227,10 @@ __device__ __forceinline__ void contract_s3_products(const Job& j, const uint16_
         {
             const int pos = head + 16 * q + 8 * h;
 #pragma unroll
-            for (int t = 0; t < 8; ++t) gm |= pos + t < tail ? ringm[(pos + t) & (F32_RING - 1)] : 0ull;
+            for (int t = 0; t < 8; t += 2) {
+                const uint4 m2 = *(const uint4*)&ringm[(pos + t) & (F32_RING - 1)];
+                gm |= ((uint64_t)m2.y << 32 | m2.x) | ((uint64_t)m2.w << 32 | m2.z);
+            }
         }
 #pragma unroll
         for (int sb = 0; sb < MSUB; ++sb) {
@@ -397,6 +399,14 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
             const int kk = tid & (KC - 1), eg = tid >> 6;
             const bool live = kk < cnt;
             const int slot = live ? ring[(head + kk) & (F32_RING - 1)] : 0;
+            if constexpr (TILE == 2) {
+                // the last chunk: entries past the list become row 0 with no
+                // MO block (the filter is done, nothing is appended after)
+                if (!live && eg == 0) {
+                    ringo[(head + kk) & (F32_RING - 1)] = 0;
+                    ringm[(head + kk) & (F32_RING - 1)] = 0ull;
+                }
+            }
             SlotR r;
             r.load(srec + slot);
 #pragma unroll 1
@@ -410,13 +420,18 @@ __device__ __forceinline__ void contract_f32_body(const Job& j, int bx, int by, 
                 }
                 tiebits |= (tie ? 1u : 0u) << i;
                 if constexpr (TILE == 2) {
+                    // quantities two at a time (packed conversions), each
+                    // half written to its own plane row
+                    uint32_t hv[3], mv[3], lv[3];
+#pragma unroll
+                    for (int d2 = 0; d2 < 3; ++d2)
+                        bf16_split3_pair(v[2 * d2], 2 * d2 + 1 < 5 ? v[2 * d2 + 1] : 0.f, hv[d2], mv[d2], lv[d2]);
 #pragma unroll
                     for (int d = 0; d < 5; ++d) {
-                        uint16_t hv, mv, lv;
-                        bf16_split3(v[d], hv, mv, lv);
-                        B3[((0 * 5 + d) * TE + e) * F32_LD3 + kk] = hv;
-                        B3[((1 * 5 + d) * TE + e) * F32_LD3 + kk] = mv;
-                        B3[((2 * 5 + d) * TE + e) * F32_LD3 + kk] = lv;
+                        const int sh = 16 * (d & 1);
+                        B3[((0 * 5 + d) * TE + e) * F32_LD3 + kk] = (uint16_t)(hv[d >> 1] >> sh);
+                        B3[((1 * 5 + d) * TE + e) * F32_LD3 + kk] = (uint16_t)(mv[d >> 1] >> sh);
+                        B3[((2 * 5 + d) * TE + e) * F32_LD3 + kk] = (uint16_t)(lv[d >> 1] >> sh);
                     }
                 } else {
 #pragma unroll
