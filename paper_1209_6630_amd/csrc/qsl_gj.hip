@@ -630,6 +630,416 @@ __device__ __forceinline__ void gjh_body(const Job& j, int bx) {
     }
 }
 
+// ---------------------------------------------------------------- two
+// columns per round (128 < n <= 224)
+// As gjh_body, but the two halves of one wave own a pair of consecutive
+// columns (column e: wave (e / 2) % 8, half e % 2, register column e / 16
+// before rotations), and a round publishes two elimination steps at once:
+// the look-ahead wave applies the round's two steps to its register column
+// 0 (both halves, in place), finds the first column's pivot, publishes its
+// multipliers, reads them back in the second half, applies that step to the
+// second column and finds its pivot.  The other waves wait once per round
+// and apply the two rank-1 updates in order.  Steps a look-ahead applied in
+// place are skipped in the regular update: a zero pivot-row entry in the
+// second half's segment, and the look-ahead wave leaves out its register
+// column 0 for the round it looked ahead from.
+
+// v[r] for a wave-uniform r < RPL <= 8, by a three-level tree of selects
+// on scalar conditions, not a chain of RPL - 1
+template <int RPL>
+__device__ __forceinline__ double select_row(const double (&v)[RPL], int r) {
+    static_assert(RPL <= 8, "three levels");
+    double t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[q] = v[q < RPL ? q : RPL - 1];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int q = 0; q < (4 >> s); ++q) t[q] = ((r >> s) & 1) ? t[2 * q + 1] : t[2 * q];
+    return t[0];
+}
+
+// Pivot of the half `half` of a register column (keys as in gjh_search):
+// its row si (0x7fffffff if none), value pv and reciprocal inv, all
+// wave-uniform.
+template <int RPL>
+__device__ __forceinline__ void gjh2_pivot(const double (&col)[RPL], int li, int half, uint32_t used, int& si,
+                                           double& pv, double& inv) {
+    uint32_t best = 0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(col[r]) >> 32) & 0x7fffffffu;
+        const uint32_t keep = ((used >> r) & 1u) - 1u;  // all ones for a candidate row
+        const uint32_t kr = ((hi & ~0xFFu) | (uint32_t)(255 - i)) & keep;
+        best = max(best, col[r] == col[r] ? kr : 0u);
+    }
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0xB1, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x4E, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x141, 0xf, 0xf, false));
+    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x140, 0xf, 0xf, false));
+    const int l0 = 32 * half;
+    const uint32_t gk = max((uint32_t)__builtin_amdgcn_readlane((int)best, l0),
+                            (uint32_t)__builtin_amdgcn_readlane((int)best, l0 + 16));
+    const bool any = gk != 0;
+    si = any ? 255 - (int)(gk & 0xFF) : 0x7fffffff;
+    const int rs = any ? si >> 5 : 0, ls = any ? si & 31 : 0;
+    double cv = col[0];
+#pragma unroll
+    for (int r = 1; r < RPL; ++r) cv = rs == r ? col[r] : cv;
+    pv = any ? readlane_f64(cv, l0 + ls) : 0.0;
+    inv = __builtin_amdgcn_rcp(pv);
+    inv = fma(inv, fma(-pv, inv, 1.0), inv);
+    inv = fma(inv, fma(-pv, inv, 1.0), inv);
+}
+
+template <int RPL, int CPW, typename Tin>
+__device__ __forceinline__ void gjh2_body(const Job& j, int bx) {
+    const Tin* __restrict__ C = (const Tin*)j.C;
+    const int n = j.n, spin = j.spin;
+    double* __restrict__ Dinv = j.Dinv;
+    double* __restrict__ logdet = j.logdet;
+    int8_t* __restrict__ sign = j.sign;
+    uint32_t* __restrict__ status = j.status;
+    constexpr int NG = 16, NT = 512;
+    constexpr int NR = 32 * RPL;  // capacity in D rows (MO index i)
+    constexpr int NC = NG * CPW;  // capacity in D columns (electron index e)
+    constexpr int QC = 32;        // rows of D^-1 staged per output pass
+    constexpr int NB = 4;         // publication buffers, by round mod NB
+    __shared__ double colbuf[NB][2][NR];
+    __shared__ int piv_idx[NB][2];
+    __shared__ double piv_val[NB][2];
+    __shared__ __align__(16) double prow[NG][CPW];
+    __shared__ int perm[NC];
+    __shared__ int invp[NR];
+    __shared__ double rowpiv[NR];
+    __shared__ double stage[QC][NC > NR ? NC : NR];
+    __shared__ double red_ld[NT / 64];
+    __shared__ int red_neg[NT / 64];
+    __shared__ int s_flag;
+    __shared__ int pub;           // last round whose pivots and columns are published
+    __shared__ int prog[NT / 64]; // last round each wave has read its inputs of
+    __shared__ int s_abort;       // a wait ran over its bound
+
+    const int w = bx;
+    const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+    const int g = wave + 8 * h;                                  // pivot-row segment of this half
+    const size_t nn = (size_t)n * n;
+    const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
+    const int nr = (n + 1) / 2;              // rounds
+
+    double M[RPL][CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int e = 16 * c + 2 * wave + h, i = li + 32 * r;
+            const Tin v = gmem(C1)[min(e, n - 1) * n + min(i, n - 1)];
+            M[r][c] = (e < n && i < n) ? (double)v : 0.0;
+        }
+    for (int k = tid; k < NB * 2 * NR; k += NT) colbuf[k / (2 * NR)][(k / NR) & 1][k % NR] = 0.0;
+    if (tid == 0) { s_flag = 0; pub = -1; s_abort = 0; }
+    if (tid < NT / 64) prog[tid] = -1;
+    __syncthreads();
+    constexpr int SPIN_LIMIT = 1 << 22;
+    auto give_up = [&]() {
+        if (lane == 0) flag_store(&s_abort, 1);
+        return false;
+    };
+    auto stop = [&](int it) {  // the abort flag is polled every 64th time
+        return (it & 63) == 63 && (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort)));
+    };
+    auto wait_consumed = [&](int round) -> bool {  // every wave has read the inputs of round
+        for (int it = 0;; ++it) {
+            const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
+            if (__ballot(pg < round) == 0) return true;
+            if (stop(it)) return give_up();
+            if (it >= 4) __builtin_amdgcn_s_sleep(1);
+        }
+    };
+    auto row_bit = [&](int p) -> uint32_t { return li == (p & 31) ? 1u << (p >> 5) : 0u; };
+    uint32_t used = 0;  // bit r: row li + 32 r already a pivot row, or past n
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+        if (li + 32 * r >= n) used |= 1u << r;
+    int rot = 0;  // rotations of this wave's register columns (mod CPW)
+
+    // Look-ahead of round rr by its owner wave: register column 0 holds the
+    // columns 2 rr (half 0) and 2 rr + 1 (half 1) with every earlier step
+    // applied; `u` marks the earlier pivot rows.  Returns false if a wait ran
+    // over its bound.
+    auto look_ahead = [&](int rr, uint32_t u) -> bool {
+        const int b = rr % NB;
+        const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
+        double col[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) col[r] = M[r][0];
+        int sc;
+        double pc, ic;
+        gjh2_pivot<RPL>(col, li, 0, u, sc, pc, ic);
+        bool ok = true;
+        if (rr >= NB && __ballot(pg < rr - NB) != 0) ok = wait_consumed(rr - NB);
+        if (h == 0) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = li + 32 * r;
+                if (i < n) colbuf[b][0][i] = i == sc ? 0.0 : -col[r] * ic;
+            }
+        }
+        if (lane == 0) { piv_idx[b][0] = sc; piv_val[b][0] = pc; }
+        if (2 * rr + 1 < n) {
+            // the first step on the second column (half 1), in place: its
+            // multipliers back from the buffer, the pivot row's entry of
+            // the second column from lane 32 + sc % 32
+            double cv[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) cv[r] = colbuf[b][0][li + 32 * r];
+            const double xc = sc < n ? readlane_f64(select_row<RPL>(col, sc >> 5), 32 + (sc & 31)) : 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const double y = fma(cv[r], xc, M[r][0]);
+                M[r][0] = h ? y : M[r][0];
+                col[r] = M[r][0];
+            }
+            int sd;
+            double pd, id;
+            gjh2_pivot<RPL>(col, li, 1, u | (sc < n ? row_bit(sc) : 0u), sd, pd, id);
+            if (h == 1) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+                    const int i = li + 32 * r;
+                    if (i < n) colbuf[b][1][i] = i == sd ? 0.0 : -col[r] * id;
+                }
+            }
+            if (lane == 0) { piv_idx[b][1] = sd; piv_val[b][1] = pd; }
+        }
+        if (ok && lane == 0) flag_store(&pub, rr);
+        return ok;
+    };
+    if (wave == 0 && !look_ahead(0, used)) {
+        // a wait ran over its bound: reported below
+    }
+
+    bool singular = false;
+    auto bad_pivot = [&](int p, double pv) {
+        if (p >= n || !(pv != 0.0) || !isfinite(pv)) {
+            singular = true;
+            if (tid == 0) s_flag = isfinite(pv) || p >= n ? 1 : 2;
+            return true;
+        }
+        return false;
+    };
+    for (int rd = 0; rd < nr; ++rd) {
+        const int b = rd % NB;
+        const int ns = 2 * rd + 1 < n ? 2 : 1;  // steps in this round
+        bool live = true;
+        int seen = rd;
+        for (int it = 0;; ++it) {
+            seen = __builtin_amdgcn_readfirstlane(flag_load(&pub));
+            if (seen >= rd) break;
+            if (stop(it)) { live = give_up(); break; }
+            if (it >= 4) __builtin_amdgcn_s_sleep(1);
+        }
+        if (!live) break;
+        // a wave behind the published rounds takes issue priority over its
+        // SIMD mates until it has caught up
+        if (seen >= rd + 2) __builtin_amdgcn_s_setprio(2);
+        else if (seen == rd + 1) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+        const int pa = __builtin_amdgcn_readfirstlane(piv_idx[b][0]);
+        const double pva = readlane_f64(piv_val[b][0], 0);
+        const int pb = ns == 2 ? __builtin_amdgcn_readfirstlane(piv_idx[b][1]) : 0;
+        const double pvb = ns == 2 ? readlane_f64(piv_val[b][1], 0) : 1.0;
+        double colv[RPL];  // multipliers of the round's first step
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][0][li + 32 * r];
+        if (bad_pivot(pa, pva) || (ns == 2 && bad_pivot(pb, pvb))) break;
+        const int own = rd & 7;  // the wave owning this round's columns
+        const int r1 = rd + 1;
+        const bool la = r1 < nr && wave == (r1 & 7);  // this wave looks ahead
+        if (la) {
+            // the round's steps on register column 0 (both halves, in place;
+            // the regular update below leaves column 0 out), then round
+            // rd + 1's pivots.  It is the step's critical path: first thing
+            // after the inputs, at raised priority over the SIMD mate.
+            __builtin_amdgcn_s_setprio(3);
+            double m0[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) m0[r] = M[r][0];
+            {
+                const double xs = select_row<RPL>(m0, pa >> 5);
+                const double x0 = readlane_f64(xs, pa & 31), x1 = readlane_f64(xs, 32 + (pa & 31));
+                const double xm = h ? x1 : x0;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][0] = fma(colv[r], xm, M[r][0]);
+            }
+            if (ns == 2) {
+                double cb[RPL];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) { cb[r] = colbuf[b][1][li + 32 * r]; m0[r] = M[r][0]; }
+                const double xs = select_row<RPL>(m0, pb >> 5);
+                const double x0 = readlane_f64(xs, pb & 31), x1 = readlane_f64(xs, 32 + (pb & 31));
+                const double xm = h ? x1 : x0;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][0] = fma(cb[r], xm, M[r][0]);
+            }
+            const bool ok = look_ahead(r1, used | row_bit(pa) | (ns == 2 ? row_bit(pb) : 0u));
+            __builtin_amdgcn_s_setprio(0);
+            if (!ok) break;
+        }
+        // the round's steps in order; column 2 rd takes pv + 1 (its owner's
+        // half 0), which turns it into -D[i][k]/pv; its owner's half 1 holds
+        // column 2 rd + 1, which the look-ahead has already updated for the
+        // first step (entry 0)
+#pragma unroll 1
+        for (int sidx = 0; sidx < ns; ++sidx) {
+            const int p = sidx ? pb : pa;
+            const double pv = sidx ? pvb : pva;
+            if (sidx) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][1][li + 32 * r];
+            }
+            if (sidx + 1 == ns && lane == 0) flag_store(&prog[wave], rd);  // after the reads of the round's inputs
+            const int lp = p & 31, rp = p >> 5;
+            if (li == lp) {
+                static_for<0, RPL>([&](auto rr) __attribute__((always_inline)) {
+                    constexpr int r = decltype(rr)::value;
+                    if (rp == r) {
+#pragma unroll
+                        for (int c = 0; c < CPW; ++c) prow[g][c] = M[r][c];
+                        asm volatile("; pivot row %0" ::"n"(r));
+                    }
+                });
+            }
+            if (wave == own && lane == 0) {
+                if (sidx == 0) {
+                    prow[own][0] = pv + 1.0;
+                    prow[own + 8][0] = 0.0;
+                } else {
+                    prow[own + 8][0] = pv + 1.0;
+                }
+            }
+            double pr[CPW];
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) pr[c] = prow[g][c];
+            if (!la) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][0] = fma(colv[r], pr[0], M[r][0]);
+            }
+#pragma unroll
+            for (int c = 1; c < CPW; ++c)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][c] = fma(colv[r], pr[c], M[r][c]);
+            used |= row_bit(p);
+            if (tid == 0) {
+                perm[2 * rd + sidx] = p;
+                rowpiv[p] = pv;
+            }
+        }
+        if (wave == own) {  // both halves done with register column 0
+            double t0[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) t0[r] = M[r][0];
+#pragma unroll
+            for (int c = 0; c + 1 < CPW; ++c)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) M[r][c] = M[r][c + 1];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) M[r][CPW - 1] = t0[r];
+            rot = rot + 1 == CPW ? 0 : rot + 1;
+        }
+    }
+    __syncthreads();
+    if (s_abort) {  // reported as a non-finite result
+        singular = true;
+        if (tid == 0) s_flag = 2;
+    }
+    double* Dw = Dinv + (size_t)w * nn;
+    if (singular) {
+        // undefined inverse: NaN, log|det| = -inf, sign = 0
+        for (size_t q = tid; q < nn; q += NT) Dw[q] = __longlong_as_double(0x7ff8000000000000ll);
+        if (tid == 0) {
+            if (logdet) logdet[2 * w + spin] = s_flag == 1 ? -INFINITY : __longlong_as_double(0x7ff8000000000000ll);
+            if (sign) sign[2 * w + spin] = 0;
+            if (status) atomicOr(status + w, s_flag == 1 ? QSL_STATUS_SINGULAR : QSL_STATUS_NONFINITE);
+        }
+        return;
+    }
+    // log|det| = sum log|pivot|; sign = sign(permutation) prod sign(pivot),
+    // the permutation's sign from the parity of its inversions
+    {
+        double ld = 0.0;
+        int neg = 0;
+        if (tid < n) {
+            ld = log(fabs(rowpiv[tid]));
+            neg = rowpiv[tid] < 0.0;
+            const int pa = perm[tid];
+            for (int b2 = tid + 1; b2 < n; ++b2) neg += perm[b2] < pa;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) {
+            ld += __shfl_xor(ld, o);
+            neg += __shfl_xor(neg, o);
+        }
+        if (lane == 0) { red_ld[wave] = ld; red_neg[wave] = neg; }
+    }
+    for (int k = tid; k < n; k += NT) invp[perm[k]] = k;
+    __syncthreads();
+    if (tid == 0) {
+        double ld = 0.0;
+        int neg = 0;
+        for (int v = 0; v < NT / 64; ++v) { ld += red_ld[v]; neg += red_neg[v]; }
+        if (logdet) logdet[2 * w + spin] = ld;
+        if (sign) sign[2 * w + spin] = (neg & 1) ? -1 : 1;
+        if (status && !isfinite(ld)) atomicOr(status + w, QSL_STATUS_NONFINITE);
+    }
+    // the pivot entries were left at pv during the elimination (the pivot row
+    // is never scaled); their value in the scaled representation is 1, and
+    // later updates of them only added terms: M[p_k][k] += 1 - pv_k
+    int ec[CPW];  // D column of each register column
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) ec[c] = 16 * (c + rot < CPW ? c + rot : c + rot - CPW) + 2 * wave + h;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        if (i >= n) continue;
+        const int kp = invp[i];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            if (ec[c] == kp) M[r][c] += 1.0 - rowpiv[i];
+    }
+    // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
+    int rowi[RPL];
+    double rs[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+        const int i = li + 32 * r;
+        rowi[r] = i < n ? invp[i] : -1;
+        rs[r] = i < n ? 1.0 / rowpiv[i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) ec[c] = ec[c] < n ? perm[ec[c]] : -1;  // destination column
+    for (int q0 = 0; q0 < n; q0 += QC) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int rr = rowi[r] - q0;
+            if (rr >= 0 && rr < QC) {
+#pragma unroll
+                for (int c = 0; c < CPW; ++c)
+                    if (ec[c] >= 0) stage[rr][ec[c]] = M[r][c] * rs[r];
+            }
+        }
+        __syncthreads();
+        const int rows = min(QC, n - q0);
+        for (int q = tid; q < rows * n; q += NT) {
+            const int rr = q / n, cc = q % n;
+            gmem(Dw)[(size_t)(q0 + rr) * n + cc] = stage[rr][cc];
+        }
+        __syncthreads();
+    }
+}
+
 template <int RPL, int CPW, typename Tin>
 __global__ __launch_bounds__(512) void gjh_kernel(Job j) {
     gjh_body<RPL, CPW, Tin>(j, blockIdx.x);
@@ -640,6 +1050,14 @@ __global__ __launch_bounds__(512) void gjh_batched(const Job* jobs, const int* p
     batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gjh_body<RPL, CPW, Tin>(j, bx); });
 }
 
+template <int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(512) void gjh2_kernel(Job j) {
+    gjh2_body<RPL, CPW, Tin>(j, blockIdx.x);
+}
+template <int RPL, int CPW, typename Tin>
+__global__ __launch_bounds__(512) void gjh2_batched(const Job* jobs, const int* prefix, int njobs) {
+    batch_block(jobs, prefix, njobs, [&](const Job& jj, int bx, int, int) { gjh2_body<RPL, CPW, Tin>(jj, bx); });
+}
 template <int NWV, int RPL, int CPW, typename Tin>
 __global__ __launch_bounds__(NWV * 64) void gj_kernel(Job j) {
     gj_body<NWV, RPL, CPW, Tin>(j, blockIdx.x);
@@ -681,8 +1099,8 @@ static hipError_t gj_dispatch(const Job& j, int v, bool batched, const Job* jobs
         case 1: QSL_GJ(4, 1, 16); break;
         case 2: QSL_GJ(8, 2, 16); break;
         default:
-            if (batched) gjh_batched<7, 14, Tin><<<g, 512, 0, st>>>(jobs, prefix, njobs);
-            else gjh_kernel<7, 14, Tin><<<g, 512, 0, st>>>(j);
+            if (batched) gjh2_batched<7, 14, Tin><<<g, 512, 0, st>>>(jobs, prefix, njobs);
+            else gjh2_kernel<7, 14, Tin><<<g, 512, 0, st>>>(j);
             break;
     }
 #undef QSL_GJ
