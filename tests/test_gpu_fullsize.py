@@ -114,13 +114,16 @@ def _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W_plan, group_of=
 
 
 @pytest.mark.parametrize("mode,tuning", [("fp32", None), ("fp32", dict(adj_group=128)),
-                                         ("fp32", dict(det_dA=1)), ("bf16x3", None)])
+                                         ("fp32", dict(det_dA=1)), ("fp32", dict(contract_tile=0)),
+                                         ("bf16x3", None)])
 def test_adjoint_434e_plan_1024_walkers(mode, tuning):
     """dA over 1024 walkers and dR of every walker against the oracle,
     through the benchmark's plan: FP32 by electron (one group of 1024, or
     eight of 128), FP32 by 32-electron range with the deterministic
     reduction (eight groups of 128), split BF16 (eight groups of 128, seven
-    electron ranges per spin); FP32 atomics across groups and ranges."""
+    electron ranges per spin); FP32 atomics across groups and ranges. The
+    default FP32 tile takes split-bf16 products in the forward and the dA;
+    tile 0 takes the FP32 MFMA kernels of both."""
     W = 1024
     print(f"[case] adjoint 434e plan W={W} mode={mode} tuning={tuning}", flush=True)
     sysm, A_up, A_dn, R = q.make_config("434e", W=W)
@@ -129,7 +132,8 @@ def test_adjoint_434e_plan_1024_walkers(mode, tuning):
     sing = (res["status"] & 1) != 0
     assert not sing.any()
     gw = res["gw"]
-    assert math.ceil(W / gw) >= (1 if mode == "fp32" and not tuning else 8)
+    one_group = mode == "fp32" and not (tuning or {}).get("adj_group") and not (tuning or {}).get("det_dA")
+    assert math.ceil(W / gw) >= (1 if one_group else 8)
     nnz = max_survivors(sysm, R[:2])
     _check_adjoint(sysm, A_up, A_dn, R, mode, g, res, gw, nnz, W, group_of=np.arange(W) // gw)
 
