@@ -15,8 +15,11 @@
 //
 // Precision modes:
 //   FP64   AO eval FP64, v_mfma_f64_16x16x4f64, 64 MOs per workgroup.
-//   FP32   AO eval FP32, v_mfma_f32_32x32x2f32, 256 MOs per workgroup, over
-//          the tile's surviving slots rather than whole windows (below).
+//   FP32   AO eval FP32, over the tile's surviving slots rather than whole
+//          windows (below), 256 MOs per workgroup; the products by default
+//          as six v_mfma_f32_32x32x16_bf16 products of exact three-way bf16
+//          splits of the FP32 operands (tile 2), or on v_mfma_f32_32x32x2f32
+//          (tiles 0 and 1).
 //   BF16X3 AO eval FP32, each operand split x = hi + lo (bf16, round to
 //          nearest even), C += Bhi Ahi + Bhi Alo + Blo Ahi on
 //          v_mfma_f32_32x32x16_bf16 with FP32 accumulation.

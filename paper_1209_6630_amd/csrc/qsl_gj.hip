@@ -4,9 +4,10 @@
 // One workgroup inverts one n x n matrix held entirely in registers, by
 // Gauss-Jordan elimination with partial pivoting on the rows of D: at step k
 // the pivot is the largest |D[i][k]| over rows not yet used (smallest i on
-// exact ties; for 128 < n <= 224, among values within 2^-12 relative of the
-// largest, which leaves the elimination as stable).  Pivot rows are not moved; the pivot sequence p_k is recorded
-// and the result is un-permuted on the way out: D^-1[k][p_j] = M[p_k][j].
+// exact ties; for 128 < n <= 224, among values within 2^-12 relative of
+// the largest, which leaves the elimination as stable).  Pivot rows are not
+// moved; the pivot sequence p_k is recorded and the result is un-permuted on
+// the way out: D^-1[k][p_j] = M[p_k][j].
 // The pivots are the diagonal of U in P D = L U, so log|det| = sum log|pivot|
 // and sign = sign(permutation) prod sign(pivot).  2 n^3 flops per matrix.
 #include <algorithm>
@@ -268,77 +269,6 @@ __device__ __forceinline__ void gj_body(const Job& j, int bx) {
     }
 }
 
-// Half-wave layout for 128 < n <= 224 (eight waves).  Half h of wave v is
-// column group g = v + 8 h of 16, so that consecutive columns belong to
-// different waves; lane li (< 32) of the half owns the D rows
-// i = li + 32 r (r < RPL) and holds M[r][c] for the D columns e = g + 16 c
-// (c < CPW): 7 x 14 values per lane cover 224 x 224 with little padding.
-// Step k: every half writes its segment of the pivot row (lane p % 32,
-// register row p / 32) to LDS and reads it back broadcast, the owner of
-// column k substituting pv + 1 in its slot; the rank-1 update then takes
-// the published column k, already scaled by -1/pv.  Before that update the
-// owner of column k + 1 applies the step to that one column, searches its
-// pivot and publishes column and pivot for step k + 1, so the search
-// overlaps the other waves' updates.  No barrier per step: the publisher
-// raises a flag in LDS, each wave records the last step whose inputs it has
-// read, and a publisher overwrites a buffer (four, by step mod 4) only once
-// every wave has read it; the waves run a few steps apart, so one
-// wave's latencies hide behind another's FMAs.
-// A wave's register columns rotate by one after its second half's step
-// (k = 16 c + v + 8), so the column a half searches next is always its
-// register column 0; after R rotations register column c holds the D
-// column e = g + 16 ((c + R) mod CPW).
-template <int RPL, typename Before>
-__device__ __forceinline__ void gjh_search(const double (&col)[RPL], int n, int li, int half, uint32_t used,
-                                           double* colout, int* piv_idx, double* piv_val, Before&& before) {
-    // One 32-bit key per candidate row (unused, i < n, not NaN): the high
-    // word of |a| (sign 0, exponent, 20 significand bits) with its low 8 bits
-    // replaced by 255 - i; 0 elsewhere.  As unsigned integers the keys order
-    // like |a| to 2^-12 relative, and among values that close the smallest
-    // row wins; the row comes back from the key.
-    uint32_t best = 0;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = li + 32 * r;
-        const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(col[r]) >> 32) & 0x7fffffffu;
-        // rows past n are marked used from the start
-        const uint32_t keep = ((used >> r) & 1u) - 1u;  // all ones for a candidate row
-        const uint32_t kr = ((hi & ~0xFFu) | (uint32_t)(255 - i)) & keep;
-        best = max(best, col[r] == col[r] ? kr : 0u);
-    }
-    // inside rows of 16 lanes by DPP (quad swaps, half-row and row mirrors),
-    // then the owning half's two rows
-    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0xB1, 0xf, 0xf, false));
-    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x4E, 0xf, 0xf, false));
-    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x141, 0xf, 0xf, false));
-    best = max(best, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)best, 0x140, 0xf, 0xf, false));
-    const int l0 = 32 * half;
-    const uint32_t gk = max((uint32_t)__builtin_amdgcn_readlane((int)best, l0),
-                            (uint32_t)__builtin_amdgcn_readlane((int)best, l0 + 16));
-    const bool any = gk != 0;
-    const int si = any ? 255 - (int)(gk & 0xFF) : 0x7fffffff;  // wave-uniform
-    // the pivot value itself: register row si / 32 of lane si % 32 of the half
-    const int rs = any ? si >> 5 : 0, ls = any ? si & 31 : 0;
-    double cv = col[0];
-#pragma unroll
-    for (int r = 1; r < RPL; ++r) cv = rs == r ? col[r] : cv;
-    const double pv = any ? readlane_f64(cv, l0 + ls) : 0.0;
-    // 1/pv: hardware reciprocal and two Newton steps (the error squares each
-    // step), shorter than the general division on this step's critical path
-    double inv = __builtin_amdgcn_rcp(pv);
-    inv = fma(inv, fma(-pv, inv, 1.0), inv);
-    inv = fma(inv, fma(-pv, inv, 1.0), inv);
-    before();  // the buffers may be overwritten from here on
-    if ((threadIdx.x & 63) >> 5 == half) {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int i = li + 32 * r;  // < 32 RPL, the buffer's length
-            if (i < n) colout[i] = i == si ? 0.0 : -col[r] * inv;
-        }
-    }
-    if ((threadIdx.x & 63) == 0) { *piv_idx = si; *piv_val = pv; }
-}
-
 // Flag accesses in LDS.  The LDS executes the DS instructions of one wave in
 // program order, so a flag written after a wave's data writes is seen only
 // once they are done, and data read after a flag was seen is the data
@@ -354,295 +284,32 @@ __device__ __forceinline__ void flag_store(int* f, int v) {
     __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <int RPL, int CPW, typename Tin>
-__device__ __forceinline__ void gjh_body(const Job& j, int bx) {
-    const Tin* __restrict__ C = (const Tin*)j.C;
-    const int n = j.n, spin = j.spin;
-    double* __restrict__ Dinv = j.Dinv;
-    double* __restrict__ logdet = j.logdet;
-    int8_t* __restrict__ sign = j.sign;
-    uint32_t* __restrict__ status = j.status;
-    constexpr int NG = 16, NT = 512;
-    constexpr int NR = 32 * RPL;  // capacity in D rows (MO index i)
-    constexpr int NC = NG * CPW;  // capacity in D columns (electron index e)
-    constexpr int QC = 32;        // rows of D^-1 staged per output pass
-    constexpr int NB = 4;         // publication buffers, by step mod NB
-    __shared__ double colbuf[NB][NR];
-    __shared__ int piv_idx[NB];
-    __shared__ double piv_val[NB];
-    __shared__ __align__(16) double prow[NG][CPW];
-    __shared__ int perm[NC];
-    __shared__ int invp[NR];
-    __shared__ double rowpiv[NR];
-    __shared__ double stage[QC][NC > NR ? NC : NR];
-    __shared__ double red_ld[NT / 64];
-    __shared__ int red_neg[NT / 64];
-    __shared__ int s_flag;
-    __shared__ int pub;           // last step whose pivot and column are published
-    __shared__ int prog[NT / 64]; // last step each wave has read its inputs of
-    __shared__ int s_abort;       // a wait ran over its bound
-
-    const int w = bx;
-    const int tid = threadIdx.x, lane = tid & 63, li = lane & 31, h = lane >> 5;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-    const int g = wave + 8 * h;                                  // column group of this half
-    const size_t nn = (size_t)n * n;
-    const Tin* C1 = C + (size_t)w * 5 * nn;  // derivative 0 block
-
-    // every load unconditional (clamped address, padding zeroed after), so
-    // that all of them are in flight together
-    double M[RPL][CPW];
-#pragma unroll
-    for (int c = 0; c < CPW; ++c)
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int e = g + NG * c, i = li + 32 * r;
-            const Tin v = gmem(C1)[min(e, n - 1) * n + min(i, n - 1)];
-            M[r][c] = (e < n && i < n) ? (double)v : 0.0;
-        }
-    for (int k = tid; k < NB * NR; k += NT) colbuf[k / NR][k % NR] = 0.0;
-    if (tid == 0) { s_flag = 0; pub = -1; s_abort = 0; }
-    if (tid < NT / 64) prog[tid] = -1;
-    __syncthreads();
-    // Waits on the flags, bounded: past SPIN_LIMIT polls (or once another
-    // wave gave up) the wave sets s_abort and leaves the elimination, so
-    // every wave reaches the end of the kernel.
-    constexpr int SPIN_LIMIT = 1 << 22;
-    auto give_up = [&]() {
-        if (lane == 0) flag_store(&s_abort, 1);
-        return false;
-    };
-    auto stop = [&](int it) {  // the abort flag is polled every 64th time
-        return (it & 63) == 63 && (it >= SPIN_LIMIT || __builtin_amdgcn_readfirstlane(flag_load(&s_abort)));
-    };
-    auto wait_consumed = [&](int step) -> bool {  // every wave has read the inputs of step
-        for (int it = 0;; ++it) {
-            const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
-            if (__ballot(pg < step) == 0) return true;
-            if (stop(it)) return give_up();
-            if (it >= 4) __builtin_amdgcn_s_sleep(1);
-        }
-    };
-    uint32_t used = 0;  // bit r: row li + 32 r already a pivot row, or past n
-#pragma unroll
-    for (int r = 0; r < RPL; ++r)
-        if (li + 32 * r >= n) used |= 1u << r;
-    int rot = 0;        // rotations of this wave's register columns (mod CPW)
-    if (wave == 0) {
-        double col[RPL];
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) col[r] = M[r][0];
-        gjh_search<RPL>(col, n, li, 0, used, colbuf[0], &piv_idx[0], &piv_val[0], [] {});
-        if (lane == 0) flag_store(&pub, 0);
-    }
-
-    bool singular = false;
-    for (int k = 0; k < n; ++k) {
-        const int b = k % NB, b1 = (k + 1) % NB;
-        // pivot and column of step k, read in one batch with the
-        // publication flag: the LDS serves a wave's reads in order, so what
-        // is read after a flag value >= k is the published data
-        int p;
-        double pv;
-        double colv[RPL];  // -D[i][k] / pv, 0 in the pivot row
-        bool live = true;
-        int seen = k;
-        for (int it = 0;; ++it) {
-            const int fv = flag_load(&pub);
-            p = __builtin_amdgcn_readfirstlane(piv_idx[b]);
-            pv = readlane_f64(piv_val[b], 0);
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) colv[r] = colbuf[b][li + 32 * r];
-            seen = __builtin_amdgcn_readfirstlane(fv);
-            if (seen >= k) break;
-            if (stop(it)) { live = give_up(); break; }
-            if (it >= 4) __builtin_amdgcn_s_sleep(1);
-        }
-        if (!live) break;
-        // a wave behind the published steps takes issue priority over its
-        // SIMD mates until it has caught up
-        if (seen >= k + 2) __builtin_amdgcn_s_setprio(2);
-        else if (seen == k + 1) __builtin_amdgcn_s_setprio(1);
-        else __builtin_amdgcn_s_setprio(0);
-        if (lane == 0) flag_store(&prog[wave], k);  // after the reads above
-        if (p >= n || !(pv != 0.0) || !isfinite(pv)) {  // zero (or NaN) pivot
-            singular = true;
-            if (tid == 0) s_flag = isfinite(pv) || p >= n ? 1 : 2;
-            break;
-        }
-        const int lp = p & 31, rp = p >> 5;  // wave-uniform
-        const int gk = k % NG;
-        if (tid == 0) {
-            perm[k] = p;
-            rowpiv[p] = pv;
-        }
-        const int k1 = k + 1;
-        const uint32_t used1 = used | (li == lp ? 1u << rp : 0u);
-        if (k1 < n && wave == (k1 & 7)) {
-            // look-ahead: column k + 1 (register column 0 of its half) after
-            // this step, its pivot, published.  It is the step's critical
-            // path: first thing after the inputs, at raised priority over
-            // the SIMD mate.
-            __builtin_amdgcn_s_setprio(3);
-            double xr = M[0][0];
-#pragma unroll
-            for (int r = 1; r < RPL; ++r) xr = rp == r ? M[r][0] : xr;
-            const int h1 = (k1 % NG) >> 3;  // half owning column k + 1
-            const double x = readlane_f64(xr, 32 * h1 + lp);  // pivot row, column k + 1
-            // buffer b1 last held step k + 1 - NB: written once every wave
-            // read it (the counters are read now, checked after the search)
-            const int pg = lane < NT / 64 ? flag_load(&prog[lane]) : 0x7fffffff;
-            double col[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) col[r] = fma(colv[r], x, M[r][0]);
-            bool ok = true;
-            gjh_search<RPL>(col, n, li, h1, used1, colbuf[b1], &piv_idx[b1], &piv_val[b1], [&] {
-                if (__ballot(pg < k1 - NB) != 0) ok = wait_consumed(k1 - NB);
-            });
-            if (ok && lane == 0) flag_store(&pub, k1);
-            __builtin_amdgcn_s_setprio(0);
-            if (!ok) break;
-        }
-        // this half's segment of the pivot row; column k takes pv + 1, which
-        // turns it into -D[i][k]/pv (the pivot row itself is untouched)
-        if (li == lp) {
-            static_for<0, RPL>([&](auto rr) __attribute__((always_inline)) {
-                constexpr int r = decltype(rr)::value;
-                if (rp == r) {
-#pragma unroll
-                    for (int c = 0; c < CPW; ++c) prow[g][c] = M[r][c];
-                    // keeps the RPL branches apart: merged, they would index
-                    // M through a pointer and move it out of registers
-                    asm volatile("; pivot row %0" ::"n"(r));
-                }
-            });
-        }
-        if (wave == (gk & 7) && lane == 0) prow[gk][0] = pv + 1.0;
-        double pr[CPW];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) pr[c] = prow[g][c];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) M[r][c] = fma(colv[r], pr[c], M[r][c]);
-        used = used1;
-        if (gk >= 8 && wave == (gk & 7)) {  // both halves done with column 0
-            double t[RPL];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) t[r] = M[r][0];
-#pragma unroll
-            for (int c = 0; c + 1 < CPW; ++c)
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) M[r][c] = M[r][c + 1];
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) M[r][CPW - 1] = t[r];
-            rot = rot + 1 == CPW ? 0 : rot + 1;
-        }
-    }
-    __syncthreads();
-    if (s_abort) {  // reported as a non-finite result
-        singular = true;
-        if (tid == 0) s_flag = 2;
-    }
-
-    double* Dw = Dinv + (size_t)w * nn;
-    if (singular) {
-        // undefined inverse: NaN, log|det| = -inf, sign = 0
-        for (size_t q = tid; q < nn; q += NT) Dw[q] = __longlong_as_double(0x7ff8000000000000ll);
-        if (tid == 0) {
-            if (logdet) logdet[2 * w + spin] = s_flag == 1 ? -INFINITY : __longlong_as_double(0x7ff8000000000000ll);
-            if (sign) sign[2 * w + spin] = 0;
-            if (status) atomicOr(status + w, s_flag == 1 ? QSL_STATUS_SINGULAR : QSL_STATUS_NONFINITE);
-        }
-        return;
-    }
-    // log|det| = sum log|pivot|; sign = sign(permutation) prod sign(pivot),
-    // the permutation's sign from the parity of its inversions
-    {
-        double ld = 0.0;
-        int neg = 0;
-        if (tid < n) {
-            ld = log(fabs(rowpiv[tid]));
-            neg = rowpiv[tid] < 0.0;
-            const int pa = perm[tid];
-            for (int b2 = tid + 1; b2 < n; ++b2) neg += perm[b2] < pa;
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) {
-            ld += __shfl_xor(ld, o);
-            neg += __shfl_xor(neg, o);
-        }
-        if (lane == 0) { red_ld[wave] = ld; red_neg[wave] = neg; }
-    }
-    for (int k = tid; k < n; k += NT) invp[perm[k]] = k;
-    __syncthreads();
-    if (tid == 0) {
-        double ld = 0.0;
-        int neg = 0;
-        for (int v = 0; v < NT / 64; ++v) { ld += red_ld[v]; neg += red_neg[v]; }
-        if (logdet) logdet[2 * w + spin] = ld;
-        if (sign) sign[2 * w + spin] = (neg & 1) ? -1 : 1;
-        if (status && !isfinite(ld)) atomicOr(status + w, QSL_STATUS_NONFINITE);
-    }
-    // the pivot entries were left at pv during the elimination (the pivot row
-    // is never scaled); their value in the scaled representation is 1, and
-    // later updates of them only added terms: M[p_k][k] += 1 - pv_k
-    int ec[CPW];  // D column of each register column
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) ec[c] = g + NG * (c + rot < CPW ? c + rot : c + rot - CPW);
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = li + 32 * r;
-        if (i >= n) continue;
-        const int kp = invp[i];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            if (ec[c] == kp) M[r][c] += 1.0 - rowpiv[i];
-    }
-    // D^-1[invp[i]][perm[e]] = M[i][e] / pivot(i), staged QC rows at a time
-    int rowi[RPL];
-    double rs[RPL];
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = li + 32 * r;
-        rowi[r] = i < n ? invp[i] : -1;
-        rs[r] = i < n ? 1.0 / rowpiv[i] : 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < CPW; ++c) ec[c] = ec[c] < n ? perm[ec[c]] : -1;  // destination column
-    for (int q0 = 0; q0 < n; q0 += QC) {
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) {
-            const int rr = rowi[r] - q0;
-            if (rr >= 0 && rr < QC) {
-#pragma unroll
-                for (int c = 0; c < CPW; ++c)
-                    if (ec[c] >= 0) stage[rr][ec[c]] = M[r][c] * rs[r];
-            }
-        }
-        __syncthreads();
-        const int rows = min(QC, n - q0);
-        for (int q = tid; q < rows * n; q += NT) {
-            const int rr = q / n, cc = q % n;
-            gmem(Dw)[(size_t)(q0 + rr) * n + cc] = stage[rr][cc];
-        }
-        __syncthreads();
-    }
-}
-
-// ---------------------------------------------------------------- two
-// columns per round (128 < n <= 224)
-// As gjh_body, but the two halves of one wave own a pair of consecutive
-// columns (column e: wave (e / 2) % 8, half e % 2, register column e / 16
-// before rotations), and a round publishes two elimination steps at once:
-// the look-ahead wave applies the round's two steps to its register column
-// 0 (both halves, in place), finds the first column's pivot, publishes its
-// multipliers, reads them back in the second half, applies that step to the
+// ------------------------------------------------------- 128 < n <= 224
+// Half-wave layout (eight waves): lane li (< 32) of either half of a wave
+// owns the D rows i = li + 32 r (r < RPL) and holds M[r][c] for CPW columns;
+// 7 x 14 values per lane cover 224 x 224 with little padding.  The two
+// halves of a wave own a pair of consecutive columns (column e: wave
+// (e / 2) % 8, half e % 2, register column e / 16 before rotations), and a
+// round publishes two elimination steps through LDS.  The wave owning the
+// next round's columns looks ahead: it applies the current round's two
+// steps to its register column 0 (both halves, in place), finds the first
+// column's pivot, publishes its multipliers -D[i][k]/pv (0 in the pivot
+// row), reads them back in the second half, applies that step to the
 // second column and finds its pivot.  The other waves wait once per round
-// and apply the two rank-1 updates in order.  Steps a look-ahead applied in
-// place are skipped in the regular update: a zero pivot-row entry in the
-// second half's segment, and the look-ahead wave leaves out its register
-// column 0 for the round it looked ahead from.
+// and apply the two rank-1 updates in order: every half writes its segment
+// of the pivot row (lane p % 32, register row p / 32) to LDS and reads it
+// back broadcast; the owner of column k substitutes pv + 1 in its slot,
+// which turns the column into -D[i][k]/pv (the pivot row itself is left
+// unscaled).  Steps a look-ahead applied in place are skipped: a zero
+// pivot-row entry in the owner's second half, and the look-ahead wave
+// leaves out its register column 0 for the round it looked ahead from.
+// No barrier per round: the publisher raises a flag in LDS, each wave
+// records the last round whose inputs it has read, and a publisher
+// overwrites a buffer (four, by round mod 4) only once every wave has read
+// it.  A wave's register columns rotate by one after the round of its own
+// columns, so the pair a wave handles next is always its register column
+// 0; after R rotations register column c holds the D columns
+// e = 16 ((c + R) mod CPW) + 2 v + h.
 
 // v[r] for a wave-uniform r < RPL <= 8, by a three-level tree of selects
 // on scalar conditions, not a chain of RPL - 1
@@ -659,9 +326,16 @@ __device__ __forceinline__ double select_row(const double (&v)[RPL], int r) {
     return t[0];
 }
 
-// Pivot of the half `half` of a register column (keys as in gjh_search):
-// its row si (0x7fffffff if none), value pv and reciprocal inv, all
-// wave-uniform.
+// Pivot of the half `half` of a register column: its row si (0x7fffffff if
+// none), value pv and reciprocal inv, all wave-uniform.  One 32-bit key per
+// candidate row (unused, not past n, not NaN): the high word of |a| (sign
+// 0, exponent, 20 significand bits) with its low 8 bits replaced by
+// 255 - i; 0 elsewhere.  As unsigned integers the keys order like |a| to
+// 2^-12 relative, and among values that close the smallest row wins; the
+// row comes back from the key.  The maximum runs inside rows of 16 lanes by
+// DPP (quad swaps, half-row and row mirrors), then over the half's two
+// rows.  1/pv: hardware reciprocal and two Newton steps (the error squares
+// each step).
 template <int RPL>
 __device__ __forceinline__ void gjh2_pivot(const double (&col)[RPL], int li, int half, uint32_t used, int& si,
                                            double& pv, double& inv) {
@@ -1038,16 +712,6 @@ __device__ __forceinline__ void gjh2_body(const Job& j, int bx) {
         }
         __syncthreads();
     }
-}
-
-template <int RPL, int CPW, typename Tin>
-__global__ __launch_bounds__(512) void gjh_kernel(Job j) {
-    gjh_body<RPL, CPW, Tin>(j, blockIdx.x);
-}
-
-template <int RPL, int CPW, typename Tin>
-__global__ __launch_bounds__(512) void gjh_batched(const Job* jobs, const int* prefix, int njobs) {
-    batch_block(jobs, prefix, njobs, [&](const Job& j, int bx, int, int) { gjh_body<RPL, CPW, Tin>(j, bx); });
 }
 
 template <int RPL, int CPW, typename Tin>
