@@ -324,7 +324,10 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
     const int ns = (n + 15) >> 4;
     // element q of M: uniform base + 32-bit byte offset (n^2 * 8 < 2^32)
     char* const Mb = (char*)v.M;
-    auto Mq = [&](uint32_t q) -> double& { return *(double*)(Mb + q * 8u); };
+    // global (not generic) accesses: a generic load also counts on the LDS
+    // counter, and the wait before a tile's products would then take the
+    // next tile's loads with it
+    auto Mq = [&](uint32_t q) { return gmem((double*)(Mb + q * 8u)); };
     for (int b = tid; b < GJ_NMAX; b += GJB_UT) curpiv[b] = 0;
     __syncthreads();
     if (tid < kn) curpiv[v.perm[k0 + tid]] = 1;
@@ -344,7 +347,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
 #pragma unroll
         for (int ks = 0; ks < NB / 4; ++ks) {
             const int k = 4 * ks + (lane >> 4);
-            const double x = Mq((uint32_t)(bl * v.ld + k0 + min(k, kn - 1)));
+            const double x = *Mq((uint32_t)(bl * v.ld + k0 + min(k, kn - 1)));
             Lr[u][ks] = (ba < n && k < kn) ? x : 0.0;
         }
         uint32_t kb = 0;
@@ -365,36 +368,35 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
         while (jt < t1 && 16 * jt >= k0 && 16 * jt < k0 + NB) ++jt;
         return jt < t1 ? jt : ns;
     };
+    // loads at clamped (valid) addresses and no select on the loaded values,
+    // so the next tile's loads stay in flight during this tile's products:
+    // an output element depends only on its own column of the T block and
+    // its own M element, and columns or rows past n are never stored; the
+    // panel's pivot rows are zeroed just before the products
     auto load = [&](int jt, int ntv, int ldv, double (&bop)[NB / 4], f64x4 (&acc)[HS]) {
-        const int ac = 16 * jt + (lane & 15);
-        const bool aok = ac < ntv;
-        const int al = min(ac, ntv - 1);
+        const int al = min(16 * jt + (lane & 15), ntv - 1);
 #pragma unroll
-        for (int ks = 0; ks < NB / 4; ++ks) {
-            const double x = v.Tg[(size_t)(4 * ks + (lane >> 4)) * ldv + al];
-            bop[ks] = aok ? x : 0.0;
-        }
+        for (int ks = 0; ks < NB / 4; ++ks) bop[ks] = *gmem(v.Tg + (size_t)(4 * ks + (lane >> 4)) * ldv + al);
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int b = b0s[u] + (lane >> 4) + 4 * r;
-                const double x = Mq((uint32_t)(min(b, ntv - 1) * ldv + al));
-                acc[u][r] = (aok & ((keep[u] >> r) & 1u)) ? x : 0.0;
+                acc[u][r] = *Mq((uint32_t)(min(b, ntv - 1) * ldv + al));
             }
     };
-    int jt = skip_panel(t0);
-    double bop[NB / 4];
-    f64x4 acc[HS];
-    if (jt < ns) load(jt, n, v.ld, bop, acc);
-#pragma unroll 1
-    while (jt < ns) {
+    // one tile: issue the loads of the tile after it into the other register
+    // set (on every pass: the last one reloads this tile, unused, so the
+    // queue has the same depth on all paths), then its products and stores
+    auto step = [&](int& jt, double (&bop)[NB / 4], f64x4 (&acc)[HS], double (&bopn)[NB / 4], f64x4 (&accn)[HS]) {
         int nt = n, ldt = v.ld;
         asm volatile("" : "+s"(nt), "+s"(ldt));  // keep the row offsets below out of registers across tiles
         const int jn = skip_panel(jt + 1);
-        double bopn[NB / 4];
-        f64x4 accn[HS];
-        if (jn < ns) load(jn, nt, ldt, bopn, accn);
+        load(jn < ns ? jn : jt, nt, ldt, bopn, accn);
+#pragma unroll
+        for (int u = 0; u < HS; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[u][r] = ((keep[u] >> r) & 1u) ? acc[u][r] : 0.0;
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
@@ -406,14 +408,33 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int b = b0s[u] + (lane >> 4) + 4 * r;
-                if ((ac < nt) & (b < nt)) Mq((uint32_t)(b * ldt + ac)) = acc[u][r];
+                if ((ac < nt) & (b < nt)) *Mq((uint32_t)(b * ldt + ac)) = acc[u][r];
             }
         }
-#pragma unroll
-        for (int ks = 0; ks < NB / 4; ++ks) bop[ks] = bopn[ks];
-#pragma unroll
-        for (int u = 0; u < HS; ++u) acc[u] = accn[u];
         jt = jn;
+    };
+    int jt = skip_panel(t0);
+    if (jt >= ns) return;
+    // two register sets used in turn, so no copy between tiles (a copy of a
+    // loaded value waits for its load)
+    double bopA[NB / 4], bopB[NB / 4];
+    f64x4 accA[HS], accB[HS];
+    load(jt, n, v.ld, bopA, accA);
+    // wait for the first tile here: the waits at the loop head are merged
+    // over both ways in, and a queue holding only these loads would make
+    // every pass wait for the whole queue, the next tile's loads included
+#pragma unroll
+    for (int ks = 0; ks < NB / 4; ++ks) asm volatile("" ::"v"(bopA[ks]));
+#pragma unroll
+    for (int u = 0; u < HS; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(accA[u][r]));
+#pragma unroll 1
+    while (true) {
+        step(jt, bopA, accA, bopB, accB);
+        if (jt >= ns) break;
+        step(jt, bopB, accB, bopA, accA);
+        if (jt >= ns) break;
     }
 }
 
