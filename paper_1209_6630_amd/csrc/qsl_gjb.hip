@@ -40,21 +40,21 @@ constexpr int GJB_NB = GJ_PANEL;
 constexpr int GJB_COPY_BLOCKS = 8;  // init / finish blocks per matrix
 
 // Launch shapes by the largest n served (NMX = 256 or GJ_NMAX): threads of
-// the panel / init / finish workgroups and of the update workgroups, rows
-// per panel thread, 16-row strips per update wave, row halves and column
-// ranges per matrix in the update.
+// the init / finish workgroups, of the panel workgroup (one row each) and of
+// the update workgroups, 16-row strips per update wave, row halves and
+// column ranges per matrix in the update.
 template <int NMX>
 struct GjbCfg {
     static constexpr int PT = NMX >= 512 ? 512 : 256;
-    static constexpr int PWAVES = PT / 64;
-    static constexpr int RPT = NMX / PT;
+    static constexpr int PNT = NMX;  // panel: one row per thread
+    static constexpr int PWAVES = PNT / 64;
     static constexpr int UT = PT;
     static constexpr int UWAVES = UT / 64;
     static constexpr int SPW = 4;
     static constexpr int HALVES = NMX / 16 / UWAVES / SPW;
     static constexpr int CHUNKS = 4;
     static constexpr int UPD_BLOCKS = HALVES * CHUNKS;
-    static_assert(HALVES >= 1 && RPT >= 1, "launch shape");
+    static_assert(HALVES >= 1 && PNT <= 1024, "launch shape");
 };
 
 struct GjbState {
@@ -169,121 +169,146 @@ __global__ __launch_bounds__(GjbCfg<NMX>::PT) void gjb_init_kernel(Job single, c
 }
 
 // ----------------------------------------------------------------- panel
+// Pivot keys: |value| as its IEEE bits (monotone for |value| >= 0) with the
+// low 10 mantissa bits replaced by 1023 - row, so the largest key is the
+// largest |value|, and the smallest row among values equal to 2^-42
+// relative; 0 for rows not eligible (used, past n, NaN).
+__device__ __forceinline__ uint64_t pivot_key(double x, int b, bool eligible) {
+    const uint64_t m = (uint64_t)__double_as_longlong(fabs(x));
+    return (eligible && !isnan(x)) ? ((m & ~0x3FFull) | (uint64_t)(0x3FF - b)) : 0ull;
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t key_max_step(uint64_t k) {
+    // every lane reads a lane of its own row: no bound control needed
+    const uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)k, CTRL, 0xf, 0xf, true);
+    const uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), CTRL, 0xf, 0xf, true);
+    const uint64_t o = ((uint64_t)hi << 32) | lo;
+    return o > k ? o : k;
+}
+// largest key over each 16-lane row (every lane of the row holds it)
+__device__ __forceinline__ uint64_t key_max_row(uint64_t k) {
+    k = key_max_step<0xB1>(k);   // quad_perm [1,0,3,2]
+    k = key_max_step<0x4E>(k);   // quad_perm [2,3,0,1]
+    k = key_max_step<0x141>(k);  // row_half_mirror
+    return key_max_step<0x140>(k);  // row_mirror
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t k, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)k, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(k >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+// largest key over the wavefront (uniform)
+__device__ __forceinline__ uint64_t key_max_wave(uint64_t k) {
+    k = key_max_row(k);
+    uint64_t m = readlane_u64(k, 0);
+#pragma unroll
+    for (int rw = 1; rw < 4; ++rw) {
+        const uint64_t o = readlane_u64(k, 16 * rw);
+        m = o > m ? o : m;
+    }
+    return m;
+}
+
+// One thread per row b holds M[b][k0 .. k0 + NB) in registers.  The panel's
+// columns are unrolled at compile time, so the column being reduced and the
+// pivot entry are plain registers (no select over the row), and no column
+// leaves the sequence early (a column past the panel or after a failed
+// pivot changes nothing that is kept).  Per column: the wave's largest
+// pivot key, one barrier, the largest of the waves' keys (16-lane DPP),
+// then one FMA per entry, P -= f (pivot row), on every row; the pivot row's
+// own scaling by 1/pv is deferred to the store.
 template <int NMX>
 __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
     using C = GjbCfg<NMX>;
-    constexpr int NB = GJB_NB, RPT = C::RPT, GJB_PT = C::PT, GJB_PWAVES = C::PWAVES;
+    constexpr int NB = GJB_NB, PNT = C::PNT, PW = C::PWAVES;
+    static_assert(PW <= 16 && NMX <= 1024, "keys hold 10-bit rows; waves compared within one 16-lane row");
     const int n = j.n;
     if (k0 >= n) return;
     const GjbView v = gjb_view(j, w);
     if (v.st->flag) return;  // singular earlier: nothing left to do
-    __shared__ double cand_a[2][GJB_PWAVES];
-    __shared__ int cand_i[2][GJB_PWAVES];
-    __shared__ double cand_row[2][GJB_PWAVES][NB];
+    __shared__ uint64_t cand_k[2][PW];
+    __shared__ double cand_row[2][PW][NB];
     __shared__ int perm_l[NB];
+    __shared__ double piv_l[NB];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kn = min(NB, n - k0);
-
-    double P[RPT][NB];  // P[r][k] = M[b][k0 + k], b = tid + 512 r
-    bool used[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int b = tid + GJB_PT * r;
-        const int bl = min(b, n - 1);  // loads at clamped (valid) addresses, then select
-        used[r] = b >= n || v.used[bl];
+    const int b = tid;  // this thread's row
+    const int bl = min(b, n - 1);  // loads at clamped (valid) addresses, then select
+    bool used = b >= n || v.used[bl];
+    double P[NB];  // P[k] = M[b][k0 + k]
+    {
         const double* row = v.M + (size_t)bl * v.ld + k0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             const double x = row[min(k, kn - 1)];
-            P[r][k] = (b < n && k < kn) ? x : 0.0;
+            P[k] = (b < n && k < kn) ? x : 0.0;
         }
     }
-    double ld = 0.0;
-    int neg = 0;
-#pragma unroll 1
-    for (int k = 0; k < kn; ++k) {
-        const int buf = k & 1;
-        double x[RPT];  // P[r][k] (k is not a compile-time index: select)
-        double best = -1.0;
-        int bi = 0x7fffffff;
+    double sc = 1.0;   // the row's pending scale (1/pv once it is a pivot row)
+    int fail = 0;      // uniform: 1 no pivot (zero column), 2 non-finite pivot
+    static_for<0, NB>([&](auto kc) __attribute__((always_inline)) {
+        constexpr int k = decltype(kc)::value, buf = k & 1;
+        const bool live = k < kn && !fail;  // uniform
+        const uint64_t wk = key_max_wave(pivot_key(P[k], b, !used));
+        if (b == 0x3FF - (int)(wk & 0x3FF) && wk != 0) {
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            x[r] = 0.0;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) x[r] = q == k ? P[r][q] : x[r];
-            const double a = fabs(x[r]);
-            if (!used[r] && a > best) { best = a; bi = tid + GJB_PT * r; }  // NaN never wins
+            for (int q = 0; q < NB; ++q) cand_row[buf][wave][q] = P[q];
         }
-        wave_argmax(best, bi);
-#pragma unroll
-        for (int r = 0; r < RPT; ++r)
-            if (tid + GJB_PT * r == bi) {
-#pragma unroll
-                for (int q = 0; q < NB; ++q) cand_row[buf][wave][q] = P[r][q];
-            }
-        if (lane == 0) {
-            cand_a[buf][wave] = best;
-            cand_i[buf][wave] = bi;
-        }
+        if (lane == 0) cand_k[buf][wave] = wk;
         __syncthreads();
-        double top = -1.0;
-        int p = 0x7fffffff, pw = 0;
-#pragma unroll
-        for (int q = 0; q < GJB_PWAVES; ++q) {
-            const double a = cand_a[buf][q];
-            const int i = cand_i[buf][q];
-            if (a > top || (a == top && i < p)) { top = a; p = i; pw = q; }
+        uint64_t top = key_max_row(lane < PW ? cand_k[buf][lane] : 0ull);
+        top = readlane_u64(top, 0);
+        const double topv = __longlong_as_double((long long)(top & ~0x3FFull));
+        const int bad = !(topv > 0.0) ? 1 : (!isfinite(topv) ? 2 : 0);
+        if (live && bad) {
+            if (tid == 0) v.st->flag = bad;
+            fail = bad;
         }
-        if (!(top > 0.0) || !isfinite(top)) {  // uniform
-            if (tid == 0) v.st->flag = (top > 0.0) ? 2 : 1;  // infinite, or zero / no pivot
-            return;
-        }
+        const int p = 0x3FF - (int)(top & 0x3FF);  // the pivot row (any row when bad)
+        const int pw = min(p >> 6, PW - 1);         // its wave
         const double pv = cand_row[buf][pw][k];
         const double inv = 1.0 / pv;
-        ld += log(fabs(pv));
-        neg += pv < 0.0;
-        if (tid == 0) {
+        const bool go = live && !bad;  // uniform
+        if (tid == 0 && go) {
             perm_l[k] = p;
+            piv_l[k] = pv;
             v.perm[k0 + k] = p;
         }
-        // pivot row: P *= 1/pv, P[k] = 1/pv; other rows: P -= f * (pivot
-        // row), P[k] = -f with f = P[k]/pv (branch-free)
-        double f[RPT], m[RPT], pk[RPT];
+        const bool piv = go && b == p;
+        // other rows: P -= f (pivot row), P[k] = -f with f = P[k] / pv.  The
+        // pivot row's scaling by 1/pv is kept aside in sc and applied when
+        // the panel is stored: its later updates are the same in the scaled
+        // and the unscaled form (f is a ratio of its own entries), and rows
+        // not yet used, which decide the pivots, never see it.  Nothing
+        // changes unless go.
+        const double f = (go && !piv) ? P[k] * inv : 0.0;
+        if (go) {
+            // the pivot row in chunks of 8 (bounded live registers)
+            static_for<0, NB / 8>([&](auto cc) __attribute__((always_inline)) {
+                constexpr int c0 = decltype(cc)::value * 8;
+                double pr[8];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const bool piv = tid + GJB_PT * r == p;
-            f[r] = piv ? 0.0 : x[r] * inv;
-            m[r] = piv ? inv : 1.0;
-            pk[r] = piv ? inv : -f[r];
-            if (piv) {
-                used[r] = true;
-                v.used[p] = 1;
-            }
+                for (int q = 0; q < 8; ++q) pr[q] = cand_row[buf][pw][c0 + q];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) P[c0 + q] = fma(-f, pr[q], P[c0 + q]);
+                __builtin_amdgcn_sched_barrier(0);
+            });
+            // the pivot row: 1/pv in column k, i.e. 1 before its scaling
+            P[k] = piv ? 1.0 : -f;
         }
-        // the pivot row in chunks of 8 (bounded live registers)
-        static_for<0, NB / 8>([&](auto cc) __attribute__((always_inline)) {
-            constexpr int c0 = decltype(cc)::value * 8;
-            double pr[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) pr[q] = cand_row[buf][pw][c0 + q];
-#pragma unroll
-            for (int r = 0; r < RPT; ++r)
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    P[r][c0 + q] = c0 + q == k ? pk[r] : fma(-f[r], pr[q], P[r][c0 + q] * m[r]);
-            __builtin_amdgcn_sched_barrier(0);
-        });
-    }
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-        const int b = tid + GJB_PT * r;
-        if (b < n) {
-            double* row = v.M + (size_t)b * v.ld + k0;
-#pragma unroll
-            for (int k = 0; k < NB; ++k)
-                if (k < kn) row[k] = P[r][k];
+        if (piv) {
+            used = true;
+            sc = inv;
+            v.used[p] = 1;
         }
+    });
+    if (fail) return;
+    if (b < n) {
+        double* row = v.M + (size_t)b * v.ld + k0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (k < kn) row[k] = P[k] * sc;
     }
     __syncthreads();
     // T[k][a] = M[p_k][a]: the pivot rows, copied before the update
@@ -291,17 +316,25 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
     for (int k = 0; k < NB; ++k) {
         const double* src = v.M + (size_t)perm_l[min(k, kn - 1)] * v.ld;
         double* dst = v.Tg + (size_t)k * v.ld;
-        for (int a = tid; a < n; a += GJB_PT) dst[a] = k < kn ? src[a] : 0.0;
+        for (int a = tid; a < n; a += PNT) dst[a] = k < kn ? src[a] : 0.0;
     }
-    if (tid == 0) {
-        v.st->ld += ld;
-        v.st->neg += neg;
+    // log|pivot| of the panel's columns (one lane each), summed in column order
+    if (wave == 0) {
+        const double pv = lane < kn ? piv_l[lane] : 1.0;
+        const double lg = log(fabs(pv));
+        const int neg = __popcll(__ballot(pv < 0.0));
+        double ld = 0.0;
+        for (int k = 0; k < kn; ++k) ld += readlane_f64(lg, k);
+        if (lane == 0) {
+            v.st->ld += ld;
+            v.st->neg += neg;
+        }
     }
 }
 
 template <int NMX, bool BATCHED>
-__global__ __launch_bounds__(GjbCfg<NMX>::PT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
-                                                                     int njobs, int k0) {
+__global__ __launch_bounds__(GjbCfg<NMX>::PNT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
+                                                                      int njobs, int k0) {
     gjb_block<BATCHED>(single, jobs, prefix, njobs, 1,
                        [&](const Job& j, int w, int) __attribute__((always_inline)) { gjb_panel_body<NMX>(j, w, k0); });
 }
@@ -524,7 +557,7 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
         gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
     hipError_t e = hipGetLastError();
     for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += GJB_NB) {
-        gjb_panel_kernel<NMX, BATCHED><<<m, C::PT, 0, st>>>(single, jobs, prefix, njobs, k0);
+        gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0);
         gjb_update_kernel<NMX, BATCHED><<<m * C::UPD_BLOCKS, C::UT, 0, st>>>(single, jobs, prefix, njobs, k0);
         e = hipGetLastError();
     }
