@@ -8,26 +8,32 @@
 // It runs on a row-major FP64 copy M[b][a] = D[b][a] in the workspace
 // (row b = MO, column a = electron), made by an LDS-tiled transpose of C_1.
 //
-// Per panel of NB = 32 columns, two kernels:
-//  panel   one 512-thread workgroup per matrix reduces the panel columns
-//          (each thread holds the panel part of two rows in registers; one
-//          barrier per column: every wave publishes its best row, all
-//          threads pick the winner from LDS), stores the reduced panel L and
-//          copies the panel's pivot rows T[k][a] = M[p_k][a].
-//  update  the composite of the panel's NB elementary steps acts on any
-//          other column v through its pivot rows only:
-//              v <- (v with the panel's pivot rows set to 0) + L v_P.
-//          That rank-NB update of the whole matrix runs on
-//          v_mfma_f64_16x16x4f64 in output tiles of 16 rows b x 16 columns
-//          a.  Eight workgroups per matrix (two halves of the rows b x four
-//          contiguous ranges of column tiles); each wave keeps its four
-//          16-row strips of L in registers and streams the tiles.
+// Panels of NB = 32 columns, two per pass:
+//  panel   one workgroup per matrix, one thread per row, reduces the panel
+//          columns in registers (one barrier per column), stores the
+//          reduced panel L and copies the panel's pivot rows
+//          T[k][a] = M[p_k][a].
+//  update  the composite of a panel's NB elementary steps acts on any other
+//          column v through its pivot rows only:
+//              v <- (v with the panel's pivot rows set to 0) + L v_P,
+//          on v_mfma_f64_16x16x4f64 in output tiles of 16 rows b x 16
+//          columns a; each wave keeps its 16-row strips of L in registers
+//          and streams the tiles of a contiguous column range.
+// A pass over panels A = [k0, k0 + NB) and B = [k0 + NB, k0 + 2 NB): panel
+// A; B's columns take A's steps (rank NB); panel B; A's columns take B's
+// steps (rank NB), which makes them the final L of both; then every other
+// column takes both at once, v <- (v with both panels' pivot rows set to 0)
+// + [L_A L_B] [v_PA; v_PB] (rank 2 NB), with v_PA and v_PB the pivot rows
+// as they were before the pass.  (B's composite applied after A's is
+// exactly that: the rows P_B of A's result are v_PB + L_A[P_B] v_PA, and
+// B's steps turn L_A into the final columns of A.)
 // Then a finish kernel writes D^-1[e][i] = M[p_e][invp(i)] (row p_e of M
 // staged in LDS, written out permuted), log|det| and sign.
 //
-// Traffic: the matrix is read and written once per panel (n^3 / NB x 16
-// bytes per matrix); flops 2 n^3 per matrix.  Separate kernels give each
-// phase its own register budget and occupancy.
+// Traffic: the matrix is read and written once per pass (n^3 / (2 NB) x 16
+// bytes per matrix), plus the two rank-NB updates of 2 NB columns; flops
+// 2 n^3 per matrix.  Separate kernels give each phase its own register
+// budget and occupancy.
 #include <algorithm>
 
 #include "qsl_internal.h"
@@ -41,8 +47,7 @@ constexpr int GJB_COPY_BLOCKS = 8;  // init / finish blocks per matrix
 
 // Launch shapes by the largest n served (NMX = 256 or GJ_NMAX): threads of
 // the init / finish workgroups, of the panel workgroup (one row each) and of
-// the update workgroups, 16-row strips per update wave, row halves and
-// column ranges per matrix in the update.
+// the update workgroups, and column ranges per matrix in the update.
 template <int NMX>
 struct GjbCfg {
     static constexpr int PT = NMX >= 512 ? 512 : 256;
@@ -50,11 +55,18 @@ struct GjbCfg {
     static constexpr int PWAVES = PNT / 64;
     static constexpr int UT = PT;
     static constexpr int UWAVES = UT / 64;
-    static constexpr int SPW = 4;
-    static constexpr int HALVES = NMX / 16 / UWAVES / SPW;
     static constexpr int CHUNKS = 4;
-    static constexpr int UPD_BLOCKS = HALVES * CHUNKS;
-    static_assert(HALVES >= 1 && PNT <= 1024, "launch shape");
+    static_assert(PNT <= 1024, "launch shape");
+};
+// The update of rank NBU (one panel, 32, or two, 64): 16-row strips per
+// wave (fewer at rank 64, whose L strips take twice the registers), row
+// parts and workgroups per matrix.
+template <int NMX, int NBU>
+struct GjbUpdCfg {
+    static constexpr int SPW = NBU == 64 ? 2 : 4;
+    static constexpr int PARTS = NMX / 16 / GjbCfg<NMX>::UWAVES / SPW;
+    static constexpr int BLOCKS = PARTS * GjbCfg<NMX>::CHUNKS;
+    static_assert(PARTS >= 1 && (NBU == 32 || NBU == 64), "update shape");
 };
 
 struct GjbState {
@@ -66,7 +78,7 @@ struct GjbState {
 // Per-matrix workspace (gj_ws_doubles(n) doubles).
 struct GjbView {
     double* M;       // [n][ld] row-major D, then the elimination
-    double* Tg;      // [NB][ld] pivot rows of the current panel
+    double* Tg;      // [2 NB][ld] pivot rows of the current two panels
     int ld;          // row stride: n rounded up to 16 (128-byte rows)
     int* perm;       // [n] pivot row of step k
     uint8_t* used;   // [n] row already a pivot
@@ -79,7 +91,7 @@ __device__ __forceinline__ GjbView gjb_view(const Job& j, int w) {
     v.M = j.gjws + (size_t)w * gj_ws_doubles(n);
     v.ld = gj_ld(n);
     v.Tg = v.M + (size_t)v.ld * n;
-    v.perm = (int*)(v.Tg + (size_t)v.ld * GJB_NB);
+    v.perm = (int*)(v.Tg + (size_t)v.ld * 2 * GJB_NB);
     v.used = (uint8_t*)(v.perm + n);
     v.st = (GjbState*)((char*)v.perm + (((size_t)5 * n + 7) / 8) * 8);
     return v;
@@ -218,7 +230,7 @@ __device__ __forceinline__ uint64_t key_max_wave(uint64_t k) {
 // then one FMA per entry, P -= f (pivot row), on every row; the pivot row's
 // own scaling by 1/pv is deferred to the store.
 template <int NMX>
-__device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
+__device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int tofs) {
     using C = GjbCfg<NMX>;
     constexpr int NB = GJB_NB, PNT = C::PNT, PW = C::PWAVES;
     static_assert(PW <= 16 && NMX <= 1024, "keys hold 10-bit rows; waves compared within one 16-lane row");
@@ -311,11 +323,11 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
             if (k < kn) row[k] = P[k] * sc;
     }
     __syncthreads();
-    // T[k][a] = M[p_k][a]: the pivot rows, copied before the update
-    // overwrites them (rows k >= kn are zero)
+    // T[tofs + k][a] = M[p_k][a]: the pivot rows, copied before the updates
+    // overwrite them (rows k >= kn are zero)
     for (int k = 0; k < NB; ++k) {
         const double* src = v.M + (size_t)perm_l[min(k, kn - 1)] * v.ld;
-        double* dst = v.Tg + (size_t)k * v.ld;
+        double* dst = v.Tg + (size_t)(tofs + k) * v.ld;
         for (int a = tid; a < n; a += PNT) dst[a] = k < kn ? src[a] : 0.0;
     }
     // log|pivot| of the panel's columns (one lane each), summed in column order
@@ -334,27 +346,39 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0) {
 
 template <int NMX, bool BATCHED>
 __global__ __launch_bounds__(GjbCfg<NMX>::PNT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
-                                                                      int njobs, int k0) {
-    gjb_block<BATCHED>(single, jobs, prefix, njobs, 1,
-                       [&](const Job& j, int w, int) __attribute__((always_inline)) { gjb_panel_body<NMX>(j, w, k0); });
+                                                                      int njobs, int k0, int tofs) {
+    gjb_block<BATCHED>(single, jobs, prefix, njobs, 1, [&](const Job& j, int w, int) __attribute__((always_inline)) {
+        gjb_panel_body<NMX>(j, w, k0, tofs);
+    });
 }
 
 // ---------------------------------------------------------------- update
-template <int NMX>
-__device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, int k0) {
+// The composite of the elimination steps of pivots kp .. kp + NB - 1 (one
+// panel, NB = 32, or two, NB = 64) applied to the columns [c_lo, c_hi) other
+// than [s_lo, s_hi): L is M's columns kp .. kp + NB - 1, the pivot rows'
+// entries are T rows tofs .. tofs + NB - 1.
+struct GjbUpd {
+    int kp, tofs, c_lo, c_hi, s_lo, s_hi;
+};
+
+template <int NMX, int NB>
+__device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, const GjbUpd& ua) {
     using C = GjbCfg<NMX>;
-    constexpr int NB = GJB_NB, HS = C::SPW, GJB_SPW = C::SPW, GJB_UT = C::UT, GJB_UWAVES = C::UWAVES;
-    constexpr int GJB_HALVES = C::HALVES, GJB_CHUNKS = C::CHUNKS;
-    const int n = j.n;
+    using U = GjbUpdCfg<NMX, NB>;
+    constexpr int HS = U::SPW, GJB_SPW = U::SPW, GJB_UT = C::UT, GJB_UWAVES = C::UWAVES;
+    constexpr int GJB_PARTS = U::PARTS, GJB_CHUNKS = C::CHUNKS;
+    const int n = j.n, k0 = ua.kp;
     if (k0 >= n) return;
+    const int tl = ua.c_lo >> 4, th = (min(ua.c_hi, n) + 15) >> 4;  // column tiles
+    if (tl >= th) return;
     const GjbView v = gjb_view(j, w);
     if (v.st->flag) return;
+    const double* __restrict__ Tg = v.Tg + (size_t)ua.tofs * v.ld;
     __shared__ unsigned char curpiv[GJ_NMAX];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int half = sub % GJB_HALVES, chunk = sub / GJB_HALVES;
+    const int part = sub % GJB_PARTS, chunk = sub / GJB_PARTS;
     const int kn = min(NB, n - k0);
-    const int ns = (n + 15) >> 4;
     // element q of M: uniform base + 32-bit byte offset (n^2 * 8 < 2^32)
     char* const Mb = (char*)v.M;
     // global (not generic) accesses: a generic load also counts on the LDS
@@ -372,7 +396,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
     double Lr[HS][NB / 4];
 #pragma unroll
     for (int u = 0; u < HS; ++u) {
-        const int strip = GJB_SPW * GJB_UWAVES * half + wave + GJB_UWAVES * u;
+        const int strip = GJB_SPW * GJB_UWAVES * part + wave + GJB_UWAVES * u;
         const int b0 = 16 * strip;
         b0s[u] = b0;
         const int ba = b0 + (lane & 15);
@@ -391,15 +415,14 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
         }
         keep[u] = kb;
     }
-    // column tiles chunk, chunk + CHUNKS, ... outside the panel, software
-    // pipelined: the next tile's T block and strips are loaded while this
-    // tile runs on MFMA and is stored
-    // chunk c owns the contiguous tile range [t0, t1), so successive tiles of
-    // a wave continue the same rows of M; the panel's two tiles are skipped
-    const int t0 = (ns * chunk) / GJB_CHUNKS, t1 = (ns * (chunk + 1)) / GJB_CHUNKS;
+    // chunk c owns a contiguous range [t0, t1) of the tiles, so successive
+    // tiles of a wave continue the same rows of M; tiles in [s_lo, s_hi) are
+    // skipped.  Software pipelined: the next tile's T block and strips are
+    // loaded while this tile runs on MFMA and is stored.
+    const int t0 = tl + ((th - tl) * chunk) / GJB_CHUNKS, t1 = tl + ((th - tl) * (chunk + 1)) / GJB_CHUNKS;
     auto skip_panel = [&](int jt) {
-        while (jt < t1 && 16 * jt >= k0 && 16 * jt < k0 + NB) ++jt;
-        return jt < t1 ? jt : ns;
+        while (jt < t1 && 16 * jt >= ua.s_lo && 16 * jt < ua.s_hi) ++jt;
+        return jt;  // t1 when none is left
     };
     // loads at clamped (valid) addresses and no select on the loaded values,
     // so the next tile's loads stay in flight during this tile's products:
@@ -409,7 +432,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
     auto load = [&](int jt, int ntv, int ldv, double (&bop)[NB / 4], f64x4 (&acc)[HS]) {
         const int al = min(16 * jt + (lane & 15), ntv - 1);
 #pragma unroll
-        for (int ks = 0; ks < NB / 4; ++ks) bop[ks] = *gmem(v.Tg + (size_t)(4 * ks + (lane >> 4)) * ldv + al);
+        for (int ks = 0; ks < NB / 4; ++ks) bop[ks] = *gmem(Tg + (size_t)(4 * ks + (lane >> 4)) * ldv + al);
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
@@ -425,7 +448,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
         int nt = n, ldt = v.ld;
         asm volatile("" : "+s"(nt), "+s"(ldt));  // keep the row offsets below out of registers across tiles
         const int jn = skip_panel(jt + 1);
-        load(jn < ns ? jn : jt, nt, ldt, bopn, accn);
+        load(jn < t1 ? jn : jt, nt, ldt, bopn, accn);
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
@@ -447,7 +470,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
         jt = jn;
     };
     int jt = skip_panel(t0);
-    if (jt >= ns) return;
+    if (jt >= t1) return;
     // two register sets used in turn, so no copy between tiles (a copy of a
     // loaded value waits for its load)
     double bopA[NB / 4], bopB[NB / 4];
@@ -465,17 +488,19 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, in
 #pragma unroll 1
     while (true) {
         step(jt, bopA, accA, bopB, accB);
-        if (jt >= ns) break;
+        if (jt >= t1) break;
         step(jt, bopB, accB, bopA, accA);
-        if (jt >= ns) break;
+        if (jt >= t1) break;
     }
 }
 
-template <int NMX, bool BATCHED>
+template <int NMX, int NBU, bool BATCHED>
 __global__ __launch_bounds__(GjbCfg<NMX>::UT) void gjb_update_kernel(Job single, const Job* jobs, const int* prefix,
-                                                                      int njobs, int k0) {
-    gjb_block<BATCHED>(single, jobs, prefix, njobs, GjbCfg<NMX>::UPD_BLOCKS,
-                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) { gjb_update_body<NMX>(j, w, sub, k0); });
+                                                                      int njobs, GjbUpd ua) {
+    gjb_block<BATCHED>(single, jobs, prefix, njobs, GjbUpdCfg<NMX, NBU>::BLOCKS,
+                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) {
+                           gjb_update_body<NMX, NBU>(j, w, sub, ua);
+                       });
 }
 
 // ---------------------------------------------------------------- finish
@@ -556,9 +581,24 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
     else
         gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
     hipError_t e = hipGetLastError();
-    for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += GJB_NB) {
-        gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0);
-        gjb_update_kernel<NMX, BATCHED><<<m * C::UPD_BLOCKS, C::UT, 0, st>>>(single, jobs, prefix, njobs, k0);
+    constexpr int NB = GJB_NB;
+    const unsigned b32 = m * GjbUpdCfg<NMX, 32>::BLOCKS, b64 = m * GjbUpdCfg<NMX, 64>::BLOCKS;
+    // two panels per pass: A = [k0, k0 + NB), B = [k0 + NB, k0 + 2 NB)
+    for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += 2 * NB) {
+        gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0, 0);
+        if (k0 + NB < nmax) {
+            // B's columns take A's steps, B is reduced, then A's columns
+            // take B's steps (they become the final L of A)
+            gjb_update_kernel<NMX, 32, BATCHED><<<b32, C::UT, 0, st>>>(single, jobs, prefix, njobs,
+                                                                       GjbUpd{k0, 0, k0 + NB, k0 + 2 * NB, 0, 0});
+            gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0 + NB, NB);
+            gjb_update_kernel<NMX, 32, BATCHED><<<b32, C::UT, 0, st>>>(single, jobs, prefix, njobs,
+                                                                       GjbUpd{k0 + NB, NB, k0, k0 + NB, 0, 0});
+        }
+        // every other column takes both panels' steps at once: rank 2 NB,
+        // the matrix streamed once per pass
+        gjb_update_kernel<NMX, 64, BATCHED><<<b64, C::UT, 0, st>>>(
+            single, jobs, prefix, njobs, GjbUpd{k0, 0, 0, 1 << 30, k0, k0 + 2 * NB});
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -577,7 +617,8 @@ static hipError_t gjb_sequence(int mode, const Job& single, const Job* jobs, con
 
 hipError_t launch_gjb(const Job& j, hipStream_t st) {
     if (!gj_blocked(j.n) || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
-    if (j.W > (int64_t)(0x7fffffff / GjbCfg<GJ_NMAX>::UPD_BLOCKS)) return hipErrorInvalidValue;
+    constexpr int most = std::max(GjbUpdCfg<GJ_NMAX, 32>::BLOCKS, GjbUpdCfg<GJ_NMAX, 64>::BLOCKS);
+    if (j.W > (int64_t)(0x7fffffff / most)) return hipErrorInvalidValue;
     return gjb_sequence<false>(j.mode, j, nullptr, nullptr, 0, (int)j.W, j.n, st);
 }
 

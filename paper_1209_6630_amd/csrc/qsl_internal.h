@@ -25,12 +25,12 @@ __host__ __device__ inline bool gj_blocked(int n) { return n >= GJ_BLOCKED_FROM;
 constexpr int GJ_NMAX = 1024;      // largest n of the blocked inversion
 constexpr int GJ_PANEL = 32;       // panel width of the blocked inversion
 // Blocked inversion workspace per matrix: the copy of D with rows padded to
-// gj_ld(n) doubles (128-byte aligned rows), the pivot rows of one panel,
+// gj_ld(n) doubles (128-byte aligned rows), the pivot rows of two panels,
 // the pivot order, row flags and state; a multiple of 16 doubles.
 __host__ __device__ inline int gj_ld(int n) { return (n + 15) & ~15; }
 __host__ __device__ inline size_t gj_ws_doubles(int n) {
     const size_t ld = (size_t)gj_ld(n);
-    return (ld * n + ld * GJ_PANEL + ((size_t)5 * n + 40) / 8 + 15) & ~(size_t)15;
+    return (ld * n + ld * 2 * GJ_PANEL + ((size_t)5 * n + 40) / 8 + 15) & ~(size_t)15;
 }
 
 // Everything the AO evaluation of one window needs, in one record (built
