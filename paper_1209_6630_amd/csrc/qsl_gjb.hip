@@ -20,9 +20,10 @@
 //          columns a; each wave keeps its 16-row strips of L in registers
 //          and streams the tiles of a contiguous column range.
 // A pass over panels A = [k0, k0 + NB) and B = [k0 + NB, k0 + 2 NB): panel
-// A; B's columns take A's steps (rank NB); panel B; A's columns take B's
-// steps (rank NB), which makes them the final L of both; then every other
-// column takes both at once, v <- (v with both panels' pivot rows set to 0)
+// A; then B's panel kernel, in which B's columns first take A's steps, B is
+// reduced, and A's columns take B's steps, which makes them the final L of
+// both (two rank-NB products per row); then every other column takes both
+// at once, v <- (v with both panels' pivot rows set to 0)
 // + [L_A L_B] [v_PA; v_PB] (rank 2 NB), with v_PA and v_PB the pivot rows
 // as they were before the pass.  (B's composite applied after A's is
 // exactly that: the rows P_B of A's result are v_PB + L_A[P_B] v_PA, and
@@ -31,8 +32,7 @@
 // staged in LDS, written out permuted), log|det| and sign.
 //
 // Traffic: the matrix is read and written once per pass (n^3 / (2 NB) x 16
-// bytes per matrix), plus the two rank-NB updates of 2 NB columns; flops
-// 2 n^3 per matrix.  Separate kernels give each phase its own register
+// bytes per matrix); flops 2 n^3 per matrix.  Separate kernels give each phase its own register
 // budget and occupancy.
 #include <algorithm>
 
@@ -229,7 +229,14 @@ __device__ __forceinline__ uint64_t key_max_wave(uint64_t k) {
 // pivot key, one barrier, the largest of the waves' keys (16-lane DPP),
 // then one FMA per entry, P -= f (pivot row), on every row; the pivot row's
 // own scaling by 1/pv is deferred to the store.
-template <int NMX>
+// SECOND: the second panel B = [k0, k0 + NB) of a pass, after the first
+// A = [k0 - NB, k0).  B's columns first take A's steps (rank NB: the rows
+// of A's pivots zeroed, plus L_A times A's pivot rows in B's columns, kept
+// in T rows 0 .. NB - 1); after B is reduced, A's columns take B's steps
+// (the rows of B's pivots zeroed, plus L_B times the rows P_B of L_A),
+// which makes them the final L of both panels.  Both are small products
+// per row, done here rather than by two update launches.
+template <int NMX, bool SECOND>
 __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int tofs) {
     using C = GjbCfg<NMX>;
     constexpr int NB = GJB_NB, PNT = C::PNT, PW = C::PWAVES;
@@ -242,6 +249,10 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
     __shared__ double cand_row[2][PW][NB];
     __shared__ int perm_l[NB];
     __shared__ double piv_l[NB];
+    // SECOND: T_A[k][q] = M[p^A_k][k0 + q] (A's pivot rows in B's columns),
+    // later L_A[p^B_k][q] (B's pivot rows in A's columns); A's pivot rows
+    __shared__ double blk[SECOND ? NB : 1][SECOND ? NB : 1];
+    __shared__ unsigned char pivA[SECOND ? PNT : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kn = min(NB, n - k0);
@@ -249,15 +260,48 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
     const int bl = min(b, n - 1);  // loads at clamped (valid) addresses, then select
     bool used = b >= n || v.used[bl];
     double P[NB];  // P[k] = M[b][k0 + k]
+    if constexpr (SECOND) {
+        pivA[tid] = 0;
+        for (int q = tid; q < NB * NB; q += PNT) {
+            const int k = q / NB, c = q % NB;
+            blk[k][c] = c < kn ? v.Tg[(size_t)k * v.ld + k0 + c] : 0.0;  // A is whole: n > k0
+        }
+        __syncthreads();
+        if (tid < NB) pivA[v.perm[k0 - NB + tid]] = 1;
+        __syncthreads();
+    }
     {
         const double* row = v.M + (size_t)bl * v.ld + k0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             const double x = row[min(k, kn - 1)];
-            P[k] = (b < n && k < kn) ? x : 0.0;
+            P[k] = (b < n && k < kn && !(SECOND && pivA[b])) ? x : 0.0;
+        }
+    }
+    if constexpr (SECOND) {
+        // + L_A[b][k] T_A[k][.]: L_A is this row's entries in A's columns,
+        // taken eight at a time (bounded live registers)
+        const double* rowA = v.M + (size_t)bl * v.ld + k0 - NB;
+#pragma unroll 1
+        for (int kc = 0; kc < NB; kc += 8) {
+            double a[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) a[i] = b < n ? rowA[kc + i] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                static_for<0, NB / 8>([&](auto cc) __attribute__((always_inline)) {
+                    constexpr int c0 = decltype(cc)::value * 8;
+                    double t[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) t[q] = blk[kc + i][c0 + q];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) P[c0 + q] = fma(a[i], t[q], P[c0 + q]);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
         }
     }
     double sc = 1.0;   // the row's pending scale (1/pv once it is a pivot row)
+    bool newpiv = false;  // the row is a pivot row of this panel
     int fail = 0;      // uniform: 1 no pivot (zero column), 2 non-finite pivot
     static_for<0, NB>([&](auto kc) __attribute__((always_inline)) {
         constexpr int k = decltype(kc)::value, buf = k & 1;
@@ -311,16 +355,49 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         }
         if (piv) {
             used = true;
+            newpiv = true;
             sc = inv;
             v.used[p] = 1;
         }
     });
     if (fail) return;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) P[k] *= sc;  // the final L of this panel
+    if constexpr (SECOND) {
+        // L_A <- (L_A with the rows of B's pivots zeroed) + L_B L_A[P_B]
+        __syncthreads();  // every thread is done with T_A
+        for (int q = tid; q < NB * NB; q += PNT) {
+            const int k = q / NB, c = q % NB;
+            blk[k][c] = k < kn ? v.M[(size_t)perm_l[k] * v.ld + k0 - NB + c] : 0.0;
+        }
+        __syncthreads();
+        if (b < n) {
+            double* rowA = v.M + (size_t)b * v.ld + k0 - NB;
+            // eight of A's columns at a time
+#pragma unroll 1
+            for (int c0 = 0; c0 < NB; c0 += 8) {
+                double x[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) x[q] = newpiv ? 0.0 : rowA[c0 + q];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    double t[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) t[q] = blk[k][c0 + q];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = fma(P[k], t[q], x[q]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) rowA[c0 + q] = x[q];
+            }
+        }
+    }
     if (b < n) {
         double* row = v.M + (size_t)b * v.ld + k0;
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-            if (k < kn) row[k] = P[k] * sc;
+            if (k < kn) row[k] = P[k];
     }
     __syncthreads();
     // T[tofs + k][a] = M[p_k][a]: the pivot rows, copied before the updates
@@ -344,11 +421,11 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
     }
 }
 
-template <int NMX, bool BATCHED>
+template <int NMX, bool BATCHED, bool SECOND>
 __global__ __launch_bounds__(GjbCfg<NMX>::PNT) void gjb_panel_kernel(Job single, const Job* jobs, const int* prefix,
                                                                       int njobs, int k0, int tofs) {
     gjb_block<BATCHED>(single, jobs, prefix, njobs, 1, [&](const Job& j, int w, int) __attribute__((always_inline)) {
-        gjb_panel_body<NMX>(j, w, k0, tofs);
+        gjb_panel_body<NMX, SECOND>(j, w, k0, tofs);
     });
 }
 
@@ -582,19 +659,14 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
         gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
     hipError_t e = hipGetLastError();
     constexpr int NB = GJB_NB;
-    const unsigned b32 = m * GjbUpdCfg<NMX, 32>::BLOCKS, b64 = m * GjbUpdCfg<NMX, 64>::BLOCKS;
+    const unsigned b64 = m * GjbUpdCfg<NMX, 64>::BLOCKS;
     // two panels per pass: A = [k0, k0 + NB), B = [k0 + NB, k0 + 2 NB)
     for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += 2 * NB) {
-        gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0, 0);
-        if (k0 + NB < nmax) {
-            // B's columns take A's steps, B is reduced, then A's columns
-            // take B's steps (they become the final L of A)
-            gjb_update_kernel<NMX, 32, BATCHED><<<b32, C::UT, 0, st>>>(single, jobs, prefix, njobs,
-                                                                       GjbUpd{k0, 0, k0 + NB, k0 + 2 * NB, 0, 0});
-            gjb_panel_kernel<NMX, BATCHED><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0 + NB, NB);
-            gjb_update_kernel<NMX, 32, BATCHED><<<b32, C::UT, 0, st>>>(single, jobs, prefix, njobs,
-                                                                       GjbUpd{k0 + NB, NB, k0, k0 + NB, 0, 0});
-        }
+        gjb_panel_kernel<NMX, BATCHED, false><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0, 0);
+        // B's columns take A's steps, B is reduced, then A's columns take
+        // B's steps (they become the final L of A): all in B's panel kernel
+        if (k0 + NB < nmax)
+            gjb_panel_kernel<NMX, BATCHED, true><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0 + NB, NB);
         // every other column takes both panels' steps at once: rank 2 NB,
         // the matrix streamed once per pass
         gjb_update_kernel<NMX, 64, BATCHED><<<b64, C::UT, 0, st>>>(
@@ -617,8 +689,7 @@ static hipError_t gjb_sequence(int mode, const Job& single, const Job* jobs, con
 
 hipError_t launch_gjb(const Job& j, hipStream_t st) {
     if (!gj_blocked(j.n) || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
-    constexpr int most = std::max(GjbUpdCfg<GJ_NMAX, 32>::BLOCKS, GjbUpdCfg<GJ_NMAX, 64>::BLOCKS);
-    if (j.W > (int64_t)(0x7fffffff / most)) return hipErrorInvalidValue;
+    if (j.W > (int64_t)(0x7fffffff / GjbUpdCfg<GJ_NMAX, 2 * GJB_NB>::BLOCKS)) return hipErrorInvalidValue;
     return gjb_sequence<false>(j.mode, j, nullptr, nullptr, 0, (int)j.W, j.n, st);
 }
 
