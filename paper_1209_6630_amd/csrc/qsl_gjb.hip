@@ -100,10 +100,16 @@ __device__ __forceinline__ GjbView gjb_view(const Job& j, int w) {
 // Block -> (Job, matrix, sub-block): one Job by value (BATCHED = false), or
 // a plan's Jobs through the prefix sums of their matrix counts.  Separate
 // instantiations keep one inlined copy of the body per kernel.
-template <bool BATCHED, typename F>
+// XCD: blocks 8 mult t + o serve matrix 8 t + o % 8, sub-block o / 8 (the
+// grid is mult times the matrix count rounded up to 8).  The hardware hands
+// consecutive blocks to the eight XCDs in turn, so all sub-blocks of a
+// matrix run on one XCD and share its L2 (the update's T block).
+template <bool BATCHED, bool XCD = false, typename F>
 __device__ __forceinline__ void gjb_block(const Job& single, const Job* __restrict__ jobs,
                                           const int* __restrict__ prefix, int njobs, int mult, F body) {
-    const int b = blockIdx.x / mult, sub = blockIdx.x % mult;
+    const int o = XCD ? (int)(blockIdx.x % (8u * mult)) : 0;
+    const int b = XCD ? (int)(blockIdx.x / (8u * mult)) * 8 + o % 8 : (int)(blockIdx.x / mult);
+    const int sub = XCD ? o / 8 : (int)(blockIdx.x % mult);
     if constexpr (!BATCHED) {
         if (b < single.W) body(single, b, sub);
     } else {
@@ -574,7 +580,7 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
 template <int NMX, int NBU, bool BATCHED>
 __global__ __launch_bounds__(GjbCfg<NMX>::UT) void gjb_update_kernel(Job single, const Job* jobs, const int* prefix,
                                                                       int njobs, GjbUpd ua) {
-    gjb_block<BATCHED>(single, jobs, prefix, njobs, GjbUpdCfg<NMX, NBU>::BLOCKS,
+    gjb_block<BATCHED, true>(single, jobs, prefix, njobs, GjbUpdCfg<NMX, NBU>::BLOCKS,
                        [&](const Job& j, int w, int sub) __attribute__((always_inline)) {
                            gjb_update_body<NMX, NBU>(j, w, sub, ua);
                        });
@@ -659,7 +665,7 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
         gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
     hipError_t e = hipGetLastError();
     constexpr int NB = GJB_NB;
-    const unsigned b64 = m * GjbUpdCfg<NMX, 64>::BLOCKS;
+    const unsigned b64 = ((m + 7) / 8 * 8) * GjbUpdCfg<NMX, 64>::BLOCKS;  // XCD-aware block order
     // two panels per pass: A = [k0, k0 + NB), B = [k0 + NB, k0 + 2 NB)
     for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += 2 * NB) {
         gjb_panel_kernel<NMX, BATCHED, false><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0, 0);
@@ -689,7 +695,7 @@ static hipError_t gjb_sequence(int mode, const Job& single, const Job* jobs, con
 
 hipError_t launch_gjb(const Job& j, hipStream_t st) {
     if (!gj_blocked(j.n) || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
-    if (j.W > (int64_t)(0x7fffffff / GjbUpdCfg<GJ_NMAX, 2 * GJB_NB>::BLOCKS)) return hipErrorInvalidValue;
+    if (j.W > (int64_t)(0x7fffffff / GjbUpdCfg<GJ_NMAX, 2 * GJB_NB>::BLOCKS) - 8) return hipErrorInvalidValue;
     return gjb_sequence<false>(j.mode, j, nullptr, nullptr, 0, (int)j.W, j.n, st);
 }
 
