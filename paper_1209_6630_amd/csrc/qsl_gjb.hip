@@ -41,6 +41,7 @@
 namespace qsl {
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
 
 constexpr int GJB_NB = GJ_PANEL;
 constexpr int GJB_COPY_BLOCKS = 8;  // init / finish blocks per matrix
@@ -468,6 +469,11 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
     // counter, and the wait before a tile's products would then take the
     // next tile's loads with it
     auto Mq = [&](uint32_t q) { return gmem((double*)(Mb + q * 8u)); };
+    // stores through a buffer resource over M's n rows: a masked element
+    // gets an offset past the end, which the hardware drops.  With no branch
+    // around them the stores count in the wait before the next tile's
+    // products, which then need not wait for them to complete.
+    const __amdgpu_buffer_rsrc_t Mr = __builtin_amdgcn_make_buffer_rsrc(v.M, (short)0, n * v.ld * 8, 0x00020000);
     for (int b = tid; b < GJ_NMAX; b += GJB_UT) curpiv[b] = 0;
     __syncthreads();
     if (tid < kn) curpiv[v.perm[k0 + tid]] = 1;
@@ -507,15 +513,24 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
         while (jt < t1 && 16 * jt >= ua.s_lo && 16 * jt < ua.s_hi) ++jt;
         return jt;  // t1 when none is left
     };
-    // loads at clamped (valid) addresses and no select on the loaded values,
-    // so the next tile's loads stay in flight during this tile's products:
-    // an output element depends only on its own column of the T block and
-    // its own M element, and columns or rows past n are never stored; the
-    // panel's pivot rows are zeroed just before the products
-    auto load = [&](int jt, int ntv, int ldv, double (&bop)[NB / 4], f64x4 (&acc)[HS]) {
-        const int al = min(16 * jt + (lane & 15), ntv - 1);
+    // The T block of a tile (NB rows x 16 columns) is staged in LDS once per
+    // workgroup (TE elements per thread), double-buffered: every wave of the
+    // workgroup streams the same tiles.  Loads at clamped (valid) addresses
+    // and no select on the loaded values, so the next tile's loads stay in
+    // flight during this tile's products: an output element depends only on
+    // its own column of the T block and its own M element, and columns or
+    // rows past n are never stored; the panel's pivot rows are zeroed just
+    // before the products.
+    constexpr int TE = NB * 16 / GJB_UT;
+    static_assert(TE * GJB_UT == NB * 16, "T block per thread");
+    __shared__ __attribute__((aligned(16))) double Ts[2][NB][16];
+    auto load = [&](int jt, int ntv, int ldv, double (&tv)[TE], f64x4 (&acc)[HS]) {
 #pragma unroll
-        for (int ks = 0; ks < NB / 4; ++ks) bop[ks] = *gmem(Tg + (size_t)(4 * ks + (lane >> 4)) * ldv + al);
+        for (int i = 0; i < TE; ++i) {
+            const int e = tid + GJB_UT * i;
+            tv[i] = *gmem(Tg + (size_t)(e >> 4) * ldv + min(16 * jt + (e & 15), ntv - 1));
+        }
+        const int al = min(16 * jt + (lane & 15), ntv - 1);
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
@@ -524,55 +539,74 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
                 acc[u][r] = *Mq((uint32_t)(min(b, ntv - 1) * ldv + al));
             }
     };
-    // one tile: issue the loads of the tile after it into the other register
-    // set (on every pass: the last one reloads this tile, unused, so the
-    // queue has the same depth on all paths), then its products and stores
-    auto step = [&](int& jt, double (&bop)[NB / 4], f64x4 (&acc)[HS], double (&bopn)[NB / 4], f64x4 (&accn)[HS]) {
+    auto put = [&](int buf, const double (&tv)[TE]) {
+#pragma unroll
+        for (int i = 0; i < TE; ++i) {
+            const int e = tid + GJB_UT * i;
+            Ts[buf][e >> 4][e & 15] = tv[i];
+        }
+    };
+    // one tile from T block buf: issue the loads of the tile after it (into
+    // the other M register set and tv; on every pass: the last one reloads
+    // this tile, unused, so the queue has the same depth on all paths), its
+    // products and stores, then the next T block into the other buffer
+    auto step = [&](int& jt, int buf, f64x4 (&acc)[HS], f64x4 (&accn)[HS]) {
         int nt = n, ldt = v.ld;
         asm volatile("" : "+s"(nt), "+s"(ldt));  // keep the row offsets below out of registers across tiles
         const int jn = skip_panel(jt + 1);
-        load(jn < t1 ? jn : jt, nt, ldt, bopn, accn);
+        double tv[TE];
+        load(jn < t1 ? jn : jt, nt, ldt, tv, accn);
 #pragma unroll
         for (int u = 0; u < HS; ++u)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[u][r] = ((keep[u] >> r) & 1u) ? acc[u][r] : 0.0;
+        // B operand: T[4 ks + lane / 16][lane % 16]
+        const double* tb = &Ts[buf][lane >> 4][lane & 15];
 #pragma unroll
-        for (int u = 0; u < HS; ++u)
+        for (int ks = 0; ks < NB / 4; ++ks) {
+            const double bop = tb[64 * ks];
 #pragma unroll
-            for (int ks = 0; ks < NB / 4; ++ks)
-                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lr[u][ks], bop[ks], acc[u], 0, 0, 0);
+            for (int u = 0; u < HS; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lr[u][ks], bop, acc[u], 0, 0, 0);
+        }
         const int ac = 16 * jt + (lane & 15);
 #pragma unroll
         for (int u = 0; u < HS; ++u) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int b = b0s[u] + (lane >> 4) + 4 * r;
-                if ((ac < nt) & (b < nt)) *Mq((uint32_t)(b * ldt + ac)) = acc[u][r];
+                const uint32_t off = (ac < nt) & (b < nt) ? (uint32_t)(b * ldt + ac) * 8u : 0x80000000u;
+                const uint64_t x = (uint64_t)__double_as_longlong(acc[u][r]);
+                const u32x2 xv = {(uint32_t)x, (uint32_t)(x >> 32)};
+                __builtin_amdgcn_raw_buffer_store_b64(xv, Mr, off, 0, 0);
             }
         }
+        put(buf ^ 1, tv);
+        __syncthreads();  // the next block is in, and every wave is done with this one
         jt = jn;
     };
     int jt = skip_panel(t0);
     if (jt >= t1) return;
     // two register sets used in turn, so no copy between tiles (a copy of a
     // loaded value waits for its load)
-    double bopA[NB / 4], bopB[NB / 4];
     f64x4 accA[HS], accB[HS];
-    load(jt, n, v.ld, bopA, accA);
+    {
+        double tv[TE];
+        load(jt, n, v.ld, tv, accA);
+        put(0, tv);
+    }
     // wait for the first tile here: the waits at the loop head are merged
     // over both ways in, and a queue holding only these loads would make
     // every pass wait for the whole queue, the next tile's loads included
 #pragma unroll
-    for (int ks = 0; ks < NB / 4; ++ks) asm volatile("" ::"v"(bopA[ks]));
-#pragma unroll
     for (int u = 0; u < HS; ++u)
 #pragma unroll
         for (int r = 0; r < 4; ++r) asm volatile("" ::"v"(accA[u][r]));
+    __syncthreads();
 #pragma unroll 1
     while (true) {
-        step(jt, bopA, accA, bopB, accB);
+        step(jt, 0, accA, accB);
         if (jt >= t1) break;
-        step(jt, bopB, accB, bopA, accA);
+        step(jt, 1, accB, accA);
         if (jt >= t1) break;
     }
 }
