@@ -42,6 +42,7 @@ namespace qsl {
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 typedef __attribute__((ext_vector_type(2))) unsigned int u32x2;
+typedef __attribute__((ext_vector_type(2))) double f64x2;
 
 constexpr int GJB_NB = GJ_PANEL;
 constexpr int GJB_COPY_BLOCKS = 8;  // init / finish blocks per matrix
@@ -278,11 +279,23 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         __syncthreads();
     }
     {
+        // the row's panel entries: 16-byte loads for a whole panel (rows are
+        // 128-byte aligned, k0 a multiple of NB), else one clamped load each
         const double* row = v.M + (size_t)bl * v.ld + k0;
+        const bool keep = b < n && !(SECOND && pivA[b]);
+        if (kn == NB) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            const double x = row[min(k, kn - 1)];
-            P[k] = (b < n && k < kn && !(SECOND && pivA[b])) ? x : 0.0;
+            for (int k = 0; k < NB; k += 2) {
+                const f64x2 x = *gmem((const f64x2*)(row + k));
+                P[k] = keep ? x.x : 0.0;
+                P[k + 1] = keep ? x.y : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const double x = *gmem(row + min(k, kn - 1));
+                P[k] = (keep && k < kn) ? x : 0.0;
+            }
         }
     }
     if constexpr (SECOND) {
@@ -293,7 +306,11 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         for (int kc = 0; kc < NB; kc += 8) {
             double a[8];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) a[i] = b < n ? rowA[kc + i] : 0.0;
+            for (int i = 0; i < 8; i += 2) {
+                const f64x2 x = *gmem((const f64x2*)(rowA + kc + i));
+                a[i] = b < n ? x.x : 0.0;
+                a[i + 1] = b < n ? x.y : 0.0;
+            }
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 static_for<0, NB / 8>([&](auto cc) __attribute__((always_inline)) {
@@ -385,7 +402,11 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
             for (int c0 = 0; c0 < NB; c0 += 8) {
                 double x[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) x[q] = newpiv ? 0.0 : rowA[c0 + q];
+                for (int q = 0; q < 8; q += 2) {
+                    const f64x2 y = *gmem((const f64x2*)(rowA + c0 + q));
+                    x[q] = newpiv ? 0.0 : y.x;
+                    x[q + 1] = newpiv ? 0.0 : y.y;
+                }
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     double t[8];
@@ -396,15 +417,20 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
                     __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) rowA[c0 + q] = x[q];
+                for (int q = 0; q < 8; q += 2) *gmem((f64x2*)(rowA + c0 + q)) = f64x2{x[q], x[q + 1]};
             }
         }
     }
     if (b < n) {
         double* row = v.M + (size_t)b * v.ld + k0;
+        if (kn == NB) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (k < kn) row[k] = P[k];
+            for (int k = 0; k < NB; k += 2) *gmem((f64x2*)(row + k)) = f64x2{P[k], P[k + 1]};
+        } else {
+#pragma unroll
+            for (int k = 0; k < NB; ++k)
+                if (k < kn) *gmem(row + k) = P[k];
+        }
     }
     __syncthreads();
     // T[tofs + k][a] = M[p_k][a]: the pivot rows, copied before the updates
@@ -412,7 +438,7 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
     for (int k = 0; k < NB; ++k) {
         const double* src = v.M + (size_t)perm_l[min(k, kn - 1)] * v.ld;
         double* dst = v.Tg + (size_t)(tofs + k) * v.ld;
-        for (int a = tid; a < n; a += PNT) dst[a] = k < kn ? src[a] : 0.0;
+        for (int a = tid; a < n; a += PNT) *gmem(dst + a) = k < kn ? *gmem(src + a) : 0.0;
     }
     // log|pivot| of the panel's columns (one lane each), summed in column order
     if (wave == 0) {
