@@ -27,12 +27,15 @@ def test_forward_configs(name, W, mode):
 
 
 @pytest.mark.parametrize("n_up,n_dn", [(1, 0), (1, 1), (3, 2), (32, 31), (33, 33), (64, 63), (65, 64),
-                                       (128, 127), (129, 100), (224, 223), (225, 224), (480, 479),
-                                       (1024, 1000)])
+                                       (128, 127), (129, 100), (224, 223), (225, 224), (257, 256),
+                                       (480, 479), (545, 511), (1024, 1000)])
 def test_forward_tile_and_inversion_boundaries(n_up, n_dn):
     """Electron counts at the 32-electron tile and at every inversion
     variant boundary (32, 64, 128, 224 register-resident, then blocked up to
-    the 1024 maximum), with s, p and d shells."""
+    the 1024 maximum), with s, p and d shells.  The blocked sizes end their
+    last pass of two 32-column panels in every way: with the second panel 1
+    (225, 545), 31 (511) or 8 (1000) columns wide, with the first panel
+    alone, whole (480) or not (479, 257), and on a whole pass (256, 1024)."""
     print(f"[case] boundaries n_up={n_up} n_dn={n_dn}", flush=True)
     nat = max(2, (n_up + n_dn) // 6 + 1)
     sysm, A_up, A_dn = random_tiny(n_atoms=nat, n_up=n_up, n_dn=n_dn, seed=n_up * 7 + n_dn)
