@@ -57,7 +57,7 @@ struct GjbCfg {
     static constexpr int PWAVES = PNT / 64;
     static constexpr int UT = PT;
     static constexpr int UWAVES = UT / 64;
-    static constexpr int CHUNKS = 4;
+    static constexpr int CHUNKS = 2;
     static_assert(PNT <= 1024, "launch shape");
 };
 // The update of rank NBU (one panel, 32, or two, 64): 16-row strips per
