@@ -302,7 +302,7 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         // + L_A[b][k] T_A[k][.]: L_A is this row's entries in A's columns,
         // taken eight at a time (bounded live registers)
         const double* rowA = v.M + (size_t)bl * v.ld + k0 - NB;
-#pragma unroll 1
+#pragma unroll
         for (int kc = 0; kc < NB; kc += 8) {
             double a[8];
 #pragma unroll
@@ -398,7 +398,7 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         if (b < n) {
             double* rowA = v.M + (size_t)b * v.ld + k0 - NB;
             // eight of A's columns at a time
-#pragma unroll 1
+#pragma unroll
             for (int c0 = 0; c0 < NB; c0 += 8) {
                 double x[8];
 #pragma unroll
@@ -435,10 +435,13 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
     __syncthreads();
     // T[tofs + k][a] = M[p_k][a]: the pivot rows, copied before the updates
     // overwrite them (rows k >= kn are zero)
-    for (int k = 0; k < NB; ++k) {
-        const double* src = v.M + (size_t)perm_l[min(k, kn - 1)] * v.ld;
-        double* dst = v.Tg + (size_t)(tofs + k) * v.ld;
-        for (int a = tid; a < n; a += PNT) *gmem(dst + a) = k < kn ? *gmem(src + a) : 0.0;
+    // (n <= PNT: one column a per thread; all loads issued before the stores)
+    if (tid < n) {
+        double t[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) t[k] = *gmem(v.M + (size_t)perm_l[min(k, kn - 1)] * v.ld + tid);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) *gmem(v.Tg + (size_t)(tofs + k) * v.ld + tid) = k < kn ? t[k] : 0.0;
     }
     // log|pivot| of the panel's columns (one lane each), summed in column order
     if (wave == 0) {
