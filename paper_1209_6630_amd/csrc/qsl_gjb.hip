@@ -3,8 +3,9 @@
 // kernel (inversion step, section "Overall performance of QMC=Chem").
 //
 // The elimination is the same as the unblocked one: at step k the pivot is
-// the largest |D[b][k]| over rows b not yet used (smallest b on exact ties),
-// pivot rows are never moved, and the inverse is un-permuted at the end.
+// the largest |D[b][k]| over rows b not yet used (the smallest b among
+// values within 2^-42 relative), pivot rows are never moved, and the
+// inverse is un-permuted at the end.
 // It runs on a row-major FP64 copy M[b][a] = D[b][a] in the workspace
 // (row b = MO, column a = electron), made by an LDS-tiled transpose of C_1.
 //
@@ -32,8 +33,8 @@
 // staged in LDS, written out permuted), log|det| and sign.
 //
 // Traffic: the matrix is read and written once per pass (n^3 / (2 NB) x 16
-// bytes per matrix); flops 2 n^3 per matrix.  Separate kernels give each phase its own register
-// budget and occupancy.
+// bytes per matrix); flops 2 n^3 per matrix.  Separate kernels give each
+// phase its own register budget and occupancy.
 #include <algorithm>
 
 #include "qsl_internal.h"
@@ -60,15 +61,14 @@ struct GjbCfg {
     static constexpr int CHUNKS = 2;
     static_assert(PNT <= 1024, "launch shape");
 };
-// The update of rank NBU (one panel, 32, or two, 64): 16-row strips per
-// wave (fewer at rank 64, whose L strips take twice the registers), row
-// parts and workgroups per matrix.
-template <int NMX, int NBU>
+// The rank-2 NB update of a pass: 16-row strips per wave (two: the strips
+// of L hold 2 NB entries per row), row parts and workgroups per matrix.
+template <int NMX>
 struct GjbUpdCfg {
-    static constexpr int SPW = NBU == 64 ? 2 : 4;
+    static constexpr int SPW = 2;
     static constexpr int PARTS = NMX / 16 / GjbCfg<NMX>::UWAVES / SPW;
     static constexpr int BLOCKS = PARTS * GjbCfg<NMX>::CHUNKS;
-    static_assert(PARTS >= 1 && (NBU == 32 || NBU == 64), "update shape");
+    static_assert(PARTS >= 1, "update shape");
 };
 
 struct GjbState {
@@ -466,27 +466,23 @@ __global__ __launch_bounds__(GjbCfg<NMX>::PNT) void gjb_panel_kernel(Job single,
 }
 
 // ---------------------------------------------------------------- update
-// The composite of the elimination steps of pivots kp .. kp + NB - 1 (one
-// panel, NB = 32, or two, NB = 64) applied to the columns [c_lo, c_hi) other
-// than [s_lo, s_hi): L is M's columns kp .. kp + NB - 1, the pivot rows'
-// entries are T rows tofs .. tofs + NB - 1.
-struct GjbUpd {
-    int kp, tofs, c_lo, c_hi, s_lo, s_hi;
-};
-
-template <int NMX, int NB>
-__device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, const GjbUpd& ua) {
+// The composite of the elimination steps of the pass's pivots k0 .. k0 +
+// NB - 1 (NB = 2 GJB_NB: both panels) applied to every column outside
+// [k0, k0 + NB): L is M's columns k0 .. k0 + NB - 1, the pivot rows' entries
+// are T's NB rows.
+template <int NMX>
+__device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, int k0) {
     using C = GjbCfg<NMX>;
-    using U = GjbUpdCfg<NMX, NB>;
+    using U = GjbUpdCfg<NMX>;
+    constexpr int NB = 2 * GJB_NB;
     constexpr int HS = U::SPW, GJB_SPW = U::SPW, GJB_UT = C::UT, GJB_UWAVES = C::UWAVES;
     constexpr int GJB_PARTS = U::PARTS, GJB_CHUNKS = C::CHUNKS;
-    const int n = j.n, k0 = ua.kp;
+    const int n = j.n;
     if (k0 >= n) return;
-    const int tl = ua.c_lo >> 4, th = (min(ua.c_hi, n) + 15) >> 4;  // column tiles
-    if (tl >= th) return;
+    const int ns = (n + 15) >> 4;  // column tiles
     const GjbView v = gjb_view(j, w);
     if (v.st->flag) return;
-    const double* __restrict__ Tg = v.Tg + (size_t)ua.tofs * v.ld;
+    const double* __restrict__ Tg = v.Tg;
     __shared__ unsigned char curpiv[GJ_NMAX];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -534,12 +530,12 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
         keep[u] = kb;
     }
     // chunk c owns a contiguous range [t0, t1) of the tiles, so successive
-    // tiles of a wave continue the same rows of M; tiles in [s_lo, s_hi) are
+    // tiles of a wave continue the same rows of M; the pass's four tiles are
     // skipped.  Software pipelined: the next tile's T block and strips are
     // loaded while this tile runs on MFMA and is stored.
-    const int t0 = tl + ((th - tl) * chunk) / GJB_CHUNKS, t1 = tl + ((th - tl) * (chunk + 1)) / GJB_CHUNKS;
+    const int t0 = (ns * chunk) / GJB_CHUNKS, t1 = (ns * (chunk + 1)) / GJB_CHUNKS;
     auto skip_panel = [&](int jt) {
-        while (jt < t1 && 16 * jt >= ua.s_lo && 16 * jt < ua.s_hi) ++jt;
+        while (jt < t1 && 16 * jt >= k0 && 16 * jt < k0 + NB) ++jt;
         return jt;  // t1 when none is left
     };
     // The T block of a tile (NB rows x 16 columns) is staged in LDS once per
@@ -640,13 +636,13 @@ __device__ __forceinline__ void gjb_update_body(const Job& j, int w, int sub, co
     }
 }
 
-template <int NMX, int NBU, bool BATCHED>
+template <int NMX, bool BATCHED>
 __global__ __launch_bounds__(GjbCfg<NMX>::UT) void gjb_update_kernel(Job single, const Job* jobs, const int* prefix,
-                                                                      int njobs, GjbUpd ua) {
-    gjb_block<BATCHED, true>(single, jobs, prefix, njobs, GjbUpdCfg<NMX, NBU>::BLOCKS,
-                       [&](const Job& j, int w, int sub) __attribute__((always_inline)) {
-                           gjb_update_body<NMX, NBU>(j, w, sub, ua);
-                       });
+                                                                      int njobs, int k0) {
+    gjb_block<BATCHED, true>(single, jobs, prefix, njobs, GjbUpdCfg<NMX>::BLOCKS,
+                             [&](const Job& j, int w, int sub) __attribute__((always_inline)) {
+                                 gjb_update_body<NMX>(j, w, sub, k0);
+                             });
 }
 
 // ---------------------------------------------------------------- finish
@@ -728,7 +724,7 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
         gjb_init_kernel<NMX, BATCHED, float><<<m * GJB_COPY_BLOCKS, C::PT, 0, st>>>(single, jobs, prefix, njobs);
     hipError_t e = hipGetLastError();
     constexpr int NB = GJB_NB;
-    const unsigned b64 = ((m + 7) / 8 * 8) * GjbUpdCfg<NMX, 64>::BLOCKS;  // XCD-aware block order
+    const unsigned bu = ((m + 7) / 8 * 8) * GjbUpdCfg<NMX>::BLOCKS;  // XCD-aware block order
     // two panels per pass: A = [k0, k0 + NB), B = [k0 + NB, k0 + 2 NB)
     for (int k0 = 0; k0 < nmax && e == hipSuccess; k0 += 2 * NB) {
         gjb_panel_kernel<NMX, BATCHED, false><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0, 0);
@@ -738,8 +734,7 @@ static hipError_t gjb_sequence_n(int mode, const Job& single, const Job* jobs, c
             gjb_panel_kernel<NMX, BATCHED, true><<<m, C::PNT, 0, st>>>(single, jobs, prefix, njobs, k0 + NB, NB);
         // every other column takes both panels' steps at once: rank 2 NB,
         // the matrix streamed once per pass
-        gjb_update_kernel<NMX, 64, BATCHED><<<b64, C::UT, 0, st>>>(
-            single, jobs, prefix, njobs, GjbUpd{k0, 0, 0, 1 << 30, k0, k0 + 2 * NB});
+        gjb_update_kernel<NMX, BATCHED><<<bu, C::UT, 0, st>>>(single, jobs, prefix, njobs, k0);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -758,7 +753,7 @@ static hipError_t gjb_sequence(int mode, const Job& single, const Job* jobs, con
 
 hipError_t launch_gjb(const Job& j, hipStream_t st) {
     if (!gj_blocked(j.n) || j.n > GJ_NMAX || !j.gjws) return hipErrorInvalidValue;
-    if (j.W > (int64_t)(0x7fffffff / GjbUpdCfg<GJ_NMAX, 2 * GJB_NB>::BLOCKS) - 8) return hipErrorInvalidValue;
+    if (j.W > (int64_t)(0x7fffffff / GjbUpdCfg<GJ_NMAX>::BLOCKS) - 8) return hipErrorInvalidValue;
     return gjb_sequence<false>(j.mode, j, nullptr, nullptr, 0, (int)j.W, j.n, st);
 }
 
