@@ -342,7 +342,7 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         const double topv = __longlong_as_double((long long)(top & ~0x3FFull));
         const int bad = !(topv > 0.0) ? 1 : (!isfinite(topv) ? 2 : 0);
         if (live && bad) {
-            if (tid == 0) v.st->flag = bad;
+            if (tid == 0) gmem(v.st)->flag = bad;
             fail = bad;
         }
         const int p = 0x3FF - (int)(top & 0x3FF);  // the pivot row (any row when bad)
@@ -353,7 +353,6 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
         if (tid == 0 && go) {
             perm_l[k] = p;
             piv_l[k] = pv;
-            v.perm[k0 + k] = p;
         }
         const bool piv = go && b == p;
         // other rows: P -= f (pivot row), P[k] = -f with f = P[k] / pv.  The
@@ -381,10 +380,14 @@ __device__ __forceinline__ void gjb_panel_body(const Job& j, int w, int k0, int 
             used = true;
             newpiv = true;
             sc = inv;
-            v.used[p] = 1;
         }
     });
     if (fail) return;
+    // the pivot order and row flags, written once the panel is done (a
+    // generic store in the column loop would make every later LDS wait
+    // include its completion)
+    if (tid < kn) gmem(v.perm)[k0 + tid] = perm_l[tid];
+    if (newpiv) gmem(v.used)[b] = 1;
 #pragma unroll
     for (int k = 0; k < NB; ++k) P[k] *= sc;  // the final L of this panel
     if constexpr (SECOND) {
