@@ -121,25 +121,6 @@ __device__ __forceinline__ void gjb_block(const Job& single, const Job* __restri
     }
 }
 
-// (|value|, row) argmax over the wavefront, smallest row on exact ties;
-// uniform result.
-__device__ __forceinline__ void wave_argmax(double& best, int& bi) {
-    argmax_step<0xB1>(best, bi);
-    argmax_step<0x4E>(best, bi);
-    argmax_step<0x141>(best, bi);
-    argmax_step<0x140>(best, bi);
-    double sb = readlane_f64(best, 0);
-    int si = __builtin_amdgcn_readlane(bi, 0);
-#pragma unroll
-    for (int rw = 1; rw < 4; ++rw) {
-        const double ob = readlane_f64(best, 16 * rw);
-        const int oi = __builtin_amdgcn_readlane(bi, 16 * rw);
-        if (ob > sb || (ob == sb && oi < si)) { sb = ob; si = oi; }
-    }
-    best = sb;
-    bi = si;
-}
-
 // ------------------------------------------------------------------ init
 // M[b][a] = D[b][a] = C_1[a][b] promoted to FP64 (32 x 32 tiles through
 // LDS: coalesced reads of C_1 rows, coalesced writes of M rows); row flags
